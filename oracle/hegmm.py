@@ -1,0 +1,304 @@
+"""Oracle HEGMM-En: planning, client packing, the cloud-side loop, unpacking.
+
+Test infrastructure only; shares no code with the GPU library.
+
+Follows Algorithm 2 (HEGMM-Enhanced) of the paper (Section III-C) built on the
+element-wise identity of Section III-A:
+
+    A.B = sum_{k<l} (eps^k o sigma(A)) (.) (omega^k o tau(B)),
+
+with the operand duplication of Theorems 5/6, column-major flattening, and the
+linear transforms realised by the diagonal method (Section III-B-1).  Readings
+where the paper is silent (layout of the result, removal of redundant partial
+products, when to relinearise, what to do when the operands do not fit one
+ciphertext) are the ones listed in the design notes and restated at each
+function below.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import bgv, ring
+from .ring import Params
+
+
+# ---------------------------------------------------------------------------
+# planning
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Plan:
+    m: int                 # original shape
+    l: int
+    n: int
+    transposed: bool       # solve B^T A^T instead (the p == n branch of Algorithm 2)
+    mo: int                # oriented problem: X (mo x l) times Y (l x no)
+    no: int
+    nb: int                # number of inner-dimension blocks (1 if the operands fit)
+    lb: int                # inner block length (zero padded)
+    d: int                 # duplication count of X (Theorem 5)
+    M: int                 # rows of the duplicated X, the column stride of the layout
+    K: int                 # loop trips
+    W: int                 # packed width of the left operand
+    eps: List[List[Tuple[int, Optional[frozenset]]]]    # per k: (z, mask slots or None)
+    omega: List[List[Tuple[int, Optional[frozenset]]]]
+    fold: List[int]        # rotation amounts summed after relinearisation (0 first)
+
+    def rotations(self, S: int) -> List[int]:
+        zs = set()
+        for terms in self.eps + self.omega:
+            for z, _ in terms:
+                if z % S:
+                    zs.add(z % S)
+        for z in self.fold:
+            if z % S:
+                zs.add(z % S)
+        return sorted(zs)
+
+
+def _constants(mo: int, lb: int, no: int):
+    d = -(-lb // mo) if mo < lb else 1
+    M = d * mo
+    K = min(mo, lb)
+    W = max(lb, no)
+    return d, M, K, W
+
+
+def orientation(m: int, l: int, n: int) -> bool:
+    """Transpose iff n is the strict smallest of (m, n) among the minima,
+    following Algorithm 2's if-order: p == m first, then p == n, else l."""
+    p = min(m, l, n)
+    if p == m:
+        return False
+    return p == n
+
+
+def plan(m: int, l: int, n: int, S: int) -> Plan:
+    if min(m, l, n) <= 0:
+        raise ValueError("dimensions must be positive")
+    tr = orientation(m, l, n)
+    mo, no = (n, m) if tr else (m, n)
+
+    def fits(lb):
+        d, M, K, W = _constants(mo, lb, no)
+        return M * W <= S
+
+    nb, lb = 1, l
+    if not fits(l):
+        nb = 2
+        while nb <= l and not fits(-(-l // nb)):
+            nb += 1
+        if nb > l:
+            raise ValueError("shape does not fit one ciphertext even with inner blocking")
+        lb = -(-l // nb)
+    d, M, K, W = _constants(mo, lb, no)
+    region = frozenset(i + j * M for i in range(M) for j in range(no))
+
+    eps, omega = [], []
+    for k in range(K):
+        eps.append(_terms(eps_diagonals(mo, lb, no, M, W, k), region, [k * M, (k - lb) * M]))
+        omega.append(_terms(omega_diagonals(lb, no, M, k), region, [k, k - lb]))
+    fold = [h * mo for h in range(d)]
+    return Plan(m, l, n, tr, mo, no, nb, lb, d, M, K, W, eps, omega, fold)
+
+
+def eps_diagonals(mo: int, lb: int, no: int, M: int, W: int, k: int) -> Dict[int, set]:
+    """Nonzero diagonals of eps^k_{M x no} on the packed left operand, as
+    {rotation z: output slots}.  Output (i, j) reads source column c = j + k,
+    or j + k - lb past the packed width W, i.e. slot i + c*M: a left rotation
+    by (c - j)*M.  Row block h = i // mo holds partial product (k + h*mo) mod
+    lb (Theorem 5); it is kept only when h*mo + k < lb, so that every partial
+    product is accumulated exactly once (the redundant copies of Algorithm 2
+    are dropped)."""
+    cand: Dict[int, set] = {}
+    for i in range(M):
+        if (i // mo) * mo + k >= lb:
+            continue
+        for j in range(no):
+            c = j + k if j + k < W else j + k - lb
+            cand.setdefault((c - j) * M, set()).add(i + j * M)
+    return cand
+
+
+def omega_diagonals(lb: int, no: int, M: int, k: int) -> Dict[int, set]:
+    """Nonzero diagonals of omega^k_{M x no}: output (i, j) reads source row
+    r = i + k, or i + k - lb past row M: a left rotation by r - i."""
+    cand: Dict[int, set] = {}
+    for i in range(M):
+        for j in range(no):
+            r = i + k if i + k < M else i + k - lb
+            cand.setdefault(r - i, set()).add(i + j * M)
+    return cand
+
+
+def _terms(cand: Dict[int, set], region: frozenset, order: Sequence[int]):
+    """Diagonal list in a fixed order; a lone diagonal covering the whole
+    output region needs no mask (None)."""
+    out = []
+    for z in order:
+        if z in cand and cand[z]:
+            out.append((z, frozenset(cand[z])))
+    assert sum(len(s) for _, s in out) == sum(len(s) for s in cand.values())
+    if len(out) == 1 and out[0][1] == region:
+        out = [(out[0][0], None)]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# client side: packing and unpacking
+# ---------------------------------------------------------------------------
+
+def oriented_operands(pl: Plan, A: np.ndarray, B: np.ndarray):
+    A = np.asarray(A, dtype=np.int64)
+    B = np.asarray(B, dtype=np.int64)
+    if pl.transposed:
+        return B.T.copy(), A.T.copy()
+    return A, B
+
+
+def pack_left(pl: Plan, X: np.ndarray, block: int, t: int, S: int) -> List[int]:
+    """x[i + c*M] = Xb[i mod mo][(i + c) mod lb] for i < M, c < W: the
+    client-side eps^0_{M x W}(sigma(Xbar)) of Algorithm 2, with Xbar the d
+    stacked copies of the block Xb, flattened column-major."""
+    Xb = np.zeros((pl.mo, pl.lb), dtype=np.int64)
+    lo = block * pl.lb
+    hi = min(pl.l, lo + pl.lb)
+    Xb[:, : hi - lo] = X[:, lo:hi]
+    x = [0] * S
+    for i in range(pl.M):
+        for c in range(pl.W):
+            x[i + c * pl.M] = int(Xb[i % pl.mo][(i + c) % pl.lb]) % t
+    return x
+
+
+def pack_right(pl: Plan, Y: np.ndarray, block: int, t: int, S: int) -> List[int]:
+    """y[r + j*M] = Yb[(r + j) mod lb][j] for r < M, j < no: the client-side
+    omega^0_{M x no}(tau(Yb)), flattened column-major."""
+    Yb = np.zeros((pl.lb, pl.no), dtype=np.int64)
+    lo = block * pl.lb
+    hi = min(pl.l, lo + pl.lb)
+    Yb[: hi - lo, :] = Y[lo:hi, :]
+    y = [0] * S
+    for r in range(pl.M):
+        for j in range(pl.no):
+            y[r + j * pl.M] = int(Yb[(r + j) % pl.lb][j]) % t
+    return y
+
+
+def unpack(pl: Plan, slots: Sequence[int]) -> np.ndarray:
+    """C[i][j] sits at slot i + j*M, or at j + i*M when the problem was transposed."""
+    C = np.zeros((pl.m, pl.n), dtype=np.int64)
+    for i in range(pl.m):
+        for j in range(pl.n):
+            s = (j + i * pl.M) if pl.transposed else (i + j * pl.M)
+            C[i, j] = int(slots[s])
+    return C
+
+
+# ---------------------------------------------------------------------------
+# cleartext twin: the same plan run on slot vectors mod t
+# ---------------------------------------------------------------------------
+
+def _rot_clear(v: Sequence[int], z: int) -> List[int]:
+    S = len(v)
+    return [v[(s + z) % S] for s in range(S)]
+
+
+def _rot_sum_clear(v, terms, t):
+    S = len(v)
+    out = [0] * S
+    for z, mask in terms:
+        r = _rot_clear(v, z)
+        for s in range(S):
+            if mask is None or s in mask:
+                out[s] = (out[s] + r[s]) % t
+    return out
+
+
+def hegmm_cleartext(pl: Plan, A, B, t: int, S: int) -> np.ndarray:
+    """Run the plan on unencrypted slot vectors: the packing/plan check that
+    needs no encryption."""
+    X, Y = oriented_operands(pl, A, B)
+    acc = [0] * S
+    for b in range(pl.nb):
+        x = pack_left(pl, X, b, t, S)
+        y = pack_right(pl, Y, b, t, S)
+        for k in range(pl.K):
+            e = _rot_sum_clear(x, pl.eps[k], t)
+            f = _rot_sum_clear(y, pl.omega[k], t)
+            acc = [(acc[s] + e[s] * f[s]) % t for s in range(S)]
+    acc = _rot_sum_clear(acc, [(z, None) for z in pl.fold], t)
+    return unpack(pl, acc)
+
+
+# ---------------------------------------------------------------------------
+# encrypted run
+# ---------------------------------------------------------------------------
+
+class MaskCache:
+    def __init__(self, P: Params):
+        self.P = P
+        self.cache: Dict[frozenset, bgv.Mask] = {}
+
+    def get(self, slots: frozenset) -> bgv.Mask:
+        m = self.cache.get(slots)
+        if m is None:
+            v = [0] * self.P.S
+            for s in slots:
+                v[s] = 1
+            m = bgv.Mask(self.P, v)
+            self.cache[slots] = m
+        return m
+
+
+def galois_elements(P: Params, shapes: Sequence[Tuple[int, int, int]]) -> List[int]:
+    gs = set()
+    for (m, l, n) in shapes:
+        pl = plan(m, l, n, P.S)
+        for z in pl.rotations(P.S):
+            gs.add(P.galois(z))
+    return sorted(gs)
+
+
+def encrypt_operand(ks: bgv.KeySet, pl: Plan, role: int, A, B, nonce: int) -> List[bgv.Ct]:
+    """Client preprocessing (Algorithm 2): pack and encrypt one operand, one
+    ciphertext per inner block.  role 0 = left (A side), 1 = right (B side)."""
+    P = ks.P
+    X, Y = oriented_operands(pl, A, B)
+    out = []
+    for b in range(pl.nb):
+        v = pack_left(pl, X, b, P.t, P.S) if role == 0 else pack_right(pl, Y, b, P.t, P.S)
+        out.append(bgv.encrypt_slots(ks, v, role=role, block=b, nonce=nonce))
+    return out
+
+
+def hegmm(ks: bgv.KeySet, pl: Plan, ctX: List[bgv.Ct], ctY: List[bgv.Ct],
+          masks: Optional[MaskCache] = None) -> bgv.Ct:
+    """Cloud side of Algorithm 2:  Acc = sum_{blocks, k < K} eps^k(ctX) x omega^k(ctY),
+    one relinearisation, then the fold sum_h Rot(R, h*mo) that gathers the d
+    row blocks (the extraction of Theorem 5's partial products)."""
+    P = ks.P
+    masks = masks or MaskCache(P)
+    acc = None
+    for b in range(pl.nb):
+        for k in range(pl.K):
+            e = bgv.rot_sum(P, ks, ctX[b], [(z, None if s is None else masks.get(s)) for z, s in pl.eps[k]])
+            f = bgv.rot_sum(P, ks, ctY[b], [(z, None if s is None else masks.get(s)) for z, s in pl.omega[k]])
+            prod = bgv.tensor(P, e, f)
+            acc = prod if acc is None else bgv.he_add(P, acc, prod)
+    R = bgv.relinearize(P, ks, acc)
+    if pl.d == 1:
+        return R
+    return bgv.rot_sum(P, ks, R, [(z, None) for z in pl.fold])
+
+
+def decrypt_result(ks: bgv.KeySet, pl: Plan, ct: bgv.Ct) -> np.ndarray:
+    return unpack(pl, bgv.decrypt_slots(ks, ct))
+
+
+def export_d7(ct: bgv.Ct) -> np.ndarray:
+    """Canonical serialisation: coefficient form, components then limbs, u64."""
+    return np.concatenate([np.ascontiguousarray(c, dtype=np.uint64).reshape(-1) for c in ct])

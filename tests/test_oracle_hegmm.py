@@ -1,0 +1,217 @@
+"""Pins for the oracle's HEGMM-En planner, packing and encrypted loop.
+
+Against the paper: the worked examples printed in its figure captions and
+text (tests/golden/paper_examples.json), the element-wise identity of
+Section III-A written out from the operator definitions, Theorem 5's
+coverage.  Against the mathematics: brute-force integer matrix products
+(decrypt(HEGMM(Enc A, Enc B)) == A.B mod t)."""
+import json
+import os
+import random
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import bgv, hegmm as H
+from oracle.ring import Params
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_examples.json")))
+
+
+# ---------------------------------------------------------------------------
+# Section III-A written out from the operator definitions (Eqs. sigma..omega)
+# ---------------------------------------------------------------------------
+
+def sigma(A):
+    m, l = len(A), len(A[0])
+    return [[A[i][(i + j) % l] for j in range(l)] for i in range(m)]
+
+
+def tau(B):
+    l, n = len(B), len(B[0])
+    return [[B[(i + j) % l][j] for j in range(n)] for i in range(l)]
+
+
+def eps(A, k, m, n):
+    l = len(A[0])
+    return [[A[i][(j + k) % l] for j in range(n)] for i in range(m)]
+
+
+def omega(B, k, m, n):
+    l = len(B)
+    return [[B[(i + k) % l][j] for j in range(n)] for i in range(m)]
+
+
+@pytest.mark.parametrize("shape", [(5, 3, 4), (2, 5, 7), (5, 4, 2), (1, 1, 1), (7, 1, 3), (3, 8, 3)])
+def test_elementwise_identity(shape):
+    m, l, n = shape
+    rng = random.Random(sum(shape))
+    A = [[rng.randrange(-9, 10) for _ in range(l)] for _ in range(m)]
+    B = [[rng.randrange(-9, 10) for _ in range(n)] for _ in range(l)]
+    sA, tB = sigma(A), tau(B)
+    C = [[0] * n for _ in range(m)]
+    for k in range(l):
+        e, w = eps(sA, k, m, n), omega(tB, k, m, n)
+        for i in range(m):
+            for j in range(n):
+                C[i][j] += e[i][j] * w[i][j]
+    want = [[sum(A[i][k] * B[k][j] for k in range(l)) for j in range(n)] for i in range(m)]
+    assert C == want
+
+
+# ---------------------------------------------------------------------------
+# worked examples printed in the paper
+# ---------------------------------------------------------------------------
+
+def test_figure_eps_example():
+    g = GOLDEN["eps1_5x3"]
+    d = H.eps_diagonals(g["M"], g["lb"], g["no"], g["M"], g["W"], g["k"])
+    assert {str(z): sorted(s) for z, s in d.items()} == g["diagonals"]
+
+
+def test_figure_omega_example():
+    g = GOLDEN["omega1_3x5"]
+    d = H.omega_diagonals(g["lb"], g["no"], g["M"], g["k"])
+    assert {str(z): len(s) for z, s in d.items()} == g["diagonal_sizes"]
+
+
+def _partials(pl, k):
+    """Partial products (k + h*mo) mod lb held by the row blocks kept at iteration k."""
+    kept = set()
+    for z, s in pl.eps[k]:
+        slots = range(pl.M * pl.no) if s is None else s
+        for x in slots:
+            kept.add((x % pl.M) // pl.mo)
+    return sorted((k + h * pl.mo) % pl.lb for h in kept)
+
+
+def test_duplicate_a_example():
+    g = GOLDEN["dupA_2x5x7"]
+    pl = H.plan(g["m"], g["l"], g["n"], 4096)
+    assert not pl.transposed and pl.d == g["d"] and pl.K == 2
+    assert _partials(pl, 0) == sorted(g["partials_k0"])
+    all_k1 = [(1 + h * pl.mo) % pl.lb for h in range(pl.d)]
+    assert all_k1 == g["partials_k1_all"]
+    assert _partials(pl, 1) == sorted(g["partials_k1_kept"])
+
+
+def test_duplicate_b_example():
+    g = GOLDEN["dupB_5x4x2"]
+    pl = H.plan(g["m"], g["l"], g["n"], 4096)
+    assert pl.transposed and pl.d == g["d"] and pl.K == 2
+    for k, want in g["partials"].items():
+        assert _partials(pl, int(k)) == want
+
+
+def test_iteration_count_example():
+    g = GOLDEN["alg1_5x3x4"]
+    pl = H.plan(g["m"], g["l"], g["n"], 4096)
+    assert pl.K == g["iterations"]
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 7), (3, 10, 4), (4, 9, 9), (6, 6, 6), (9, 4, 3), (5, 13, 2)])
+def test_theorem5_each_partial_once(shape):
+    m, l, n = shape
+    pl = H.plan(m, l, n, 4096)
+    seen = []
+    for k in range(pl.K):
+        seen += _partials(pl, k)
+    assert sorted(seen) == list(range(pl.lb))
+    assert pl.K == min(m, l, n) or pl.K == min(pl.mo, pl.lb)
+
+
+# ---------------------------------------------------------------------------
+# the plan on cleartext slot vectors vs brute-force matrix products
+# ---------------------------------------------------------------------------
+
+def test_cleartext_twin_random_shapes():
+    rng = np.random.default_rng(11)
+    for (m, l, n) in workloads.random_shapes(rng, 150, 1, 12):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        pl = H.plan(m, l, n, 256)
+        assert (H.hegmm_cleartext(pl, A, B, 12289, 256) == workloads.plain_matmul_mod(A, B, 12289)).all(), (m, l, n)
+        # at most two diagonals per transform, and <= 2 rotations each
+        assert all(len(t) <= 2 for t in pl.eps + pl.omega)
+
+
+def test_cleartext_twin_blocked_shapes():
+    rng = np.random.default_rng(12)
+    count = 0
+    for (m, l, n) in workloads.random_shapes(rng, 300, 2, 30):
+        try:
+            pl = H.plan(m, l, n, 64)
+        except ValueError:
+            assert m * n > 64
+            continue
+        if pl.nb == 1:
+            continue
+        count += 1
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        assert (H.hegmm_cleartext(pl, A, B, 12289, 64) == workloads.plain_matmul_mod(A, B, 12289)).all(), (m, l, n)
+        if count > 40:
+            break
+    assert count > 10
+
+
+def test_headline_plan_counts():
+    pl = H.plan(64, 32, 48, 4096)
+    assert (pl.transposed, pl.d, pl.M, pl.K, pl.W, pl.nb) == (False, 1, 64, 32, 48, 1)
+    assert len(pl.rotations(4096)) == 124
+    tiny = H.plan(4, 3, 5, 512)
+    assert sorted(z if z < 256 else z - 512 for z in tiny.rotations(512)) == [-8, -4, -2, -1, 1, 2, 4, 8]
+    large = H.plan(128, 96, 128, 16384)
+    assert large.nb == 1 and large.M * large.W == 16384
+
+
+def test_batched_grid_fit_counts():
+    grid = range(8, 65, 8)
+    fit = sum(1 for m in grid for l in grid for n in grid if H.plan(m, l, n, 4096).nb == 1)
+    assert fit == 468
+
+
+# ---------------------------------------------------------------------------
+# encrypted end to end
+# ---------------------------------------------------------------------------
+
+def run_encrypted(P, shapes, seed):
+    ks = bgv.KeySet(P, seed, H.galois_elements(P, shapes))
+    rng = np.random.default_rng(seed)
+    masks = H.MaskCache(P)
+    for idx, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        pl = H.plan(m, l, n, P.S)
+        cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=idx)
+        cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=idx)
+        C = H.hegmm(ks, pl, cx, cy, masks)
+        assert len(C) == 2
+        got = H.decrypt_result(ks, pl, C)
+        assert (got == workloads.plain_matmul_mod(A, B, P.t)).all(), (m, l, n)
+
+
+def test_encrypted_small_shapes_alpha1():
+    P = Params(128, 12289, 3, 1)
+    # d > 1 (fold), transposed, l-min, square, blocked (M*W > 64)
+    run_encrypted(P, [(2, 5, 7), (5, 4, 2), (6, 3, 5), (4, 4, 4), (3, 11, 6), (1, 6, 1)], 77)
+
+
+def test_encrypted_small_shapes_alpha2():
+    P = Params(128, 12289, 4, 2)
+    run_encrypted(P, [(3, 7, 5), (7, 5, 3), (2, 9, 4)], 78)
+
+
+def test_tiny_config_end_to_end():
+    cfg = workloads.TINY
+    P = Params(cfg.N, cfg.t, cfg.L, cfg.alpha)
+    A, B = workloads.tiny_operands()
+    pl = H.plan(4, 3, 5, P.S)
+    ks = bgv.KeySet(P, cfg.seed, H.galois_elements(P, [(4, 3, 5)]))
+    cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=1)
+    cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=1)
+    C = H.hegmm(ks, pl, cx, cy)
+    assert (H.decrypt_result(ks, pl, C) == workloads.plain_matmul_mod(A, B, P.t)).all()
+    mu = bgv.decrypt_poly(ks, C)
+    assert bgv.noise_bits(ks, C, mu) < np.log2(float(P.Q)) - 2
