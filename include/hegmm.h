@@ -1,0 +1,176 @@
+/*
+ * hegmm.h -- C ABI of the MI355X (gfx950) HE matrix-multiplication library.
+ *
+ * Problem (the paper's Section III-A): C_{m x n} = A_{m x l} x B_{l x n} for
+ * arbitrary positive m, l, n, computed on encrypted operands.  Clients encrypt
+ * A and B, the cloud multiplies the ciphertexts, clients decrypt (Section II-A
+ * and the client/cloud split of Algorithm 2: preprocessing on the client,
+ * multiplication on the cloud, encrypted result returned).  The cloud-side
+ * method is HEGMM-Enhanced (Algorithm 2, Section III-C), built from the SIMD
+ * primitives HE-Add, HE-Mult, HE-CMult and HE-Rot over the ring
+ * Z_q[X]/(X^N + 1) (Section IV-A), realised here as BGV with hybrid key
+ * switching.
+ *
+ * Conventions common to every call:
+ *  - Every function returns hg_status; 0 is success, a negative value an
+ *    error, and hg_last_error() then gives a thread-local message.
+ *  - Handles (hg_ctx, hg_ct) are opaque and owned by the caller, who frees
+ *    them with hg_ctx_destroy / hg_ct_free.  The library never frees caller
+ *    memory and keeps no caller pointer after a call returns.
+ *  - Host pointers (matrices, serialisation buffers, shapes) are plain host
+ *    memory read or written before the call returns.  Ciphertext payloads
+ *    live in device memory owned by their hg_ct.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    hg_hegmm / hg_rotate / hg_mul only enqueue work; their outputs are valid
+ *    once the stream reaches that point.  Inputs must stay alive until then.
+ *  - Matrix entries are signed 64-bit integers reduced mod t (negative values
+ *    map to value + t); results are returned in [0, t).
+ *  - Not thread safe: one thread per context at a time.
+ */
+#ifndef HEGMM_H
+#define HEGMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hg_status;
+enum {
+    HG_OK = 0,
+    HG_EINVAL = -1,   /* bad argument: non-positive dimension, null pointer, mismatched handles */
+    HG_ENOFIT = -2,   /* shape cannot be planned into one ciphertext row, even with inner blocking */
+    HG_ENOKEY = -3,   /* a rotation key this shape needs was not generated */
+    HG_ENOMEM = -4,   /* device or host allocation failed */
+    HG_EDEVICE = -5,  /* HIP runtime error, or no gfx950 device */
+    HG_ESTATE = -6    /* call not allowed in this state (e.g. encrypt after hg_drop_secret) */
+};
+
+typedef struct hg_ctx hg_ctx;  /* parameters, device tables, device-resident evaluation keys */
+typedef struct hg_ct hg_ct;    /* one packed operand/result: nb >= 1 ciphertexts on the device */
+
+/* BGV parameter set.  N: ring degree, a power of two in [64, 16384].
+ * t: plaintext modulus, prime, t = 1 (mod 2N) so that all N/2 slots of a
+ * rotation row are usable.  L: ciphertext primes (1..12).  alpha: special
+ * primes, also the number of primes per key-switching digit (1..4, L+alpha
+ * <= 16).  The primes are the first L+alpha primes below 2^50 that are
+ * 1 (mod 2N), in descending order; the alpha largest are the special ones.
+ * The error distribution is the discrete Gaussian of width 3.2 on [-19, 19]. */
+typedef struct {
+    uint32_t N;
+    uint64_t t;
+    uint32_t L;
+    uint32_t alpha;
+} hg_params;
+
+/* Create a context on HIP device `hip_device` (must be gfx950).
+ * Errors: HG_EINVAL (parameters out of range), HG_EDEVICE, HG_ENOMEM. */
+hg_status hg_ctx_create(const hg_params *params, int hip_device, hg_ctx **out);
+void hg_ctx_destroy(hg_ctx *ctx);
+
+/* Key generation (client role).  Samples the secret key from `seed` and
+ * generates, on the device, the relinearisation key and every rotation key
+ * that the HEGMM-En plans of the given shapes need.  `shapes` holds nshapes
+ * triples (m, l, n), row after row.  May be called again to add the keys of
+ * more shapes under the same seed.  Errors: HG_EINVAL, HG_ENOFIT (a shape
+ * cannot be planned), HG_ESTATE (after hg_drop_secret with a new seed). */
+hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t nshapes);
+
+/* Forget the secret key (server role): evaluation keys stay, encrypt and
+ * decrypt then fail with HG_ESTATE while hg_hegmm still works. */
+hg_status hg_drop_secret(hg_ctx *ctx);
+
+/* Client preprocessing of Algorithm 2: pack one operand of the product
+ * A (m x l) x B (l x n) for the cloud and encrypt it.  role 0: X points to
+ * A (row-major m x l); role 1: X points to B (row-major l x n).  The packing
+ * depends on the whole shape (duplication count, orientation, inner
+ * blocking).  `nonce` selects the encryption randomness; the same (role,
+ * nonce, shape) must not be reused for different data.  *out receives a new
+ * handle.  Errors: HG_EINVAL, HG_ENOFIT, HG_ESTATE. */
+hg_status hg_encrypt(hg_ctx *ctx, int role, const int64_t *X, int m, int l, int n,
+                     uint64_t nonce, hg_ct **out);
+
+/* Cloud multiplication of Algorithm 2 (HEGMM-En) on encrypted operands made
+ * by hg_encrypt for the same (m, l, n).  *ctC receives a new result handle;
+ * the work is enqueued on `stream`.  Errors: HG_EINVAL (shape differs from
+ * the operands'), HG_ENOFIT, HG_ENOKEY, HG_EDEVICE. */
+hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n,
+                   hg_ct **ctC, void *stream);
+
+/* Many independent HE matmuls of (possibly) different shapes in one call.
+ * mln holds cnt triples.  The products share the launches of each phase
+ * (one hoisting launch, one key-switching launch, ...), and rotations that
+ * several products need read each key once per launch.  C[i] receives new
+ * handles.  Errors as hg_hegmm; on error no handle is returned. */
+hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B,
+                         const int32_t *mln, hg_ct **C, void *stream);
+
+/* Decrypt a result made by hg_hegmm for shape (m, l, n) and unpack it into
+ * C (row-major m x n, values in [0, t)).  Synchronises the device.
+ * Errors: HG_EINVAL, HG_ESTATE. */
+hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ctC, int m, int l, int n, uint64_t *C);
+
+/* Canonical serialisation: coefficient form, residues in [0, q_i), the
+ * ciphertexts of the handle in order, each component c0 then c1 (then c2),
+ * each limb q_0..q_{L-1}, N little-endian u64 words per limb.  *needed gets
+ * the word count; buf may be NULL to query it.  Errors: HG_EINVAL (buffer
+ * too small). */
+hg_status hg_ct_export(hg_ctx *ctx, const hg_ct *ct, uint64_t *buf, size_t nwords, size_t *needed);
+
+/* Rebuild a handle from hg_ct_export output (ncts ciphertexts of
+ * `components` components each).  Words must be residues in [0, q_i).
+ * Errors: HG_EINVAL. */
+hg_status hg_ct_import(hg_ctx *ctx, const uint64_t *buf, size_t nwords, int ncts, int components,
+                       hg_ct **out);
+
+void hg_ct_free(hg_ct *ct);
+
+/* ---- single-ciphertext primitives (Section II-A set) ----------------- */
+
+/* Encrypt / decrypt a raw slot vector (row 0: S = N/2 values mod t; row 1 is
+ * zero).  Errors: HG_EINVAL, HG_ESTATE. */
+hg_status hg_encrypt_slots(hg_ctx *ctx, const int64_t *slots, uint64_t nonce, hg_ct **out);
+hg_status hg_decrypt_slots(hg_ctx *ctx, const hg_ct *ct, uint64_t *slots);
+
+/* HE-Rot: left rotation of the slots by z (negative z rotates right).  Needs
+ * the rotation key of z (generated by hg_keygen_rotations or as part of a
+ * shape's plan).  Errors: HG_ENOKEY, HG_EINVAL. */
+hg_status hg_rotate(hg_ctx *ctx, const hg_ct *ct, int z, hg_ct **out, void *stream);
+
+/* Generate rotation keys for explicit amounts (client role). */
+hg_status hg_keygen_rotations(hg_ctx *ctx, const int32_t *z, size_t count);
+
+/* HE-Mult: tensor product followed by relinearisation. */
+hg_status hg_mul(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void *stream);
+
+/* HE-Add. */
+hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void *stream);
+
+/* HE-CMult by a 0/1 (or any mod-t) slot vector of length S. */
+hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream);
+
+/* ---- introspection ---------------------------------------------------- */
+
+/* Plan of a shape: out[0..9] = transposed, nb, lb, d, M, K, W, rotations,
+ * masked diagonals, key-switched terms. Errors: HG_EINVAL, HG_ENOFIT. */
+hg_status hg_plan_info(hg_ctx *ctx, int m, int l, int n, int64_t *out10);
+
+/* The primes of the context: out[0..L-1] = q_0.., out[L..L+alpha-1] = p_0.. */
+hg_status hg_primes(hg_ctx *ctx, uint64_t *out);
+
+/* Per-phase timing of the last hg_hegmm / hg_hegmm_batch call in
+ * milliseconds, measured with HIP events on its stream (out[0..7]:
+ * hoist, inner product, division by P, tensor/accumulate, relinearise,
+ * fold, total, inner-product kernel alone).  Only filled when timing was
+ * enabled with hg_set_timing(ctx, 1); synchronises the stream. */
+hg_status hg_set_timing(hg_ctx *ctx, int enable);
+hg_status hg_last_timing(hg_ctx *ctx, double *out8);
+
+const char *hg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

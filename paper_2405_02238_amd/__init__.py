@@ -1,0 +1,266 @@
+"""Python binding of the MI355X HE matrix-multiplication library (libhegmm.so).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+The binding loads the in-tree `libhegmm.so` (built by `build.py`) and raises
+if it is missing; there is no fallback.  torch is used only to name the HIP
+stream work is enqueued on.
+
+Names follow include/hegmm.h: keygen / encrypt / hegmm / decrypt are the
+client-encrypt, cloud-multiply, client-decrypt split of the paper's
+Algorithm 2 (HEGMM-Enhanced) for C = A x B of arbitrary shape.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhegmm.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hegmm.h")
+
+HG_OK, HG_EINVAL, HG_ENOFIT, HG_ENOKEY, HG_ENOMEM, HG_EDEVICE, HG_ESTATE = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {-1: "EINVAL", -2: "ENOFIT", -3: "ENOKEY", -4: "ENOMEM", -5: "EDEVICE", -6: "ESTATE"}
+
+
+class HGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_uint32),
+                ("alpha", ctypes.c_uint32)]
+
+
+_lib = None
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+_SIGS = {
+    "hg_ctx_create": [ctypes.POINTER(_Params), ctypes.c_int, _PP],
+    "hg_keygen": [_P, ctypes.c_uint64, _i32p, ctypes.c_size_t],
+    "hg_keygen_rotations": [_P, _i32p, ctypes.c_size_t],
+    "hg_drop_secret": [_P],
+    "hg_encrypt": [_P, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _PP],
+    "hg_hegmm": [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _PP, _P],
+    "hg_hegmm_batch": [_P, ctypes.c_size_t, _PP, _PP, _i32p, _PP, _P],
+    "hg_decrypt": [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p],
+    "hg_ct_export": [_P, _P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
+    "hg_ct_import": [_P, _u64p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _PP],
+    "hg_encrypt_slots": [_P, _i64p, ctypes.c_uint64, _PP],
+    "hg_decrypt_slots": [_P, _P, _u64p],
+    "hg_rotate": [_P, _P, ctypes.c_int, _PP, _P],
+    "hg_mul": [_P, _P, _P, _PP, _P],
+    "hg_add": [_P, _P, _P, _PP, _P],
+    "hg_cmul": [_P, _P, _i64p, _PP, _P],
+    "hg_plan_info": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p],
+    "hg_primes": [_P, _u64p],
+    "hg_set_timing": [_P, ctypes.c_int],
+    "hg_last_timing": [_P, _f64p],
+}
+
+
+def declared_symbols() -> List[str]:
+    """Every entry point declared in include/hegmm.h."""
+    import re
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hg_[a-z_0-9]+)\s*\(", text)))
+
+
+def load(path: str = LIB_PATH):
+    """Load libhegmm.so; raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2405_02238_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    lib.hg_ctx_destroy.argtypes = [_P]
+    lib.hg_ctx_destroy.restype = None
+    lib.hg_ct_free.argtypes = [_P]
+    lib.hg_ct_free.restype = None
+    lib.hg_last_error.argtypes = []
+    lib.hg_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int):
+    if code != HG_OK:
+        raise HGError(code, _lib.hg_last_error().decode())
+
+
+def current_stream() -> Optional[int]:
+    """The HIP stream torch currently uses on its device (None: null stream)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+class Ciphertext:
+    """Handle of a device ciphertext (packed operand, result or raw slot ct)."""
+
+    def __init__(self, ctx: "Context", ptr: int):
+        self.ctx = ctx
+        self.ptr = ptr
+
+    def free(self):
+        if self.ptr:
+            _lib.hg_ct_free(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def export(self) -> np.ndarray:
+        """Canonical serialisation (coefficient form, residues in [0, q_i))."""
+        need = ctypes.c_size_t(0)
+        _check(_lib.hg_ct_export(self.ctx.ptr, self.ptr, None, 0, ctypes.byref(need)))
+        buf = np.empty(need.value, dtype=np.uint64)
+        _check(_lib.hg_ct_export(self.ctx.ptr, self.ptr, buf.ctypes.data, need.value, ctypes.byref(need)))
+        return buf
+
+
+class Context:
+    """hg_ctx: one BGV parameter set on one GPU."""
+
+    def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0):
+        load()
+        p = _Params(N, t, L, alpha)
+        out = ctypes.c_void_p()
+        _check(_lib.hg_ctx_create(ctypes.byref(p), device, ctypes.byref(out)))
+        self.ptr = out.value
+        self.N, self.t, self.L, self.alpha = N, t, L, alpha
+        self.S = N // 2
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            _lib.hg_ctx_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ct(self, out: ctypes.c_void_p) -> Ciphertext:
+        return Ciphertext(self, out.value)
+
+    def keygen(self, seed: int, shapes: Sequence[Tuple[int, int, int]] = ()):
+        arr = np.ascontiguousarray(np.array(list(shapes), dtype=np.int32).reshape(-1))
+        _check(_lib.hg_keygen(self.ptr, seed, arr, len(shapes)))
+
+    def keygen_rotations(self, zs: Sequence[int]):
+        arr = np.ascontiguousarray(np.array(list(zs), dtype=np.int32))
+        _check(_lib.hg_keygen_rotations(self.ptr, arr, len(arr)))
+
+    def drop_secret(self):
+        _check(_lib.hg_drop_secret(self.ptr))
+
+    def encrypt(self, role: int, X: np.ndarray, m: int, l: int, n: int, nonce: int = 0) -> Ciphertext:
+        X = np.ascontiguousarray(np.asarray(X, dtype=np.int64).reshape(-1))
+        out = ctypes.c_void_p()
+        _check(_lib.hg_encrypt(self.ptr, role, X, m, l, n, nonce, ctypes.byref(out)))
+        return self._ct(out)
+
+    def hegmm(self, A: Ciphertext, B: Ciphertext, m: int, l: int, n: int, stream: Optional[int] = None) -> Ciphertext:
+        out = ctypes.c_void_p()
+        s = current_stream() if stream is None else stream
+        _check(_lib.hg_hegmm(self.ptr, A.ptr, B.ptr, m, l, n, ctypes.byref(out), s))
+        return self._ct(out)
+
+    def hegmm_batch(self, As: Sequence[Ciphertext], Bs: Sequence[Ciphertext], shapes, stream=None) -> List[Ciphertext]:
+        cnt = len(As)
+        pa = (ctypes.c_void_p * cnt)(*[a.ptr for a in As])
+        pb = (ctypes.c_void_p * cnt)(*[b.ptr for b in Bs])
+        pc = (ctypes.c_void_p * cnt)()
+        mln = np.ascontiguousarray(np.array(list(shapes), dtype=np.int32).reshape(-1))
+        s = current_stream() if stream is None else stream
+        _check(_lib.hg_hegmm_batch(self.ptr, cnt, ctypes.cast(pa, _PP), ctypes.cast(pb, _PP), mln,
+                                   ctypes.cast(pc, _PP), s))
+        return [Ciphertext(self, pc[i]) for i in range(cnt)]
+
+    def decrypt(self, C: Ciphertext, m: int, l: int, n: int) -> np.ndarray:
+        out = np.empty(m * n, dtype=np.uint64)
+        _check(_lib.hg_decrypt(self.ptr, C.ptr, m, l, n, out))
+        return out.reshape(m, n).astype(np.int64)
+
+    def import_ct(self, words: np.ndarray, ncts: int, comps: int = 2) -> Ciphertext:
+        w = np.ascontiguousarray(words, dtype=np.uint64)
+        out = ctypes.c_void_p()
+        _check(_lib.hg_ct_import(self.ptr, w, w.size, ncts, comps, ctypes.byref(out)))
+        return self._ct(out)
+
+    def encrypt_slots(self, slots: Sequence[int], nonce: int = 0) -> Ciphertext:
+        v = np.zeros(self.S, dtype=np.int64)
+        v[: len(slots)] = np.asarray(slots, dtype=np.int64)
+        out = ctypes.c_void_p()
+        _check(_lib.hg_encrypt_slots(self.ptr, v, nonce, ctypes.byref(out)))
+        return self._ct(out)
+
+    def decrypt_slots(self, ct: Ciphertext) -> np.ndarray:
+        out = np.empty(self.S, dtype=np.uint64)
+        _check(_lib.hg_decrypt_slots(self.ptr, ct.ptr, out))
+        return out.astype(np.int64)
+
+    def rotate(self, ct: Ciphertext, z: int, stream=None) -> Ciphertext:
+        out = ctypes.c_void_p()
+        _check(_lib.hg_rotate(self.ptr, ct.ptr, z, ctypes.byref(out), current_stream() if stream is None else stream))
+        return self._ct(out)
+
+    def mul(self, a: Ciphertext, b: Ciphertext, stream=None) -> Ciphertext:
+        out = ctypes.c_void_p()
+        _check(_lib.hg_mul(self.ptr, a.ptr, b.ptr, ctypes.byref(out), current_stream() if stream is None else stream))
+        return self._ct(out)
+
+    def add(self, a: Ciphertext, b: Ciphertext, stream=None) -> Ciphertext:
+        out = ctypes.c_void_p()
+        _check(_lib.hg_add(self.ptr, a.ptr, b.ptr, ctypes.byref(out), current_stream() if stream is None else stream))
+        return self._ct(out)
+
+    def cmul(self, a: Ciphertext, slots: Sequence[int], stream=None) -> Ciphertext:
+        v = np.zeros(self.S, dtype=np.int64)
+        v[: len(slots)] = np.asarray(slots, dtype=np.int64)
+        out = ctypes.c_void_p()
+        _check(_lib.hg_cmul(self.ptr, a.ptr, v, ctypes.byref(out), current_stream() if stream is None else stream))
+        return self._ct(out)
+
+    def plan_info(self, m: int, l: int, n: int) -> dict:
+        out = np.zeros(10, dtype=np.int64)
+        _check(_lib.hg_plan_info(self.ptr, m, l, n, out))
+        keys = ["transposed", "nb", "lb", "d", "M", "K", "W", "rotations", "masks", "ks_terms"]
+        return dict(zip(keys, (int(x) for x in out)))
+
+    def primes(self) -> List[int]:
+        out = np.zeros(self.L + self.alpha, dtype=np.uint64)
+        _check(_lib.hg_primes(self.ptr, out))
+        return [int(x) for x in out]
+
+    def set_timing(self, on: bool):
+        _check(_lib.hg_set_timing(self.ptr, 1 if on else 0))
+
+    def last_timing(self) -> dict:
+        out = np.zeros(8, dtype=np.float64)
+        _check(_lib.hg_last_timing(self.ptr, out))
+        keys = ["hoist", "inner_product", "div_by_p", "tensor", "relin", "fold", "total", "ip_kernel"]
+        return dict(zip(keys, (float(x) for x in out)))

@@ -1,0 +1,309 @@
+// extern "C" entry points declared in include/hegmm.h.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <string>
+
+#include "../../include/hegmm.h"
+#include "context.h"
+
+struct hg_ctx {
+    hg::Ctx *c;
+};
+struct hg_ct {
+    hg::Ct *c;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+template <class F>
+hg_status guard(F &&f) {
+    try {
+        f();
+        return HG_OK;
+    } catch (hg::Error &e) {
+        g_err = e.what();
+        return e.code;
+    } catch (std::bad_alloc &) {
+        g_err = "host allocation failed";
+        return HG_ENOMEM;
+    } catch (std::exception &e) {
+        g_err = e.what();
+        return HG_EINVAL;
+    }
+}
+
+void need(bool cond, const char *msg) {
+    if (!cond) throw hg::Error(HG_EINVAL, msg);
+}
+
+hg_ct *wrap(hg::Ct *c) {
+    hg_ct *h = new hg_ct;
+    h->c = c;
+    return h;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+
+extern "C" {
+
+const char *hg_last_error(void) { return g_err.c_str(); }
+
+hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
+    return guard([&] {
+        need(p && out, "null argument");
+        *out = nullptr;
+        hg::Ctx *c = new hg::Ctx(p->N, p->t, p->L, p->alpha, dev);
+        hg_ctx *h = new hg_ctx;
+        h->c = c;
+        *out = h;
+    });
+}
+
+void hg_ctx_destroy(hg_ctx *ctx) {
+    if (!ctx) return;
+    delete ctx->c;
+    delete ctx;
+}
+
+hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t nshapes) {
+    return guard([&] {
+        need(ctx && (shapes || nshapes == 0), "null argument");
+        hg::Ctx &C = *ctx->c;
+        HGCHK(hipSetDevice(C.device));
+        std::vector<int> gal;
+        for (size_t i = 0; i < nshapes; ++i) {
+            const hg::PlanEntry &pe = C.plan_for(shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
+            for (int z : pe.plan.rotations(C.S)) gal.push_back(C.galois_of(z));
+        }
+        C.keygen(seed, gal);
+    });
+}
+
+hg_status hg_keygen_rotations(hg_ctx *ctx, const int32_t *z, size_t count) {
+    return guard([&] {
+        need(ctx && (z || count == 0), "null argument");
+        hg::Ctx &C = *ctx->c;
+        if (!C.has_secret) throw hg::Error(HG_ESTATE, "keygen with a seed first");
+        HGCHK(hipSetDevice(C.device));
+        std::vector<int> gal;
+        for (size_t i = 0; i < count; ++i) gal.push_back(C.galois_of(z[i]));
+        C.keygen(C.seed, gal);
+    });
+}
+
+hg_status hg_drop_secret(hg_ctx *ctx) {
+    return guard([&] {
+        need(ctx, "null context");
+        ctx->c->drop_secret();
+    });
+}
+
+hg_status hg_encrypt(hg_ctx *ctx, int role, const int64_t *X, int m, int l, int n, uint64_t nonce, hg_ct **out) {
+    return guard([&] {
+        need(ctx && X && out, "null argument");
+        *out = nullptr;
+        need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
+        HGCHK(hipSetDevice(ctx->c->device));
+        *out = wrap(ctx->c->encrypt_matrix(role, X, m, l, n, nonce));
+    });
+}
+
+hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B, const int32_t *mln,
+                         hg_ct **C, void *stream) {
+    std::vector<hg::Ct *> made;
+    hg_status st = guard([&] {
+        need(ctx && A && B && mln && C, "null argument");
+        hg::Ctx &X = *ctx->c;
+        HGCHK(hipSetDevice(X.device));
+        std::vector<hg::Ctx::Request> reqs;
+        for (size_t i = 0; i < cnt; ++i) {
+            need(A[i] && B[i], "null operand");
+            need(A[i]->c->ctx == &X && B[i]->c->ctx == &X, "operand from another context");
+            need(mln[3 * i] > 0 && mln[3 * i + 1] > 0 && mln[3 * i + 2] > 0, "dimensions must be positive");
+            hg::Ct *o = new hg::Ct();
+            o->ctx = &X;
+            o->ncts = 1;
+            o->comps = 2;
+            o->m = mln[3 * i]; o->l = mln[3 * i + 1]; o->n = mln[3 * i + 2];
+            o->side = 2;
+            made.push_back(o);
+            o->d = X.dev_alloc(o->words());
+            reqs.push_back({A[i]->c, B[i]->c, mln[3 * i], mln[3 * i + 1], mln[3 * i + 2], o});
+        }
+        X.hegmm_batch(reqs, as_stream(stream));
+    });
+    if (st != HG_OK) {
+        for (auto *o : made) delete o;
+        return st;
+    }
+    for (size_t i = 0; i < cnt; ++i) C[i] = wrap(made[i]);
+    return HG_OK;
+}
+
+hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n, hg_ct **ctC, void *stream) {
+    if (ctC) *ctC = nullptr;
+    int32_t mln[3] = {m, l, n};
+    return hg_hegmm_batch(ctx, 1, &ctA, &ctB, mln, ctC, stream);
+}
+
+hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ct, int m, int l, int n, uint64_t *C) {
+    return guard([&] {
+        need(ctx && ct && C, "null argument");
+        hg::Ctx &X = *ctx->c;
+        need(ct->c->side == 2 && ct->c->m == m && ct->c->l == l && ct->c->n == n, "not a result of this shape");
+        HGCHK(hipSetDevice(X.device));
+        HGCHK(hipDeviceSynchronize());
+        const hg::PlanEntry &pe = X.plan_for(m, l, n);
+        std::vector<uint64_t> slots = X.decrypt_slot_values(*ct->c, 0);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < n; ++j) C[(size_t)i * n + j] = slots[hg::result_slot(pe.plan, i, j)];
+    });
+}
+
+hg_status hg_ct_export(hg_ctx *ctx, const hg_ct *ct, uint64_t *buf, size_t nwords, size_t *needed) {
+    return guard([&] {
+        need(ctx && ct, "null argument");
+        const size_t w = ct->c->words();
+        if (needed) *needed = w;
+        if (!buf) return;
+        need(nwords >= w, "buffer too small");
+        HGCHK(hipSetDevice(ctx->c->device));
+        HGCHK(hipDeviceSynchronize());
+        ctx->c->export_ct(*ct->c, buf, nullptr);
+    });
+}
+
+hg_status hg_ct_import(hg_ctx *ctx, const uint64_t *buf, size_t nwords, int ncts, int comps, hg_ct **out) {
+    return guard([&] {
+        need(ctx && buf && out, "null argument");
+        *out = nullptr;
+        need(ncts > 0 && (comps == 2 || comps == 3), "bad ciphertext count or component count");
+        hg::Ctx &X = *ctx->c;
+        need(nwords == (size_t)ncts * comps * X.L * X.N, "word count does not match");
+        HGCHK(hipSetDevice(X.device));
+        *out = wrap(X.import_ct(buf, ncts, comps, nullptr));
+    });
+}
+
+void hg_ct_free(hg_ct *ct) {
+    if (!ct) return;
+    delete ct->c;
+    delete ct;
+}
+
+hg_status hg_encrypt_slots(hg_ctx *ctx, const int64_t *slots, uint64_t nonce, hg_ct **out) {
+    return guard([&] {
+        need(ctx && slots && out, "null argument");
+        *out = nullptr;
+        hg::Ctx &X = *ctx->c;
+        HGCHK(hipSetDevice(X.device));
+        std::vector<uint64_t> v(X.S);
+        for (int s = 0; s < X.S; ++s) {
+            int64_t r = slots[s] % (int64_t)X.t;
+            v[s] = (uint64_t)(r < 0 ? r + (int64_t)X.t : r);
+        }
+        *out = wrap(X.encrypt_slots(v, 2, 0, nonce));
+    });
+}
+
+hg_status hg_decrypt_slots(hg_ctx *ctx, const hg_ct *ct, uint64_t *slots) {
+    return guard([&] {
+        need(ctx && ct && slots, "null argument");
+        hg::Ctx &X = *ctx->c;
+        HGCHK(hipSetDevice(X.device));
+        HGCHK(hipDeviceSynchronize());
+        std::vector<uint64_t> v = X.decrypt_slot_values(*ct->c, 0);
+        std::memcpy(slots, v.data(), v.size() * sizeof(uint64_t));
+    });
+}
+
+hg_status hg_rotate(hg_ctx *ctx, const hg_ct *ct, int z, hg_ct **out, void *stream) {
+    return guard([&] {
+        need(ctx && ct && out, "null argument");
+        *out = nullptr;
+        *out = wrap(ctx->c->rotate(*ct->c, z, as_stream(stream)));
+    });
+}
+
+hg_status hg_mul(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void *stream) {
+    return guard([&] {
+        need(ctx && a && b && out, "null argument");
+        *out = nullptr;
+        *out = wrap(ctx->c->mul(*a->c, *b->c, as_stream(stream)));
+    });
+}
+
+hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void *stream) {
+    return guard([&] {
+        need(ctx && a && b && out, "null argument");
+        *out = nullptr;
+        *out = wrap(ctx->c->add(*a->c, *b->c, as_stream(stream)));
+    });
+}
+
+hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream) {
+    return guard([&] {
+        need(ctx && a && slots && out, "null argument");
+        *out = nullptr;
+        hg::Ctx &X = *ctx->c;
+        std::vector<uint64_t> v(X.S);
+        for (int s = 0; s < X.S; ++s) {
+            int64_t r = slots[s] % (int64_t)X.t;
+            v[s] = (uint64_t)(r < 0 ? r + (int64_t)X.t : r);
+        }
+        *out = wrap(X.cmul(*a->c, v, as_stream(stream)));
+    });
+}
+
+hg_status hg_plan_info(hg_ctx *ctx, int m, int l, int n, int64_t *out) {
+    return guard([&] {
+        need(ctx && out, "null argument");
+        hg::Ctx &X = *ctx->c;
+        hg::Plan p;
+        try {
+            p = hg::make_plan(m, l, n, X.S);
+        } catch (std::invalid_argument &e) {
+            throw hg::Error(HG_EINVAL, e.what());
+        } catch (std::range_error &e) {
+            throw hg::Error(HG_ENOFIT, e.what());
+        }
+        out[0] = p.transposed;
+        out[1] = p.nb;
+        out[2] = p.lb;
+        out[3] = p.d;
+        out[4] = p.M;
+        out[5] = p.K;
+        out[6] = p.W;
+        out[7] = (int64_t)p.rotations(X.S).size();
+        out[8] = (int64_t)p.masks.size();
+        out[9] = p.key_switched_terms(X.S);
+    });
+}
+
+hg_status hg_primes(hg_ctx *ctx, uint64_t *out) {
+    return guard([&] {
+        need(ctx && out, "null argument");
+        for (size_t i = 0; i < ctx->c->qs.size(); ++i) out[i] = ctx->c->qs[i];
+    });
+}
+
+hg_status hg_set_timing(hg_ctx *ctx, int enable) {
+    return guard([&] {
+        need(ctx, "null context");
+        ctx->c->timing.enabled = enable != 0;
+    });
+}
+
+hg_status hg_last_timing(hg_ctx *ctx, double *out8) {
+    return guard([&] {
+        need(ctx && out8, "null argument");
+        for (int i = 0; i < 8; ++i) out8[i] = ctx->c->timing.ms[i];
+    });
+}
+
+}  // extern "C"

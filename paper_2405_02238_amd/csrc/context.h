@@ -1,0 +1,129 @@
+// Library context: parameters, device tables, keys, plans, workspaces.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.h"
+#include "planner.h"
+
+namespace hg {
+
+// Error carrying an hg_status code.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void hip_check(hipError_t e, const char *what);
+#define HGCHK(x) ::hg::hip_check((x), #x)
+
+struct Ctx;
+
+// A packed operand/result: ncts ciphertexts of `comps` components, each
+// comps x L x N doubles in evaluation form, one device allocation.
+struct Ct {
+    Ctx *ctx = nullptr;
+    int ncts = 1, comps = 2;
+    int m = 0, l = 0, n = 0;   // shape (0 for raw slot ciphertexts)
+    int side = -1;             // packed side (0 left, 1 right, 2 result, -1 raw)
+    double *d = nullptr;
+    size_t words() const;      // doubles in total
+    double *ct(int i) const;   // start of ciphertext i
+    ~Ct();
+};
+
+struct PlanEntry {
+    Plan plan;
+    std::vector<const double *> mask_ptrs;   // device masks, plan.masks order
+};
+
+// Per-stream scratch arena, grown on demand.
+struct Arena {
+    void *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    void *pinned = nullptr;      // host staging for descriptor tables
+    size_t pinned_cap = 0;
+    hipEvent_t staged = nullptr; // completion of the last copy out of `pinned`
+};
+
+struct Timing {
+    bool enabled = false;
+    double ms[8] = {0};
+};
+
+struct Ctx {
+    int device = 0;
+    int N = 0, logN = 0, L = 0, alpha = 0, beta = 0, nExt = 0, S = 0;
+    uint64_t t = 0, zeta = 0;
+    std::vector<uint64_t> qs;     // extended basis: q_0..q_{L-1}, p_0..p_{alpha-1}
+    DevTables T;                  // device tables (pointers)
+    std::vector<void *> owned;    // device allocations released at destroy
+
+    // keys
+    bool has_secret = false;
+    uint64_t seed = 0;
+    double *s_eval = nullptr;     // nExt x N, evaluation form
+    double *s2_eval = nullptr;    // L x N (s^2 over Q)
+    double *relin_key = nullptr;
+    std::map<int, double *> rot_keys;   // Galois element -> key
+    size_t key_words() const { return (size_t)beta * 2 * nExt * N; }
+
+    // plans and masks
+    std::map<std::tuple<int, int, int>, std::unique_ptr<PlanEntry>> plans;
+    std::map<std::string, double *> mask_cache;   // slot bitmap -> device mask (nExt x N)
+
+    std::map<hipStream_t, Arena> arenas;
+    Timing timing;
+
+    Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device);
+    ~Ctx();
+
+    double *dev_alloc(size_t words);
+    const PlanEntry &plan_for(int m, int l, int n);
+
+    void keygen(uint64_t seed, const std::vector<int> &galois);
+    void drop_secret();
+    int galois_of(int z) const;   // 5^(z mod S) mod 2N
+
+    // encode slot values (S values in [0, t)) into a centered-lifted plaintext
+    // polynomial (N doubles, coefficient form) on `st`
+    void encode_slots(const std::vector<uint64_t> &slots, double *mu, hipStream_t st);
+    double *mask_for(const std::vector<uint8_t> &bitmap);
+
+    Ct *encrypt_slots(const std::vector<uint64_t> &slots, int side, int block, uint64_t nonce,
+                      Ct *into = nullptr, int into_index = 0);
+    Ct *encrypt_matrix(int role, const int64_t *X, int m, int l, int n, uint64_t nonce);
+    std::vector<uint64_t> decrypt_poly(const Ct &c, int index);   // mu in [0, t), N values
+    std::vector<uint64_t> decrypt_slot_values(const Ct &c, int index);
+
+    // cloud side
+    struct Request {
+        const Ct *A;
+        const Ct *B;
+        int m, l, n;
+        Ct *out;
+    };
+    void hegmm_batch(std::vector<Request> &reqs, hipStream_t st);
+    Ct *rotate(const Ct &c, int z, hipStream_t st);
+    Ct *mul(const Ct &a, const Ct &b, hipStream_t st);
+    Ct *add(const Ct &a, const Ct &b, hipStream_t st);
+    Ct *cmul(const Ct &a, const std::vector<uint64_t> &slots, hipStream_t st);
+
+    void export_ct(const Ct &c, uint64_t *buf, hipStream_t st);
+    Ct *import_ct(const uint64_t *buf, int ncts, int comps, hipStream_t st);
+
+    // canonical (coefficient form, [0,q)) residues of an L-row polynomial
+    std::vector<uint64_t> to_host_canonical(const double *eval_rows, int rows, hipStream_t st);
+
+    Arena &arena(hipStream_t st);
+};
+
+}  // namespace hg

@@ -1,0 +1,471 @@
+// Cloud-side executor: HEGMM-En (Algorithm 2) for one or many requests, and
+// the single-ciphertext primitives, as a fixed sequence of batched launches.
+//
+// For a set of "rotation-sum" jobs  T(ct) = sum_z mask_z (.) Rot(ct, z)  the
+// executor runs, each phase as one launch over every job of every request:
+//   1. hoist: inverse transform of each source c1, digit lift (ModUp) fused
+//      into the forward transform of every lifted row;
+//   2. inner products of the permuted digits with the rotation keys, masked
+//      and summed per job (key-switched terms only);
+//   3. division by P: inverse transform of the special-prime rows (storing
+//      the centered correction r_k), forward transform of the correction
+//      delta over the ciphertext primes;
+//   4. finish: masked permuted c0 (and c1 for unrotated terms) plus
+//      (U - delta) P^-1, consumed directly by the tensor accumulation.
+// Relinearisation (once per product, after the accumulation) and the fold
+// of the d row blocks reuse phases 1-4 with a single job per request.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "context.h"
+
+namespace hg {
+
+namespace {
+
+// Host-side description of one phase-1..4 pass.
+struct Pass {
+    std::vector<const double *> srcs;   // eval-form c1 of each hoisted source (L x N)
+    std::vector<int2> ip_jobs;          // (first term, count) per key-switched job
+    std::vector<IpTerm> ip_terms;
+    std::vector<FinJob> fin_jobs;
+    std::vector<FinTerm> fin_terms;
+    std::vector<const double *> keys;
+    std::map<const double *, int> key_index;
+    std::vector<const double *> masks;
+    std::map<const double *, int> mask_index;
+
+    int key_id(const double *k) {
+        auto it = key_index.find(k);
+        if (it != key_index.end()) return it->second;
+        keys.push_back(k);
+        return key_index[k] = (int)keys.size() - 1;
+    }
+    int mask_id(const double *m) {
+        if (!m) return -1;
+        auto it = mask_index.find(m);
+        if (it != mask_index.end()) return it->second;
+        masks.push_back(m);
+        return mask_index[m] = (int)masks.size() - 1;
+    }
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Byte layout of everything a pass needs in the arena.
+struct Layout {
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t off = total;
+        total = align_up(total + bytes, 256);
+        return off;
+    }
+};
+
+}  // namespace
+
+namespace {
+
+struct Exec {
+    Ctx &C;
+    hipStream_t st;
+    const DevTables &T;
+    int N, L, nExt, beta, alpha;
+    Exec(Ctx &c, hipStream_t s)
+        : C(c), st(s), T(c.T), N(c.N), L(c.L), nExt(c.nExt), beta(c.beta), alpha(c.alpha) {}
+
+    // Adds a job to `ps`.  terms: (z, mask pointer or null).  Returns the job index.
+    int add_job(Pass &ps, const double *ct, const std::vector<std::pair<int, const double *>> &terms,
+                int src, const double *relin_key) {
+        FinJob fj;
+        fj.c0 = ct;
+        fj.c1 = ct + (size_t)L * N;
+        fj.t0 = (int)ps.fin_terms.size();
+        fj.ks = -1;
+        std::vector<IpTerm> ipt;
+        for (auto &tm : terms) {
+            const int g = C.galois_of(tm.first);
+            const int mid = ps.mask_id(tm.second);
+            ps.fin_terms.push_back({g, mid});
+            if (g != 1) {
+                auto it = C.rot_keys.find(g);
+                if (it == C.rot_keys.end())
+                    throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
+                ipt.push_back({src, g, mid, ps.key_id(it->second)});
+            }
+        }
+        if (relin_key) ipt.push_back({src, 1, -1, ps.key_id(relin_key)});
+        fj.nt = (int)ps.fin_terms.size() - fj.t0;
+        if (!ipt.empty()) {
+            fj.ks = (int)ps.ip_jobs.size();
+            ps.ip_jobs.push_back(make_int2((int)ps.ip_terms.size(), (int)ipt.size()));
+            ps.ip_terms.insert(ps.ip_terms.end(), ipt.begin(), ipt.end());
+        }
+        ps.fin_jobs.push_back(fj);
+        return (int)ps.fin_jobs.size() - 1;
+    }
+
+    // Runs phases 1-3 of a pass; returns device pointers to U and delta.
+    // Descriptor tables are copied into the arena first.
+    struct Dev {
+        double *U = nullptr, *delta = nullptr;
+        FinJob *jobs = nullptr;
+        FinTerm *terms = nullptr;
+        const double *const *masks = nullptr;
+        char *extra = nullptr;   // caller-requested table space
+    };
+
+    Dev run(Pass &ps, const void *extra_host, size_t extra_bytes, hipEvent_t *tev = nullptr) {
+        Arena &A = C.arena(st);
+        const int nsrc = (int)ps.srcs.size();
+        const int nks = (int)ps.ip_jobs.size();
+        Layout lay;
+        const size_t o_coef = lay.add((size_t)nsrc * L * N * 8);
+        const size_t o_y = lay.add((size_t)nsrc * beta * nExt * N * 8);
+        const size_t o_U = lay.add((size_t)nks * 2 * nExt * N * 8);
+        const size_t o_rk = lay.add((size_t)nks * 2 * alpha * N * 8);
+        const size_t o_d = lay.add((size_t)nks * 2 * L * N * 8);
+        // tables (one contiguous block copied from pinned staging)
+        Layout tl;
+        const size_t t_ipj = tl.add(ps.ip_jobs.size() * sizeof(int2));
+        const size_t t_ipt = tl.add(ps.ip_terms.size() * sizeof(IpTerm));
+        const size_t t_fj = tl.add(ps.fin_jobs.size() * sizeof(FinJob));
+        const size_t t_ft = tl.add(ps.fin_terms.size() * sizeof(FinTerm));
+        const size_t t_keys = tl.add(ps.keys.size() * sizeof(void *));
+        const size_t t_masks = tl.add(ps.masks.size() * sizeof(void *));
+        const size_t t_extra = tl.add(extra_bytes);
+        tl.add(256);   // never empty
+        const size_t o_tab = lay.add(tl.total);
+        if (lay.total > A.cap) {
+            HGCHK(hipStreamSynchronize(st));
+            if (A.base) HGCHK(hipFree(A.base));
+            A.cap = align_up(lay.total + lay.total / 4, 1 << 20);
+            HGCHK(hipMalloc(&A.base, A.cap));
+        }
+        if (tl.total > A.pinned_cap) {
+            HGCHK(hipEventSynchronize(A.staged));
+            if (A.pinned) HGCHK(hipHostFree(A.pinned));
+            A.pinned_cap = align_up(tl.total * 2, 1 << 16);
+            HGCHK(hipHostMalloc(&A.pinned, A.pinned_cap, hipHostMallocDefault));
+        }
+        HGCHK(hipEventSynchronize(A.staged));   // the previous copy out of staging is done
+        char *h = (char *)A.pinned;
+        auto put = [&](size_t off, const void *src, size_t bytes) {
+            if (bytes) std::memcpy(h + off, src, bytes);
+        };
+        put(t_ipj, ps.ip_jobs.data(), ps.ip_jobs.size() * sizeof(int2));
+        put(t_ipt, ps.ip_terms.data(), ps.ip_terms.size() * sizeof(IpTerm));
+        put(t_fj, ps.fin_jobs.data(), ps.fin_jobs.size() * sizeof(FinJob));
+        put(t_ft, ps.fin_terms.data(), ps.fin_terms.size() * sizeof(FinTerm));
+        put(t_keys, ps.keys.data(), ps.keys.size() * sizeof(void *));
+        put(t_masks, ps.masks.data(), ps.masks.size() * sizeof(void *));
+        put(t_extra, extra_host, extra_bytes);
+        char *base = (char *)A.base;
+        HGCHK(hipMemcpyAsync(base + o_tab, h, tl.total, hipMemcpyHostToDevice, st));
+        HGCHK(hipEventRecord(A.staged, st));
+
+        Dev dv;
+        char *tab = base + o_tab;
+        dv.jobs = (FinJob *)(tab + t_fj);
+        dv.terms = (FinTerm *)(tab + t_ft);
+        dv.masks = (const double *const *)(tab + t_masks);
+        dv.extra = tab + t_extra;
+        dv.U = (double *)(base + o_U);
+        dv.delta = (double *)(base + o_d);
+        double *coef = (double *)(base + o_coef);
+        double *y = (double *)(base + o_y);
+        double *rk = (double *)(base + o_rk);
+
+        if (nks > 0) {
+            // 1. hoist every source once: c1 -> coefficient form -> lifted digits
+            for (int s = 0; s < nsrc; ++s) {
+                NttArgs a;
+                a.out = coef + (size_t)s * L * N;
+                a.in = ps.srcs[s];
+                a.rows = L;
+                a.per = L;
+                ntt_inv(T, STORE_PLAIN, a, st);
+            }
+            NttArgs mu;
+            mu.out = y;
+            mu.in = coef;
+            mu.rows = nsrc * beta * nExt;
+            mu.in_stride = (long long)L * N;
+            ntt_fwd(T, LOAD_MODUP, mu, st);
+            if (tev) HGCHK(hipEventRecord(tev[0], st));
+            // 2. inner products
+            ip_launch(T, dv.U, y, (const double *const *)(tab + t_keys), dv.masks, (const int2 *)(tab + t_ipj),
+                      (const IpTerm *)(tab + t_ipt), nks, st);
+            if (tev) HGCHK(hipEventRecord(tev[1], st));
+            // 3. division by P
+            NttArgs md;
+            md.out = rk;
+            md.in = dv.U;
+            md.rows = nks * 2 * alpha;
+            md.per = alpha;
+            md.prime_base = L;
+            md.out_stride = (long long)alpha * N;
+            md.in_stride = (long long)nExt * N;
+            md.in_offset = (long long)L * N;
+            ntt_inv(T, STORE_MDR, md, st);
+            NttArgs dl;
+            dl.out = dv.delta;
+            dl.in = rk;
+            dl.rows = nks * 2 * L;
+            dl.in_stride = (long long)alpha * N;
+            ntt_fwd(T, LOAD_DELTA, dl, st);
+            if (tev) HGCHK(hipEventRecord(tev[2], st));
+        } else if (tev) {
+            for (int i = 0; i < 3; ++i) HGCHK(hipEventRecord(tev[i], st));
+        }
+        return dv;
+    }
+};
+
+}  // namespace
+
+void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
+    HGCHK(hipSetDevice(device));
+    Exec ex(*this, st);
+    const size_t ctw = (size_t)L * N;
+    // --- validate and plan ---
+    struct RInfo {
+        const PlanEntry *pe;
+        const Ct *X;
+        const Ct *Y;
+    };
+    std::vector<RInfo> info;
+    for (auto &r : reqs) {
+        if (!r.A || !r.B) throw Error(-1, "null operand");
+        const PlanEntry &pe = plan_for(r.m, r.l, r.n);
+        const Ct *A = r.A, *B = r.B;
+        if (A->m != r.m || A->l != r.l || A->n != r.n || B->m != r.m || B->l != r.l || B->n != r.n)
+            throw Error(-1, "operand shape differs from (m, l, n)");
+        if (A->side != side_of_role(pe.plan, 0) || B->side != side_of_role(pe.plan, 1))
+            throw Error(-1, "operands must be hg_encrypt outputs for roles 0 (A) and 1 (B)");
+        if (A->ncts != pe.plan.nb || B->ncts != pe.plan.nb) throw Error(-1, "block count mismatch");
+        const Ct *X = A->side == 0 ? A : B;
+        const Ct *Y = A->side == 0 ? B : A;
+        info.push_back({&pe, X, Y});
+        for (auto &rz : pe.plan.rotations(S))
+            if (!rot_keys.count(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
+    }
+    const int nreq = (int)reqs.size();
+    hipEvent_t ev[10] = {nullptr};
+    if (timing.enabled) {
+        for (auto &e : ev) HGCHK(hipEventCreate(&e));
+        HGCHK(hipEventRecord(ev[9], st));
+    }
+
+    // --- phases 1-4 for every eps^k / omega^k transform, tensor-accumulated ---
+    Pass ps;
+    std::vector<int2> req_pairs(nreq);
+    for (int ri = 0; ri < nreq; ++ri) {
+        const Plan &p = info[ri].pe->plan;
+        const auto &mp = info[ri].pe->mask_ptrs;
+        req_pairs[ri] = make_int2((int)ps.fin_jobs.size() / 2, p.nb * p.K);
+        for (int b = 0; b < p.nb; ++b) {
+            const double *xc = info[ri].X->ct(b);
+            const double *yc = info[ri].Y->ct(b);
+            int sx = -1, sy = -1;
+            for (int k = 0; k < p.K; ++k) {
+                std::vector<std::pair<int, const double *>> te, tw;
+                bool kx = false, ky = false;
+                for (auto &tm : p.eps[k]) {
+                    te.push_back({tm.z, tm.mask >= 0 ? mp[tm.mask] : nullptr});
+                    kx |= galois_of(tm.z) != 1;
+                }
+                for (auto &tm : p.omega[k]) {
+                    tw.push_back({tm.z, tm.mask >= 0 ? mp[tm.mask] : nullptr});
+                    ky |= galois_of(tm.z) != 1;
+                }
+                if (kx && sx < 0) { sx = (int)ps.srcs.size(); ps.srcs.push_back(xc + ctw); }
+                if (ky && sy < 0) { sy = (int)ps.srcs.size(); ps.srcs.push_back(yc + ctw); }
+                ex.add_job(ps, xc, te, sx, nullptr);
+                ex.add_job(ps, yc, tw, sy, nullptr);
+            }
+        }
+    }
+    // accumulators: one 3 x L x N block per request, in a pass-owned buffer
+    double *acc = nullptr;
+    HGCHK(hipMallocAsync((void **)&acc, (size_t)nreq * 3 * ctw * sizeof(double), st));
+    std::vector<double *> acc_ptrs(nreq);
+    for (int ri = 0; ri < nreq; ++ri) acc_ptrs[ri] = acc + (size_t)ri * 3 * ctw;
+    std::vector<char> extra(req_pairs.size() * sizeof(int2) + acc_ptrs.size() * sizeof(void *));
+    std::memcpy(extra.data(), req_pairs.data(), req_pairs.size() * sizeof(int2));
+    std::memcpy(extra.data() + req_pairs.size() * sizeof(int2), acc_ptrs.data(), acc_ptrs.size() * sizeof(void *));
+    Exec::Dev dv = ex.run(ps, extra.data(), extra.size(), timing.enabled ? ev : nullptr);
+    fin_tensor_launch(T, dv.jobs, dv.terms, dv.U, dv.delta, dv.masks, (const int2 *)dv.extra,
+                      (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
+    if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
+
+    // --- relinearise once per product (lazy) ---
+    std::vector<double *> R(nreq, nullptr);
+    double *rbuf = nullptr;
+    int nfold = 0;
+    for (int ri = 0; ri < nreq; ++ri) nfold += info[ri].pe->plan.d > 1;
+    if (nfold) HGCHK(hipMallocAsync((void **)&rbuf, (size_t)nfold * 2 * ctw * sizeof(double), st));
+    {
+        Pass pr;
+        int fi = 0;
+        for (int ri = 0; ri < nreq; ++ri) {
+            Ct *out = reqs[ri].out;
+            R[ri] = info[ri].pe->plan.d > 1 ? rbuf + (size_t)(fi++) * 2 * ctw : out->d;
+            // a job over (Acc0, Acc1) with the unrotated term, plus the key
+            // switch of Acc2 (the hoisted source) under the key for s^2
+            pr.srcs.push_back(acc_ptrs[ri] + 2 * ctw);
+            ex.add_job(pr, acc_ptrs[ri], {{0, nullptr}}, ri, relin_key);
+        }
+        Exec::Dev d2 = ex.run(pr, R.data(), R.size() * sizeof(void *));
+        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.U, d2.delta, d2.masks, (double *const *)d2.extra, nreq, st);
+    }
+    if (timing.enabled) HGCHK(hipEventRecord(ev[4], st));
+
+    // --- fold the d row blocks: C = sum_h Rot(R, h*mo) ---
+    if (nfold) {
+        Pass pf;
+        std::vector<double *> outs;
+        for (int ri = 0; ri < nreq; ++ri) {
+            const Plan &p = info[ri].pe->plan;
+            if (p.d == 1) continue;
+            std::vector<std::pair<int, const double *>> terms;
+            for (int z : p.fold) terms.push_back({z, nullptr});
+            const int src = (int)pf.srcs.size();
+            pf.srcs.push_back(R[ri] + ctw);
+            ex.add_job(pf, R[ri], terms, src, nullptr);
+            outs.push_back(reqs[ri].out->d);
+        }
+        Exec::Dev d3 = ex.run(pf, outs.data(), outs.size() * sizeof(void *));
+        fin_rotsum_launch(T, d3.jobs, d3.terms, d3.U, d3.delta, d3.masks, (double *const *)d3.extra,
+                          (int)outs.size(), st);
+        HGCHK(hipFreeAsync(rbuf, st));
+    }
+    HGCHK(hipFreeAsync(acc, st));
+    if (timing.enabled) {
+        HGCHK(hipEventRecord(ev[5], st));
+        HGCHK(hipEventSynchronize(ev[5]));
+        float ms;
+        auto el = [&](hipEvent_t a, hipEvent_t b) {
+            HGCHK(hipEventElapsedTime(&ms, a, b));
+            return (double)ms;
+        };
+        timing.ms[0] = el(ev[9], ev[0]);
+        timing.ms[1] = el(ev[0], ev[1]);
+        timing.ms[2] = el(ev[1], ev[2]);
+        timing.ms[3] = el(ev[2], ev[3]);
+        timing.ms[4] = el(ev[3], ev[4]);
+        timing.ms[5] = el(ev[4], ev[5]);
+        timing.ms[6] = el(ev[9], ev[5]);
+        timing.ms[7] = timing.ms[1];
+        for (auto &e : ev) (void)hipEventDestroy(e);
+    }
+}
+
+Ct *Ctx::rotate(const Ct &c, int z, hipStream_t st) {
+    HGCHK(hipSetDevice(device));
+    if (c.comps != 2 || c.ncts != 1) throw Error(-1, "rotate takes one two-component ciphertext");
+    Ct *o = new Ct();
+    o->ctx = this;
+    o->d = dev_alloc(o->words());
+    try {
+        Exec ex(*this, st);
+        Pass ps;
+        ps.srcs.push_back(c.d + (size_t)L * N);
+        ex.add_job(ps, c.d, {{z, nullptr}}, 0, nullptr);
+        double *outp = o->d;
+        Exec::Dev dv = ex.run(ps, &outp, sizeof(void *));
+        fin_rotsum_launch(T, dv.jobs, dv.terms, dv.U, dv.delta, dv.masks, (double *const *)dv.extra, 1, st);
+    } catch (...) {
+        delete o;
+        throw;
+    }
+    return o;
+}
+
+Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
+    HGCHK(hipSetDevice(device));
+    if (a.comps != 2 || b.comps != 2 || a.ncts != 1 || b.ncts != 1) throw Error(-1, "mul takes two-component ciphertexts");
+    const size_t ctw = (size_t)L * N;
+    Ct *o = new Ct();
+    o->ctx = this;
+    o->d = dev_alloc(o->words());
+    try {
+        Exec ex(*this, st);
+        double *acc = nullptr;
+        HGCHK(hipMallocAsync((void **)&acc, 3 * ctw * sizeof(double), st));
+        Pass ps;
+        ex.add_job(ps, a.d, {{0, nullptr}}, -1, nullptr);
+        ex.add_job(ps, b.d, {{0, nullptr}}, -1, nullptr);
+        struct { int2 rp; double *ap; } ext{make_int2(0, 1), acc};
+        static_assert(sizeof(ext) == 16, "layout");
+        Exec::Dev dv = ex.run(ps, &ext, sizeof(ext));
+        fin_tensor_launch(T, dv.jobs, dv.terms, dv.U, dv.delta, dv.masks, (const int2 *)dv.extra,
+                          (double *const *)(dv.extra + 8), 1, st);
+        Pass pr;
+        pr.srcs.push_back(acc + 2 * ctw);
+        ex.add_job(pr, acc, {{0, nullptr}}, 0, relin_key);
+        double *outp = o->d;
+        Exec::Dev d2 = ex.run(pr, &outp, sizeof(void *));
+        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.U, d2.delta, d2.masks, (double *const *)d2.extra, 1, st);
+        HGCHK(hipFreeAsync(acc, st));
+    } catch (...) {
+        delete o;
+        throw;
+    }
+    return o;
+}
+
+Ct *Ctx::add(const Ct &a, const Ct &b, hipStream_t st) {
+    if (a.comps != b.comps || a.ncts != b.ncts) throw Error(-1, "add: mismatched ciphertexts");
+    Ct *o = new Ct();
+    o->ctx = this;
+    o->ncts = a.ncts;
+    o->comps = a.comps;
+    o->d = dev_alloc(o->words());
+    add_rows(T, o->d, a.d, b.d, a.ncts * a.comps * L, 0, L, st);
+    return o;
+}
+
+Ct *Ctx::cmul(const Ct &a, const std::vector<uint64_t> &slots, hipStream_t st) {
+    std::vector<uint8_t> key(S);
+    // masks are cached by bitmap; general slot values go through a one-off plaintext
+    bool binary = true;
+    for (int s = 0; s < S; ++s) {
+        uint64_t v = s < (int)slots.size() ? slots[s] % t : 0;
+        binary &= v <= 1;
+        key[s] = (uint8_t)v;
+    }
+    double *m = nullptr;
+    bool own = false;
+    if (binary) {
+        m = mask_for(key);
+    } else {
+        double *mu = dev_alloc(N);
+        encode_slots(slots, mu, st);
+        m = dev_alloc((size_t)nExt * N);
+        broadcast_rows(mu, m, N, nExt, st);
+        NttArgs na;
+        na.out = m; na.in = m; na.rows = nExt; na.per = nExt;
+        na.out_stride = na.in_stride = (long long)nExt * N;
+        ntt_fwd(T, LOAD_PLAIN, na, st);
+        HGCHK(hipStreamSynchronize(st));
+        (void)hipFree(mu);
+        own = true;
+    }
+    Ct *o = new Ct();
+    o->ctx = this;
+    o->ncts = a.ncts;
+    o->comps = a.comps;
+    o->d = dev_alloc(o->words());
+    for (int c = 0; c < a.ncts * a.comps; ++c)
+        mul_rows(T, o->d + (size_t)c * L * N, a.d + (size_t)c * L * N, m, L, 0, L, st);
+    if (own) {
+        HGCHK(hipStreamSynchronize(st));
+        (void)hipFree(m);
+    }
+    return o;
+}
+
+}  // namespace hg

@@ -1,0 +1,149 @@
+// Device data layout and kernel launchers.
+//
+// Layout in HBM (all doubles holding exact integers, see arith.h):
+//  - a polynomial over a set of primes is `rows x N`, one row per prime,
+//    limb-major (all N residues of a prime contiguous), 256-byte aligned;
+//  - a ciphertext is components x L x N (c0 rows, then c1 rows), kept in the
+//    evaluation form produced by k_ntt_fwd (bit-reversed order);
+//  - the extended basis orders its rows q_0..q_{L-1}, p_0..p_{alpha-1}; the
+//    plaintext modulus t has prime index L + alpha in the tables;
+//  - hoisted digits of a source polynomial: beta x (L+alpha) x N;
+//  - a switching key: beta x 2 x (L+alpha) x N (b_j rows, then a_j rows).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hg {
+
+// Per-context tables on the device.
+struct DevTables {
+    int N = 0, logN = 0, L = 0, alpha = 0, beta = 0, nExt = 0;
+    double2 *qt = nullptr;      // [nExt + 1]: (q, fl(1/q)); index nExt is t
+    double *twf = nullptr;      // [nExt + 1][N]: psi^brv(i), centered
+    double *twi = nullptr;      // [nExt + 1][N]: psi^-brv(i), centered
+    double *ninv = nullptr;     // [nExt + 1]: N^-1, centered
+    double *mu_invhat = nullptr;  // [L]: ((D_j/q_i) mod q_i)^-1 for q_i in digit j
+    double *mu_hat = nullptr;     // [L][nExt]: (D_j/q_i) mod prime r
+    double *md_coef = nullptr;    // [alpha]: N^-1 t^-1 (P/p_k)^-1 mod p_k, centered
+    double *md_hat = nullptr;     // [alpha][L]: t (P/p_k) mod q_i
+    double *pinv = nullptr;       // [L]: P^-1 mod q_i, centered
+    double t = 0.0, tinv = 0.0;   // plaintext modulus and fl(1/t), by value
+};
+
+// One key-switched (rotation or relinearisation) term of an inner-product job.
+struct IpTerm {
+    int src;    // hoisted digit set
+    int g;      // Galois element (1 = no permutation)
+    int mask;   // index into the mask pointer table, -1 = none
+    int key;    // index into the key pointer table
+};
+
+// One term of a finishing job (contributions that need no key switch).
+struct FinTerm {
+    int g;      // Galois element applied to c0 (1 also adds the c1 term)
+    int mask;   // -1 = none
+};
+
+struct FinJob {
+    const double *c0;   // L x N, evaluation form
+    const double *c1;
+    int ks;             // key-switch slot (row in U / delta), -1 if none
+    int t0, nt;         // terms [t0, t0 + nt)
+};
+
+enum NttLoad { LOAD_PLAIN = 0, LOAD_MODUP = 1, LOAD_DELTA = 2 };
+enum NttStore { STORE_PLAIN = 0, STORE_MDR = 1, STORE_CANON = 2 };
+
+struct NttArgs {
+    double *out = nullptr;
+    const double *in = nullptr;
+    int rows = 0;
+    int per = 1;               // rows per group
+    int prime_base = 0;
+    long long out_stride = 0;  // elements between groups
+    long long in_stride = 0;
+    long long in_offset = 0;
+};
+
+// Forward transform of `rows` rows (natural order in, bit-reversed out).
+//  LOAD_PLAIN: row r = group r/per, prime prime_base + r%per, in place allowed.
+//  LOAD_MODUP: rows are (src, digit j, prime r) over nsrc sources; `in` holds
+//              coefficient-form L-row sources with stride in_stride; output
+//              row index (src*beta + j)*nExt + r, contiguous.
+//  LOAD_DELTA: rows are (slot, i) with i over the L ciphertext primes; `in`
+//              holds alpha rows of centered r_k per slot (stride in_stride);
+//              output contiguous slot*L + i.
+void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s);
+
+// Inverse transform (bit-reversed in, natural out).
+//  STORE_PLAIN: times N^-1.
+//  STORE_MDR:   row = (slot, k), prime L + k; output centered
+//               r_k = [u_{p_k} N^-1 t^-1 (P/p_k)^-1]_{p_k}, exact.
+//  STORE_CANON: times N^-1, canonical residue in [0, q).
+void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s);
+
+// Inner products: U[job][c][r][p] = sum over the job's terms of
+// mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)].
+void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+               const double *const *masks, const int2 *jobs, const IpTerm *terms, int njobs,
+               hipStream_t s);
+
+// Tensor-accumulate: per request, sum over its (eps job, omega job) pairs of
+// the tensor product of the two finished transforms.
+void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms,
+                       const double *U, const double *delta, const double *const *masks,
+                       const int2 *req_pairs, double *const *acc, int nreq, hipStream_t s);
+
+// Finish rotation sums: out[job] = (sum mask*phi(c0) + (U0-d0)/P, sum_{g=1} mask*c1 + (U1-d1)/P).
+void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms,
+                       const double *U, const double *delta, const double *const *masks,
+                       double *const *out, int njobs, hipStream_t s);
+
+// Allow the transform kernels the full LDS of a CDNA4 workgroup (call once
+// per device before the first transform with N > 4096).
+void kernels_init();
+
+// ---- utilities ----
+void u64_to_dbl(const uint64_t *in, double *out, size_t n, hipStream_t s);
+void dbl_to_u64(const double *in, uint64_t *out, size_t n, hipStream_t s);
+void mul_rows(const DevTables &T, double *out, const double *a, const double *b, int rows,
+              int prime_base, int per, hipStream_t s);
+void add_rows(const DevTables &T, double *out, const double *a, const double *b, int rows,
+              int prime_base, int per, hipStream_t s);
+
+// Sampling (counter-based SplitMix64 streams): rows x N uniform residues
+// (draw first + r*N + i), N ternary or Gaussian integers (draw first + i).
+void sample_uniform(const DevTables &T, double *out, uint64_t s0, uint64_t first, int rows,
+                    int prime_base, hipStream_t s);
+void sample_small(double *out, uint64_t s0, uint64_t first, int N, int kind, hipStream_t s);
+
+// Reduce a small signed integer polynomial (N doubles) into rows x N.
+void broadcast_rows(const double *x, double *out, int N, int rows, hipStream_t s);
+// out[r] = x[r] * c[r] + y[r] for a per-row constant (used by key generation)
+void axpy_rows(const DevTables &T, double *out, const double *x, const double *c, const double *y,
+               int rows, hipStream_t s);
+// Scatter row-0 slot values (S doubles in [0,t)) to the evaluation positions
+// of the t-transform (bit-reversed order); row 1 positions get 0.
+void scatter_slots(const DevTables &T, const double *slots, double *out, hipStream_t s);
+// Gather row-0 slots from a t-transform evaluation vector.
+void gather_slots(const DevTables &T, const double *ev, double *slots, hipStream_t s);
+// Automorphism in evaluation form: out[p] = in[perm_g(p)] for rows.
+void automorph_rows(const DevTables &T, double *out, const double *in, int rows, int g, hipStream_t s);
+// Centered canonical representative per row (prime_base + r % per).
+void center_rows(const DevTables &T, double *x, int rows, int prime_base, int per, hipStream_t s);
+// Switching-key digit, evaluation form over the extended basis:
+// b[r] = t e[r] - a[r] s[r] + gadget[r] s'[r].
+void keygen_combine(const DevTables &T, double *b, const double *a, const double *e, const double *s_,
+                    const double *sp, const double *gadget, hipStream_t s);
+// Encryption: noisy = t e + mu (small integers, N values), then
+// c0[r] = noisy_eval[r] - a[r] s[r] over the L ciphertext primes.
+void enc_noisy(const DevTables &T, double *out, const double *e, const double *mu, hipStream_t s);
+void enc_combine(const DevTables &T, double *c0, const double *noisy_eval, const double *a, const double *s_,
+                 hipStream_t s);
+// Decryption: v[r] = c0 + c1 s (+ c2 s^2) over the L ciphertext primes.
+void dec_combine(const DevTables &T, double *v, const double *ct, int comps, const double *s_,
+                 const double *s2, hipStream_t s);
+// Integer polynomial values (|x| < t/2) times t: out = t * x (used for errors).
+void scale_small(double *out, const double *x, double c, int N, hipStream_t s);
+
+}  // namespace hg

@@ -1,0 +1,171 @@
+// HEGMM-En planner; see planner.h.
+#include "planner.h"
+
+#include <algorithm>
+#include <map>
+#include <set>
+#include <stdexcept>
+
+namespace hg {
+
+namespace {
+
+struct Consts { int d, M, K, W; };
+
+Consts constants(int mo, int lb, int no) {
+    Consts c;
+    c.d = mo < lb ? (lb + mo - 1) / mo : 1;  // Theorem 5: ceil(l/m) copies when m < l
+    c.M = c.d * mo;
+    c.K = std::min(mo, lb);                  // p = min(m, l, n) loop trips (Algorithm 2)
+    c.W = std::max(lb, no);                  // packed width max(l, N) of the left operand
+    return c;
+}
+
+// Add the diagonals found in `cand` (z -> slot list) in the order given; a
+// lone diagonal that covers the whole M x no region needs no mask.
+void add_terms(Plan &p, std::vector<Term> &out, std::map<int, std::vector<int>> &cand,
+               const int order[2], int S, size_t region) {
+    std::vector<std::pair<int, std::vector<int> *>> found;
+    for (int i = 0; i < 2; ++i) {
+        auto it = cand.find(order[i]);
+        if (it != cand.end() && !it->second.empty()) found.push_back({order[i], &it->second});
+    }
+    if (found.size() == 1 && found[0].second->size() == region) {
+        out.push_back({found[0].first, -1});
+        return;
+    }
+    for (auto &f : found) {
+        std::vector<uint8_t> bm(S, 0);
+        for (int s : *f.second) bm[s] = 1;
+        p.masks.push_back(std::move(bm));
+        out.push_back({f.first, (int)p.masks.size() - 1});
+    }
+}
+
+}  // namespace
+
+Plan make_plan(int m, int l, int n, int S) {
+    if (m <= 0 || l <= 0 || n <= 0) throw std::invalid_argument("dimensions must be positive");
+    Plan p;
+    p.m = m; p.l = l; p.n = n;
+    // Orientation in Algorithm 2's order: p == m duplicates A; else p == n
+    // duplicates B, realised as the transposed problem B^T A^T; else no
+    // duplication.
+    int pm = std::min(m, std::min(l, n));
+    p.transposed = (pm != m) && (pm == n);
+    p.mo = p.transposed ? n : m;
+    p.no = p.transposed ? m : n;
+
+    auto fits = [&](int lb) {
+        Consts c = constants(p.mo, lb, p.no);
+        return (long long)c.M * c.W <= S;
+    };
+    p.nb = 1;
+    p.lb = l;
+    if (!fits(l)) {
+        int nb = 2;
+        while (nb <= l && !fits((l + nb - 1) / nb)) ++nb;
+        if (nb > l) throw std::range_error("shape does not fit one ciphertext row");
+        p.nb = nb;
+        p.lb = (l + nb - 1) / nb;
+    }
+    Consts c = constants(p.mo, p.lb, p.no);
+    p.d = c.d; p.M = c.M; p.K = c.K; p.W = c.W;
+    const int M = p.M, mo = p.mo, no = p.no, lb = p.lb, W = p.W;
+    const size_t region = (size_t)M * no;
+
+    for (int k = 0; k < p.K; ++k) {
+        // eps^k: output (i, j) takes source column c = j + k (j + k - lb once
+        // past the packed width), a left rotation by (c - j) * M.  Row block
+        // h = i / mo carries partial product (k + h*mo) mod lb (Theorem 5) and
+        // is masked out when h*mo + k >= lb, so no partial product is added
+        // twice.
+        std::map<int, std::vector<int>> cand;
+        for (int j = 0; j < no; ++j) {
+            int cc = j + k < W ? j + k : j + k - lb;
+            int z = (cc - j) * M;
+            for (int i = 0; i < M; ++i) {
+                if ((i / mo) * mo + k >= lb) continue;
+                cand[z].push_back(i + j * M);
+            }
+        }
+        std::vector<Term> e;
+        int eo[2] = {k * M, (k - lb) * M};
+        add_terms(p, e, cand, eo, S, region);
+        p.eps.push_back(e);
+        // omega^k: output (i, j) takes source row r = i + k (i + k - lb past M).
+        cand.clear();
+        for (int j = 0; j < no; ++j)
+            for (int i = 0; i < M; ++i) {
+                int r = i + k < M ? i + k : i + k - lb;
+                cand[r - i].push_back(i + j * M);
+            }
+        std::vector<Term> w;
+        int wo[2] = {k, k - lb};
+        add_terms(p, w, cand, wo, S, region);
+        p.omega.push_back(w);
+    }
+    for (int h = 0; h < p.d; ++h) p.fold.push_back(h * mo);
+    return p;
+}
+
+std::vector<int> Plan::rotations(int S) const {
+    std::set<int> zs;
+    auto addz = [&](int z) {
+        int r = ((z % S) + S) % S;
+        if (r) zs.insert(r);
+    };
+    for (auto &v : eps) for (auto &t : v) addz(t.z);
+    for (auto &v : omega) for (auto &t : v) addz(t.z);
+    for (int z : fold) addz(z);
+    return std::vector<int>(zs.begin(), zs.end());
+}
+
+int Plan::key_switched_terms(int S) const {
+    int c = 0;
+    auto cnt = [&](const std::vector<Term> &v) {
+        for (auto &t : v) c += (((t.z % S) + S) % S) != 0;
+    };
+    for (int b = 0; b < nb; ++b) {
+        for (auto &v : eps) cnt(v);
+        for (auto &v : omega) cnt(v);
+    }
+    for (int z : fold) c += (((z % S) + S) % S) != 0;
+    return c;
+}
+
+std::vector<uint64_t> pack_operand(const Plan &p, int side, const int64_t *X, int block, uint64_t t, int S) {
+    std::vector<uint64_t> v(S, 0);
+    auto modt = [&](int64_t x) -> uint64_t {
+        int64_t r = x % (int64_t)t;
+        return (uint64_t)(r < 0 ? r + (int64_t)t : r);
+    };
+    const int lo = block * p.lb;
+    // entries of the oriented operands, zero outside the block
+    if (side == 0) {
+        // left operand Xo (mo x l): A itself, or B^T when transposed (X = B, l x n)
+        auto xo = [&](int i, int c) -> int64_t {
+            int cg = lo + c;
+            if (cg >= p.l) return 0;
+            return p.transposed ? X[(size_t)cg * p.n + i] : X[(size_t)i * p.l + cg];
+        };
+        // x[i + c*M] = Xb[i mod mo][(i + c) mod lb]: eps^0_{M x W}(sigma(Xbar))
+        for (int i = 0; i < p.M; ++i)
+            for (int c = 0; c < p.W; ++c)
+                v[i + (size_t)c * p.M] = modt(xo(i % p.mo, (i + c) % p.lb));
+    } else {
+        // right operand Yo (l x no): B itself, or A^T when transposed (X = A, m x l)
+        auto yo = [&](int r, int j) -> int64_t {
+            int rg = lo + r;
+            if (rg >= p.l) return 0;
+            return p.transposed ? X[(size_t)j * p.l + rg] : X[(size_t)rg * p.n + j];
+        };
+        // y[r + j*M] = Yb[(r + j) mod lb][j]: omega^0_{M x no}(tau(Yb))
+        for (int r = 0; r < p.M; ++r)
+            for (int j = 0; j < p.no; ++j)
+                v[r + (size_t)j * p.M] = modt(yo((r + j) % p.lb, j));
+    }
+    return v;
+}
+
+}  // namespace hg

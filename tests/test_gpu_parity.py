@@ -1,0 +1,142 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Every comparison is on the canonical serialisation (coefficient form,
+residues in [0, q_i)), element by element; the bar is bit-identity.  Results
+are also decrypted and compared with brute-force matrix products."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_02238_amd as hg  # noqa: E402
+from oracle import bgv, hegmm as H  # noqa: E402
+from oracle.ring import Params  # noqa: E402
+
+
+def flat(ct):
+    return H.export_d7(ct)
+
+
+class Pair:
+    """A library context and the oracle's key set for the same parameters and seed."""
+
+    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=()):
+        self.P = Params(N, t, L, alpha)
+        self.ctx = hg.Context(N, t, L, alpha)
+        self.ctx.keygen(seed, shapes)
+        if zs:
+            self.ctx.keygen_rotations(zs)
+        gal = H.galois_elements(self.P, shapes) + [self.P.galois(z) for z in zs]
+        self.ks = bgv.KeySet(self.P, seed, gal)
+        self.masks = H.MaskCache(self.P)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    c = workloads.TINY
+    return Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(4, 3, 5), (2, 5, 7), (5, 4, 2), (3, 11, 6), (7, 7, 7)],
+                zs=[1, 3, -2, 17])
+
+
+def test_primes(tiny):
+    assert tiny.ctx.primes() == tiny.P.ext
+
+
+def test_encrypt_bits(tiny):
+    rng = np.random.default_rng(1)
+    v = rng.integers(0, tiny.P.t, tiny.P.S)
+    got = tiny.ctx.encrypt_slots(v, nonce=9).export()
+    want = flat(bgv.encrypt_slots(tiny.ks, [int(x) for x in v], role=2, block=0, nonce=9))
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_export_import_roundtrip(tiny):
+    v = np.arange(tiny.P.S) % tiny.P.t
+    ct = tiny.ctx.encrypt_slots(v, nonce=3)
+    w = ct.export()
+    back = tiny.ctx.import_ct(w, 1, 2)
+    assert np.array_equal(back.export(), w)
+    assert np.array_equal(tiny.ctx.decrypt_slots(back), v)
+
+
+@pytest.mark.parametrize("z", [1, 3, -2, 17])
+def test_rotate_bits(tiny, z):
+    rng = np.random.default_rng(10 + z)
+    v = [int(x) for x in rng.integers(0, tiny.P.t, tiny.P.S)]
+    ct = tiny.ctx.encrypt_slots(v, nonce=20 + z)
+    got = tiny.ctx.rotate(ct, z).export()
+    oc = bgv.encrypt_slots(tiny.ks, v, role=2, block=0, nonce=20 + z)
+    want = flat(bgv.rotate(tiny.P, tiny.ks, oc, z))
+    assert np.array_equal(got, want)
+    dec = tiny.ctx.decrypt_slots(tiny.ctx.import_ct(got, 1, 2))
+    assert list(dec) == [v[(s + z) % tiny.P.S] for s in range(tiny.P.S)]
+
+
+def test_mul_bits(tiny):
+    rng = np.random.default_rng(5)
+    a = [int(x) for x in rng.integers(0, tiny.P.t, tiny.P.S)]
+    b = [int(x) for x in rng.integers(0, tiny.P.t, tiny.P.S)]
+    ca, cb = tiny.ctx.encrypt_slots(a, nonce=1), tiny.ctx.encrypt_slots(b, nonce=2)
+    got = tiny.ctx.mul(ca, cb).export()
+    oa = bgv.encrypt_slots(tiny.ks, a, role=2, block=0, nonce=1)
+    ob = bgv.encrypt_slots(tiny.ks, b, role=2, block=0, nonce=2)
+    want = flat(bgv.he_mult(tiny.P, tiny.ks, oa, ob))
+    assert np.array_equal(got, want)
+
+
+def run_pair(pair, m, l, n, A, B, nonce):
+    ctx, P, ks = pair.ctx, pair.P, pair.ks
+    ca = ctx.encrypt(0, A, m, l, n, nonce=nonce)
+    cb = ctx.encrypt(1, B, m, l, n, nonce=nonce)
+    pl = H.plan(m, l, n, P.S)
+    ox = H.encrypt_operand(ks, pl, 0, A, B, nonce)
+    oy = H.encrypt_operand(ks, pl, 1, A, B, nonce)
+    # operands: bit-identical packing + encryption
+    left, right = (cb, ca) if pl.transposed else (ca, cb)
+    assert np.array_equal(left.export(), np.concatenate([flat(c) for c in ox]))
+    assert np.array_equal(right.export(), np.concatenate([flat(c) for c in oy]))
+    cc = ctx.hegmm(ca, cb, m, l, n)
+    got = cc.export()
+    want = flat(H.hegmm(ks, pl, ox, oy, pair.masks))
+    assert np.array_equal(got, want), (m, l, n)
+    C = ctx.decrypt(cc, m, l, n)
+    assert np.array_equal(C, workloads.plain_matmul_mod(A, B, P.t))
+
+
+def test_hegmm_tiny_config(tiny):
+    A, B = workloads.tiny_operands()
+    run_pair(tiny, 4, 3, 5, A, B, nonce=1)
+
+
+@pytest.mark.parametrize("shape", [(2, 5, 7), (5, 4, 2), (3, 11, 6), (7, 7, 7)],
+                         ids=["dupA-fold", "transposed", "blocked", "square"])
+def test_hegmm_shapes(tiny, shape):
+    m, l, n = shape
+    rng = np.random.default_rng(sum(shape))
+    A = rng.integers(-8, 9, size=(m, l))
+    B = rng.integers(-8, 9, size=(l, n))
+    run_pair(tiny, m, l, n, A, B, nonce=7)
+
+
+def test_hegmm_alpha2():
+    pair = Pair(1024, 12289, 4, 2, 99, shapes=[(3, 7, 5), (6, 4, 9)])
+    rng = np.random.default_rng(3)
+    for (m, l, n) in [(3, 7, 5), (6, 4, 9)]:
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        run_pair(pair, m, l, n, A, B, nonce=5)
+
+
+def test_hegmm_headline_full_size():
+    """64x32x48 at N = 8192: the whole output ciphertext against the oracle."""
+    c = workloads.HEADLINE
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(64, 32, 48)])
+    A, B = workloads.headline_operands()
+    run_pair(pair, 64, 32, 48, A, B, nonce=1)
