@@ -140,10 +140,12 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_) {
             md_hat[(size_t)k * L + i] = (double)hmul(t % qs[i], h, qs[i]);
         }
     }
+    std::vector<double> pmod(L);
     for (int i = 0; i < L; ++i) {
         uint64_t P = 1;
         for (int k = 0; k < alpha; ++k) P = hmul(P, qs[L + k] % qs[i], qs[i]);
         pinv[i] = centered_d(hinv(P, qs[i]), qs[i]);
+        pmod[i] = centered_d(P, qs[i]);
     }
     auto up = [&](const void *src, size_t bytes) -> void * {
         void *p = nullptr;
@@ -162,6 +164,7 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_) {
     T.md_coef = (double *)up(md_coef.data(), md_coef.size() * sizeof(double));
     T.md_hat = (double *)up(md_hat.data(), md_hat.size() * sizeof(double));
     T.pinv = (double *)up(pinv.data(), pinv.size() * sizeof(double));
+    T.pmod = (double *)up(pmod.data(), pmod.size() * sizeof(double));
     T.t = (double)t;
     T.tinv = 1.0 / (double)t;
 }

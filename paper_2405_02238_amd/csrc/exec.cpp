@@ -28,7 +28,7 @@ namespace {
 // Host-side description of one phase-1..4 pass.
 struct Pass {
     std::vector<const double *> srcs;   // eval-form c1 of each hoisted source (L x N)
-    std::vector<int2> ip_jobs;          // (first term, count) per key-switched job
+    std::vector<IpJob> ip_jobs;         // key-switched jobs
     std::vector<IpTerm> ip_terms;
     std::vector<FinJob> fin_jobs;
     std::vector<FinTerm> fin_terms;
@@ -76,72 +76,108 @@ struct Exec {
     Exec(Ctx &c, hipStream_t s)
         : C(c), st(s), T(c.T), N(c.N), L(c.L), nExt(c.nExt), beta(c.beta), alpha(c.alpha) {}
 
-    // Adds a job to `ps`.  terms: (z, mask pointer or null).  Returns the job index.
+    // Adds a job to `ps`: the rotation sum sum_z mask_z (.) Rot(ct, z) over
+    // `terms` (z, mask pointer or null), plus the key switch of the hoisted
+    // source `src` under relin_key when given.  Jobs that need no key switch
+    // are finished from their plain terms.  Returns the job index.
     int add_job(Pass &ps, const double *ct, const std::vector<std::pair<int, const double *>> &terms,
                 int src, const double *relin_key) {
         FinJob fj;
         fj.c0 = ct;
         fj.c1 = ct + (size_t)L * N;
         fj.t0 = (int)ps.fin_terms.size();
+        fj.nt = 0;
         fj.ks = -1;
-        std::vector<IpTerm> ipt;
-        for (auto &tm : terms) {
-            const int g = C.galois_of(tm.first);
-            const int mid = ps.mask_id(tm.second);
-            ps.fin_terms.push_back({g, mid});
-            if (g != 1) {
-                auto it = C.rot_keys.find(g);
-                if (it == C.rot_keys.end())
-                    throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
-                ipt.push_back({src, g, mid, ps.key_id(it->second)});
+        bool ks = relin_key != nullptr;
+        for (auto &tm : terms) ks |= C.galois_of(tm.first) != 1;
+        if (!ks) {
+            for (auto &tm : terms) ps.fin_terms.push_back({1, ps.mask_id(tm.second)});
+            fj.nt = (int)ps.fin_terms.size() - fj.t0;
+        } else {
+            IpJob ij;
+            ij.c0 = fj.c0;
+            ij.c1 = fj.c1;
+            ij.src = src;
+            ij.t0 = (int)ps.ip_terms.size();
+            ij.pad = 0;
+            for (auto &tm : terms) {
+                const int g = C.galois_of(tm.first);
+                const int mid = ps.mask_id(tm.second);
+                if (g == 1) {
+                    ps.ip_terms.push_back({1, mid, -1, IP_PLAIN});
+                } else {
+                    auto it = C.rot_keys.find(g);
+                    if (it == C.rot_keys.end())
+                        throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
+                    ps.ip_terms.push_back({g, mid, ps.key_id(it->second), IP_ROT});
+                }
             }
-        }
-        if (relin_key) ipt.push_back({src, 1, -1, ps.key_id(relin_key)});
-        fj.nt = (int)ps.fin_terms.size() - fj.t0;
-        if (!ipt.empty()) {
+            if (relin_key) ps.ip_terms.push_back({1, -1, ps.key_id(relin_key), IP_RELIN});
+            ij.nt = (int)ps.ip_terms.size() - ij.t0;
             fj.ks = (int)ps.ip_jobs.size();
-            ps.ip_jobs.push_back(make_int2((int)ps.ip_terms.size(), (int)ipt.size()));
-            ps.ip_terms.insert(ps.ip_terms.end(), ipt.begin(), ipt.end());
+            ps.ip_jobs.push_back(ij);
         }
         ps.fin_jobs.push_back(fj);
         return (int)ps.fin_jobs.size() - 1;
     }
 
-    // Runs phases 1-3 of a pass; returns device pointers to U and delta.
-    // Descriptor tables are copied into the arena first.
+    // Device views of a staged pass.
     struct Dev {
-        double *U = nullptr, *delta = nullptr;
+        double *U = nullptr, *E = nullptr;
         FinJob *jobs = nullptr;
         FinTerm *terms = nullptr;
         const double *const *masks = nullptr;
         char *extra = nullptr;   // caller-requested table space
+        // internal
+        char *tab = nullptr;
+        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_srcs = 0;
+        double *coef = nullptr, *y = nullptr, *rk = nullptr;
+        int nsrc = 0, nks = 0;
     };
 
-    Dev run(Pass &ps, const void *extra_host, size_t extra_bytes, hipEvent_t *tev = nullptr) {
+    struct Staged {
+        Pass *ps;
+        const void *extra;
+        size_t extra_bytes;
+        Dev dv;
+    };
+
+    // Lay out the scratch of several passes that run one after another on
+    // the stream (one scratch region sized for the largest, one descriptor
+    // table block per pass) and copy every table with a single transfer.
+    void stage(std::vector<Staged> &sp) {
         Arena &A = C.arena(st);
-        const int nsrc = (int)ps.srcs.size();
-        const int nks = (int)ps.ip_jobs.size();
-        Layout lay;
-        const size_t o_coef = lay.add((size_t)nsrc * L * N * 8);
-        const size_t o_y = lay.add((size_t)nsrc * beta * nExt * N * 8);
-        const size_t o_U = lay.add((size_t)nks * 2 * nExt * N * 8);
-        const size_t o_rk = lay.add((size_t)nks * 2 * alpha * N * 8);
-        const size_t o_d = lay.add((size_t)nks * 2 * L * N * 8);
-        // tables (one contiguous block copied from pinned staging)
+        size_t scratch = 0;
+        std::vector<size_t> toff(sp.size());
         Layout tl;
-        const size_t t_ipj = tl.add(ps.ip_jobs.size() * sizeof(int2));
-        const size_t t_ipt = tl.add(ps.ip_terms.size() * sizeof(IpTerm));
-        const size_t t_fj = tl.add(ps.fin_jobs.size() * sizeof(FinJob));
-        const size_t t_ft = tl.add(ps.fin_terms.size() * sizeof(FinTerm));
-        const size_t t_keys = tl.add(ps.keys.size() * sizeof(void *));
-        const size_t t_masks = tl.add(ps.masks.size() * sizeof(void *));
-        const size_t t_extra = tl.add(extra_bytes);
+        struct Off { size_t ipj, ipt, fj, ft, keys, masks, extra, srcs; };
+        std::vector<Off> off(sp.size());
+        for (size_t i = 0; i < sp.size(); ++i) {
+            Pass &ps = *sp[i].ps;
+            const size_t nsrc = ps.srcs.size(), nks = ps.ip_jobs.size();
+            Layout lay;
+            lay.add(nsrc * L * N * 8);
+            lay.add(nsrc * beta * nExt * N * 8);
+            lay.add(nks * 2 * nExt * N * 8);
+            lay.add(nks * 2 * alpha * N * 8);
+            lay.add(nks * 2 * L * N * 8);
+            scratch = std::max(scratch, lay.total);
+            Off &o = off[i];
+            o.ipj = tl.add(ps.ip_jobs.size() * sizeof(IpJob));
+            o.ipt = tl.add(ps.ip_terms.size() * sizeof(IpTerm));
+            o.fj = tl.add(ps.fin_jobs.size() * sizeof(FinJob));
+            o.ft = tl.add(ps.fin_terms.size() * sizeof(FinTerm));
+            o.keys = tl.add(ps.keys.size() * sizeof(void *));
+            o.masks = tl.add(ps.masks.size() * sizeof(void *));
+            o.extra = tl.add(sp[i].extra_bytes);
+            o.srcs = tl.add(ps.srcs.size() * sizeof(void *));
+        }
         tl.add(256);   // never empty
-        const size_t o_tab = lay.add(tl.total);
-        if (lay.total > A.cap) {
+        const size_t total = scratch + tl.total;
+        if (total > A.cap) {
             HGCHK(hipStreamSynchronize(st));
             if (A.base) HGCHK(hipFree(A.base));
-            A.cap = align_up(lay.total + lay.total / 4, 1 << 20);
+            A.cap = align_up(total + total / 4, 1 << 20);
             HGCHK(hipMalloc(&A.base, A.cap));
         }
         if (tl.total > A.pinned_cap) {
@@ -152,58 +188,72 @@ struct Exec {
         }
         HGCHK(hipEventSynchronize(A.staged));   // the previous copy out of staging is done
         char *h = (char *)A.pinned;
-        auto put = [&](size_t off, const void *src, size_t bytes) {
-            if (bytes) std::memcpy(h + off, src, bytes);
-        };
-        put(t_ipj, ps.ip_jobs.data(), ps.ip_jobs.size() * sizeof(int2));
-        put(t_ipt, ps.ip_terms.data(), ps.ip_terms.size() * sizeof(IpTerm));
-        put(t_fj, ps.fin_jobs.data(), ps.fin_jobs.size() * sizeof(FinJob));
-        put(t_ft, ps.fin_terms.data(), ps.fin_terms.size() * sizeof(FinTerm));
-        put(t_keys, ps.keys.data(), ps.keys.size() * sizeof(void *));
-        put(t_masks, ps.masks.data(), ps.masks.size() * sizeof(void *));
-        put(t_extra, extra_host, extra_bytes);
         char *base = (char *)A.base;
-        HGCHK(hipMemcpyAsync(base + o_tab, h, tl.total, hipMemcpyHostToDevice, st));
+        char *tab = base + scratch;
+        auto put = [&](size_t o, const void *src, size_t bytes) {
+            if (bytes) std::memcpy(h + o, src, bytes);
+        };
+        for (size_t i = 0; i < sp.size(); ++i) {
+            Pass &ps = *sp[i].ps;
+            const Off &o = off[i];
+            put(o.ipj, ps.ip_jobs.data(), ps.ip_jobs.size() * sizeof(IpJob));
+            put(o.ipt, ps.ip_terms.data(), ps.ip_terms.size() * sizeof(IpTerm));
+            put(o.fj, ps.fin_jobs.data(), ps.fin_jobs.size() * sizeof(FinJob));
+            put(o.ft, ps.fin_terms.data(), ps.fin_terms.size() * sizeof(FinTerm));
+            put(o.keys, ps.keys.data(), ps.keys.size() * sizeof(void *));
+            put(o.masks, ps.masks.data(), ps.masks.size() * sizeof(void *));
+            put(o.extra, sp[i].extra, sp[i].extra_bytes);
+            put(o.srcs, ps.srcs.data(), ps.srcs.size() * sizeof(void *));
+            Dev &dv = sp[i].dv;
+            dv.tab = tab;
+            dv.jobs = (FinJob *)(tab + o.fj);
+            dv.terms = (FinTerm *)(tab + o.ft);
+            dv.masks = (const double *const *)(tab + o.masks);
+            dv.extra = tab + o.extra;
+            dv.t_ipj = o.ipj;
+            dv.t_ipt = o.ipt;
+            dv.t_keys = o.keys;
+            dv.t_srcs = o.srcs;
+            dv.nsrc = (int)ps.srcs.size();
+            dv.nks = (int)ps.ip_jobs.size();
+            Layout lay;
+            dv.coef = (double *)(base + lay.add((size_t)dv.nsrc * L * N * 8));
+            dv.y = (double *)(base + lay.add((size_t)dv.nsrc * beta * nExt * N * 8));
+            dv.U = (double *)(base + lay.add((size_t)dv.nks * 2 * nExt * N * 8));
+            dv.rk = (double *)(base + lay.add((size_t)dv.nks * 2 * alpha * N * 8));
+            dv.E = (double *)(base + lay.add((size_t)dv.nks * 2 * L * N * 8));
+        }
+        HGCHK(hipMemcpyAsync(tab, h, tl.total, hipMemcpyHostToDevice, st));
         HGCHK(hipEventRecord(A.staged, st));
+    }
 
-        Dev dv;
-        char *tab = base + o_tab;
-        dv.jobs = (FinJob *)(tab + t_fj);
-        dv.terms = (FinTerm *)(tab + t_ft);
-        dv.masks = (const double *const *)(tab + t_masks);
-        dv.extra = tab + t_extra;
-        dv.U = (double *)(base + o_U);
-        dv.delta = (double *)(base + o_d);
-        double *coef = (double *)(base + o_coef);
-        double *y = (double *)(base + o_y);
-        double *rk = (double *)(base + o_rk);
-
-        if (nks > 0) {
+    // Phases 1-3 of a staged pass: hoist, inner products, division by P.
+    void launch(const Dev &dv, hipEvent_t *tev = nullptr) {
+        if (dv.nks > 0) {
             // 1. hoist every source once: c1 -> coefficient form -> lifted digits
-            for (int s = 0; s < nsrc; ++s) {
-                NttArgs a;
-                a.out = coef + (size_t)s * L * N;
-                a.in = ps.srcs[s];
-                a.rows = L;
-                a.per = L;
-                ntt_inv(T, STORE_PLAIN, a, st);
-            }
+            NttArgs a;
+            a.out = dv.coef;
+            a.in_tab = (const double *const *)(dv.tab + dv.t_srcs);
+            a.rows = dv.nsrc * L;
+            a.per = L;
+            a.out_stride = (long long)L * N;
+            ntt_inv(T, STORE_PLAIN, a, st);
             NttArgs mu;
-            mu.out = y;
-            mu.in = coef;
-            mu.rows = nsrc * beta * nExt;
+            mu.out = dv.y;
+            mu.in = dv.coef;
+            mu.rows = dv.nsrc * beta * nExt;
             mu.in_stride = (long long)L * N;
             ntt_fwd(T, LOAD_MODUP, mu, st);
             if (tev) HGCHK(hipEventRecord(tev[0], st));
             // 2. inner products
-            ip_launch(T, dv.U, y, (const double *const *)(tab + t_keys), dv.masks, (const int2 *)(tab + t_ipj),
-                      (const IpTerm *)(tab + t_ipt), nks, st);
+            ip_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
+                      (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks, st);
             if (tev) HGCHK(hipEventRecord(tev[1], st));
             // 3. division by P
             NttArgs md;
-            md.out = rk;
+            md.out = dv.rk;
             md.in = dv.U;
-            md.rows = nks * 2 * alpha;
+            md.rows = dv.nks * 2 * alpha;
             md.per = alpha;
             md.prime_base = L;
             md.out_stride = (long long)alpha * N;
@@ -211,16 +261,24 @@ struct Exec {
             md.in_offset = (long long)L * N;
             ntt_inv(T, STORE_MDR, md, st);
             NttArgs dl;
-            dl.out = dv.delta;
-            dl.in = rk;
-            dl.rows = nks * 2 * L;
+            dl.out = dv.E;
+            dl.in = dv.rk;
+            dl.aux = dv.U;
+            dl.rows = dv.nks * 2 * L;
             dl.in_stride = (long long)alpha * N;
             ntt_fwd(T, LOAD_DELTA, dl, st);
             if (tev) HGCHK(hipEventRecord(tev[2], st));
         } else if (tev) {
             for (int i = 0; i < 3; ++i) HGCHK(hipEventRecord(tev[i], st));
         }
-        return dv;
+    }
+
+    // Stage and launch a single pass.
+    Dev run(Pass &ps, const void *extra_host, size_t extra_bytes, hipEvent_t *tev = nullptr) {
+        std::vector<Staged> sp{{&ps, extra_host, extra_bytes, Dev()}};
+        stage(sp);
+        launch(sp[0].dv, tev);
+        return sp[0].dv;
     }
 };
 
@@ -259,7 +317,7 @@ void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
         HGCHK(hipEventRecord(ev[9], st));
     }
 
-    // --- phases 1-4 for every eps^k / omega^k transform, tensor-accumulated ---
+    // --- main pass: every eps^k / omega^k transform, then tensor accumulation ---
     Pass ps;
     std::vector<int2> req_pairs(nreq);
     for (int ri = 0; ri < nreq; ++ri) {
@@ -288,59 +346,63 @@ void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
             }
         }
     }
-    // accumulators: one 3 x L x N block per request, in a pass-owned buffer
+    // request-lifetime buffers: accumulators (3 x L x N) and relinearised R (2 x L x N, fold only)
+    int nfold = 0;
+    for (int ri = 0; ri < nreq; ++ri) nfold += info[ri].pe->plan.d > 1;
     double *acc = nullptr;
-    HGCHK(hipMallocAsync((void **)&acc, (size_t)nreq * 3 * ctw * sizeof(double), st));
+    HGCHK(hipMallocAsync((void **)&acc, ((size_t)nreq * 3 + (size_t)nfold * 2) * ctw * sizeof(double), st));
+    double *rbuf = acc + (size_t)nreq * 3 * ctw;
     std::vector<double *> acc_ptrs(nreq);
     for (int ri = 0; ri < nreq; ++ri) acc_ptrs[ri] = acc + (size_t)ri * 3 * ctw;
     std::vector<char> extra(req_pairs.size() * sizeof(int2) + acc_ptrs.size() * sizeof(void *));
     std::memcpy(extra.data(), req_pairs.data(), req_pairs.size() * sizeof(int2));
     std::memcpy(extra.data() + req_pairs.size() * sizeof(int2), acc_ptrs.data(), acc_ptrs.size() * sizeof(void *));
-    Exec::Dev dv = ex.run(ps, extra.data(), extra.size(), timing.enabled ? ev : nullptr);
-    fin_tensor_launch(T, dv.jobs, dv.terms, dv.U, dv.delta, dv.masks, (const int2 *)dv.extra,
-                      (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
-    if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
 
-    // --- relinearise once per product (lazy) ---
+    // --- relinearisation pass: once per product (lazy) ---
+    Pass pr;
     std::vector<double *> R(nreq, nullptr);
-    double *rbuf = nullptr;
-    int nfold = 0;
-    for (int ri = 0; ri < nreq; ++ri) nfold += info[ri].pe->plan.d > 1;
-    if (nfold) HGCHK(hipMallocAsync((void **)&rbuf, (size_t)nfold * 2 * ctw * sizeof(double), st));
     {
-        Pass pr;
         int fi = 0;
         for (int ri = 0; ri < nreq; ++ri) {
-            Ct *out = reqs[ri].out;
-            R[ri] = info[ri].pe->plan.d > 1 ? rbuf + (size_t)(fi++) * 2 * ctw : out->d;
+            R[ri] = info[ri].pe->plan.d > 1 ? rbuf + (size_t)(fi++) * 2 * ctw : reqs[ri].out->d;
             // a job over (Acc0, Acc1) with the unrotated term, plus the key
             // switch of Acc2 (the hoisted source) under the key for s^2
             pr.srcs.push_back(acc_ptrs[ri] + 2 * ctw);
             ex.add_job(pr, acc_ptrs[ri], {{0, nullptr}}, ri, relin_key);
         }
-        Exec::Dev d2 = ex.run(pr, R.data(), R.size() * sizeof(void *));
-        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.U, d2.delta, d2.masks, (double *const *)d2.extra, nreq, st);
     }
-    if (timing.enabled) HGCHK(hipEventRecord(ev[4], st));
+    // --- fold pass: C = sum_h Rot(R, h*mo) for the products with d > 1 ---
+    Pass pf;
+    std::vector<double *> outs;
+    for (int ri = 0; ri < nreq; ++ri) {
+        const Plan &p = info[ri].pe->plan;
+        if (p.d == 1) continue;
+        std::vector<std::pair<int, const double *>> terms;
+        for (int z : p.fold) terms.push_back({z, nullptr});
+        const int src = (int)pf.srcs.size();
+        pf.srcs.push_back(R[ri] + ctw);
+        ex.add_job(pf, R[ri], terms, src, nullptr);
+        outs.push_back(reqs[ri].out->d);
+    }
+    std::vector<Exec::Staged> sp;
+    sp.push_back({&ps, extra.data(), extra.size(), Exec::Dev()});
+    sp.push_back({&pr, R.data(), R.size() * sizeof(void *), Exec::Dev()});
+    if (nfold) sp.push_back({&pf, outs.data(), outs.size() * sizeof(void *), Exec::Dev()});
+    ex.stage(sp);
 
-    // --- fold the d row blocks: C = sum_h Rot(R, h*mo) ---
+    const Exec::Dev &dv = sp[0].dv;
+    ex.launch(dv, timing.enabled ? ev : nullptr);
+    fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
+                      (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
+    if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
+    const Exec::Dev &d2 = sp[1].dv;
+    ex.launch(d2);
+    fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, nreq, st);
+    if (timing.enabled) HGCHK(hipEventRecord(ev[4], st));
     if (nfold) {
-        Pass pf;
-        std::vector<double *> outs;
-        for (int ri = 0; ri < nreq; ++ri) {
-            const Plan &p = info[ri].pe->plan;
-            if (p.d == 1) continue;
-            std::vector<std::pair<int, const double *>> terms;
-            for (int z : p.fold) terms.push_back({z, nullptr});
-            const int src = (int)pf.srcs.size();
-            pf.srcs.push_back(R[ri] + ctw);
-            ex.add_job(pf, R[ri], terms, src, nullptr);
-            outs.push_back(reqs[ri].out->d);
-        }
-        Exec::Dev d3 = ex.run(pf, outs.data(), outs.size() * sizeof(void *));
-        fin_rotsum_launch(T, d3.jobs, d3.terms, d3.U, d3.delta, d3.masks, (double *const *)d3.extra,
-                          (int)outs.size(), st);
-        HGCHK(hipFreeAsync(rbuf, st));
+        const Exec::Dev &d3 = sp[2].dv;
+        ex.launch(d3);
+        fin_rotsum_launch(T, d3.jobs, d3.terms, d3.E, d3.masks, (double *const *)d3.extra, (int)outs.size(), st);
     }
     HGCHK(hipFreeAsync(acc, st));
     if (timing.enabled) {
@@ -359,7 +421,7 @@ void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
         timing.ms[5] = el(ev[4], ev[5]);
         timing.ms[6] = el(ev[9], ev[5]);
         timing.ms[7] = timing.ms[1];
-        for (auto &e : ev) (void)hipEventDestroy(e);
+        for (auto &x : ev) (void)hipEventDestroy(x);
     }
 }
 
@@ -376,7 +438,7 @@ Ct *Ctx::rotate(const Ct &c, int z, hipStream_t st) {
         ex.add_job(ps, c.d, {{z, nullptr}}, 0, nullptr);
         double *outp = o->d;
         Exec::Dev dv = ex.run(ps, &outp, sizeof(void *));
-        fin_rotsum_launch(T, dv.jobs, dv.terms, dv.U, dv.delta, dv.masks, (double *const *)dv.extra, 1, st);
+        fin_rotsum_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (double *const *)dv.extra, 1, st);
     } catch (...) {
         delete o;
         throw;
@@ -401,14 +463,14 @@ Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
         struct { int2 rp; double *ap; } ext{make_int2(0, 1), acc};
         static_assert(sizeof(ext) == 16, "layout");
         Exec::Dev dv = ex.run(ps, &ext, sizeof(ext));
-        fin_tensor_launch(T, dv.jobs, dv.terms, dv.U, dv.delta, dv.masks, (const int2 *)dv.extra,
+        fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
                           (double *const *)(dv.extra + 8), 1, st);
         Pass pr;
         pr.srcs.push_back(acc + 2 * ctw);
         ex.add_job(pr, acc, {{0, nullptr}}, 0, relin_key);
         double *outp = o->d;
         Exec::Dev d2 = ex.run(pr, &outp, sizeof(void *));
-        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.U, d2.delta, d2.masks, (double *const *)d2.extra, 1, st);
+        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, 1, st);
         HGCHK(hipFreeAsync(acc, st));
     } catch (...) {
         delete o;

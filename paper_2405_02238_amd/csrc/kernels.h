@@ -27,27 +27,42 @@ struct DevTables {
     double *md_coef = nullptr;    // [alpha]: N^-1 t^-1 (P/p_k)^-1 mod p_k, centered
     double *md_hat = nullptr;     // [alpha][L]: t (P/p_k) mod q_i
     double *pinv = nullptr;       // [L]: P^-1 mod q_i, centered
+    double *pmod = nullptr;       // [L]: P mod q_i, centered
     double t = 0.0, tinv = 0.0;   // plaintext modulus and fl(1/t), by value
 };
 
-// One key-switched (rotation or relinearisation) term of an inner-product job.
+// Terms of an inner-product job.  A job computes, over the extended basis,
+//   U = P * sum_plain mask (.) phi_g(c0)   [+ P * mask (.) c1 on component 1 when g = 1]
+//     + sum_rot   mask (.) KS_g(src)        (inner product of the permuted hoisted digits)
+//     + KS_relin(src)
+// so that the division by P of U yields the finished rotation sum directly.
+enum IpKind { IP_ROT = 0, IP_PLAIN = 1, IP_RELIN = 2 };
+
 struct IpTerm {
-    int src;    // hoisted digit set
     int g;      // Galois element (1 = no permutation)
     int mask;   // index into the mask pointer table, -1 = none
-    int key;    // index into the key pointer table
+    int key;    // index into the key pointer table, -1 = none (IP_PLAIN)
+    int kind;   // IpKind
 };
 
-// One term of a finishing job (contributions that need no key switch).
+struct IpJob {
+    const double *c0;   // L x N, evaluation form (source of the unswitched part)
+    const double *c1;
+    int src;            // hoisted digit set for the key-switched terms
+    int t0, nt;         // terms [t0, t0 + nt)
+    int pad;
+};
+
+// One term of a finishing job without key switching (the identity transforms).
 struct FinTerm {
-    int g;      // Galois element applied to c0 (1 also adds the c1 term)
+    int g;      // must be 1
     int mask;   // -1 = none
 };
 
 struct FinJob {
     const double *c0;   // L x N, evaluation form
     const double *c1;
-    int ks;             // key-switch slot (row in U / delta), -1 if none
+    int ks;             // key-switch slot: the finished output is E[ks]; -1: use the terms
     int t0, nt;         // terms [t0, t0 + nt)
 };
 
@@ -63,6 +78,8 @@ struct NttArgs {
     long long out_stride = 0;  // elements between groups
     long long in_stride = 0;
     long long in_offset = 0;
+    const double *const *in_tab = nullptr;  // LOAD_PLAIN / inverse: per-group source pointers (device)
+    const double *aux = nullptr;            // LOAD_DELTA: U (the un-divided sums), slot stride nExt*N
 };
 
 // Forward transform of `rows` rows (natural order in, bit-reversed out).
@@ -72,7 +89,9 @@ struct NttArgs {
 //              row index (src*beta + j)*nExt + r, contiguous.
 //  LOAD_DELTA: rows are (slot, i) with i over the L ciphertext primes; `in`
 //              holds alpha rows of centered r_k per slot (stride in_stride);
-//              output contiguous slot*L + i.
+//              the transform of delta_i is subtracted from U_i (aux) and the
+//              difference multiplied by P^-1: output E_i = (U_i - delta_i)/P,
+//              contiguous slot*L + i.
 void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s);
 
 // Inverse transform (bit-reversed in, natural out).
@@ -82,22 +101,27 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s);
 //  STORE_CANON: times N^-1, canonical residue in [0, q).
 void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s);
 
-// Inner products: U[job][c][r][p] = sum over the job's terms of
-// mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)].
+// Row count below which a transform is split into a column pass and a block
+// pass of 1024-element workgroups (spreading each row over N/1024 CUs);
+// rows longer than 16384 always use the split form.
+void ntt_set_split_rows(int rows);
+
+// Inner products: U[job][c][r][p] = sum over the job's key-switched terms of
+// mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
+// the unswitched part on the ciphertext primes (see IpTerm).
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-               const double *const *masks, const int2 *jobs, const IpTerm *terms, int njobs,
+               const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
                hipStream_t s);
 
 // Tensor-accumulate: per request, sum over its (eps job, omega job) pairs of
-// the tensor product of the two finished transforms.
-void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms,
-                       const double *U, const double *delta, const double *const *masks,
-                       const int2 *req_pairs, double *const *acc, int nreq, hipStream_t s);
+// the tensor product of the two finished transforms (E slots or plain terms).
+void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,
+                       const double *const *masks, const int2 *req_pairs, double *const *acc, int nreq,
+                       hipStream_t s);
 
-// Finish rotation sums: out[job] = (sum mask*phi(c0) + (U0-d0)/P, sum_{g=1} mask*c1 + (U1-d1)/P).
-void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms,
-                       const double *U, const double *delta, const double *const *masks,
-                       double *const *out, int njobs, hipStream_t s);
+// Finished rotation sums written as ciphertexts: out[job] = E[ks] (or the plain terms).
+void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,
+                       const double *const *masks, double *const *out, int njobs, hipStream_t s);
 
 // Allow the transform kernels the full LDS of a CDNA4 workgroup (call once
 // per device before the first transform with N > 4096).

@@ -3,299 +3,181 @@
 #include "kernels.h"
 
 #include "arith.h"
+#include "dev_common.h"
 #include "gauss_cdt.h"
 
 namespace hg {
 
 namespace {
 
-constexpr int NTT_THREADS_MAX = 512;
-
-__device__ __forceinline__ int brev_bits(int x, int bits) {
-    return (int)(__brev((unsigned)x) >> (32 - bits));
-}
-
-// Evaluation-form automorphism X -> X^g: position p holds the value at
-// psi^(2 brv(p) + 1).  The permuted polynomial's value there is the source
-// value at psi^((2 brv(p) + 1) g): natural index ((2i+1) g mod 2N - 1) / 2.
-__device__ __forceinline__ int perm_index(int p, int g, int logN) {
-    int i = brev_bits(p, logN);
-    int twoN = 2 << logN;
-    int e = (int)(((long long)(2 * i + 1) * g) & (twoN - 1));
-    return brev_bits((e - 1) >> 1, logN);
-}
-
-// One workgroup transforms one row held in LDS.  Rounds of up to three
-// radix-2 stages run in registers on groups of eight elements; LDS carries
-// the data between rounds.
-template <int LOAD>
-__global__ void __launch_bounds__(NTT_THREADS_MAX)
-k_ntt_fwd(DevTables T, NttArgs a) {
-    extern __shared__ double sh[];
-    const int row = blockIdx.x;
-    const int logN = T.logN;
-    const int N = 1 << logN;
-    int prime;
-    double *out;
-    if (LOAD == LOAD_MODUP) {
-        const int r = row % T.nExt;
-        const int j = (row / T.nExt) % T.beta;
-        const int src = row / (T.nExt * T.beta);
-        prime = r;
-        out = a.out + (size_t)row * N;
-        const double *c = a.in + (size_t)src * a.in_stride;
-        const int d0 = j * T.alpha;
-        const int d1 = min(d0 + T.alpha, T.L);
-        const double qr = T.qt[r].x, qir = T.qt[r].y;
-        if (r >= d0 && r < d1) {
-            for (int i = threadIdx.x; i < N; i += blockDim.x) sh[i] = c[(size_t)r * N + i];
-        } else if (d1 - d0 == 1) {
-            // one-prime digit: the centered residue itself is the lift
-            const double qd = T.qt[d0].x, qid = T.qt[d0].y;
-            for (int i = threadIdx.x; i < N; i += blockDim.x)
-                sh[i] = centerm(c[(size_t)d0 * N + i], qd, qid);
-        } else {
-            for (int i = threadIdx.x; i < N; i += blockDim.x) {
-                double acc = 0.0;
-                for (int s = d0; s < d1; ++s) {
-                    const double qs = T.qt[s].x, qis = T.qt[s].y;
-                    double ct = centerm(mulm(c[(size_t)s * N + i], T.mu_invhat[s], qs, qis), qs, qis);
-                    acc += mulm(ct, T.mu_hat[s * T.nExt + r], qr, qir);
-                }
-                sh[i] = redm(acc, qr, qir);
-            }
-        }
-    } else if (LOAD == LOAD_DELTA) {
-        const int i_q = row % T.L;
-        const int slot = row / T.L;
-        prime = i_q;
-        out = a.out + (size_t)row * N;
-        const double *rk = a.in + (size_t)slot * a.in_stride;
-        const double qr = T.qt[i_q].x, qir = T.qt[i_q].y;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            double acc = 0.0;
-            for (int k = 0; k < T.alpha; ++k)
-                acc += mulm(rk[(size_t)k * N + i], T.md_hat[k * T.L + i_q], qr, qir);
-            sh[i] = redm(acc, qr, qir);
-        }
-    } else {
-        const int g = row / a.per, rr = row % a.per;
-        prime = a.prime_base + rr;
-        out = a.out + (size_t)g * a.out_stride + (size_t)rr * N;
-        const double *in = a.in + (size_t)g * a.in_stride + a.in_offset + (size_t)rr * N;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) sh[i] = in[i];
-    }
-    __syncthreads();
-    const double q = T.qt[prime].x, qi = T.qt[prime].y;
-    const double *tw = T.twf + (size_t)prime * N;
-    for (int s0 = 0; s0 < logN;) {
-        const int k = min(3, logN - s0);
-        const int lts = logN - s0 - k;           // log2 of the smallest half-size ts
-        const int ts = 1 << lts;
-        const int ngroups = N >> k;
-        for (int grp = threadIdx.x; grp < ngroups; grp += blockDim.x) {
-            const int low = grp & (ts - 1);
-            const int blk = grp >> lts;
-            const int base = (blk << (lts + k)) + low;
-            double x[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b < (1 << k)) x[b] = sh[base + b * ts];
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                if (u >= k) break;
-                const int m = 1 << (s0 + u);
-                const int half = 1 << (k - 1 - u);
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    if (b >= (1 << k) || (b & half)) continue;
-                    const double w = tw[m + (blk << u) + (b >> (k - u))];
-                    const double t = mulm(x[b + half], w, q, qi);
-                    const double X = x[b];
-                    x[b] = redm(X + t, q, qi);
-                    x[b + half] = redm(X - t, q, qi);
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b < (1 << k)) sh[base + b * ts] = x[b];
-        }
-        __syncthreads();
-        s0 += k;
-    }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = sh[i];
-}
-
-template <int STORE>
-__global__ void __launch_bounds__(NTT_THREADS_MAX)
-k_ntt_inv(DevTables T, NttArgs a) {
-    extern __shared__ double sh[];
-    const int row = blockIdx.x;
-    const int logN = T.logN;
-    const int N = 1 << logN;
-    const int g = row / a.per, rr = row % a.per;
-    const int prime = a.prime_base + rr;
-    double *out = a.out + (size_t)g * a.out_stride + (size_t)rr * N;
-    const double *in = a.in + (size_t)g * a.in_stride + a.in_offset + (size_t)rr * N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[i] = in[i];
-    __syncthreads();
-    const double q = T.qt[prime].x, qi = T.qt[prime].y;
-    const double *tw = T.twi + (size_t)prime * N;
-    for (int shi = logN - 1; shi >= 0;) {
-        const int k = min(3, shi + 1);
-        const int lts = logN - shi - 1;          // first stage of the round has half-size ts
-        const int ts = 1 << lts;
-        const int ngroups = N >> k;
-        for (int grp = threadIdx.x; grp < ngroups; grp += blockDim.x) {
-            const int low = grp & (ts - 1);
-            const int blk = grp >> lts;
-            const int base = (blk << (lts + k)) + low;
-            double x[8];
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b < (1 << k)) x[b] = sh[base + b * ts];
-#pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                if (u >= k) break;
-                const int h = N >> (lts + u + 1);     // N / (2 t), t = ts << u
-                const int d = 1 << u;
-#pragma unroll
-                for (int b = 0; b < 8; ++b) {
-                    if (b >= (1 << k) || (b & d)) continue;
-                    const double w = tw[h + (blk << (k - u - 1)) + (b >> (u + 1))];
-                    const double X = x[b], Y = x[b + d];
-                    x[b] = redm(X + Y, q, qi);
-                    x[b + d] = mulm(X - Y, w, q, qi);
-                }
-            }
-#pragma unroll
-            for (int b = 0; b < 8; ++b)
-                if (b < (1 << k)) sh[base + b * ts] = x[b];
-        }
-        __syncthreads();
-        shi -= k;
-    }
-    if (STORE == STORE_MDR) {
-        const double c = T.md_coef[rr];
-        for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = centerm(mulm(sh[i], c, q, qi), q, qi);
-    } else {
-        const double c = T.ninv[prime];
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            double v = mulm(sh[i], c, q, qi);
-            if (STORE == STORE_CANON) v = canonm(centerm(v, q, qi), q);
-            out[i] = v;
-        }
-    }
-}
-
 constexpr int EW_THREADS = 256;
 
+constexpr int IP_THREADS = 256;
+
 // Key-switching inner products with the automorphism folded into the gather
-// of the hoisted digits.  grid: (N / 256, nExt, jobs).
-__global__ void __launch_bounds__(EW_THREADS)
+// of the hoisted digits; two consecutive positions per thread (16-byte key
+// loads), the digit loop unrolled (BETA digits) so that all key loads of a
+// term are in flight together.  grid: (N / 512, nExt, jobs).
+template <int BETA>
+__global__ void __launch_bounds__(IP_THREADS)
 k_ip(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
-     const int2 *jobs, const IpTerm *terms) {
+     const IpJob *jobs, const IpTerm *terms) {
     const int N = 1 << T.logN;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     const int r = blockIdx.y;
     const int job = blockIdx.z;
     if (p >= N) return;
     const double q = T.qt[r].x, qi = T.qt[r].y;
-    const size_t plane = (size_t)T.nExt * N;           // one digit (or component) of all primes
-    const int2 jt = jobs[job];
-    double acc0 = 0.0, acc1 = 0.0;
-    for (int tix = jt.x; tix < jt.x + jt.y; ++tix) {
+    const size_t plane = (size_t)T.nExt * N;   // one digit (or component) of all primes
+    const IpJob J = jobs[job];
+    const bool qrow = r < T.L;
+    double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;   // key-switched sums
+    double c0x = 0.0, c0y = 0.0, c1x = 0.0, c1y = 0.0;   // unswitched sums (ciphertext primes)
+    for (int tix = J.t0; tix < J.t0 + J.nt; ++tix) {
         const IpTerm tm = terms[tix];
-        const int pp = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
-        const double *ys = y + (size_t)tm.src * T.beta * plane + (size_t)r * N + pp;
-        const double *kb = keys[tm.key] + (size_t)r * N + p;
-        double s0 = 0.0, s1 = 0.0;
-        for (int j = 0; j < T.beta; ++j) {
-            const double yv = ys[(size_t)j * plane];
-            s0 += mulm(yv, kb[(size_t)(2 * j) * plane], q, qi);
-            s1 += mulm(yv, kb[(size_t)(2 * j + 1) * plane], q, qi);
+        double2 mv = make_double2(1.0, 1.0);
+        if (tm.mask >= 0) mv = *(const double2 *)(masks[tm.mask] + (size_t)r * N + p);
+        const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
+        const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
+        if (tm.kind != IP_PLAIN) {
+            const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
+            const double *kb = keys[tm.key] + (size_t)r * N + p;
+            double y0[BETA], y1[BETA];
+            double2 kbv[BETA], kav[BETA];
+#pragma unroll
+            for (int j = 0; j < BETA; ++j) {
+                y0[j] = ys[(size_t)j * plane + pp0];
+                y1[j] = ys[(size_t)j * plane + pp1];
+                kbv[j] = *(const double2 *)(kb + (size_t)(2 * j) * plane);
+                kav[j] = *(const double2 *)(kb + (size_t)(2 * j + 1) * plane);
+            }
+            double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+#pragma unroll
+            for (int j = 0; j < BETA; ++j) {
+                s0x += mulm(y0[j], kbv[j].x, q, qi);
+                s0y += mulm(y1[j], kbv[j].y, q, qi);
+                s1x += mulm(y0[j], kav[j].x, q, qi);
+                s1y += mulm(y1[j], kav[j].y, q, qi);
+            }
+            s0x = redm(s0x, q, qi);
+            s0y = redm(s0y, q, qi);
+            s1x = redm(s1x, q, qi);
+            s1y = redm(s1y, q, qi);
+            if (tm.mask >= 0) {
+                s0x = mulm(s0x, mv.x, q, qi);
+                s0y = mulm(s0y, mv.y, q, qi);
+                s1x = mulm(s1x, mv.x, q, qi);
+                s1y = mulm(s1y, mv.y, q, qi);
+            }
+            a0x = redm(a0x + s0x, q, qi);
+            a0y = redm(a0y + s0y, q, qi);
+            a1x = redm(a1x + s1x, q, qi);
+            a1y = redm(a1y + s1y, q, qi);
         }
-        s0 = redm(s0, q, qi);
-        s1 = redm(s1, q, qi);
-        if (tm.mask >= 0) {
-            const double mv = masks[tm.mask][(size_t)r * N + p];
-            s0 = mulm(s0, mv, q, qi);
-            s1 = mulm(s1, mv, q, qi);
+        if (qrow && tm.kind != IP_RELIN) {
+            double x0 = J.c0[(size_t)r * N + pp0], x1 = J.c0[(size_t)r * N + pp1];
+            if (tm.mask >= 0) {
+                x0 = mulm(x0, mv.x, q, qi);
+                x1 = mulm(x1, mv.y, q, qi);
+            }
+            c0x = redm(c0x + x0, q, qi);
+            c0y = redm(c0y + x1, q, qi);
+            if (tm.g == 1) {
+                const double2 w = *(const double2 *)(J.c1 + (size_t)r * N + p);
+                double z0 = w.x, z1 = w.y;
+                if (tm.mask >= 0) {
+                    z0 = mulm(z0, mv.x, q, qi);
+                    z1 = mulm(z1, mv.y, q, qi);
+                }
+                c1x = redm(c1x + z0, q, qi);
+                c1y = redm(c1y + z1, q, qi);
+            }
         }
-        acc0 = redm(acc0 + s0, q, qi);
-        acc1 = redm(acc1 + s1, q, qi);
+    }
+    if (qrow) {
+        const double P = T.pmod[r];
+        a0x = redm(a0x + mulm(c0x, P, q, qi), q, qi);
+        a0y = redm(a0y + mulm(c0y, P, q, qi), q, qi);
+        a1x = redm(a1x + mulm(c1x, P, q, qi), q, qi);
+        a1y = redm(a1y + mulm(c1y, P, q, qi), q, qi);
     }
     double *u = U + (size_t)job * 2 * plane + (size_t)r * N + p;
-    u[0] = acc0;
-    u[plane] = acc1;
+    *(double2 *)u = make_double2(a0x, a0y);
+    *(double2 *)(u + plane) = make_double2(a1x, a1y);
 }
 
-// One finished rotation sum at (prime i, position p).
+// One finished rotation sum at (prime i, position p): a key-switched job's
+// output sits in E; an identity job adds its (masked) c0, c1.
 __device__ __forceinline__ void finish_one(const DevTables &T, const FinJob &J, const FinTerm *terms,
-                                           const double *U, const double *delta,
-                                           const double *const *masks, int i, int p, double q, double qi,
-                                           double &e0, double &e1) {
+                                           const double *E, const double *const *masks, int i, int p, double q,
+                                           double qi, double &e0, double &e1) {
     const int N = 1 << T.logN;
     const size_t off = (size_t)i * N;
+    if (J.ks >= 0) {
+        const size_t plane = (size_t)T.L * N;
+        const double *e = E + (size_t)J.ks * 2 * plane + off + p;
+        e0 = e[0];
+        e1 = e[plane];
+        return;
+    }
     e0 = 0.0;
     e1 = 0.0;
     for (int t = J.t0; t < J.t0 + J.nt; ++t) {
         const FinTerm ft = terms[t];
-        if (ft.g == 1) {
-            double x0 = J.c0[off + p], x1 = J.c1[off + p];
-            if (ft.mask >= 0) {
-                const double mv = masks[ft.mask][off + p];
-                x0 = mulm(x0, mv, q, qi);
-                x1 = mulm(x1, mv, q, qi);
-            }
-            e0 = redm(e0 + x0, q, qi);
-            e1 = redm(e1 + x1, q, qi);
-        } else {
-            double x0 = J.c0[off + perm_index(p, ft.g, T.logN)];
-            if (ft.mask >= 0) x0 = mulm(x0, masks[ft.mask][off + p], q, qi);
-            e0 = redm(e0 + x0, q, qi);
+        double x0 = J.c0[off + p], x1 = J.c1[off + p];
+        if (ft.mask >= 0) {
+            const double mv = masks[ft.mask][off + p];
+            x0 = mulm(x0, mv, q, qi);
+            x1 = mulm(x1, mv, q, qi);
         }
-    }
-    if (J.ks >= 0) {
-        const size_t uplane = (size_t)T.nExt * N;
-        const size_t dplane = (size_t)T.L * N;
-        const double *u = U + (size_t)J.ks * 2 * uplane + off + p;
-        const double *dl = delta + (size_t)J.ks * 2 * dplane + off + p;
-        const double pinv = T.pinv[i];
-        e0 = redm(e0 + mulm(u[0] - dl[0], pinv, q, qi), q, qi);
-        e1 = redm(e1 + mulm(u[uplane] - dl[dplane], pinv, q, qi), q, qi);
+        e0 = redm(e0 + x0, q, qi);
+        e1 = redm(e1 + x1, q, qi);
     }
 }
 
-__global__ void __launch_bounds__(EW_THREADS)
-k_fin_tensor(DevTables T, const FinJob *jobs, const FinTerm *terms, const double *U, const double *delta,
-             const double *const *masks, const int2 *req_pairs, double *const *acc) {
+constexpr int FT_P = 64;  // positions per block of the tensor accumulation
+constexpr int FT_C = 4;   // pair chunks per block, reduced through LDS
+
+// Tensor accumulation: block (64 positions x 4 pair chunks) per (prime i,
+// request); each thread sums a strided quarter of the request's (eps, omega)
+// pairs, then the four partial sums are added in LDS.
+__global__ void __launch_bounds__(FT_P * FT_C)
+k_fin_tensor(DevTables T, const FinJob *jobs, const FinTerm *terms, const double *E, const double *const *masks,
+             const int2 *req_pairs, double *const *acc) {
+    __shared__ double part[3][FT_C][FT_P];
     const int N = 1 << T.logN;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.x * FT_P + threadIdx.x;
+    const int c = threadIdx.y;
     const int i = blockIdx.y;
     const int req = blockIdx.z;
-    if (p >= N) return;
     const double q = T.qt[i].x, qi = T.qt[i].y;
     const int2 pr = req_pairs[req];
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int pi = pr.x; pi < pr.x + pr.y; ++pi) {
-        double e0, e1, f0, f1;
-        finish_one(T, jobs[2 * pi], terms, U, delta, masks, i, p, q, qi, e0, e1);
-        finish_one(T, jobs[2 * pi + 1], terms, U, delta, masks, i, p, q, qi, f0, f1);
-        a0 = redm(a0 + mulm(e0, f0, q, qi), q, qi);
-        a1 = redm(a1 + mulm(e0, f1, q, qi) + mulm(e1, f0, q, qi), q, qi);
-        a2 = redm(a2 + mulm(e1, f1, q, qi), q, qi);
+    if (p < N) {
+        for (int pi = pr.x + c; pi < pr.x + pr.y; pi += FT_C) {
+            double e0, e1, f0, f1;
+            finish_one(T, jobs[2 * pi], terms, E, masks, i, p, q, qi, e0, e1);
+            finish_one(T, jobs[2 * pi + 1], terms, E, masks, i, p, q, qi, f0, f1);
+            a0 = redm(a0 + mulm(e0, f0, q, qi), q, qi);
+            a1 = redm(a1 + mulm(e0, f1, q, qi) + mulm(e1, f0, q, qi), q, qi);
+            a2 = redm(a2 + mulm(e1, f1, q, qi), q, qi);
+        }
     }
-    const size_t plane = (size_t)T.L * N;
-    double *o = acc[req] + (size_t)i * N + p;
-    o[0] = a0;
-    o[plane] = a1;
-    o[2 * plane] = a2;
+    part[0][c][threadIdx.x] = a0;
+    part[1][c][threadIdx.x] = a1;
+    part[2][c][threadIdx.x] = a2;
+    __syncthreads();
+    if (c < 3 && p < N) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < FT_C; ++k) s += part[c][k][threadIdx.x];
+        acc[req][(size_t)c * T.L * N + (size_t)i * N + p] = redm(s, q, qi);
+    }
 }
 
 __global__ void __launch_bounds__(EW_THREADS)
-k_fin_rotsum(DevTables T, const FinJob *jobs, const FinTerm *terms, const double *U, const double *delta,
-             const double *const *masks, double *const *out) {
+k_fin_rotsum(DevTables T, const FinJob *jobs, const FinTerm *terms, const double *E, const double *const *masks,
+             double *const *out) {
     const int N = 1 << T.logN;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = blockIdx.y;
@@ -303,7 +185,7 @@ k_fin_rotsum(DevTables T, const FinJob *jobs, const FinTerm *terms, const double
     if (p >= N) return;
     const double q = T.qt[i].x, qi = T.qt[i].y;
     double e0, e1;
-    finish_one(T, jobs[job], terms, U, delta, masks, i, p, q, qi, e0, e1);
+    finish_one(T, jobs[job], terms, E, masks, i, p, q, qi, e0, e1);
     double *o = out[job] + (size_t)i * N + p;
     o[0] = e0;
     o[(size_t)T.L * N] = e1;
@@ -505,64 +387,35 @@ bool g_cdt_uploaded[64] = {false};
 
 }  // namespace
 
-void kernels_init() {
-    const int lds = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_MODUP>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-}
-
-static int ntt_threads(int N) { return min(N / 8, NTT_THREADS_MAX) < 64 ? 64 : min(N / 8, NTT_THREADS_MAX); }
-
-void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) {
-    if (a.rows <= 0) return;
-    const int N = T.N;
-    const size_t lds = (size_t)N * sizeof(double);
-    dim3 grid(a.rows), block(ntt_threads(N));
-    switch (mode) {
-        case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd<LOAD_MODUP>, grid, block, lds, s, T, a); break;
-        case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd<LOAD_DELTA>, grid, block, lds, s, T, a); break;
-        default: hipLaunchKernelGGL(k_ntt_fwd<LOAD_PLAIN>, grid, block, lds, s, T, a); break;
-    }
-}
-
-void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s) {
-    if (a.rows <= 0) return;
-    const int N = T.N;
-    const size_t lds = (size_t)N * sizeof(double);
-    dim3 grid(a.rows), block(ntt_threads(N));
-    switch (mode) {
-        case STORE_MDR: hipLaunchKernelGGL(k_ntt_inv<STORE_MDR>, grid, block, lds, s, T, a); break;
-        case STORE_CANON: hipLaunchKernelGGL(k_ntt_inv<STORE_CANON>, grid, block, lds, s, T, a); break;
-        default: hipLaunchKernelGGL(k_ntt_inv<STORE_PLAIN>, grid, block, lds, s, T, a); break;
-    }
-}
-
 static dim3 ew_grid(int N, int y, int z = 1) { return dim3((N + EW_THREADS - 1) / EW_THREADS, y, z); }
 
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-               const double *const *masks, const int2 *jobs, const IpTerm *terms, int njobs, hipStream_t s) {
+               const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, hipStream_t s) {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_ip, ew_grid(T.N, T.nExt, njobs), dim3(EW_THREADS), 0, s, T, U, y, keys, masks, jobs, terms);
+    dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, njobs);
+    switch (T.beta) {
+#define HG_IP_CASE(B) \
+    case B: hipLaunchKernelGGL(k_ip<B>, grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms); break;
+        HG_IP_CASE(1) HG_IP_CASE(2) HG_IP_CASE(3) HG_IP_CASE(4) HG_IP_CASE(5) HG_IP_CASE(6)
+        HG_IP_CASE(7) HG_IP_CASE(8) HG_IP_CASE(9) HG_IP_CASE(10) HG_IP_CASE(11) HG_IP_CASE(12)
+#undef HG_IP_CASE
+        default: break;
+    }
 }
 
-void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *U,
-                       const double *delta, const double *const *masks, const int2 *req_pairs,
-                       double *const *acc, int nreq, hipStream_t s) {
-    if (nreq <= 0) return;
-    hipLaunchKernelGGL(k_fin_tensor, ew_grid(T.N, T.L, nreq), dim3(EW_THREADS), 0, s, T, jobs, terms, U, delta,
-                       masks, req_pairs, acc);
-}
-
-void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *U,
-                       const double *delta, const double *const *masks, double *const *out, int njobs,
+void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,
+                       const double *const *masks, const int2 *req_pairs, double *const *acc, int nreq,
                        hipStream_t s) {
+    if (nreq <= 0) return;
+    dim3 grid((T.N + FT_P - 1) / FT_P, T.L, nreq);
+    hipLaunchKernelGGL(k_fin_tensor, grid, dim3(FT_P, FT_C), 0, s, T, jobs, terms, E, masks, req_pairs, acc);
+}
+
+void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,
+                       const double *const *masks, double *const *out, int njobs, hipStream_t s) {
     if (njobs <= 0) return;
-    hipLaunchKernelGGL(k_fin_rotsum, ew_grid(T.N, T.L, njobs), dim3(EW_THREADS), 0, s, T, jobs, terms, U, delta,
-                       masks, out);
+    hipLaunchKernelGGL(k_fin_rotsum, ew_grid(T.N, T.L, njobs), dim3(EW_THREADS), 0, s, T, jobs, terms, E, masks,
+                       out);
 }
 
 void u64_to_dbl(const uint64_t *in, double *out, size_t n, hipStream_t s) {

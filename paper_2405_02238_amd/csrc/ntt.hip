@@ -1,0 +1,475 @@
+// Negacyclic number-theoretic transforms on gfx950.
+//
+// Forward: Cooley-Tukey with the 2N-th root psi merged into the twiddles
+// (Poeppelmann-Oder-Gueneysu 2015; Longa-Naehrig 2016), natural order in,
+// bit-reversed order out: position p holds a(psi^(2 brv(p) + 1)).
+// Inverse: Gentleman-Sande with psi^-1 twiddles, bit-reversed in, natural
+// out, scaled by N^-1.
+//
+// One workgroup owns one row (one prime of one polynomial); the row lives in
+// LDS, padded by one double every 16 so that the strided accesses of the late
+// rounds hit distinct banks.  Each round runs up to four radix-2 stages in
+// registers on groups of 16 elements (one group per thread), so an 8192-point
+// row takes four LDS round trips.  Reductions are lazy: a forward stage whose
+// outputs feed another multiplication keeps them unreduced (|x| < 2q), every
+// second stage reduces.
+//
+// The load and store steps fuse the neighbouring work of key switching:
+// LOAD_MODUP lifts one digit of a coefficient-form polynomial to the prime of
+// the row (ModUp), LOAD_DELTA forms the correction delta of the division by P
+// from the centered r_k rows, STORE_MDR turns an inverse-transformed special
+// prime row into the exact centered r_k.
+#include "arith.h"
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace hg {
+
+namespace {
+
+constexpr int NTT_THREADS_MAX = 512;
+constexpr int SPLIT_ELEMS = 1024;            // elements per workgroup in the split transform
+constexpr int SPLIT_THREADS = SPLIT_ELEMS / 16;
+
+__device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
+
+// K forward stages [s0, s0 + K) of nsub independent 2^ls-point transforms
+// stored one after another in LDS.  Sub-transform sb takes its stage-s
+// twiddles from tw[C * 2^s + local], C = cb + sb * cs (C = 1 for a whole row
+// or for the columns of a split row; 2^a + block for the blocks of a split
+// row).  Stage s is global stage sg0 + s; odd global stages, the last global
+// stage, and (force_last) the last local stage reduce their outputs.
+template <int K>
+__device__ __forceinline__ void fwd_round(double *sh, const double *__restrict__ tw, int ls, int nsub, int s0,
+                                          int cb, int cs, int sg0, int logN, bool force_last, double q, double qi) {
+    const int lts = ls - s0 - K;
+    const int ts = 1 << lts;
+    const int lgps = ls - K;  // log2 groups per sub-transform
+    const int ngroups = nsub << lgps;
+    for (int grp = threadIdx.x; grp < ngroups; grp += blockDim.x) {
+        const int sb = grp >> lgps;
+        const int lg = grp & ((1 << lgps) - 1);
+        const int low = lg & (ts - 1);
+        const int blk = lg >> lts;
+        const int base = (sb << ls) + (blk << (lts + K)) + low;
+        const int C = cb + sb * cs;
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * ts)];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int s = s0 + u;
+            const int sg = sg0 + s;
+            const bool red = (sg & 1) || (sg == logN - 1) || (force_last && s == ls - 1);
+            const int half = 1 << (K - 1 - u);
+            const double *twu = tw + (C << s) + (blk << u);
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & half) continue;
+                const double w = twu[b >> (K - u)];
+                const double t = mulm(x[b + half], w, q, qi);
+                const double X = x[b];
+                if (red) {
+                    x[b] = redm(X + t, q, qi);
+                    x[b + half] = redm(X - t, q, qi);
+                } else {
+                    x[b] = X + t;
+                    x[b + half] = X - t;
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * ts)] = x[b];
+    }
+}
+
+// K inverse stages of nsub independent 2^ls-point transforms; the first
+// stage has half-size 2^lts.  Twiddles tw[C * (2^ls >> (lt + 1)) + local].
+template <int K>
+__device__ __forceinline__ void inv_round(double *sh, const double *__restrict__ tw, int ls, int nsub, int lts,
+                                          int cb, int cs, double q, double qi) {
+    const int n = 1 << ls;
+    const int ts = 1 << lts;
+    const int lgps = ls - K;
+    const int ngroups = nsub << lgps;
+    for (int grp = threadIdx.x; grp < ngroups; grp += blockDim.x) {
+        const int sb = grp >> lgps;
+        const int lg = grp & ((1 << lgps) - 1);
+        const int low = lg & (ts - 1);
+        const int blk = lg >> lts;
+        const int base = (sb << ls) + (blk << (lts + K)) + low;
+        const int C = cb + sb * cs;
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * ts)];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int d = 1 << u;
+            const double *twu = tw + (n >> (lts + u + 1)) * C + (blk << (K - u - 1));
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & d) continue;
+                const double w = twu[b >> (u + 1)];
+                const double X = x[b], Y = x[b + d];
+                x[b] = redm(X + Y, q, qi);
+                x[b + d] = mulm(X - Y, w, q, qi);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * ts)] = x[b];
+    }
+}
+
+// All forward stages [s0, ls) of the sub-transforms, in rounds of four.
+__device__ __forceinline__ void fwd_stages(double *sh, const double *tw, int ls, int nsub, int s0, int cb, int cs,
+                                           int sg0, int logN, bool force_last, double q, double qi) {
+    for (; s0 + 4 <= ls; s0 += 4) {
+        fwd_round<4>(sh, tw, ls, nsub, s0, cb, cs, sg0, logN, force_last, q, qi);
+        __syncthreads();
+    }
+    switch (ls - s0) {
+        case 3: fwd_round<3>(sh, tw, ls, nsub, s0, cb, cs, sg0, logN, force_last, q, qi); __syncthreads(); break;
+        case 2: fwd_round<2>(sh, tw, ls, nsub, s0, cb, cs, sg0, logN, force_last, q, qi); __syncthreads(); break;
+        case 1: fwd_round<1>(sh, tw, ls, nsub, s0, cb, cs, sg0, logN, force_last, q, qi); __syncthreads(); break;
+        default: break;
+    }
+}
+
+__device__ __forceinline__ void inv_stages(double *sh, const double *tw, int ls, int nsub, int cb, int cs, double q,
+                                           double qi) {
+    int lts = 0;
+    for (; lts + 4 <= ls; lts += 4) {
+        inv_round<4>(sh, tw, ls, nsub, lts, cb, cs, q, qi);
+        __syncthreads();
+    }
+    switch (ls - lts) {
+        case 3: inv_round<3>(sh, tw, ls, nsub, lts, cb, cs, q, qi); __syncthreads(); break;
+        case 2: inv_round<2>(sh, tw, ls, nsub, lts, cb, cs, q, qi); __syncthreads(); break;
+        case 1: inv_round<1>(sh, tw, ls, nsub, lts, cb, cs, q, qi); __syncthreads(); break;
+        default: break;
+    }
+}
+
+// ---- per-row addressing and the fused load / store steps ----
+
+struct FwdRow {
+    int prime;
+    double *out;
+    const double *in;    // PLAIN: the row; MODUP: the source's L coefficient rows; DELTA: r_k rows
+    const double *aux;   // DELTA: the U row
+    int d0, d1;          // MODUP: digit primes
+};
+
+template <int LOAD>
+__device__ __forceinline__ FwdRow fwd_row(const DevTables &T, const NttArgs &a, int row) {
+    const int N = 1 << T.logN;
+    FwdRow R;
+    R.aux = nullptr;
+    R.d0 = R.d1 = 0;
+    if (LOAD == LOAD_MODUP) {
+        const int r = row % T.nExt;
+        const int j = (row / T.nExt) % T.beta;
+        const int src = row / (T.nExt * T.beta);
+        R.prime = r;
+        R.out = a.out + (size_t)row * N;
+        R.in = a.in + (size_t)src * a.in_stride;
+        R.d0 = j * T.alpha;
+        R.d1 = min(R.d0 + T.alpha, T.L);
+    } else if (LOAD == LOAD_DELTA) {
+        const int i_q = row % T.L;
+        const int slot = row / T.L;
+        R.prime = i_q;
+        R.out = a.out + (size_t)row * N;
+        R.aux = a.aux + (size_t)slot * T.nExt * N + (size_t)i_q * N;
+        R.in = a.in + (size_t)slot * a.in_stride;
+    } else {
+        const int g = row / a.per, rr = row % a.per;
+        R.prime = a.prime_base + rr;
+        R.out = a.out + (size_t)g * a.out_stride + (size_t)rr * N;
+        R.in = (a.in_tab ? a.in_tab[g] : a.in + (size_t)g * a.in_stride) + a.in_offset + (size_t)rr * N;
+    }
+    return R;
+}
+
+// Input value at position i of the row (before any stage).
+template <int LOAD>
+__device__ __forceinline__ double fwd_load(const DevTables &T, const FwdRow &R, int i) {
+    const int N = 1 << T.logN;
+    if (LOAD == LOAD_MODUP) {
+        const int r = R.prime;
+        if (r >= R.d0 && r < R.d1) return R.in[(size_t)r * N + i];
+        if (R.d1 - R.d0 == 1) {
+            // one-prime digit: the centered residue itself is the lift
+            return centerm(R.in[(size_t)R.d0 * N + i], T.qt[R.d0].x, T.qt[R.d0].y);
+        }
+        const double qr = T.qt[r].x, qir = T.qt[r].y;
+        double acc = 0.0;
+        for (int s = R.d0; s < R.d1; ++s) {
+            const double qs = T.qt[s].x, qis = T.qt[s].y;
+            const double ct = centerm(mulm(R.in[(size_t)s * N + i], T.mu_invhat[s], qs, qis), qs, qis);
+            acc += mulm(ct, T.mu_hat[s * T.nExt + r], qr, qir);
+        }
+        return redm(acc, qr, qir);
+    } else if (LOAD == LOAD_DELTA) {
+        const int iq = R.prime;
+        const double qr = T.qt[iq].x, qir = T.qt[iq].y;
+        if (T.alpha == 1) return mulm(R.in[i], T.md_hat[iq], qr, qir);
+        double acc = 0.0;
+        for (int k = 0; k < T.alpha; ++k) acc += mulm(R.in[(size_t)k * N + i], T.md_hat[k * T.L + iq], qr, qir);
+        return redm(acc, qr, qir);
+    } else {
+        return R.in[i];
+    }
+}
+
+// Final store of position i (after the last stage).
+template <int LOAD>
+__device__ __forceinline__ void fwd_store(const DevTables &T, const FwdRow &R, int i, double v, double q, double qi) {
+    if (LOAD == LOAD_DELTA) {
+        // E = (U - delta) * P^-1: the finished, divided output of the job
+        R.out[i] = mulm(R.aux[i] - v, T.pinv[R.prime], q, qi);
+    } else {
+        R.out[i] = v;
+    }
+}
+
+struct InvRow {
+    int prime, rr;
+    double *out;
+    const double *in;
+};
+
+__device__ __forceinline__ InvRow inv_row(const DevTables &T, const NttArgs &a, int row) {
+    const int N = 1 << T.logN;
+    InvRow R;
+    const int g = row / a.per;
+    R.rr = row % a.per;
+    R.prime = a.prime_base + R.rr;
+    R.out = a.out + (size_t)g * a.out_stride + (size_t)R.rr * N;
+    R.in = (a.in_tab ? a.in_tab[g] : a.in + (size_t)g * a.in_stride) + a.in_offset + (size_t)R.rr * N;
+    return R;
+}
+
+template <int STORE>
+__device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, int i, double v, double q, double qi) {
+    if (STORE == STORE_MDR) {
+        R.out[i] = centerm(mulm(v, T.md_coef[R.rr], q, qi), q, qi);
+    } else {
+        double x = mulm(v, T.ninv[R.prime], q, qi);
+        if (STORE == STORE_CANON) x = canonm(centerm(x, q, qi), q);
+        R.out[i] = x;
+    }
+}
+
+// ---- one workgroup per row ----
+
+template <int LOAD>
+__global__ void __launch_bounds__(NTT_THREADS_MAX)
+k_ntt_fwd(DevTables T, NttArgs a) {
+    extern __shared__ double sh[];
+    const int logN = T.logN;
+    const int N = 1 << logN;
+    const FwdRow R = fwd_row<LOAD>(T, a, blockIdx.x);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
+    __syncthreads();
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    fwd_stages(sh, T.twf + (size_t)R.prime * N, logN, 1, 0, 1, 0, 0, logN, false, q, qi);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) fwd_store<LOAD>(T, R, i, sh[lds_ix(i)], q, qi);
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(NTT_THREADS_MAX)
+k_ntt_inv(DevTables T, NttArgs a) {
+    extern __shared__ double sh[];
+    const int logN = T.logN;
+    const int N = 1 << logN;
+    const InvRow R = inv_row(T, a, blockIdx.x);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = R.in[i];
+    __syncthreads();
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    inv_stages(sh, T.twi + (size_t)R.prime * N, logN, 1, 1, 0, q, qi);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) inv_store<STORE>(T, R, i, sh[lds_ix(i)], q, qi);
+}
+
+// ---- split rows: N = N1 x N2, N1 = 2^a (column length), N2 = 2^b ----
+// Forward stages 0..a-1 pair elements of the same column {c + N2 j}; stages
+// a..logN-1 pair elements of the same contiguous block of N2.  Each pass is
+// one launch of SPLIT_ELEMS-element workgroups; the row goes through L2/HBM
+// between them.  Used when few rows would leave most CUs idle, and for rows
+// too long for one workgroup's LDS.
+
+__device__ __forceinline__ void split_dims(int logN, int &a, int &b) {
+    a = (logN + 1) >> 1;
+    b = logN - a;
+}
+
+template <int LOAD>
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_ntt_fwd_cols(DevTables T, NttArgs a) {
+    __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
+    const int logN = T.logN;
+    int la, lb;
+    split_dims(logN, la, lb);
+    const int N2 = 1 << lb;
+    const int cw = SPLIT_ELEMS >> la;                // columns per workgroup
+    const int wpr = N2 / cw;                         // workgroups per row
+    const int row = blockIdx.x / wpr;
+    const int c0 = (blockIdx.x % wpr) * cw;
+    const FwdRow R = fwd_row<LOAD>(T, a, row);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
+        const int cc = e % cw, j = e / cw;
+        sh[lds_ix((cc << la) + j)] = fwd_load<LOAD>(T, R, c0 + cc + (j << lb));
+    }
+    __syncthreads();
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    fwd_stages(sh, T.twf + (size_t)R.prime * (1 << logN), la, cw, 0, 1, 0, 0, logN, true, q, qi);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
+        const int cc = e % cw, j = e / cw;
+        R.out[c0 + cc + (j << lb)] = sh[lds_ix((cc << la) + j)];
+    }
+}
+
+template <int LOAD>
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_ntt_fwd_blocks(DevTables T, NttArgs a) {
+    __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
+    const int logN = T.logN;
+    int la, lb;
+    split_dims(logN, la, lb);
+    const int N = 1 << logN;
+    const int bw = SPLIT_ELEMS >> lb;                // blocks per workgroup
+    const int wpr = N / SPLIT_ELEMS;
+    const int row = blockIdx.x / wpr;
+    const int off = (blockIdx.x % wpr) * SPLIT_ELEMS;
+    const FwdRow R = fwd_row<LOAD>(T, a, row);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = R.out[off + e];
+    __syncthreads();
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    const int B0 = off >> lb;
+    fwd_stages(sh, T.twf + (size_t)R.prime * N, lb, bw, 0, (1 << la) + B0, 1, la, logN, false, q, qi);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) fwd_store<LOAD>(T, R, off + e, sh[lds_ix(e)], q, qi);
+}
+
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_ntt_inv_blocks(DevTables T, NttArgs a) {
+    __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
+    const int logN = T.logN;
+    int la, lb;
+    split_dims(logN, la, lb);
+    const int N = 1 << logN;
+    const int bw = SPLIT_ELEMS >> lb;
+    const int wpr = N / SPLIT_ELEMS;
+    const int row = blockIdx.x / wpr;
+    const int off = (blockIdx.x % wpr) * SPLIT_ELEMS;
+    const InvRow R = inv_row(T, a, row);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = R.in[off + e];
+    __syncthreads();
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    const int B0 = off >> lb;
+    inv_stages(sh, T.twi + (size_t)R.prime * N, lb, bw, (1 << la) + B0, 1, q, qi);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) R.out[off + e] = sh[lds_ix(e)];
+}
+
+template <int STORE>
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_ntt_inv_cols(DevTables T, NttArgs a) {
+    __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
+    const int logN = T.logN;
+    int la, lb;
+    split_dims(logN, la, lb);
+    const int N2 = 1 << lb;
+    const int cw = SPLIT_ELEMS >> la;
+    const int wpr = N2 / cw;
+    const int row = blockIdx.x / wpr;
+    const int c0 = (blockIdx.x % wpr) * cw;
+    const InvRow R = inv_row(T, a, row);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
+        const int cc = e % cw, j = e / cw;
+        sh[lds_ix((cc << la) + j)] = R.out[c0 + cc + (j << lb)];
+    }
+    __syncthreads();
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    inv_stages(sh, T.twi + (size_t)R.prime * (1 << logN), la, cw, 1, 0, q, qi);
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
+        const int cc = e % cw, j = e / cw;
+        inv_store<STORE>(T, R, c0 + cc + (j << lb), sh[lds_ix((cc << la) + j)], q, qi);
+    }
+}
+
+int ntt_threads(int N) {
+    int t = N / 16;
+    if (t < 64) t = 64;
+    if (t > NTT_THREADS_MAX) t = NTT_THREADS_MAX;
+    return t;
+}
+
+size_t ntt_lds_bytes(int N) { return (size_t)(N + N / 16) * sizeof(double); }
+
+int g_split_rows = 0;     // row counts below this use the split transform (N >= 2048); 0: only N > 16384
+
+bool use_split(const DevTables &T, int rows) {
+    if (T.N > 16384) return true;
+    return T.N >= 2 * SPLIT_ELEMS && rows < g_split_rows;
+}
+
+}  // namespace
+
+void kernels_init() {
+    const int lds = 160 * 1024;
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_MODUP>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+void ntt_set_split_rows(int rows) { g_split_rows = rows; }
+
+void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) {
+    if (a.rows <= 0) return;
+    if (use_split(T, a.rows)) {
+        dim3 grid((unsigned)(a.rows * (T.N / SPLIT_ELEMS))), block(SPLIT_THREADS);
+        switch (mode) {
+            case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd_cols<LOAD_MODUP>, grid, block, 0, s, T, a); break;
+            case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd_cols<LOAD_DELTA>, grid, block, 0, s, T, a); break;
+            default: hipLaunchKernelGGL(k_ntt_fwd_cols<LOAD_PLAIN>, grid, block, 0, s, T, a); break;
+        }
+        switch (mode) {
+            case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd_blocks<LOAD_MODUP>, grid, block, 0, s, T, a); break;
+            case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd_blocks<LOAD_DELTA>, grid, block, 0, s, T, a); break;
+            default: hipLaunchKernelGGL(k_ntt_fwd_blocks<LOAD_PLAIN>, grid, block, 0, s, T, a); break;
+        }
+        return;
+    }
+    const size_t lds = ntt_lds_bytes(T.N);
+    dim3 grid(a.rows), block(ntt_threads(T.N));
+    switch (mode) {
+        case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd<LOAD_MODUP>, grid, block, lds, s, T, a); break;
+        case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd<LOAD_DELTA>, grid, block, lds, s, T, a); break;
+        default: hipLaunchKernelGGL(k_ntt_fwd<LOAD_PLAIN>, grid, block, lds, s, T, a); break;
+    }
+}
+
+void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s) {
+    if (a.rows <= 0) return;
+    if (use_split(T, a.rows)) {
+        dim3 grid((unsigned)(a.rows * (T.N / SPLIT_ELEMS))), block(SPLIT_THREADS);
+        hipLaunchKernelGGL(k_ntt_inv_blocks, grid, block, 0, s, T, a);
+        switch (mode) {
+            case STORE_MDR: hipLaunchKernelGGL(k_ntt_inv_cols<STORE_MDR>, grid, block, 0, s, T, a); break;
+            case STORE_CANON: hipLaunchKernelGGL(k_ntt_inv_cols<STORE_CANON>, grid, block, 0, s, T, a); break;
+            default: hipLaunchKernelGGL(k_ntt_inv_cols<STORE_PLAIN>, grid, block, 0, s, T, a); break;
+        }
+        return;
+    }
+    const size_t lds = ntt_lds_bytes(T.N);
+    dim3 grid(a.rows), block(ntt_threads(T.N));
+    switch (mode) {
+        case STORE_MDR: hipLaunchKernelGGL(k_ntt_inv<STORE_MDR>, grid, block, lds, s, T, a); break;
+        case STORE_CANON: hipLaunchKernelGGL(k_ntt_inv<STORE_CANON>, grid, block, lds, s, T, a); break;
+        default: hipLaunchKernelGGL(k_ntt_inv<STORE_PLAIN>, grid, block, lds, s, T, a); break;
+    }
+}
+
+}  // namespace hg
