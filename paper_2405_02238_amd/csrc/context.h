@@ -82,6 +82,7 @@ struct Ctx {
 
     std::map<hipStream_t, Arena> arenas;
     Timing timing;
+    int fuse_rows = 64;   // passes with at most this many rows per chain use the fused kernels
 
     Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device);
     ~Ctx();

@@ -229,7 +229,15 @@ struct Exec {
 
     // Phases 1-3 of a staged pass: hoist, inner products, division by P.
     void launch(const Dev &dv, hipEvent_t *tev = nullptr) {
+        // few rows: one fused launch per chain (latency bound); many rows:
+        // separate launches (throughput bound)
+        const bool fuse_hoist = fused_ok(T) && dv.nsrc * beta * nExt <= C.fuse_rows;
+        const bool fuse_md = fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows;
+        if (dv.nks > 0 && fuse_hoist) {
+            hoist_fused(T, dv.y, (const double *const *)(dv.tab + dv.t_srcs), dv.nsrc, st);
+        }
         if (dv.nks > 0) {
+            if (!fuse_hoist) {
             // 1. hoist every source once: c1 -> coefficient form -> lifted digits
             NttArgs a;
             a.out = dv.coef;
@@ -244,12 +252,18 @@ struct Exec {
             mu.rows = dv.nsrc * beta * nExt;
             mu.in_stride = (long long)L * N;
             ntt_fwd(T, LOAD_MODUP, mu, st);
+            }
             if (tev) HGCHK(hipEventRecord(tev[0], st));
             // 2. inner products
             ip_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
                       (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks, st);
             if (tev) HGCHK(hipEventRecord(tev[1], st));
             // 3. division by P
+            if (fuse_md) {
+                moddown_fused(T, dv.E, dv.U, dv.nks * 2, st);
+                if (tev) HGCHK(hipEventRecord(tev[2], st));
+                return;
+            }
             NttArgs md;
             md.out = dv.rk;
             md.in = dv.U;

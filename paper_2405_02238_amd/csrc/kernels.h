@@ -101,6 +101,14 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s);
 //  STORE_CANON: times N^-1, canonical residue in [0, q).
 void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s);
 
+// Fused chains for one-prime digits (alpha = 1, N <= 16384), one workgroup
+// per output row, for passes with few rows:
+//  hoist_fused:   y[src][j][r] = NTT_r(center(INTT_j(c1[src] row j)))
+//  moddown_fused: E[slot][i] = (U_i - NTT_i(t (P/p) center(INTT_p(U_p) ...))) P^-1
+bool fused_ok(const DevTables &T);
+void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s);
+void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s);
+
 // Row count below which a transform is split into a column pass and a block
 // pass of 1024-element workgroups (spreading each row over N/1024 CUs);
 // rows longer than 16384 always use the split form.

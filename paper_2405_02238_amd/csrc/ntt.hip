@@ -27,11 +27,253 @@ namespace hg {
 
 namespace {
 
-constexpr int NTT_THREADS_MAX = 512;
+constexpr int NTT_THREADS_MAX = 1024;
 constexpr int SPLIT_ELEMS = 1024;            // elements per workgroup in the split transform
 constexpr int SPLIT_THREADS = SPLIT_ELEMS / 16;
 
 __device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
+
+// ---- whole rows with the size known at compile time ----
+// Round R of a 2^LOGN-point forward transform covers stages [S0, S0 + K).
+// Each thread owns a group of 2^K elements; all twiddles of the round are
+// loaded into registers before the butterflies, so one memory latency is paid
+// per round, and whether a stage reduces is decided at compile time.
+template <int LOGN, int S0, int K>
+__device__ __forceinline__ void fwd_round_c(double *sh, const double *__restrict__ tw, double q, double qi) {
+    constexpr int N = 1 << LOGN;
+    constexpr int LTS = LOGN - S0 - K;
+    constexpr int TS = 1 << LTS;
+    constexpr int NG = N >> K;
+    for (int grp = threadIdx.x; grp < NG; grp += blockDim.x) {
+        const int low = grp & (TS - 1);
+        const int blk = grp >> LTS;
+        const int base = (blk << (LTS + K)) + low;
+        double w[(1 << K) - 1];
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+            for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (S0 + u)) + (blk << u) + c];
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            constexpr int dummy = 0;
+            (void)dummy;
+            const bool red = ((S0 + u) & 1) || (S0 + u == LOGN - 1);
+            const int half = 1 << (K - 1 - u);
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & half) continue;
+                const double t = mulm(x[b + half], w[(1 << u) - 1 + (b >> (K - u))], q, qi);
+                const double X = x[b];
+                if (red) {
+                    x[b] = redm(X + t, q, qi);
+                    x[b + half] = redm(X - t, q, qi);
+                } else {
+                    x[b] = X + t;
+                    x[b + half] = X - t;
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+    }
+}
+
+template <int LOGN, int S0>
+__device__ __forceinline__ void fwd_rows_c(double *sh, const double *tw, double q, double qi) {
+    if constexpr (S0 < LOGN) {
+        constexpr int K = (LOGN - S0) < 4 ? (LOGN - S0) : 4;
+        fwd_round_c<LOGN, S0, K>(sh, tw, q, qi);
+        __syncthreads();
+        fwd_rows_c<LOGN, S0 + K>(sh, tw, q, qi);
+    }
+}
+
+template <int LOGN, int LTS, int K>
+__device__ __forceinline__ void inv_round_c(double *sh, const double *__restrict__ tw, double q, double qi) {
+    constexpr int N = 1 << LOGN;
+    constexpr int TS = 1 << LTS;
+    constexpr int NG = N >> K;
+    for (int grp = threadIdx.x; grp < NG; grp += blockDim.x) {
+        const int low = grp & (TS - 1);
+        const int blk = grp >> LTS;
+        const int base = (blk << (LTS + K)) + low;
+        // stage u needs 2^(K-u-1) twiddles; offsets within w: 0, 2^(K-1), ...
+        double w[(1 << K) - 1];
+        int wo = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+#pragma unroll
+            for (int c = 0; c < (1 << (K - u - 1)); ++c)
+                w[wo + c] = tw[(N >> (LTS + u + 1)) + (blk << (K - u - 1)) + c];
+            wo += 1 << (K - u - 1);
+        }
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        wo = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int d = 1 << u;
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & d) continue;
+                const double X = x[b], Y = x[b + d];
+                x[b] = redm(X + Y, q, qi);
+                x[b + d] = mulm(X - Y, w[wo + (b >> (u + 1))], q, qi);
+            }
+            wo += 1 << (K - u - 1);
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+    }
+}
+
+template <int LOGN, int LTS>
+__device__ __forceinline__ void inv_rows_c(double *sh, const double *tw, double q, double qi) {
+    if constexpr (LTS < LOGN) {
+        constexpr int K = (LOGN - LTS) < 4 ? (LOGN - LTS) : 4;
+        inv_round_c<LOGN, LTS, K>(sh, tw, q, qi);
+        __syncthreads();
+        inv_rows_c<LOGN, LTS + K>(sh, tw, q, qi);
+    }
+}
+
+// Prefetching variant for one group per thread (blockDim = N / 16): the
+// twiddles of round R+1 are loaded while round R computes.
+template <int LOGN, int S0>
+struct FwdRound {
+    static constexpr int K = (LOGN - S0) < 4 ? (LOGN - S0) : 4;
+    static constexpr int LTS = LOGN - S0 - K;
+    static constexpr int NW = (1 << K) - 1;
+    __device__ static __forceinline__ void load_tw(double *w, const double *__restrict__ tw, int grp) {
+        const int blk = grp >> LTS;
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+            for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (S0 + u)) + (blk << u) + c];
+    }
+};
+
+template <int LOGN, int S0>
+__device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict__ tw, double q, double qi, int grp,
+                                            const double *wcur) {
+    if constexpr (S0 < LOGN && FwdRound<LOGN, S0>::K < 4) {
+        // a short tail round has more groups than threads: plain loop
+        fwd_round_c<LOGN, S0, FwdRound<LOGN, S0>::K>(sh, tw, q, qi);
+        __syncthreads();
+    } else if constexpr (S0 < LOGN) {
+        using RD = FwdRound<LOGN, S0>;
+        constexpr int K = RD::K, LTS = RD::LTS, TS = 1 << LTS;
+        const int low = grp & (TS - 1);
+        const int blk = grp >> LTS;
+        const int base = (blk << (LTS + K)) + low;
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        constexpr int S1 = S0 + K;
+        constexpr bool PF = S1 < LOGN && FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::K == 4;
+        constexpr int NWN = PF ? FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::NW : 1;
+        double wnext[NWN];
+        if constexpr (PF) FwdRound<LOGN, S1>::load_tw(wnext, tw, grp);
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const bool red = ((S0 + u) & 1) || (S0 + u == LOGN - 1);
+            const int half = 1 << (K - 1 - u);
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & half) continue;
+                const double t = mulm(x[b + half], wcur[(1 << u) - 1 + (b >> (K - u))], q, qi);
+                const double X = x[b];
+                if (red) {
+                    x[b] = redm(X + t, q, qi);
+                    x[b + half] = redm(X - t, q, qi);
+                } else {
+                    x[b] = X + t;
+                    x[b + half] = X - t;
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        __syncthreads();
+        if constexpr (S1 < LOGN) fwd_rows_pf<LOGN, S1>(sh, tw, q, qi, grp, wnext);
+    }
+}
+
+template <int LOGN, int LTS0>
+struct InvRound {
+    static constexpr int K = (LOGN - LTS0) < 4 ? (LOGN - LTS0) : 4;
+    static constexpr int NW = (1 << K) - 1;
+    __device__ static __forceinline__ void load_tw(double *w, const double *__restrict__ tw, int grp) {
+        constexpr int N = 1 << LOGN;
+        const int blk = grp >> LTS0;
+        int wo = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+#pragma unroll
+            for (int c = 0; c < (1 << (K - u - 1)); ++c) w[wo + c] = tw[(N >> (LTS0 + u + 1)) + (blk << (K - u - 1)) + c];
+            wo += 1 << (K - u - 1);
+        }
+    }
+};
+
+template <int LOGN, int LTS0>
+__device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict__ tw, double q, double qi, int grp,
+                                            const double *wcur) {
+    if constexpr (LTS0 < LOGN && InvRound<LOGN, LTS0>::K < 4) {
+        inv_round_c<LOGN, LTS0, InvRound<LOGN, LTS0>::K>(sh, tw, q, qi);
+        __syncthreads();
+    } else if constexpr (LTS0 < LOGN) {
+        using RD = InvRound<LOGN, LTS0>;
+        constexpr int K = RD::K, TS = 1 << LTS0;
+        const int low = grp & (TS - 1);
+        const int blk = grp >> LTS0;
+        const int base = (blk << (LTS0 + K)) + low;
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        constexpr int L1 = LTS0 + K;
+        constexpr bool PF = L1 < LOGN && InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::K == 4;
+        constexpr int NWN = PF ? InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::NW : 1;
+        double wnext[NWN];
+        if constexpr (PF) InvRound<LOGN, L1>::load_tw(wnext, tw, grp);
+        int wo = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int d = 1 << u;
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & d) continue;
+                const double X = x[b], Y = x[b + d];
+                x[b] = redm(X + Y, q, qi);
+                x[b + d] = mulm(X - Y, wcur[wo + (b >> (u + 1))], q, qi);
+            }
+            wo += 1 << (K - u - 1);
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        __syncthreads();
+        if constexpr (L1 < LOGN) inv_rows_pf<LOGN, L1>(sh, tw, q, qi, grp, wnext);
+    }
+}
+
+// Whole-row stages with twiddle prefetch when every thread owns exactly one
+// group; the first round's twiddles are loaded before the caller's row load
+// completes (w0 filled by the caller).
+template <int LOGN>
+__device__ __forceinline__ void fwd_row_stages(double *sh, const double *tw, double q, double qi, const double *w0) {
+    if (blockDim.x == (1 << LOGN) / 16) fwd_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
+    else fwd_rows_c<LOGN, 0>(sh, tw, q, qi);
+}
+
+template <int LOGN>
+__device__ __forceinline__ void inv_row_stages(double *sh, const double *tw, double q, double qi, const double *w0) {
+    if (blockDim.x == (1 << LOGN) / 16) inv_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
+    else inv_rows_c<LOGN, 0>(sh, tw, q, qi);
+}
 
 // K forward stages [s0, s0 + K) of nsub independent 2^ls-point transforms
 // stored one after another in LDS.  Sub-transform sb takes its stage-s
@@ -263,31 +505,35 @@ __device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, i
 
 // ---- one workgroup per row ----
 
-template <int LOAD>
+template <int LOAD, int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS_MAX)
 k_ntt_fwd(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
-    const int logN = T.logN;
-    const int N = 1 << logN;
+    constexpr int N = 1 << LOGN;
     const FwdRow R = fwd_row<LOAD>(T, a, blockIdx.x);
+    const double *tw = T.twf + (size_t)R.prime * N;
+    double w0[FwdRound<LOGN, 0>::NW];
+    if (blockDim.x == N / 16 && FwdRound<LOGN, 0>::K == 4) FwdRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    fwd_stages(sh, T.twf + (size_t)R.prime * N, logN, 1, 0, 1, 0, 0, logN, false, q, qi);
+    fwd_row_stages<LOGN>(sh, tw, q, qi, w0);
     for (int i = threadIdx.x; i < N; i += blockDim.x) fwd_store<LOAD>(T, R, i, sh[lds_ix(i)], q, qi);
 }
 
-template <int STORE>
+template <int STORE, int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS_MAX)
 k_ntt_inv(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
-    const int logN = T.logN;
-    const int N = 1 << logN;
+    constexpr int N = 1 << LOGN;
     const InvRow R = inv_row(T, a, blockIdx.x);
+    const double *tw = T.twi + (size_t)R.prime * N;
+    double w0[InvRound<LOGN, 0>::NW];
+    if (blockDim.x == N / 16 && InvRound<LOGN, 0>::K == 4) InvRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = R.in[i];
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    inv_stages(sh, T.twi + (size_t)R.prime * N, logN, 1, 1, 0, q, qi);
+    inv_row_stages<LOGN>(sh, tw, q, qi, w0);
     for (int i = threadIdx.x; i < N; i += blockDim.x) inv_store<STORE>(T, R, i, sh[lds_ix(i)], q, qi);
 }
 
@@ -396,6 +642,86 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
     }
 }
 
+// ---- fused chains for passes with few rows (single-prime digits) ----
+
+// Hoisting, one workgroup per lifted row (src, digit j, prime r): the
+// evaluation-form row j of the source's c1 is inverse-transformed, centered
+// (the digit lift of a one-prime digit) and forward-transformed under prime
+// r, all in LDS.  Row r = j is the source row itself.
+template <int LOGN>
+__global__ void __launch_bounds__(NTT_THREADS_MAX)
+k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
+    extern __shared__ double sh[];
+    constexpr int N = 1 << LOGN;
+    const int row = blockIdx.x;
+    const int r = row % T.nExt;
+    const int j = (row / T.nExt) % T.beta;
+    const int src = row / (T.nExt * T.beta);
+    const double *c = srcs[src] + (size_t)j * N;
+    double *out = y + (size_t)row * N;
+    if (r == j) {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = c[i];
+        return;
+    }
+    const double *twj = T.twi + (size_t)j * N;
+    double wi[InvRound<LOGN, 0>::NW];
+    if (blockDim.x == N / 16 && InvRound<LOGN, 0>::K == 4) InvRound<LOGN, 0>::load_tw(wi, twj, threadIdx.x);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = c[i];
+    __syncthreads();
+    const double qj = T.qt[j].x, qij = T.qt[j].y;
+    inv_row_stages<LOGN>(sh, twj, qj, qij, wi);
+    const double *twr = T.twf + (size_t)r * N;
+    double wf[FwdRound<LOGN, 0>::NW];
+    if (blockDim.x == N / 16 && FwdRound<LOGN, 0>::K == 4) FwdRound<LOGN, 0>::load_tw(wf, twr, threadIdx.x);
+    const double nj = T.ninv[j];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int x = lds_ix(i);
+        sh[x] = centerm(mulm(sh[x], nj, qj, qij), qj, qij);
+    }
+    __syncthreads();
+    const double q = T.qt[r].x, qi = T.qt[r].y;
+    fwd_row_stages<LOGN>(sh, twr, q, qi, wf);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = sh[lds_ix(i)];
+}
+
+// Division by P for one special prime, one workgroup per output row
+// (slot, i): inverse transform of U's special row, exact centered r,
+// delta_i = t (P/p) r mod q_i, forward transform, E_i = (U_i - delta_i) P^-1.
+template <int LOGN>
+__global__ void __launch_bounds__(NTT_THREADS_MAX)
+k_moddown_fused(DevTables T, double *E, const double *U) {
+    extern __shared__ double sh[];
+    constexpr int N = 1 << LOGN;
+    const int row = blockIdx.x;
+    const int iq = row % T.L;
+    const int slot = row / T.L;
+    const double *u = U + (size_t)slot * T.nExt * N;
+    const int pk = T.L;   // the special prime's index
+    const double *twp = T.twi + (size_t)pk * N;
+    double wi[InvRound<LOGN, 0>::NW];
+    if (blockDim.x == N / 16 && InvRound<LOGN, 0>::K == 4) InvRound<LOGN, 0>::load_tw(wi, twp, threadIdx.x);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
+    __syncthreads();
+    const double qp = T.qt[pk].x, qip = T.qt[pk].y;
+    inv_row_stages<LOGN>(sh, twp, qp, qip, wi);
+    const double *twq = T.twf + (size_t)iq * N;
+    double wf[FwdRound<LOGN, 0>::NW];
+    if (blockDim.x == N / 16 && FwdRound<LOGN, 0>::K == 4) FwdRound<LOGN, 0>::load_tw(wf, twq, threadIdx.x);
+    const double q = T.qt[iq].x, qi = T.qt[iq].y;
+    const double cf = T.md_coef[0], h = T.md_hat[iq];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int x = lds_ix(i);
+        const double rk = centerm(mulm(sh[x], cf, qp, qip), qp, qip);
+        sh[x] = mulm(rk, h, q, qi);
+    }
+    __syncthreads();
+    fwd_row_stages<LOGN>(sh, twq, q, qi, wf);
+    const double pinv = T.pinv[iq];
+    const double *ui = u + (size_t)iq * N;
+    double *out = E + (size_t)row * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = mulm(ui[i] - sh[lds_ix(i)], pinv, q, qi);
+}
+
 int ntt_threads(int N) {
     int t = N / 16;
     if (t < 64) t = 64;
@@ -412,16 +738,40 @@ bool use_split(const DevTables &T, int rows) {
     return T.N >= 2 * SPLIT_ELEMS && rows < g_split_rows;
 }
 
+// Dispatch on log2 N for the compile-time-size kernels.
+#define HG_LOGN_SWITCH(LN, CALL) \
+    switch (LN) {                 \
+        case 6: CALL(6); break;   \
+        case 7: CALL(7); break;   \
+        case 8: CALL(8); break;   \
+        case 9: CALL(9); break;   \
+        case 10: CALL(10); break; \
+        case 11: CALL(11); break; \
+        case 12: CALL(12); break; \
+        case 13: CALL(13); break; \
+        case 14: CALL(14); break; \
+        default: break;           \
+    }
+
+template <int LN>
+void set_lds_attrs() {
+    const int lds = 160 * 1024;
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_PLAIN, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_MODUP, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 }  // namespace
 
 void kernels_init() {
-    const int lds = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_MODUP>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+#define HG_INIT(LN) set_lds_attrs<LN>()
+    for (int ln = 6; ln <= 14; ++ln) HG_LOGN_SWITCH(ln, HG_INIT)
+#undef HG_INIT
 }
 
 void ntt_set_split_rows(int rows) { g_split_rows = rows; }
@@ -444,11 +794,14 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) 
     }
     const size_t lds = ntt_lds_bytes(T.N);
     dim3 grid(a.rows), block(ntt_threads(T.N));
-    switch (mode) {
-        case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd<LOAD_MODUP>, grid, block, lds, s, T, a); break;
-        case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd<LOAD_DELTA>, grid, block, lds, s, T, a); break;
-        default: hipLaunchKernelGGL(k_ntt_fwd<LOAD_PLAIN>, grid, block, lds, s, T, a); break;
+#define HG_FWD(LN)                                                                                        \
+    switch (mode) {                                                                                      \
+        case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd<LOAD_MODUP, LN>), grid, block, lds, s, T, a); break; \
+        case LOAD_DELTA: hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA, LN>), grid, block, lds, s, T, a); break; \
+        default: hipLaunchKernelGGL((k_ntt_fwd<LOAD_PLAIN, LN>), grid, block, lds, s, T, a); break;         \
     }
+    HG_LOGN_SWITCH(T.logN, HG_FWD)
+#undef HG_FWD
 }
 
 void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s) {
@@ -465,11 +818,32 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
     }
     const size_t lds = ntt_lds_bytes(T.N);
     dim3 grid(a.rows), block(ntt_threads(T.N));
-    switch (mode) {
-        case STORE_MDR: hipLaunchKernelGGL(k_ntt_inv<STORE_MDR>, grid, block, lds, s, T, a); break;
-        case STORE_CANON: hipLaunchKernelGGL(k_ntt_inv<STORE_CANON>, grid, block, lds, s, T, a); break;
-        default: hipLaunchKernelGGL(k_ntt_inv<STORE_PLAIN>, grid, block, lds, s, T, a); break;
+#define HG_INV(LN)                                                                                          \
+    switch (mode) {                                                                                        \
+        case STORE_MDR: hipLaunchKernelGGL((k_ntt_inv<STORE_MDR, LN>), grid, block, lds, s, T, a); break;     \
+        case STORE_CANON: hipLaunchKernelGGL((k_ntt_inv<STORE_CANON, LN>), grid, block, lds, s, T, a); break; \
+        default: hipLaunchKernelGGL((k_ntt_inv<STORE_PLAIN, LN>), grid, block, lds, s, T, a); break;         \
     }
+    HG_LOGN_SWITCH(T.logN, HG_INV)
+#undef HG_INV
+}
+
+bool fused_ok(const DevTables &T) { return T.alpha == 1 && T.N <= 16384; }
+
+void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s) {
+    if (nsrc <= 0) return;
+#define HG_HF(LN) \
+    hipLaunchKernelGGL(k_hoist_fused<LN>, dim3(nsrc * T.beta * T.nExt), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, y, srcs)
+    HG_LOGN_SWITCH(T.logN, HG_HF)
+#undef HG_HF
+}
+
+void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s) {
+    if (nslots <= 0) return;
+#define HG_MF(LN) \
+    hipLaunchKernelGGL(k_moddown_fused<LN>, dim3(nslots * T.L), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, E, U)
+    HG_LOGN_SWITCH(T.logN, HG_MF)
+#undef HG_MF
 }
 
 }  // namespace hg
