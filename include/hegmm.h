@@ -151,6 +151,21 @@ hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void 
 /* HE-CMult by a 0/1 (or any mod-t) slot vector of length S. */
 hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream);
 
+/* ---- tuning ----------------------------------------------------------- */
+
+/* Set an execution knob of the context (used by the autotuner; results are
+ * bit-identical for every setting).  Names:
+ *   "fuse_rows"  passes with at most this many rows per transform chain run
+ *                the fused one-workgroup-per-row kernels (alpha = 1 only)
+ *   "ip_chunk"   jobs per workgroup of the key-stationary inner products;
+ *                0 disables key grouping
+ *   "split_rows" transforms of fewer rows than this split each row over
+ *                N/1024 workgroups (two passes)
+ *   "batch_window" products per launch group inside hg_hegmm_batch
+ *                (0: all at once)
+ * Errors: HG_EINVAL (unknown name or negative value). */
+hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value);
+
 /* ---- introspection ---------------------------------------------------- */
 
 /* Plan of a shape: out[0..9] = transposed, nb, lb, d, M, K, W, rotations,

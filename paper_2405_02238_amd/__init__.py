@@ -64,6 +64,7 @@ _SIGS = {
     "hg_plan_info": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p],
     "hg_primes": [_P, _u64p],
     "hg_set_timing": [_P, ctypes.c_int],
+    "hg_tune": [_P, ctypes.c_char_p, ctypes.c_int64],
     "hg_last_timing": [_P, _f64p],
 }
 
@@ -255,6 +256,10 @@ class Context:
         out = np.zeros(self.L + self.alpha, dtype=np.uint64)
         _check(_lib.hg_primes(self.ptr, out))
         return [int(x) for x in out]
+
+    def tune(self, name: str, value: int):
+        """Set an execution knob (results are bit-identical for every value)."""
+        _check(_lib.hg_tune(self.ptr, name.encode(), int(value)))
 
     def set_timing(self, on: bool):
         _check(_lib.hg_set_timing(self.ptr, 1 if on else 0))

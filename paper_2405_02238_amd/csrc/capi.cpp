@@ -292,6 +292,20 @@ hg_status hg_primes(hg_ctx *ctx, uint64_t *out) {
     });
 }
 
+hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
+    return guard([&] {
+        need(ctx && name, "null argument");
+        need(value >= 0 && value < (1LL << 30), "value out of range");
+        hg::Ctx &X = *ctx->c;
+        const std::string n(name);
+        if (n == "fuse_rows") X.fuse_rows = (int)value;
+        else if (n == "ip_chunk") X.ip_chunk = (int)value;
+        else if (n == "split_rows") hg::ntt_set_split_rows((int)value);
+        else if (n == "batch_window") X.batch_window = (int)value;
+        else throw hg::Error(HG_EINVAL, "unknown tuning knob " + n);
+    });
+}
+
 hg_status hg_set_timing(hg_ctx *ctx, int enable) {
     return guard([&] {
         need(ctx, "null context");

@@ -82,7 +82,9 @@ struct Ctx {
 
     std::map<hipStream_t, Arena> arenas;
     Timing timing;
-    int fuse_rows = 64;   // passes with at most this many rows per chain use the fused kernels
+    int fuse_rows = 512;  // passes with at most this many rows per chain use the fused kernels
+    int ip_chunk = 0;     // jobs per workgroup in the key-stationary inner products (0: off)
+    int batch_window = 64; // products per launch group in hegmm_batch (0: all)
 
     Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device);
     ~Ctx();
@@ -113,6 +115,7 @@ struct Ctx {
         Ct *out;
     };
     void hegmm_batch(std::vector<Request> &reqs, hipStream_t st);
+    void hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st);
     Ct *rotate(const Ct &c, int z, hipStream_t st);
     Ct *mul(const Ct &a, const Ct &b, hipStream_t st);
     Ct *add(const Ct &a, const Ct &b, hipStream_t st);

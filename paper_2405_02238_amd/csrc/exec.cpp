@@ -130,7 +130,8 @@ struct Exec {
         char *extra = nullptr;   // caller-requested table space
         // internal
         char *tab = nullptr;
-        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_srcs = 0;
+        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_srcs = 0, t_chunks = 0, t_jlist = 0;
+        int nchunks = 0;   // > 0: key-stationary inner products over job groups
         double *coef = nullptr, *y = nullptr, *rk = nullptr;
         int nsrc = 0, nks = 0;
     };
@@ -142,6 +143,40 @@ struct Exec {
         Dev dv;
     };
 
+    // Group a pass's key-switched jobs by their tuple of (kind, Galois element,
+    // key) terms so that one workgroup reads each tuple's keys once for many
+    // jobs.  Returns false (ungrouped launch) when groups would not repeat or a
+    // job has more than two key-switched terms.
+    bool group_jobs(const Pass &ps, std::vector<int2> &chunks, std::vector<int> &jlist) {
+        const int nj = (int)ps.ip_jobs.size();
+        if (C.ip_chunk <= 0 || nj < 2 || beta > 8) return false;
+        std::map<std::vector<int>, std::vector<int>> groups;
+        for (int j = 0; j < nj; ++j) {
+            const IpJob &J = ps.ip_jobs[j];
+            std::vector<int> key;
+            for (int t = 0; t < J.nt; ++t) {
+                const IpTerm &tm = ps.ip_terms[J.t0 + t];
+                key.push_back(tm.kind);
+                key.push_back(tm.kind == IP_PLAIN ? 0 : tm.g);
+                key.push_back(tm.kind == IP_PLAIN ? 0 : tm.key);
+            }
+            int ks = 0;
+            for (int t = 0; t < J.nt; ++t) ks += ps.ip_terms[J.t0 + t].kind != IP_PLAIN;
+            if (ks > 2) return false;
+            groups[key].push_back(j);
+        }
+        if ((int)groups.size() * 4 > nj * 3) return false;   // little reuse: plain launch
+        for (auto &kv : groups) {
+            const auto &v = kv.second;
+            for (size_t o = 0; o < v.size(); o += C.ip_chunk) {
+                const int cnt = (int)std::min<size_t>(C.ip_chunk, v.size() - o);
+                chunks.push_back(make_int2((int)jlist.size(), cnt));
+                jlist.insert(jlist.end(), v.begin() + o, v.begin() + o + cnt);
+            }
+        }
+        return true;
+    }
+
     // Lay out the scratch of several passes that run one after another on
     // the stream (one scratch region sized for the largest, one descriptor
     // table block per pass) and copy every table with a single transfer.
@@ -150,8 +185,15 @@ struct Exec {
         size_t scratch = 0;
         std::vector<size_t> toff(sp.size());
         Layout tl;
-        struct Off { size_t ipj, ipt, fj, ft, keys, masks, extra, srcs; };
+        struct Off { size_t ipj, ipt, fj, ft, keys, masks, extra, srcs, chunks, jlist; };
         std::vector<Off> off(sp.size());
+        std::vector<std::vector<int2>> chunks(sp.size());
+        std::vector<std::vector<int>> jlists(sp.size());
+        for (size_t i = 0; i < sp.size(); ++i)
+            if (!group_jobs(*sp[i].ps, chunks[i], jlists[i])) {
+                chunks[i].clear();
+                jlists[i].clear();
+            }
         for (size_t i = 0; i < sp.size(); ++i) {
             Pass &ps = *sp[i].ps;
             const size_t nsrc = ps.srcs.size(), nks = ps.ip_jobs.size();
@@ -171,6 +213,8 @@ struct Exec {
             o.masks = tl.add(ps.masks.size() * sizeof(void *));
             o.extra = tl.add(sp[i].extra_bytes);
             o.srcs = tl.add(ps.srcs.size() * sizeof(void *));
+            o.chunks = tl.add(chunks[i].size() * sizeof(int2));
+            o.jlist = tl.add(jlists[i].size() * sizeof(int));
         }
         tl.add(256);   // never empty
         const size_t total = scratch + tl.total;
@@ -204,7 +248,12 @@ struct Exec {
             put(o.masks, ps.masks.data(), ps.masks.size() * sizeof(void *));
             put(o.extra, sp[i].extra, sp[i].extra_bytes);
             put(o.srcs, ps.srcs.data(), ps.srcs.size() * sizeof(void *));
+            put(o.chunks, chunks[i].data(), chunks[i].size() * sizeof(int2));
+            put(o.jlist, jlists[i].data(), jlists[i].size() * sizeof(int));
             Dev &dv = sp[i].dv;
+            dv.t_chunks = o.chunks;
+            dv.t_jlist = o.jlist;
+            dv.nchunks = (int)chunks[i].size();
             dv.tab = tab;
             dv.jobs = (FinJob *)(tab + o.fj);
             dv.terms = (FinTerm *)(tab + o.ft);
@@ -255,8 +304,14 @@ struct Exec {
             }
             if (tev) HGCHK(hipEventRecord(tev[0], st));
             // 2. inner products
-            ip_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
-                      (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks, st);
+            if (dv.nchunks > 0)
+                ip_grouped_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
+                                  (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt),
+                                  (const int2 *)(dv.tab + dv.t_chunks), (const int *)(dv.tab + dv.t_jlist),
+                                  dv.nchunks, st);
+            else
+                ip_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
+                          (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks, st);
             if (tev) HGCHK(hipEventRecord(tev[1], st));
             // 3. division by P
             if (fuse_md) {
@@ -300,6 +355,18 @@ struct Exec {
 
 void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
     HGCHK(hipSetDevice(device));
+    if (batch_window > 0 && (int)reqs.size() > batch_window) {
+        for (size_t o = 0; o < reqs.size(); o += batch_window) {
+            std::vector<Request> part(reqs.begin() + o,
+                                      reqs.begin() + std::min(reqs.size(), o + (size_t)batch_window));
+            hegmm_batch_window(part, st);
+        }
+        return;
+    }
+    hegmm_batch_window(reqs, st);
+}
+
+void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     Exec ex(*this, st);
     const size_t ctw = (size_t)L * N;
     // --- validate and plan ---

@@ -121,6 +121,12 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
                hipStream_t s);
 
+// Key-stationary variant: chunks[c] = (offset into job_list, count) of jobs
+// sharing one tuple of key-switched terms (at most two per job, beta <= 8).
+void ip_grouped_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+                       const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
+                       const int *job_list, int nchunks, hipStream_t s);
+
 // Tensor-accumulate: per request, sum over its (eps job, omega job) pairs of
 // the tensor product of the two finished transforms (E slots or plain terms).
 void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,

@@ -106,6 +106,116 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const d
     *(double2 *)(u + plane) = make_double2(a1x, a1y);
 }
 
+// Key-stationary inner products for batches: jobs that key-switch with the
+// same tuple of (Galois element, key) terms share a group; one workgroup
+// loads the group's key words for its positions once and loops over up to a
+// chunk of the group's jobs, each with its own source digits, masks and c0.
+// chunks[c] = (first index into job_list, count); the group's term layout is
+// that of its first job.  At most two key-switched terms per job.
+template <int BETA>
+__global__ void __launch_bounds__(IP_THREADS)
+k_ip_grouped(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
+             const IpJob *jobs, const IpTerm *terms, const int2 *chunks, const int *job_list) {
+    const int N = 1 << T.logN;
+    const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int r = blockIdx.y;
+    if (p >= N) return;
+    const double q = T.qt[r].x, qi = T.qt[r].y;
+    const size_t plane = (size_t)T.nExt * N;
+    const bool qrow = r < T.L;
+    const int2 ch = chunks[blockIdx.z];
+    const IpJob J0 = jobs[job_list[ch.x]];
+    // the group's key words at (r, p, p+1)
+    double2 kb[2][BETA], ka[2][BETA];
+    int kt[2] = {-1, -1};   // term positions (within a job) of the key-switched terms
+    int nk = 0;
+    for (int t = 0; t < J0.nt && nk < 2; ++t) {
+        const IpTerm tm = terms[J0.t0 + t];
+        if (tm.kind == IP_PLAIN) continue;
+        kt[nk] = t;
+        const double *kp = keys[tm.key] + (size_t)r * N + p;
+#pragma unroll
+        for (int j = 0; j < BETA; ++j) {
+            kb[nk][j] = *(const double2 *)(kp + (size_t)(2 * j) * plane);
+            ka[nk][j] = *(const double2 *)(kp + (size_t)(2 * j + 1) * plane);
+        }
+        ++nk;
+    }
+    for (int e = 0; e < ch.y; ++e) {
+        const int job = job_list[ch.x + e];
+        const IpJob J = jobs[job];
+        double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
+        double c0x = 0.0, c0y = 0.0, c1x = 0.0, c1y = 0.0;
+        int ki = 0;
+        for (int t = 0; t < J.nt; ++t) {
+            const IpTerm tm = terms[J.t0 + t];
+            double2 mv = make_double2(1.0, 1.0);
+            if (tm.mask >= 0) mv = *(const double2 *)(masks[tm.mask] + (size_t)r * N + p);
+            const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
+            const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
+            if (tm.kind != IP_PLAIN) {
+                const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
+                double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+#pragma unroll
+                for (int j = 0; j < BETA; ++j) {
+                    const double y0 = ys[(size_t)j * plane + pp0];
+                    const double y1 = ys[(size_t)j * plane + pp1];
+                    const double2 b = ki == 0 ? kb[0][j] : kb[1][j];
+                    const double2 a = ki == 0 ? ka[0][j] : ka[1][j];
+                    s0x += mulm(y0, b.x, q, qi);
+                    s0y += mulm(y1, b.y, q, qi);
+                    s1x += mulm(y0, a.x, q, qi);
+                    s1y += mulm(y1, a.y, q, qi);
+                }
+                ++ki;
+                s0x = redm(s0x, q, qi);
+                s0y = redm(s0y, q, qi);
+                s1x = redm(s1x, q, qi);
+                s1y = redm(s1y, q, qi);
+                if (tm.mask >= 0) {
+                    s0x = mulm(s0x, mv.x, q, qi);
+                    s0y = mulm(s0y, mv.y, q, qi);
+                    s1x = mulm(s1x, mv.x, q, qi);
+                    s1y = mulm(s1y, mv.y, q, qi);
+                }
+                a0x = redm(a0x + s0x, q, qi);
+                a0y = redm(a0y + s0y, q, qi);
+                a1x = redm(a1x + s1x, q, qi);
+                a1y = redm(a1y + s1y, q, qi);
+            }
+            if (qrow && tm.kind != IP_RELIN) {
+                double x0 = J.c0[(size_t)r * N + pp0], x1 = J.c0[(size_t)r * N + pp1];
+                if (tm.mask >= 0) {
+                    x0 = mulm(x0, mv.x, q, qi);
+                    x1 = mulm(x1, mv.y, q, qi);
+                }
+                c0x = redm(c0x + x0, q, qi);
+                c0y = redm(c0y + x1, q, qi);
+                if (tm.g == 1) {
+                    const double2 w = *(const double2 *)(J.c1 + (size_t)r * N + p);
+                    double z0 = w.x, z1 = w.y;
+                    if (tm.mask >= 0) {
+                        z0 = mulm(z0, mv.x, q, qi);
+                        z1 = mulm(z1, mv.y, q, qi);
+                    }
+                    c1x = redm(c1x + z0, q, qi);
+                    c1y = redm(c1y + z1, q, qi);
+                }
+            }
+        }
+        if (qrow) {
+            const double P = T.pmod[r];
+            a0x = redm(a0x + mulm(c0x, P, q, qi), q, qi);
+            a0y = redm(a0y + mulm(c0y, P, q, qi), q, qi);
+            a1x = redm(a1x + mulm(c1x, P, q, qi), q, qi);
+            a1y = redm(a1y + mulm(c1y, P, q, qi), q, qi);
+        }
+        double *u = U + (size_t)job * 2 * plane + (size_t)r * N + p;
+        *(double2 *)u = make_double2(a0x, a0y);
+        *(double2 *)(u + plane) = make_double2(a1x, a1y);
+    }
+}
+
 // One finished rotation sum at (prime i, position p): a key-switched job's
 // output sits in E; an identity job adds its (masked) c0, c1.
 __device__ __forceinline__ void finish_one(const DevTables &T, const FinJob &J, const FinTerm *terms,
@@ -399,6 +509,24 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
         HG_IP_CASE(1) HG_IP_CASE(2) HG_IP_CASE(3) HG_IP_CASE(4) HG_IP_CASE(5) HG_IP_CASE(6)
         HG_IP_CASE(7) HG_IP_CASE(8) HG_IP_CASE(9) HG_IP_CASE(10) HG_IP_CASE(11) HG_IP_CASE(12)
 #undef HG_IP_CASE
+        default: break;
+    }
+}
+
+void ip_grouped_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+                       const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
+                       const int *job_list, int nchunks, hipStream_t s) {
+    if (nchunks <= 0) return;
+    dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, nchunks);
+    switch (T.beta) {
+#define HG_IPG_CASE(B)                                                                                          \
+    case B:                                                                                                    \
+        hipLaunchKernelGGL(k_ip_grouped<B>, grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms, chunks, \
+                           job_list);                                                                          \
+        break;
+        HG_IPG_CASE(1) HG_IPG_CASE(2) HG_IPG_CASE(3) HG_IPG_CASE(4) HG_IPG_CASE(5) HG_IPG_CASE(6)
+        HG_IPG_CASE(7) HG_IPG_CASE(8)
+#undef HG_IPG_CASE
         default: break;
     }
 }

@@ -140,3 +140,52 @@ def test_hegmm_headline_full_size():
     pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(64, 32, 48)])
     A, B = workloads.headline_operands()
     run_pair(pair, 64, 32, 48, A, B, nonce=1)
+
+
+def test_batch_matches_alone_and_oracle(tiny):
+    """Products batched into shared launches give the same bits as alone, and
+    as the oracle (repeated shapes share key groups in the batch)."""
+    shapes = [(2, 5, 7), (5, 4, 2), (3, 11, 6), (7, 7, 7), (4, 3, 5), (2, 5, 7), (7, 7, 7)]
+    rng = np.random.default_rng(21)
+    mats = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    ctx = tiny.ctx
+    As = [ctx.encrypt(0, A, *s, nonce=100 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    Bs = [ctx.encrypt(1, B, *s, nonce=100 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    outs = ctx.hegmm_batch(As, Bs, shapes)
+    for i, (s, (A, B)) in enumerate(zip(shapes, mats)):
+        alone = ctx.hegmm(As[i], Bs[i], *s)
+        assert np.array_equal(outs[i].export(), alone.export()), s
+        assert np.array_equal(ctx.decrypt(outs[i], *s), workloads.plain_matmul_mod(A, B, tiny.P.t)), s
+    for i in (0, 2, 6):
+        m, l, n = shapes[i]
+        A, B = mats[i]
+        pl = H.plan(m, l, n, tiny.P.S)
+        ox = H.encrypt_operand(tiny.ks, pl, 0, A, B, 100 + i)
+        oy = H.encrypt_operand(tiny.ks, pl, 1, A, B, 100 + i)
+        want = flat(H.hegmm(tiny.ks, pl, ox, oy, tiny.masks))
+        assert np.array_equal(outs[i].export(), want), shapes[i]
+
+
+def test_batched_workload_sampled():
+    """The 256-request mixed-shape batch at N = 8192: every result decrypts to
+    A.B mod t, and sampled results equal the oracle bit for bit."""
+    c = workloads.BATCHED
+    reqs = workloads.batched_requests(256)
+    shapes = [(m, l, n) for (m, l, n, _, _) in reqs]
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, shapes)
+    As = [ctx.encrypt(0, A, m, l, n, nonce=i) for i, (m, l, n, A, B) in enumerate(reqs)]
+    Bs = [ctx.encrypt(1, B, m, l, n, nonce=i) for i, (m, l, n, A, B) in enumerate(reqs)]
+    outs = ctx.hegmm_batch(As, Bs, shapes)
+    for i, (m, l, n, A, B) in enumerate(reqs):
+        assert np.array_equal(ctx.decrypt(outs[i], m, l, n), workloads.plain_matmul_mod(A, B, c.t)), (i, m, l, n)
+    P = Params(c.N, c.t, c.L, c.alpha)
+    blocked = [i for i, s in enumerate(shapes) if H.plan(*s, P.S).nb > 1]
+    folded = [i for i, s in enumerate(shapes) if H.plan(*s, P.S).d > 1 and H.plan(*s, P.S).nb == 1]
+    sample = [0] + blocked[:1] + folded[:1]
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [shapes[i] for i in sample]))
+    for i in sample:
+        m, l, n, A, B = reqs[i]
+        pl = H.plan(m, l, n, P.S)
+        want = flat(H.hegmm(ks, pl, H.encrypt_operand(ks, pl, 0, A, B, i), H.encrypt_operand(ks, pl, 1, A, B, i)))
+        assert np.array_equal(outs[i].export(), want), (i, m, l, n)
