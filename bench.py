@@ -35,9 +35,57 @@ def parse():
                     help="bounded CPU-oracle sample: run whole oracle matmuls until this much time passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batched"],
-                    help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step")
+    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "serving"],
+                    help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step; "
+                         "serving: 512 Poisson arrivals at N=16384 through the continuous-batching server")
+    ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
+    ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
+    ap.add_argument("--max-batch", type=int, default=32, help="serving: products per launch group")
+    ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: admitted footprint limit")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB three times with a plain elementwise "
+                         "kernel (the reference point that scales the HBM byte counters of a --pmc run)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_ip_headline_traffic.md")
+IP_SOURCE = os.path.join(ROOT, "paper_2405_02238_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the transform-pass inner-product kernel, from
+    the committed counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by
+    what the same counter reads for a plain copy of known size).  None when
+    there is no summary or the kernel source changed since it was taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    with open(IP_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("kernel source sha256") != sha:
+        return None
+    try:
+        return float(fields["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    """A plain elementwise copy (read mib MiB, write mib MiB), three launches."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    print(f"# copy probe: 3 x {mib} MiB read + {mib} MiB written", file=sys.stderr, flush=True)
 
 
 def ip_kernel_bytes(ctx, plan_info, N, L, alpha, nsrc):
@@ -104,15 +152,88 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_serving(args):
+    """Poisson arrivals (mean 200/s) of mixed-shape products at N=16384 served
+    by the continuous-batching loop; latency from arrival to result in host
+    memory.  Also the same requests all at once (capacity) and one at a time
+    on the plain path."""
+    import torch
+    import paper_2405_02238_amd as hg
+    from paper_2405_02238_amd import serving
+    import workloads
+
+    cfg = workloads.SERVING
+    reqs = workloads.serving_requests(args.requests)
+    shapes = sorted({(m, l, n) for (_, m, l, n, _, _) in reqs})
+    ctx = hg.Context(cfg.N, cfg.t, cfg.L, cfg.alpha)
+    t0 = time.perf_counter()
+    ctx.keygen(cfg.seed, shapes)
+    torch.cuda.synchronize()
+    keygen_s = time.perf_counter() - t0
+    cts, timed = [], []
+    for i, (at, m, l, n, A, B) in enumerate(reqs):
+        ca, cb = ctx.encrypt(0, A, m, l, n, nonce=i), ctx.encrypt(1, B, m, l, n, nonce=i)
+        cts.append((ca, cb))
+        timed.append((at, m, l, n, ca.export(), cb.export()))
+    print(f"# serving setup: {len(reqs)} requests, {len(shapes)} shapes, keygen {keygen_s:.1f} s",
+          file=sys.stderr, flush=True)
+    budget = int(args.budget_gib * (1 << 30))
+    # one-at-a-time plain path on resident operands
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    alone = [ctx.hegmm(cts[i][0], cts[i][1], *timed[i][1:4]) for i in range(len(reqs))]
+    torch.cuda.synchronize()
+    alone_s = time.perf_counter() - t0
+    alone_words = [alone[i].export() for i in range(0, len(reqs), 16)]
+    del alone
+    out = {}
+    with hg.Server(ctx, max_batch=args.max_batch, lanes=args.lanes, hbm_budget=budget) as srv:
+        warm = [(0.0,) + t[1:] for t in timed[: min(len(timed), 2 * args.max_batch)]]
+        for _ in range(max(1, args.warmup)):
+            serving.replay(srv, warm)
+        print("# serving warm-up done", file=sys.stderr, flush=True)
+        res, lat, span = serving.replay(srv, timed)
+        st = srv.stats()
+        print(f"# poisson replay: {span:.2f} s", file=sys.stderr, flush=True)
+        sat = [(0.0,) + t[1:] for t in timed]
+        res2, lat2, span2 = serving.replay(srv, sat)
+        print(f"# saturated replay: {span2:.2f} s", file=sys.stderr, flush=True)
+    ok = 0
+    for i, (at, m, l, n, A, B) in enumerate(reqs):
+        C = ctx.decrypt(ctx.import_ct(res[i], 1, 2), m, l, n)
+        ok += int(np.array_equal(C, workloads.plain_matmul_mod(A, B, cfg.t)))
+    same = all(np.array_equal(res[i * 16], w) and np.array_equal(res2[i * 16], w) for i, w in enumerate(alone_words))
+    value = len(reqs) / span if ok == len(reqs) and same else 0.0
+    out = {"metric": "HE matmuls/s served with p50/p99 latency, Poisson 200 req/s, N=16384", "value": value,
+           "unit": "HE matmuls/s", "n_gpus": 1, "steps": 1, "warmup": args.warmup,
+           "ms_per_step": span * 1000.0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{len(reqs)} HEGMM-En requests, Poisson arrivals mean 200/s, (m,l,n) uniform over "
+                                  "{16,...,128}^3 with ml,ln,mn <= 8192, BGV N=16384 t=65537 L=6 alpha=2, "
+                                  "entries in [-8,8]",
+                      "lanes": args.lanes, "max_batch": args.max_batch, "hbm_budget_bytes": budget},
+           "p50_ms": serving.percentile_ms(lat, 50), "p99_ms": serving.percentile_ms(lat, 99),
+           "max_ms": float(lat.max() * 1000.0),
+           "mean_group": st["mean_group"], "peak_lanes_busy": st["peak_lanes_busy"],
+           "peak_footprint_bytes": st["peak_footprint"],
+           "capacity_matmuls_per_s": len(reqs) / span2,
+           "capacity_p50_ms": serving.percentile_ms(lat2, 50), "capacity_p99_ms": serving.percentile_ms(lat2, 99),
+           "one_at_a_time_matmuls_per_s": len(reqs) / alone_s,
+           "decrypt_ok": ok, "served_equals_alone_bits": same}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
-    if args.workload == "batched":
-        return run_batched(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
               "the hot path shards across GPUs as described in DESIGN.md but no multi-GPU run is made.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "serving":
+        return run_serving(args)
     import torch
     import paper_2405_02238_amd as hg
     import workloads
@@ -226,11 +347,13 @@ def main():
         "phase_ms": phases,
         "roofline": {"kernel": "k_ip (key-switch inner products)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": ip_bytes, "avg_launch_ms": ip_ms},
         "cpu_baseline": cpu_info,
     }
     print(json.dumps(out), flush=True)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
 
 
 if __name__ == "__main__":

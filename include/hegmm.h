@@ -51,7 +51,8 @@ enum {
 typedef struct hg_ctx hg_ctx;  /* parameters, device tables, device-resident evaluation keys */
 typedef struct hg_ct hg_ct;    /* one packed operand/result: nb >= 1 ciphertexts on the device */
 
-/* BGV parameter set.  N: ring degree, a power of two in [64, 16384].
+/* BGV parameter set.  N: ring degree, a power of two in [64, 32768]
+ * (rows longer than 16384 use two-pass transforms).
  * t: plaintext modulus, prime, t = 1 (mod 2N) so that all N/2 slots of a
  * rotation row are usable.  L: ciphertext primes (1..12).  alpha: special
  * primes, also the number of primes per key-switching digit (1..4, L+alpha
@@ -150,6 +151,62 @@ hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void 
 
 /* HE-CMult by a 0/1 (or any mod-t) slot vector of length S. */
 hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream);
+
+/* ---- serving: continuous batching ------------------------------------ */
+
+/* A request loop on its own thread, for the cloud side of Algorithm 2 under
+ * a stream of independent products of mixed shapes.  Clients submit the
+ * serialised operands (hg_ct_export words of hg_encrypt outputs for that
+ * shape; what a client sends to the cloud).  The server admits queued
+ * requests in arrival order while the sum of their modelled device
+ * footprints (hg_request_footprint) stays within hbm_budget, launches each
+ * admitted group through the batched executor on one of `lanes` streams so
+ * that groups overlap on the device, and admits new arrivals as soon as a
+ * lane and budget are free.  Keys stay resident in the context.  Each result
+ * is bit-identical to hg_hegmm of the same operands alone.
+ * While a server exists its thread owns the context: the caller may use only
+ * hg_server_* and hg_request_footprint on it until hg_server_destroy, which
+ * finishes every submitted request first.  hg_server_submit and
+ * hg_server_wait may be called from several threads. */
+typedef struct hg_server hg_server;
+typedef struct {
+    int32_t max_batch;     /* products per launch group, >= 1 */
+    int32_t lanes;         /* launch groups in flight at once, 1..8, one stream each */
+    uint64_t hbm_budget;   /* bytes of modelled footprint admitted at once; 0 = no limit.
+                              A request larger than the budget still runs when nothing else does. */
+} hg_server_config;
+
+/* Errors: HG_EINVAL (configuration out of range), HG_EDEVICE. */
+hg_status hg_server_create(hg_ctx *ctx, const hg_server_config *cfg, hg_server **out);
+
+/* Queue one product.  a_words / b_words: nb * 2 * L * N words each (nb the
+ * shape's inner block count), residues in [0, q_i); copied before return.
+ * *ticket identifies the request.  Errors: HG_EINVAL (word count, residue
+ * range, dimensions), HG_ENOKEY (shape not listed in hg_keygen). */
+hg_status hg_server_submit(hg_server *srv, const uint64_t *a_words, size_t a_nwords, const uint64_t *b_words,
+                           size_t b_nwords, int m, int l, int n, uint64_t *ticket);
+
+/* Block until the request is done.  c_words (may be NULL) receives the
+ * result's hg_ct_export words (2 * L * N, one ciphertext of the shape's
+ * result; hg_ct_import with ncts 1, components 2 gives a handle for
+ * hg_decrypt).  times3 (may be NULL) receives the submit, start and done
+ * times in seconds since the server was created; done is when the result was
+ * back in host memory.  A ticket can be waited for once.  Errors: HG_EINVAL
+ * (unknown ticket, buffer too small), or the error of the request's launch. */
+hg_status hg_server_wait(hg_server *srv, uint64_t ticket, uint64_t *c_words, size_t c_nwords, double *times3);
+
+/* out8: completed requests, launch groups, mean group size, peak admitted
+ * footprint (bytes), peak groups in flight, queued requests, admitted
+ * footprint now, seconds since creation. */
+hg_status hg_server_stats(hg_server *srv, double *out8);
+
+/* Finish every submitted request, stop the thread, release the lanes. */
+void hg_server_destroy(hg_server *srv);
+
+/* Modelled device bytes that one product of this shape holds while it runs
+ * (operands, result, accumulator, pass scratch, staging).
+ * Errors: HG_EINVAL, HG_ENOFIT. */
+hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes);
 
 /* ---- tuning ----------------------------------------------------------- */
 

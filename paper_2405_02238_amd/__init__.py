@@ -31,6 +31,10 @@ class HGError(RuntimeError):
         self.code = code
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("lanes", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_uint32),
                 ("alpha", ctypes.c_uint32)]
@@ -66,6 +70,12 @@ _SIGS = {
     "hg_set_timing": [_P, ctypes.c_int],
     "hg_tune": [_P, ctypes.c_char_p, ctypes.c_int64],
     "hg_last_timing": [_P, _f64p],
+    "hg_request_footprint": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)],
+    "hg_server_create": [_P, _P, _PP],
+    "hg_server_submit": [_P, _u64p, ctypes.c_size_t, _u64p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                         ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)],
+    "hg_server_wait": [_P, ctypes.c_uint64, _P, ctypes.c_size_t, _P],
+    "hg_server_stats": [_P, _f64p],
 }
 
 
@@ -92,6 +102,8 @@ def load(path: str = LIB_PATH):
     lib.hg_ctx_destroy.restype = None
     lib.hg_ct_free.argtypes = [_P]
     lib.hg_ct_free.restype = None
+    lib.hg_server_destroy.argtypes = [_P]
+    lib.hg_server_destroy.restype = None
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -269,3 +281,61 @@ class Context:
         _check(_lib.hg_last_timing(self.ptr, out))
         keys = ["hoist", "inner_product", "div_by_p", "tensor", "relin", "fold", "total", "ip_kernel"]
         return dict(zip(keys, (float(x) for x in out)))
+
+    def request_footprint(self, m: int, l: int, n: int) -> int:
+        out = ctypes.c_uint64(0)
+        _check(_lib.hg_request_footprint(self.ptr, m, l, n, ctypes.byref(out)))
+        return int(out.value)
+
+
+class Server:
+    """hg_server: continuous-batching request loop over a keyed context.
+
+    While it exists its thread owns the context; use only submit / wait /
+    stats until close()."""
+
+    def __init__(self, ctx: Context, max_batch: int = 64, lanes: int = 2, hbm_budget: int = 0):
+        cfg = _ServerConfig(max_batch, lanes, hbm_budget)
+        out = ctypes.c_void_p()
+        _check(_lib.hg_server_create(ctx.ptr, ctypes.byref(cfg), ctypes.byref(out)))
+        self.ptr = out.value
+        self.ctx = ctx
+        self.words = 2 * ctx.L * ctx.N
+
+    def submit(self, a_words: np.ndarray, b_words: np.ndarray, m: int, l: int, n: int) -> int:
+        a = np.ascontiguousarray(a_words, dtype=np.uint64)
+        b = np.ascontiguousarray(b_words, dtype=np.uint64)
+        t = ctypes.c_uint64(0)
+        _check(_lib.hg_server_submit(self.ptr, a, a.size, b, b.size, m, l, n, ctypes.byref(t)))
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(result words, (submit, start, done) seconds on the server clock)."""
+        out = np.empty(self.words, dtype=np.uint64)
+        times = np.zeros(3, dtype=np.float64)
+        _check(_lib.hg_server_wait(self.ptr, ticket, out.ctypes.data, out.size, times.ctypes.data))
+        return out, tuple(float(x) for x in times)
+
+    def stats(self) -> dict:
+        out = np.zeros(8, dtype=np.float64)
+        _check(_lib.hg_server_stats(self.ptr, out))
+        keys = ["done", "groups", "mean_group", "peak_footprint", "peak_lanes_busy", "queued", "footprint",
+                "clock"]
+        return dict(zip(keys, (float(x) for x in out)))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            _lib.hg_server_destroy(self.ptr)
+            self.ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

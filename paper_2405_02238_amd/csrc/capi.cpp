@@ -6,12 +6,16 @@
 
 #include "../../include/hegmm.h"
 #include "context.h"
+#include "server.h"
 
 struct hg_ctx {
     hg::Ctx *c;
 };
 struct hg_ct {
     hg::Ct *c;
+};
+struct hg_server {
+    hg::Server *s;
 };
 
 namespace {
@@ -318,6 +322,63 @@ hg_status hg_last_timing(hg_ctx *ctx, double *out8) {
         need(ctx && out8, "null argument");
         for (int i = 0; i < 8; ++i) out8[i] = ctx->c->timing.ms[i];
     });
+}
+
+hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes) {
+    return guard([&] {
+        need(ctx && bytes, "null argument");
+        hg::Ctx &X = *ctx->c;
+        hg::Plan p;
+        try {
+            p = hg::make_plan(m, l, n, X.S);
+        } catch (std::invalid_argument &e) {
+            throw hg::Error(HG_EINVAL, e.what());
+        } catch (std::range_error &e) {
+            throw hg::Error(HG_ENOFIT, e.what());
+        }
+        *bytes = hg::request_footprint(X, p);
+    });
+}
+
+hg_status hg_server_create(hg_ctx *ctx, const hg_server_config *cfg, hg_server **out) {
+    return guard([&] {
+        need(ctx && cfg && out, "null argument");
+        *out = nullptr;
+        hg::ServerConfig sc;
+        sc.max_batch = cfg->max_batch;
+        sc.lanes = cfg->lanes;
+        sc.budget = cfg->hbm_budget;
+        hg::Server *s = new hg::Server(*ctx->c, sc);
+        *out = new hg_server{s};
+    });
+}
+
+hg_status hg_server_submit(hg_server *srv, const uint64_t *a_words, size_t a_nwords, const uint64_t *b_words,
+                           size_t b_nwords, int m, int l, int n, uint64_t *ticket) {
+    return guard([&] {
+        need(srv && ticket, "null argument");
+        *ticket = srv->s->submit(a_words, a_nwords, b_words, b_nwords, m, l, n);
+    });
+}
+
+hg_status hg_server_wait(hg_server *srv, uint64_t ticket, uint64_t *c_words, size_t c_nwords, double *times3) {
+    return guard([&] {
+        need(srv, "null server");
+        srv->s->wait(ticket, c_words, c_nwords, times3);
+    });
+}
+
+hg_status hg_server_stats(hg_server *srv, double *out8) {
+    return guard([&] {
+        need(srv && out8, "null argument");
+        srv->s->stats(out8);
+    });
+}
+
+void hg_server_destroy(hg_server *srv) {
+    if (!srv) return;
+    delete srv->s;
+    delete srv;
 }
 
 }  // extern "C"

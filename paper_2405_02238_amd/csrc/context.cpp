@@ -52,7 +52,7 @@ double centered_d(uint64_t x, uint64_t m) { return (double)centered_of(x, m); }
 size_t Ct::words() const { return (size_t)ncts * comps * ctx->L * ctx->N; }
 double *Ct::ct(int i) const { return d + (size_t)i * comps * ctx->L * ctx->N; }
 Ct::~Ct() {
-    if (d) (void)hipFree(d);
+    if (d && owns) (void)hipFree(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -60,7 +60,7 @@ Ct::~Ct() {
 // ---------------------------------------------------------------------------
 
 Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_) {
-    if (N_ < 64 || N_ > 16384 || (N_ & (N_ - 1))) throw Error(-1, "N must be a power of two in [64, 16384]");
+    if (N_ < 64 || N_ > 32768 || (N_ & (N_ - 1))) throw Error(-1, "N must be a power of two in [64, 32768]");
     if (L_ < 1 || L_ > 12 || alpha_ < 1 || alpha_ > 4 || L_ + alpha_ > 16)
         throw Error(-1, "need 1 <= L <= 12, 1 <= alpha <= 4, L + alpha <= 16");
     if (t_ < 3 || t_ >= (1ULL << 30) || !is_prime_u64(t_) || (t_ - 1) % (2 * N_) != 0)

@@ -34,6 +34,7 @@ struct Ct {
     int m = 0, l = 0, n = 0;   // shape (0 for raw slot ciphertexts)
     int side = -1;             // packed side (0 left, 1 right, 2 result, -1 raw)
     double *d = nullptr;
+    bool owns = true;          // false: a view into memory owned elsewhere
     size_t words() const;      // doubles in total
     double *ct(int i) const;   // start of ciphertext i
     ~Ct();

@@ -277,7 +277,7 @@ struct Exec {
     }
 
     // Phases 1-3 of a staged pass: hoist, inner products, division by P.
-    void launch(const Dev &dv, hipEvent_t *tev = nullptr) {
+    void launch(const Dev &dv, hipEvent_t *tev = nullptr, bool transform_pass = false) {
         // few rows: one fused launch per chain (latency bound); many rows:
         // separate launches (throughput bound)
         const bool fuse_hoist = fused_ok(T) && dv.nsrc * beta * nExt <= C.fuse_rows;
@@ -311,7 +311,8 @@ struct Exec {
                                   dv.nchunks, st);
             else
                 ip_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
-                          (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks, st);
+                          (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks,
+                          transform_pass, st);
             if (tev) HGCHK(hipEventRecord(tev[1], st));
             // 3. division by P
             if (fuse_md) {
@@ -472,7 +473,7 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     ex.stage(sp);
 
     const Exec::Dev &dv = sp[0].dv;
-    ex.launch(dv, timing.enabled ? ev : nullptr);
+    ex.launch(dv, timing.enabled ? ev : nullptr, true);
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
                       (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));

@@ -119,7 +119,7 @@ void ntt_set_split_rows(int rows);
 // the unswitched part on the ciphertext primes (see IpTerm).
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
-               hipStream_t s);
+               bool transform_pass, hipStream_t s);
 
 // Key-stationary variant: chunks[c] = (offset into job_list, count) of jobs
 // sharing one tuple of key-switched terms (at most two per job, beta <= 8).

@@ -18,7 +18,9 @@ constexpr int IP_THREADS = 256;
 // of the hoisted digits; two consecutive positions per thread (16-byte key
 // loads), the digit loop unrolled (BETA digits) so that all key loads of a
 // term are in flight together.  grid: (N / 512, nExt, jobs).
-template <int BETA>
+// TAG only names the launch for profilers (0: the eps/omega transform pass,
+// 1: relinearisation, fold and single-ciphertext passes); the code is the same.
+template <int BETA, int TAG>
 __global__ void __launch_bounds__(IP_THREADS)
 k_ip(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
      const IpJob *jobs, const IpTerm *terms) {
@@ -500,12 +502,18 @@ bool g_cdt_uploaded[64] = {false};
 static dim3 ew_grid(int N, int y, int z = 1) { return dim3((N + EW_THREADS - 1) / EW_THREADS, y, z); }
 
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-               const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, hipStream_t s) {
+               const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, bool transform_pass,
+               hipStream_t s) {
     if (njobs <= 0) return;
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, njobs);
     switch (T.beta) {
-#define HG_IP_CASE(B) \
-    case B: hipLaunchKernelGGL(k_ip<B>, grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms); break;
+#define HG_IP_CASE(B)                                                                                        \
+    case B:                                                                                                  \
+        if (transform_pass)                                                                                  \
+            hipLaunchKernelGGL((k_ip<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_ip<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms); \
+        break;
         HG_IP_CASE(1) HG_IP_CASE(2) HG_IP_CASE(3) HG_IP_CASE(4) HG_IP_CASE(5) HG_IP_CASE(6)
         HG_IP_CASE(7) HG_IP_CASE(8) HG_IP_CASE(9) HG_IP_CASE(10) HG_IP_CASE(11) HG_IP_CASE(12)
 #undef HG_IP_CASE

@@ -1,0 +1,339 @@
+// Continuous-batching request loop (see server.h).
+#include "server.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace hg {
+
+uint64_t request_footprint(const Ctx &C, const Plan &p) {
+    const uint64_t w = 8, N = C.N, L = C.L, nExt = C.nExt, beta = C.beta, alpha = C.alpha;
+    const uint64_t ct = 2 * L * N * w;
+    uint64_t nks = 0;
+    for (int k = 0; k < p.K; ++k) {
+        bool ke = false, kw = false;
+        for (auto &t : p.eps[k]) ke |= ((t.z % C.S) + C.S) % C.S != 0;
+        for (auto &t : p.omega[k]) kw |= ((t.z % C.S) + C.S) % C.S != 0;
+        nks += (uint64_t)ke + (uint64_t)kw;
+    }
+    nks *= (uint64_t)p.nb;
+    const uint64_t nsrc = 2 * (uint64_t)p.nb;
+    const uint64_t operands = 2 * (uint64_t)p.nb * ct;
+    const uint64_t result = ct;
+    const uint64_t acc = 3 * L * N * w + (p.d > 1 ? ct : 0);
+    const uint64_t scratch = nsrc * (L + beta * nExt) * N * w + nks * 2 * (nExt + alpha + L) * N * w;
+    const uint64_t staging = operands / 2;   // canonical words of the operands, then of the result
+    return operands + result + acc + scratch + staging;
+}
+
+Server::Server(Ctx &c, const ServerConfig &cf) : C(c), cfg(cf), lanes(cf.lanes) {
+    if (cfg.max_batch < 1 || cfg.lanes < 1 || cfg.lanes > 8) throw Error(-1, "server: bad configuration");
+    HGCHK(hipSetDevice(C.device));
+    for (auto &ln : lanes) {
+        HGCHK(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
+        HGCHK(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+    }
+    origin = std::chrono::steady_clock::now();
+    th = std::thread([this] { loop(); });
+}
+
+Server::~Server() {
+    {
+        std::lock_guard<std::mutex> g(mu);
+        stop = true;
+    }
+    cv_sub.notify_all();
+    if (th.joinable()) th.join();
+    (void)hipSetDevice(C.device);
+    for (auto &ln : lanes) {
+        if (ln.st) (void)hipStreamSynchronize(ln.st);
+        if (ln.pin_in) (void)hipHostFree(ln.pin_in);
+        if (ln.pin_out) (void)hipHostFree(ln.pin_out);
+        if (ln.done) (void)hipEventDestroy(ln.done);
+        // the executor's scratch arena of this stream goes with the stream
+        auto it = C.arenas.find(ln.st);
+        if (it != C.arenas.end()) {
+            if (it->second.base) (void)hipFree(it->second.base);
+            if (it->second.pinned) (void)hipHostFree(it->second.pinned);
+            if (it->second.staged) (void)hipEventDestroy(it->second.staged);
+            C.arenas.erase(it);
+        }
+        if (ln.st) (void)hipStreamDestroy(ln.st);
+    }
+}
+
+double Server::now() const {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - origin).count();
+}
+
+uint64_t Server::submit(const uint64_t *a, size_t na, const uint64_t *b, size_t nbw, int m, int l, int n) {
+    if (!a || !b) throw Error(-1, "null operand");
+    if (m <= 0 || l <= 0 || n <= 0) throw Error(-1, "dimensions must be positive");
+    // plans and keys are made by hg_keygen before serving; look up only
+    auto it = C.plans.find(std::make_tuple(m, l, n));
+    if (it == C.plans.end()) throw Error(-3, "shape has no plan and keys (list it in hg_keygen)");
+    const PlanEntry *pe = it->second.get();
+    for (int z : pe->plan.rotations(C.S))
+        if (!C.rot_keys.count(C.galois_of(z))) throw Error(-3, "missing rotation key for z = " + std::to_string(z));
+    const size_t ctw = (size_t)2 * C.L * C.N;
+    const size_t want = (size_t)pe->plan.nb * ctw;
+    if (na != want || nbw != want) throw Error(-1, "operand word count differs from the shape's packing");
+    for (int side = 0; side < 2; ++side) {
+        const uint64_t *w = side ? b : a;
+        for (size_t r = 0; r < want / C.N; ++r) {
+            const uint64_t q = C.qs[r % C.L];
+            const uint64_t *row = w + r * C.N;
+            for (int i = 0; i < C.N; ++i)
+                if (row[i] >= q) throw Error(-1, "residue out of range");
+        }
+    }
+    auto rq = std::make_unique<Req>();
+    rq->m = m;
+    rq->l = l;
+    rq->n = n;
+    rq->pe = pe;
+    rq->a.assign(a, a + na);
+    rq->b.assign(b, b + nbw);
+    rq->footprint = request_footprint(C, pe->plan);
+    uint64_t id;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        id = next_id++;
+        rq->id = id;
+        rq->t_submit = now();
+        pending.push_back(rq.get());
+        reqs[id] = std::move(rq);
+    }
+    cv_sub.notify_one();
+    return id;
+}
+
+void Server::wait(uint64_t id, uint64_t *c, size_t nc, double *times) {
+    std::unique_ptr<Req> rq;
+    {
+        std::unique_lock<std::mutex> g(mu);
+        auto it = reqs.find(id);
+        if (it == reqs.end()) throw Error(-1, "unknown ticket");
+        Req *r = it->second.get();
+        cv_done.wait(g, [&] { return r->status == 2 || r->status < 0; });
+        rq = std::move(it->second);
+        reqs.erase(it);
+    }
+    if (rq->status < 0) throw Error(rq->status, rq->err);
+    if (times) {
+        times[0] = rq->t_submit;
+        times[1] = rq->t_start;
+        times[2] = rq->t_done;
+    }
+    if (c) {
+        if (nc < rq->c.size()) throw Error(-1, "result buffer too small");
+        std::memcpy(c, rq->c.data(), rq->c.size() * sizeof(uint64_t));
+    }
+}
+
+void Server::stats(double *o) {
+    std::lock_guard<std::mutex> g(mu);
+    o[0] = (double)n_done;
+    o[1] = (double)n_batches;
+    o[2] = n_batches ? sum_batch / n_batches : 0.0;
+    o[3] = (double)max_inflight;
+    o[4] = (double)max_overlap;
+    o[5] = (double)pending.size();
+    o[6] = (double)inflight;
+    o[7] = now();
+}
+
+void Server::launch(Lane &ln, std::vector<Req *> &batch) {
+    const hipStream_t st = ln.st;
+    const size_t N = C.N, L = C.L;
+    const size_t ctw = 2 * L * N;
+    size_t in_words = 0;
+    for (Req *r : batch) in_words += r->a.size() + r->b.size();
+    const size_t out_words = batch.size() * ctw;
+    // the lane is idle (its last group completed), so its staging can be replaced
+    if (in_words * 8 > ln.pin_in_cap) {
+        if (ln.pin_in) HGCHK(hipHostFree(ln.pin_in));
+        ln.pin_in_cap = in_words * 8 + in_words * 4;
+        HGCHK(hipHostMalloc(&ln.pin_in, ln.pin_in_cap, hipHostMallocDefault));
+    }
+    if (out_words * 8 > ln.pin_out_cap) {
+        if (ln.pin_out) HGCHK(hipHostFree(ln.pin_out));
+        ln.pin_out_cap = out_words * 8 + out_words * 4;
+        HGCHK(hipHostMalloc(&ln.pin_out, ln.pin_out_cap, hipHostMallocDefault));
+    }
+    uint64_t *pin = (uint64_t *)ln.pin_in;
+    size_t o = 0;
+    for (Req *r : batch) {
+        std::memcpy(pin + o, r->a.data(), r->a.size() * 8);
+        o += r->a.size();
+        std::memcpy(pin + o, r->b.data(), r->b.size() * 8);
+        o += r->b.size();
+    }
+    // device buffer: operands (in_words doubles), results (out_words
+    // doubles), canonical staging (in_words words; in_words >= 2 out_words)
+    char *dbuf = nullptr;
+    HGCHK(hipMallocAsync((void **)&dbuf, (2 * in_words + out_words) * 8, st));
+    double *ops = (double *)dbuf;
+    double *outs = ops + in_words;
+    uint64_t *stage = (uint64_t *)(outs + out_words);
+    HGCHK(hipMemcpyAsync(stage, pin, in_words * 8, hipMemcpyHostToDevice, st));
+    u64_to_dbl(stage, ops, in_words, st);
+    NttArgs a;
+    a.out = ops;
+    a.in = ops;
+    a.rows = (int)(in_words / N);
+    a.per = (int)L;
+    a.out_stride = a.in_stride = (long long)(L * N);
+    ntt_fwd(C.T, LOAD_PLAIN, a, st);
+
+    ln.cts.clear();
+    std::vector<Ctx::Request> rq;
+    o = 0;
+    for (size_t i = 0; i < batch.size(); ++i) {
+        Req *r = batch[i];
+        const Plan &p = r->pe->plan;
+        auto mk = [&](double *d, int side, int ncts) {
+            auto c = std::make_unique<Ct>();
+            c->ctx = &C;
+            c->owns = false;
+            c->ncts = ncts;
+            c->comps = 2;
+            c->m = r->m;
+            c->l = r->l;
+            c->n = r->n;
+            c->side = side;
+            c->d = d;
+            ln.cts.push_back(std::move(c));
+            return ln.cts.back().get();
+        };
+        Ct *A = mk(ops + o, side_of_role(p, 0), p.nb);
+        o += r->a.size();
+        Ct *B = mk(ops + o, side_of_role(p, 1), p.nb);
+        o += r->b.size();
+        Ct *Cc = mk(outs + i * ctw, 2, 1);
+        rq.push_back({A, B, r->m, r->l, r->n, Cc});
+    }
+    C.hegmm_batch_window(rq, st);
+    // results to canonical words (the operand region is free by now)
+    NttArgs e;
+    e.out = ops;
+    e.in = outs;
+    e.rows = (int)(out_words / N);
+    e.per = (int)L;
+    e.out_stride = e.in_stride = (long long)(L * N);
+    ntt_inv(C.T, STORE_CANON, e, st);
+    dbl_to_u64(ops, stage, out_words, st);
+    HGCHK(hipMemcpyAsync(ln.pin_out, stage, out_words * 8, hipMemcpyDeviceToHost, st));
+    HGCHK(hipFreeAsync(dbuf, st));
+    HGCHK(hipEventRecord(ln.done, st));
+}
+
+void Server::finish(Lane &ln, int code, const std::string &msg) {
+    const size_t ctw = 2 * (size_t)C.L * C.N;
+    const double t = now();
+    std::vector<std::vector<uint64_t>> res(ln.batch.size());
+    if (code == 0) {
+        const uint64_t *po = (const uint64_t *)ln.pin_out;
+        for (size_t i = 0; i < ln.batch.size(); ++i) res[i].assign(po + i * ctw, po + (i + 1) * ctw);
+    }
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (size_t i = 0; i < ln.batch.size(); ++i) {
+            Req *r = ln.batch[i];
+            r->t_done = t;
+            if (code == 0) {
+                r->c = std::move(res[i]);
+                r->status = 2;
+                ++n_done;
+            } else {
+                r->status = code;
+                r->err = msg;
+            }
+            r->a.clear();
+            r->a.shrink_to_fit();
+            r->b.clear();
+            r->b.shrink_to_fit();
+        }
+        inflight -= ln.footprint;
+    }
+    ln.footprint = 0;
+    ln.batch.clear();
+    ln.cts.clear();
+    ln.busy = false;
+    cv_done.notify_all();
+}
+
+void Server::loop() {
+    (void)hipSetDevice(C.device);
+    for (;;) {
+        bool progressed = false;
+        // 1. completed groups
+        for (auto &ln : lanes) {
+            if (!ln.busy) continue;
+            const hipError_t e = hipEventQuery(ln.done);
+            if (e == hipSuccess) {
+                finish(ln, 0, "");
+                progressed = true;
+            } else if (e != hipErrorNotReady) {
+                finish(ln, -5, std::string("device error: ") + hipGetErrorString(e));
+                progressed = true;
+            }
+        }
+        // 2. admit pending requests in arrival order onto free lanes
+        for (auto &ln : lanes) {
+            if (ln.busy) continue;
+            std::vector<Req *> batch;
+            uint64_t fp = 0;
+            {
+                std::lock_guard<std::mutex> g(mu);
+                while (!pending.empty() && (int)batch.size() < cfg.max_batch) {
+                    Req *r = pending.front();
+                    const bool fits = cfg.budget == 0 || inflight + fp + r->footprint <= cfg.budget ||
+                                      (inflight == 0 && batch.empty());   // a lone request always runs
+                    if (!fits) break;
+                    pending.pop_front();
+                    fp += r->footprint;
+                    batch.push_back(r);
+                }
+                if (batch.empty()) break;
+                inflight += fp;
+                max_inflight = std::max(max_inflight, inflight);
+                const double t = now();
+                for (Req *r : batch) {
+                    r->status = 1;
+                    r->t_start = t;
+                }
+                ++n_batches;
+                sum_batch += (double)batch.size();
+                uint64_t busy = 1;
+                for (auto &o : lanes) busy += o.busy;
+                max_overlap = std::max(max_overlap, busy);
+            }
+            ln.batch = batch;
+            ln.footprint = fp;
+            ln.busy = true;
+            try {
+                launch(ln, ln.batch);
+            } catch (Error &e) {
+                (void)hipStreamSynchronize(ln.st);
+                finish(ln, e.code, e.what());
+            } catch (std::exception &e) {
+                (void)hipStreamSynchronize(ln.st);
+                finish(ln, -1, e.what());
+            }
+            progressed = true;
+        }
+        // 3. leave when stopped and drained; otherwise wait for work
+        std::unique_lock<std::mutex> g(mu);
+        bool any_busy = false;
+        for (auto &ln : lanes) any_busy |= ln.busy;
+        if (stop && pending.empty() && !any_busy) break;
+        if (progressed) continue;
+        if (any_busy)
+            cv_sub.wait_for(g, std::chrono::microseconds(20));
+        else
+            cv_sub.wait(g, [&] { return stop || !pending.empty(); });
+    }
+}
+
+}  // namespace hg

@@ -189,3 +189,68 @@ def test_batched_workload_sampled():
         pl = H.plan(m, l, n, P.S)
         want = flat(H.hegmm(ks, pl, H.encrypt_operand(ks, pl, 0, A, B, i), H.encrypt_operand(ks, pl, 1, A, B, i)))
         assert np.array_equal(outs[i].export(), want), (i, m, l, n)
+
+
+def test_serving_mix_equals_alone():
+    """Continuous batching at N = 16384 (6 + 2 primes): requests arriving
+    while others run are admitted into overlapping launch groups; every
+    served result equals the product alone bit for bit, decrypts to A.B mod t,
+    and one of them equals the oracle."""
+    from paper_2405_02238_amd import serving
+    c = workloads.SERVING
+    reqs = workloads.serving_requests(24)
+    shapes = sorted({(m, l, n) for (_, m, l, n, _, _) in reqs})
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, shapes)
+    cts, timed = [], []
+    for i, (at, m, l, n, A, B) in enumerate(reqs):
+        ca, cb = ctx.encrypt(0, A, m, l, n, nonce=i), ctx.encrypt(1, B, m, l, n, nonce=i)
+        cts.append((ca, cb))
+        # arrivals compressed tenfold so that groups overlap
+        timed.append((at / 10.0, m, l, n, ca.export(), cb.export()))
+    budget = 3 * max(ctx.request_footprint(m, l, n) for (_, m, l, n, _, _) in reqs)
+    with hg.Server(ctx, max_batch=8, lanes=2, hbm_budget=budget) as srv:
+        results, lat, _ = serving.replay(srv, timed)
+        st = srv.stats()
+    assert st["done"] == len(reqs)
+    assert st["peak_footprint"] <= budget or st["mean_group"] == 1
+    for i, (at, m, l, n, A, B) in enumerate(reqs):
+        alone = ctx.hegmm(cts[i][0], cts[i][1], m, l, n)
+        assert np.array_equal(results[i], alone.export()), (i, m, l, n)
+        C = ctx.decrypt(ctx.import_ct(results[i], 1, 2), m, l, n)
+        assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t)), (i, m, l, n)
+    i = min(range(len(reqs)), key=lambda k: reqs[k][1] * reqs[k][2] * reqs[k][3])
+    _, m, l, n, A, B = reqs[i]
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [(m, l, n)]))
+    pl = H.plan(m, l, n, P.S)
+    want = flat(H.hegmm(ks, pl, H.encrypt_operand(ks, pl, 0, A, B, i), H.encrypt_operand(ks, pl, 1, A, B, i)))
+    assert np.array_equal(results[i], want), (i, m, l, n)
+
+
+def test_serving_errors_and_budget():
+    """Unkeyed shapes and malformed operands are refused at submission; a
+    budget below one request still serves it alone."""
+    c = workloads.TINY
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, [(4, 3, 5)])
+    A, B = workloads.tiny_operands()
+    wa = ctx.encrypt(0, A, 4, 3, 5, nonce=3).export()
+    wb = ctx.encrypt(1, B, 4, 3, 5, nonce=3).export()
+    with hg.Server(ctx, max_batch=4, lanes=1, hbm_budget=1) as srv:
+        with pytest.raises(hg.HGError) as e:
+            srv.submit(wa, wb, 5, 3, 4)
+        assert e.value.code == hg.HG_ENOKEY
+        with pytest.raises(hg.HGError) as e:
+            srv.submit(wa[:-1], wb, 4, 3, 5)
+        assert e.value.code == hg.HG_EINVAL
+        bad = wa.copy()
+        bad[0] = np.uint64(2 ** 63)
+        with pytest.raises(hg.HGError):
+            srv.submit(bad, wb, 4, 3, 5)
+        tickets = [srv.submit(wa, wb, 4, 3, 5) for _ in range(3)]
+        outs = [srv.wait(t)[0] for t in tickets]
+        assert srv.stats()["mean_group"] == 1.0
+    for o in outs:
+        assert np.array_equal(ctx.decrypt(ctx.import_ct(o, 1, 2), 4, 3, 5),
+                              workloads.plain_matmul_mod(A, B, c.t))
