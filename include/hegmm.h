@@ -108,9 +108,11 @@ hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l
 hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B,
                          const int32_t *mln, hg_ct **C, void *stream);
 
-/* Decrypt a result made by hg_hegmm for shape (m, l, n) and unpack it into
- * C (row-major m x n, values in [0, t)).  Synchronises the device.
- * Errors: HG_EINVAL, HG_ESTATE. */
+/* Decrypt a result made by hg_hegmm for shape (m, l, n) -- or the
+ * hg_ct_import (one ciphertext, two components) of its exported words, such
+ * as a served result -- and unpack it into C (row-major m x n, values in
+ * [0, t)).  Synchronises the device.  Errors: HG_EINVAL (a packed operand or
+ * a result of another shape), HG_ESTATE. */
 hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ctC, int m, int l, int n, uint64_t *C);
 
 /* Canonical serialisation: coefficient form, residues in [0, q_i), the
@@ -212,6 +214,9 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
 
 /* Set an execution knob of the context (used by the autotuner; results are
  * bit-identical for every setting).  Names:
+ *   "pipeline"   chunks (1..16) of a pass whose inner products overlap the
+ *                division by P of the previous chunk on a second stream
+ *                (1: no overlap, one stream)
  *   "fuse_rows"  passes with at most this many rows per transform chain run
  *                the fused one-workgroup-per-row kernels (alpha = 1 only)
  *   "ip_chunk"   jobs per workgroup of the key-stationary inner products;
@@ -232,13 +237,16 @@ hg_status hg_plan_info(hg_ctx *ctx, int m, int l, int n, int64_t *out10);
 /* The primes of the context: out[0..L-1] = q_0.., out[L..L+alpha-1] = p_0.. */
 hg_status hg_primes(hg_ctx *ctx, uint64_t *out);
 
-/* Per-phase timing of the last hg_hegmm / hg_hegmm_batch call in
- * milliseconds, measured with HIP events on its stream (out[0..7]:
- * hoist, inner product, division by P, tensor/accumulate, relinearise,
- * fold, total, inner-product kernel alone).  Only filled when timing was
- * enabled with hg_set_timing(ctx, 1); synchronises the stream. */
+/* Per-phase timing of the last hg_hegmm / hg_hegmm_batch call (of its last
+ * launch window) in milliseconds, measured with HIP events on its stream
+ * (out[0..8]: hoist, inner products, division by P, tensor/accumulate,
+ * relinearise, fold, total, the mean duration of one inner-product launch of
+ * the transform pass, and the number of those launches).  With pipelining
+ * the inner-product and division phases overlap: out[1] ends with the last
+ * inner-product launch and out[2] with the last division.  Only filled when
+ * timing was enabled with hg_set_timing(ctx, 1); synchronises the stream. */
 hg_status hg_set_timing(hg_ctx *ctx, int enable);
-hg_status hg_last_timing(hg_ctx *ctx, double *out8);
+hg_status hg_last_timing(hg_ctx *ctx, double *out9);
 
 const char *hg_last_error(void);
 

@@ -277,9 +277,10 @@ class Context:
         _check(_lib.hg_set_timing(self.ptr, 1 if on else 0))
 
     def last_timing(self) -> dict:
-        out = np.zeros(8, dtype=np.float64)
+        out = np.zeros(9, dtype=np.float64)
         _check(_lib.hg_last_timing(self.ptr, out))
-        keys = ["hoist", "inner_product", "div_by_p", "tensor", "relin", "fold", "total", "ip_kernel"]
+        keys = ["hoist", "inner_product", "div_by_p", "tensor", "relin", "fold", "total", "ip_kernel",
+                "ip_launches"]
         return dict(zip(keys, (float(x) for x in out)))
 
     def request_footprint(self, m: int, l: int, n: int) -> int:

@@ -159,7 +159,10 @@ hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ct, int m, int l, int n, uint64_t
     return guard([&] {
         need(ctx && ct && C, "null argument");
         hg::Ctx &X = *ctx->c;
-        need(ct->c->side == 2 && ct->c->m == m && ct->c->l == l && ct->c->n == n, "not a result of this shape");
+        const hg::Ct &R = *ct->c;
+        const bool result = R.side == 2 && R.m == m && R.l == l && R.n == n;
+        const bool imported = R.side == -1 && R.ncts == 1 && R.comps == 2;   // hg_ct_import of a result
+        need(result || imported, "not a result of this shape");
         HGCHK(hipSetDevice(X.device));
         HGCHK(hipDeviceSynchronize());
         const hg::PlanEntry &pe = X.plan_for(m, l, n);
@@ -306,6 +309,10 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
         else if (n == "ip_chunk") X.ip_chunk = (int)value;
         else if (n == "split_rows") hg::ntt_set_split_rows((int)value);
         else if (n == "batch_window") X.batch_window = (int)value;
+        else if (n == "pipeline") {
+            need(value >= 1 && value <= 16, "pipeline must be in [1, 16]");
+            X.pipeline = (int)value;
+        }
         else throw hg::Error(HG_EINVAL, "unknown tuning knob " + n);
     });
 }
@@ -317,10 +324,10 @@ hg_status hg_set_timing(hg_ctx *ctx, int enable) {
     });
 }
 
-hg_status hg_last_timing(hg_ctx *ctx, double *out8) {
+hg_status hg_last_timing(hg_ctx *ctx, double *out9) {
     return guard([&] {
-        need(ctx && out8, "null argument");
-        for (int i = 0; i < 8; ++i) out8[i] = ctx->c->timing.ms[i];
+        need(ctx && out9, "null argument");
+        for (int i = 0; i < 9; ++i) out9[i] = ctx->c->timing.ms[i];
     });
 }
 

@@ -177,6 +177,11 @@ Ctx::~Ctx() {
         if (kv.second.pinned) (void)hipHostFree(kv.second.pinned);
         if (kv.second.staged) (void)hipEventDestroy(kv.second.staged);
     }
+    for (auto &kv : aux) {
+        for (auto &ring : kv.second.ev)
+            for (hipEvent_t e : ring) (void)hipEventDestroy(e);
+        if (kv.second.side) (void)hipStreamDestroy(kv.second.side);
+    }
     for (auto &kv : mask_cache) (void)hipFree(kv.second);
     for (auto &kv : rot_keys) (void)hipFree(kv.second);
     if (relin_key) (void)hipFree(relin_key);
@@ -189,6 +194,31 @@ double *Ctx::dev_alloc(size_t words) {
     void *p = nullptr;
     HGCHK(hipMalloc(&p, std::max<size_t>(words, 32) * sizeof(double)));
     return (double *)p;
+}
+
+hipStream_t Ctx::side_stream(hipStream_t st) {
+    StreamAux &a = aux[st];
+    if (!a.side) HGCHK(hipStreamCreateWithFlags(&a.side, hipStreamNonBlocking));
+    return a.side;
+}
+
+hipEvent_t Ctx::event(hipStream_t st, bool timing) {
+    // a ring per kind: an event is re-recorded only after 512 others, long
+    // after every wait on its earlier record was enqueued and every timing
+    // pair read back (a timed call synchronises at its end)
+    constexpr size_t RING = 512;
+    StreamAux &a = aux[st];
+    auto &ring = a.ev[timing ? 1 : 0];
+    size_t &nx = a.next[timing ? 1 : 0];
+    if (ring.size() < RING) {
+        hipEvent_t e;
+        HGCHK(hipEventCreateWithFlags(&e, timing ? hipEventDefault : hipEventDisableTiming));
+        ring.push_back(e);
+        return e;
+    }
+    hipEvent_t e = ring[nx];
+    nx = (nx + 1) % RING;
+    return e;
 }
 
 Arena &Ctx::arena(hipStream_t st) {

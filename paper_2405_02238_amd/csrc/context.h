@@ -57,7 +57,16 @@ struct Arena {
 
 struct Timing {
     bool enabled = false;
-    double ms[8] = {0};
+    double ms[9] = {0};
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ip_pairs;   // transform-pass inner-product launches
+};
+
+// Per user stream: the second stream of the pipelined passes and two rings
+// of reusable events (ordering, timing).
+struct StreamAux {
+    hipStream_t side = nullptr;
+    std::vector<hipEvent_t> ev[2];
+    size_t next[2] = {0, 0};
 };
 
 struct Ctx {
@@ -86,6 +95,10 @@ struct Ctx {
     int fuse_rows = 512;  // passes with at most this many rows per chain use the fused kernels
     int ip_chunk = 0;     // jobs per workgroup in the key-stationary inner products (0: off)
     int batch_window = 64; // products per launch group in hegmm_batch (0: all)
+    int pipeline = 1;      // chunks of a pass whose inner products and division by P overlap (1: off)
+    std::map<hipStream_t, StreamAux> aux;
+    hipStream_t side_stream(hipStream_t st);
+    hipEvent_t event(hipStream_t st, bool timing);
 
     Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device);
     ~Ctx();

@@ -276,17 +276,55 @@ struct Exec {
         HGCHK(hipEventRecord(A.staged, st));
     }
 
+    // Division by P of the key-switched jobs [j0, j1) of a staged pass.
+    void moddown(const Dev &dv, int j0, int j1, bool fuse, hipStream_t s) {
+        const int nj = j1 - j0;
+        if (nj <= 0) return;
+        double *U = dv.U + (size_t)j0 * 2 * nExt * N;
+        double *E = dv.E + (size_t)j0 * 2 * L * N;
+        if (fuse) {
+            moddown_fused(T, E, U, nj * 2, s);
+            return;
+        }
+        double *rk = dv.rk + (size_t)j0 * 2 * alpha * N;
+        NttArgs md;
+        md.out = rk;
+        md.in = U;
+        md.rows = nj * 2 * alpha;
+        md.per = alpha;
+        md.prime_base = L;
+        md.out_stride = (long long)alpha * N;
+        md.in_stride = (long long)nExt * N;
+        md.in_offset = (long long)L * N;
+        ntt_inv(T, STORE_MDR, md, s);
+        NttArgs dl;
+        dl.out = E;
+        dl.in = rk;
+        dl.aux = U;
+        dl.rows = nj * 2 * L;
+        dl.in_stride = (long long)alpha * N;
+        ntt_fwd(T, LOAD_DELTA, dl, s);
+    }
+
     // Phases 1-3 of a staged pass: hoist, inner products, division by P.
-    void launch(const Dev &dv, hipEvent_t *tev = nullptr, bool transform_pass = false) {
+    // With C.pipeline > 1 the key-switched jobs run in that many chunks: the
+    // inner products of chunk c+1 (bandwidth bound) overlap the division by
+    // P of chunk c (transform bound) on a second stream; `st` then waits for
+    // the last division.  Timing events (tev) bracket the phases on `st`;
+    // ip_ms accumulates the duration of each inner-product launch.
+    void launch(const Dev &dv, hipEvent_t *tev = nullptr, bool transform_pass = false, Timing *tm = nullptr) {
         // few rows: one fused launch per chain (latency bound); many rows:
         // separate launches (throughput bound)
         const bool fuse_hoist = fused_ok(T) && dv.nsrc * beta * nExt <= C.fuse_rows;
-        const bool fuse_md = fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows;
         if (dv.nks > 0 && fuse_hoist) {
             hoist_fused(T, dv.y, (const double *const *)(dv.tab + dv.t_srcs), dv.nsrc, st);
         }
-        if (dv.nks > 0) {
-            if (!fuse_hoist) {
+        if (dv.nks <= 0) {
+            if (tev)
+                for (int i = 0; i < 3; ++i) HGCHK(hipEventRecord(tev[i], st));
+            return;
+        }
+        if (!fuse_hoist) {
             // 1. hoist every source once: c1 -> coefficient form -> lifted digits
             NttArgs a;
             a.out = dv.coef;
@@ -301,46 +339,53 @@ struct Exec {
             mu.rows = dv.nsrc * beta * nExt;
             mu.in_stride = (long long)L * N;
             ntt_fwd(T, LOAD_MODUP, mu, st);
-            }
-            if (tev) HGCHK(hipEventRecord(tev[0], st));
-            // 2. inner products
-            if (dv.nchunks > 0)
-                ip_grouped_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
-                                  (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt),
-                                  (const int2 *)(dv.tab + dv.t_chunks), (const int *)(dv.tab + dv.t_jlist),
-                                  dv.nchunks, st);
-            else
-                ip_launch(T, dv.U, dv.y, (const double *const *)(dv.tab + dv.t_keys), dv.masks,
-                          (const IpJob *)(dv.tab + dv.t_ipj), (const IpTerm *)(dv.tab + dv.t_ipt), dv.nks,
-                          transform_pass, st);
-            if (tev) HGCHK(hipEventRecord(tev[1], st));
-            // 3. division by P
-            if (fuse_md) {
-                moddown_fused(T, dv.E, dv.U, dv.nks * 2, st);
-                if (tev) HGCHK(hipEventRecord(tev[2], st));
-                return;
-            }
-            NttArgs md;
-            md.out = dv.rk;
-            md.in = dv.U;
-            md.rows = dv.nks * 2 * alpha;
-            md.per = alpha;
-            md.prime_base = L;
-            md.out_stride = (long long)alpha * N;
-            md.in_stride = (long long)nExt * N;
-            md.in_offset = (long long)L * N;
-            ntt_inv(T, STORE_MDR, md, st);
-            NttArgs dl;
-            dl.out = dv.E;
-            dl.in = dv.rk;
-            dl.aux = dv.U;
-            dl.rows = dv.nks * 2 * L;
-            dl.in_stride = (long long)alpha * N;
-            ntt_fwd(T, LOAD_DELTA, dl, st);
-            if (tev) HGCHK(hipEventRecord(tev[2], st));
-        } else if (tev) {
-            for (int i = 0; i < 3; ++i) HGCHK(hipEventRecord(tev[i], st));
         }
+        if (tev) HGCHK(hipEventRecord(tev[0], st));
+        const double *const *keys = (const double *const *)(dv.tab + dv.t_keys);
+        const IpJob *jobs = (const IpJob *)(dv.tab + dv.t_ipj);
+        const IpTerm *terms = (const IpTerm *)(dv.tab + dv.t_ipt);
+        // 2. inner products
+        if (dv.nchunks > 0) {
+            ip_grouped_launch(T, dv.U, dv.y, keys, dv.masks, jobs, terms, (const int2 *)(dv.tab + dv.t_chunks),
+                              (const int *)(dv.tab + dv.t_jlist), dv.nchunks, st);
+            if (tev) HGCHK(hipEventRecord(tev[1], st));
+            moddown(dv, 0, dv.nks, fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows, st);
+            if (tev) HGCHK(hipEventRecord(tev[2], st));
+            return;
+        }
+        const int nch = std::max(1, std::min(C.pipeline, dv.nks));
+        // a chunk's division by P is fused when the chunk is small enough
+        const int per_chunk = (dv.nks + nch - 1) / nch;
+        const bool fuse_md = fused_ok(T) && per_chunk * 2 * L <= C.fuse_rows;
+        hipStream_t s2 = nch > 1 ? C.side_stream(st) : st;
+        for (int c = 0; c < nch; ++c) {
+            const int j0 = (int)((long long)dv.nks * c / nch), j1 = (int)((long long)dv.nks * (c + 1) / nch);
+            hipEvent_t t0 = nullptr, t1 = nullptr;
+            if (tm) {
+                t0 = C.event(st, true);
+                t1 = C.event(st, true);
+                HGCHK(hipEventRecord(t0, st));
+            }
+            ip_launch(T, dv.U + (size_t)j0 * 2 * nExt * N, dv.y, keys, dv.masks, jobs + j0, terms, j1 - j0,
+                      transform_pass, st);
+            if (tm) {
+                HGCHK(hipEventRecord(t1, st));
+                tm->ip_pairs.push_back({t0, t1});
+            }
+            if (s2 != st) {
+                hipEvent_t ev = C.event(st, false);
+                HGCHK(hipEventRecord(ev, st));
+                HGCHK(hipStreamWaitEvent(s2, ev, 0));
+            }
+            moddown(dv, j0, j1, fuse_md, s2);
+        }
+        if (tev) HGCHK(hipEventRecord(tev[1], st));
+        if (s2 != st) {
+            hipEvent_t ev = C.event(st, false);
+            HGCHK(hipEventRecord(ev, s2));
+            HGCHK(hipStreamWaitEvent(st, ev, 0));
+        }
+        if (tev) HGCHK(hipEventRecord(tev[2], st));
     }
 
     // Stage and launch a single pass.
@@ -473,7 +518,8 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     ex.stage(sp);
 
     const Exec::Dev &dv = sp[0].dv;
-    ex.launch(dv, timing.enabled ? ev : nullptr, true);
+    timing.ip_pairs.clear();
+    ex.launch(dv, timing.enabled ? ev : nullptr, true, timing.enabled ? &timing : nullptr);
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
                       (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
@@ -502,7 +548,11 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
         timing.ms[4] = el(ev[3], ev[4]);
         timing.ms[5] = el(ev[4], ev[5]);
         timing.ms[6] = el(ev[9], ev[5]);
-        timing.ms[7] = timing.ms[1];
+        double ip = 0;
+        for (auto &pr : timing.ip_pairs) ip += el(pr.first, pr.second);
+        timing.ms[7] = timing.ip_pairs.empty() ? 0.0 : ip / timing.ip_pairs.size();
+        timing.ms[8] = (double)timing.ip_pairs.size();
+        timing.ip_pairs.clear();
         for (auto &x : ev) (void)hipEventDestroy(x);
     }
 }

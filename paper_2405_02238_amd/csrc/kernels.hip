@@ -14,6 +14,15 @@ constexpr int EW_THREADS = 256;
 
 constexpr int IP_THREADS = 256;
 
+// Two consecutive words read once per launch (key and mask streams): a
+// non-temporal load, so that the stream does not evict the hoisted digits
+// and ciphertext rows that every job gathers from L2.
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_stream2(const double *p) {
+    const dvec2 v = __builtin_nontemporal_load((const dvec2 *)p);
+    return make_double2(v.x, v.y);
+}
+
 // Key-switching inner products with the automorphism folded into the gather
 // of the hoisted digits; two consecutive positions per thread (16-byte key
 // loads), the digit loop unrolled (BETA digits) so that all key loads of a
@@ -38,7 +47,7 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const d
     for (int tix = J.t0; tix < J.t0 + J.nt; ++tix) {
         const IpTerm tm = terms[tix];
         double2 mv = make_double2(1.0, 1.0);
-        if (tm.mask >= 0) mv = *(const double2 *)(masks[tm.mask] + (size_t)r * N + p);
+        if (tm.mask >= 0) mv = ld_stream2(masks[tm.mask] + (size_t)r * N + p);
         const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
         const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
         if (tm.kind != IP_PLAIN) {
@@ -50,8 +59,8 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const d
             for (int j = 0; j < BETA; ++j) {
                 y0[j] = ys[(size_t)j * plane + pp0];
                 y1[j] = ys[(size_t)j * plane + pp1];
-                kbv[j] = *(const double2 *)(kb + (size_t)(2 * j) * plane);
-                kav[j] = *(const double2 *)(kb + (size_t)(2 * j + 1) * plane);
+                kbv[j] = ld_stream2(kb + (size_t)(2 * j) * plane);
+                kav[j] = ld_stream2(kb + (size_t)(2 * j + 1) * plane);
             }
             double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
 #pragma unroll

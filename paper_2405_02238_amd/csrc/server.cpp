@@ -58,6 +58,14 @@ Server::~Server() {
             if (it->second.staged) (void)hipEventDestroy(it->second.staged);
             C.arenas.erase(it);
         }
+        auto ax = C.aux.find(ln.st);
+        if (ax != C.aux.end()) {
+            if (ax->second.side) (void)hipStreamSynchronize(ax->second.side);
+            for (auto &ring : ax->second.ev)
+                for (hipEvent_t e : ring) (void)hipEventDestroy(e);
+            if (ax->second.side) (void)hipStreamDestroy(ax->second.side);
+            C.aux.erase(ax);
+        }
         if (ln.st) (void)hipStreamDestroy(ln.st);
     }
 }

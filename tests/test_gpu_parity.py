@@ -254,3 +254,43 @@ def test_serving_errors_and_budget():
     for o in outs:
         assert np.array_equal(ctx.decrypt(ctx.import_ct(o, 1, 2), 4, 3, 5),
                               workloads.plain_matmul_mod(A, B, c.t))
+
+
+def _sha(words):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
+
+
+def test_large_operands_and_product():
+    """128x96x128 at N = 32768 (8 + 2 primes, two-pass transforms): packed
+    operands bit-identical to the oracle's encryption, the product decrypts
+    to A.B mod t, and (when the oracle's digest file is present) the result
+    equals the oracle's bit for bit."""
+    import json
+    import os
+    c = workloads.LARGE
+    m, l, n = 128, 96, 128
+    A, B = workloads.large_operands()
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, [(m, l, n)])
+    ca = ctx.encrypt(0, A, m, l, n, nonce=1)
+    cb = ctx.encrypt(1, B, m, l, n, nonce=1)
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ks = bgv.KeySet(P, c.seed, [], relin=False)
+    pl = H.plan(m, l, n, P.S)
+    assert not pl.transposed
+    assert np.array_equal(ca.export(), np.concatenate([flat(x) for x in H.encrypt_operand(ks, pl, 0, A, B, 1)]))
+    assert np.array_equal(cb.export(), np.concatenate([flat(y) for y in H.encrypt_operand(ks, pl, 1, A, B, 1)]))
+    cc = ctx.hegmm(ca, cb, m, l, n)
+    w = cc.export()
+    assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "large_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip("oracle digest of the large product not generated (tests/golden/make_large_golden.py)")
+    g = json.load(open(path))
+    assert g["nonce"] == 1 and g["seed"] == c.seed
+    assert _sha(ca.export()) == g["left_operand_sha256"]
+    assert w.size == g["result_words"]
+    for i, v in g["result_samples"].items():
+        assert int(w[int(i)]) == v, i
+    assert _sha(w) == g["result_sha256"]
