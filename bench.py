@@ -283,7 +283,8 @@ def run_large(args):
         "config": {"workload": "HEGMM-En A(128x96) x B(96x128), BGV N=32768 t=786433 L=8 alpha=2, "
                                "entries in [-4,4], one ciphertext per operand (16384 of 16384 slots)"},
         "bit_exact": bit_exact, "decrypt_ok": ok, "key_switches_per_matmul": info["ks_terms"] + 1,
-        "rotations_per_s": value * info["ks_terms"], "phase_ms": phases,
+        "rotations_per_s": value * info["ks_terms"],
+        "phase_ms": phases,
         "roofline": {"kernel": "k_ip (key-switch inner products)", "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "algorithmic_bytes_per_launch": ip_bytes, "avg_launch_ms": phases["ip_kernel"]}}), flush=True)
@@ -390,6 +391,20 @@ def main():
     ip_bytes = ip_kernel_bytes(ctx, info, cfg.N, cfg.L, cfg.alpha, nsrc=2, launches=launches)
     achieved = ip_bytes / (ip_ms * 1e-3) / 1e9
 
+    # standalone (non-hoisted) rotations: one hg_rotate per rotation amount of
+    # the plan (eps^k: z = kM and (k - l)M; omega^k: z = k and k - l; k = 1..K-1)
+    M = info["M"]
+    zs = [z for k in range(1, info["K"]) for z in (k * M, (k - l) * M, k, k - l)]
+    ct1 = ctx.encrypt_slots(np.arange(ctx.S) % cfg.t, nonce=77)
+    rots = [ctx.rotate(ct1, z) for z in zs[:8]]   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        rots = [ctx.rotate(ct1, z) for z in zs]
+    torch.cuda.synchronize()
+    rot_standalone = 3 * len(zs) / (time.perf_counter() - t0)
+    del rots
+
     value = 1000.0 / ms_per_step if (decrypt_ok and bit_exact is not False) else 0.0
     out = {
         "metric": "HE matmuls/sec (bit-exact) at N=8192 64x32x48",
@@ -413,6 +428,8 @@ def main():
         "repeat_identical": same_all,
         "key_switches_per_matmul": ks_per_matmul,
         "rotations_per_s": value * info["ks_terms"],
+        "rotations_per_s_standalone": rot_standalone,
+        "rotation_amounts": len(zs),
         "phase_ms": phases,
         "roofline": {"kernel": "k_ip<4,0> (transform-pass key-switch inner products)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

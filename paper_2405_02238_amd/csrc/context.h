@@ -93,7 +93,7 @@ struct Ctx {
     std::map<hipStream_t, Arena> arenas;
     Timing timing;
     int fuse_rows = 512;  // passes with at most this many rows per chain use the fused kernels
-    int ip_chunk = 0;     // jobs per workgroup in the key-stationary inner products (0: off)
+    int ip_chunk = 16;    // terms sharing a key per workgroup in the key-stationary inner products (0: off)
     int batch_window = 64; // products per launch group in hegmm_batch (0: all)
     int pipeline = 1;      // chunks of a pass whose inner products and division by P overlap (1: off)
     std::map<hipStream_t, StreamAux> aux;

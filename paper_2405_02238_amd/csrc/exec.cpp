@@ -130,8 +130,9 @@ struct Exec {
         char *extra = nullptr;   // caller-requested table space
         // internal
         char *tab = nullptr;
-        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_srcs = 0, t_chunks = 0, t_jlist = 0;
-        int nchunks = 0;   // > 0: key-stationary inner products over job groups
+        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_srcs = 0, t_chunks = 0, t_tasks = 0;
+        int nchunks = 0;          // > 0: key-stationary inner products
+        std::vector<int> rounds;  // first chunk of each round, then the chunk count
         double *coef = nullptr, *y = nullptr, *rk = nullptr;
         int nsrc = 0, nks = 0;
     };
@@ -143,37 +144,45 @@ struct Exec {
         Dev dv;
     };
 
-    // Group a pass's key-switched jobs by their tuple of (kind, Galois element,
-    // key) terms so that one workgroup reads each tuple's keys once for many
-    // jobs.  Returns false (ungrouped launch) when groups would not repeat or a
-    // job has more than two key-switched terms.
-    bool group_jobs(const Pass &ps, std::vector<int2> &chunks, std::vector<int> &jlist) {
+    // Key-stationary schedule of a pass's key-switched terms: round s takes
+    // the s-th key-switched term of every job that has one; within a round,
+    // tasks (job, term) with the same key form chunks of at most ip_chunk.
+    // rounds[s] is the first chunk of round s (rounds.back() = chunk count).
+    // Returns false (one plain launch) when key grouping is off or keys would
+    // be used fewer than twice on average.
+    bool group_jobs(const Pass &ps, std::vector<int2> &chunks, std::vector<int2> &tasks, std::vector<int> &rounds) {
         const int nj = (int)ps.ip_jobs.size();
-        if (C.ip_chunk <= 0 || nj < 2 || beta > 8) return false;
-        std::map<std::vector<int>, std::vector<int>> groups;
+        if (C.ip_chunk <= 0 || nj < 2) return false;
+        std::vector<std::map<int, std::vector<int2>>> by_round;   // round -> key -> tasks
         for (int j = 0; j < nj; ++j) {
             const IpJob &J = ps.ip_jobs[j];
-            std::vector<int> key;
-            for (int t = 0; t < J.nt; ++t) {
-                const IpTerm &tm = ps.ip_terms[J.t0 + t];
-                key.push_back(tm.kind);
-                key.push_back(tm.kind == IP_PLAIN ? 0 : tm.g);
-                key.push_back(tm.kind == IP_PLAIN ? 0 : tm.key);
-            }
-            int ks = 0;
-            for (int t = 0; t < J.nt; ++t) ks += ps.ip_terms[J.t0 + t].kind != IP_PLAIN;
-            if (ks > 2) return false;
-            groups[key].push_back(j);
-        }
-        if ((int)groups.size() * 4 > nj * 3) return false;   // little reuse: plain launch
-        for (auto &kv : groups) {
-            const auto &v = kv.second;
-            for (size_t o = 0; o < v.size(); o += C.ip_chunk) {
-                const int cnt = (int)std::min<size_t>(C.ip_chunk, v.size() - o);
-                chunks.push_back(make_int2((int)jlist.size(), cnt));
-                jlist.insert(jlist.end(), v.begin() + o, v.begin() + o + cnt);
+            int s = 0;
+            for (int t = J.t0; t < J.t0 + J.nt; ++t) {
+                const IpTerm &tm = ps.ip_terms[t];
+                if (tm.kind == IP_PLAIN) continue;
+                if ((int)by_round.size() <= s) by_round.emplace_back();
+                by_round[s][tm.key].push_back(make_int2(j, t));
+                ++s;
             }
         }
+        size_t groups = 0, ntask = 0;
+        for (auto &rd : by_round) {
+            groups += rd.size();
+            for (auto &kv : rd) ntask += kv.second.size();
+        }
+        if (groups * 2 > ntask) return false;   // keys used fewer than twice on average
+        for (auto &rd : by_round) {
+            rounds.push_back((int)chunks.size());
+            for (auto &kv : rd) {
+                const auto &v = kv.second;
+                for (size_t o = 0; o < v.size(); o += C.ip_chunk) {
+                    const int cnt = (int)std::min<size_t>(C.ip_chunk, v.size() - o);
+                    chunks.push_back(make_int2((int)tasks.size(), cnt));
+                    tasks.insert(tasks.end(), v.begin() + o, v.begin() + o + cnt);
+                }
+            }
+        }
+        rounds.push_back((int)chunks.size());
         return true;
     }
 
@@ -188,11 +197,13 @@ struct Exec {
         struct Off { size_t ipj, ipt, fj, ft, keys, masks, extra, srcs, chunks, jlist; };
         std::vector<Off> off(sp.size());
         std::vector<std::vector<int2>> chunks(sp.size());
-        std::vector<std::vector<int>> jlists(sp.size());
+        std::vector<std::vector<int2>> tasks(sp.size());
+        std::vector<std::vector<int>> rounds(sp.size());
         for (size_t i = 0; i < sp.size(); ++i)
-            if (!group_jobs(*sp[i].ps, chunks[i], jlists[i])) {
+            if (!group_jobs(*sp[i].ps, chunks[i], tasks[i], rounds[i])) {
                 chunks[i].clear();
-                jlists[i].clear();
+                tasks[i].clear();
+                rounds[i].clear();
             }
         for (size_t i = 0; i < sp.size(); ++i) {
             Pass &ps = *sp[i].ps;
@@ -214,7 +225,7 @@ struct Exec {
             o.extra = tl.add(sp[i].extra_bytes);
             o.srcs = tl.add(ps.srcs.size() * sizeof(void *));
             o.chunks = tl.add(chunks[i].size() * sizeof(int2));
-            o.jlist = tl.add(jlists[i].size() * sizeof(int));
+            o.jlist = tl.add(tasks[i].size() * sizeof(int2));
         }
         tl.add(256);   // never empty
         const size_t total = scratch + tl.total;
@@ -249,11 +260,12 @@ struct Exec {
             put(o.extra, sp[i].extra, sp[i].extra_bytes);
             put(o.srcs, ps.srcs.data(), ps.srcs.size() * sizeof(void *));
             put(o.chunks, chunks[i].data(), chunks[i].size() * sizeof(int2));
-            put(o.jlist, jlists[i].data(), jlists[i].size() * sizeof(int));
+            put(o.jlist, tasks[i].data(), tasks[i].size() * sizeof(int2));
             Dev &dv = sp[i].dv;
             dv.t_chunks = o.chunks;
-            dv.t_jlist = o.jlist;
+            dv.t_tasks = o.jlist;
             dv.nchunks = (int)chunks[i].size();
+            dv.rounds = rounds[i];
             dv.tab = tab;
             dv.jobs = (FinJob *)(tab + o.fj);
             dv.terms = (FinTerm *)(tab + o.ft);
@@ -346,8 +358,22 @@ struct Exec {
         const IpTerm *terms = (const IpTerm *)(dv.tab + dv.t_ipt);
         // 2. inner products
         if (dv.nchunks > 0) {
-            ip_grouped_launch(T, dv.U, dv.y, keys, dv.masks, jobs, terms, (const int2 *)(dv.tab + dv.t_chunks),
-                              (const int *)(dv.tab + dv.t_jlist), dv.nchunks, st);
+            const int2 *chunks = (const int2 *)(dv.tab + dv.t_chunks);
+            for (size_t s = 0; s + 1 < dv.rounds.size(); ++s) {
+                hipEvent_t t0 = nullptr, t1 = nullptr;
+                if (tm) {
+                    t0 = C.event(st, true);
+                    t1 = C.event(st, true);
+                    HGCHK(hipEventRecord(t0, st));
+                }
+                ip_keyed_launch(T, dv.U, dv.y, keys, dv.masks, jobs, terms, chunks + dv.rounds[s],
+                                (const int2 *)(dv.tab + dv.t_tasks), dv.rounds[s + 1] - dv.rounds[s], s == 0,
+                                transform_pass, st);
+                if (tm) {
+                    HGCHK(hipEventRecord(t1, st));
+                    tm->ip_pairs.push_back({t0, t1});
+                }
+            }
             if (tev) HGCHK(hipEventRecord(tev[1], st));
             moddown(dv, 0, dv.nks, fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows, st);
             if (tev) HGCHK(hipEventRecord(tev[2], st));
@@ -372,6 +398,7 @@ struct Exec {
                 HGCHK(hipEventRecord(t1, st));
                 tm->ip_pairs.push_back({t0, t1});
             }
+            if (tev && c == nch - 1) HGCHK(hipEventRecord(tev[1], st));
             if (s2 != st) {
                 hipEvent_t ev = C.event(st, false);
                 HGCHK(hipEventRecord(ev, st));
@@ -379,7 +406,6 @@ struct Exec {
             }
             moddown(dv, j0, j1, fuse_md, s2);
         }
-        if (tev) HGCHK(hipEventRecord(tev[1], st));
         if (s2 != st) {
             hipEvent_t ev = C.event(st, false);
             HGCHK(hipEventRecord(ev, s2));

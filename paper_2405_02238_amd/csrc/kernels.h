@@ -121,11 +121,13 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
                bool transform_pass, hipStream_t s);
 
-// Key-stationary variant: chunks[c] = (offset into job_list, count) of jobs
-// sharing one tuple of key-switched terms (at most two per job, beta <= 8).
-void ip_grouped_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-                       const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
-                       const int *job_list, int nchunks, hipStream_t s);
+// Key-stationary variant, one launch per round of key-switched terms:
+// tasks[i] = (job, term); chunks[c] = (first task, count), all tasks of a
+// chunk share one key and no job appears twice in a round.  The first round
+// writes U (adding each job's unswitched part), later rounds add to it.
+void ip_keyed_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+                     const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
+                     const int2 *tasks, int nchunks, bool first_round, bool transform_pass, hipStream_t s);
 
 // Tensor-accumulate: per request, sum over its (eps job, omega job) pairs of
 // the tensor product of the two finished transforms (E slots or plain terms).

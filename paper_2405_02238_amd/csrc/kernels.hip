@@ -2,6 +2,8 @@
 // inner products, the division by P, tensor accumulation, sampling.
 #include "kernels.h"
 
+#include <algorithm>
+
 #include "arith.h"
 #include "dev_common.h"
 #include "gauss_cdt.h"
@@ -13,6 +15,8 @@ namespace {
 constexpr int EW_THREADS = 256;
 
 constexpr int IP_THREADS = 256;
+
+constexpr int MAX_GRID_Z = 65535;   // launches with more z blocks are split
 
 // Two consecutive words read once per launch (key and mask streams): a
 // non-temporal load, so that the stream does not evict the hoisted digits
@@ -117,16 +121,20 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const d
     *(double2 *)(u + plane) = make_double2(a1x, a1y);
 }
 
-// Key-stationary inner products for batches: jobs that key-switch with the
-// same tuple of (Galois element, key) terms share a group; one workgroup
-// loads the group's key words for its positions once and loops over up to a
-// chunk of the group's jobs, each with its own source digits, masks and c0.
-// chunks[c] = (first index into job_list, count); the group's term layout is
-// that of its first job.  At most two key-switched terms per job.
-template <int BETA>
+// Key-stationary inner products for batches.  The key-switched terms of a
+// pass are split into rounds: round s holds the s-th key-switched term of
+// every job that has one.  Within a round, terms that use the same key form
+// chunks; one workgroup loads the chunk's key words at its positions once
+// and applies them to every term of the chunk (each with its own job's
+// hoisted digits and mask).  Round 0 also adds each job's unswitched part
+// (P * masked c0 of every term, and c1 of unrotated terms) and writes U;
+// later rounds add to U.  A job appears at most once per round, so no two
+// workgroups of a launch write the same words.  tasks[i] = (job, term);
+// chunks[c] = (first task, count), all of one key.
+template <int BETA, int TAG>
 __global__ void __launch_bounds__(IP_THREADS)
-k_ip_grouped(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
-             const IpJob *jobs, const IpTerm *terms, const int2 *chunks, const int *job_list) {
+k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
+           const IpJob *jobs, const IpTerm *terms, const int2 *chunks, const int2 *tasks, int first_round) {
     const int N = 1 << T.logN;
     const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     const int r = blockIdx.y;
@@ -135,93 +143,91 @@ k_ip_grouped(DevTables T, double *U, const double *y, const double *const *keys,
     const size_t plane = (size_t)T.nExt * N;
     const bool qrow = r < T.L;
     const int2 ch = chunks[blockIdx.z];
-    const IpJob J0 = jobs[job_list[ch.x]];
-    // the group's key words at (r, p, p+1)
-    double2 kb[2][BETA], ka[2][BETA];
-    int kt[2] = {-1, -1};   // term positions (within a job) of the key-switched terms
-    int nk = 0;
-    for (int t = 0; t < J0.nt && nk < 2; ++t) {
-        const IpTerm tm = terms[J0.t0 + t];
-        if (tm.kind == IP_PLAIN) continue;
-        kt[nk] = t;
-        const double *kp = keys[tm.key] + (size_t)r * N + p;
+    double2 kb[BETA], ka[BETA];
+    {
+        const double *kp = keys[terms[tasks[ch.x].y].key] + (size_t)r * N + p;
 #pragma unroll
         for (int j = 0; j < BETA; ++j) {
-            kb[nk][j] = *(const double2 *)(kp + (size_t)(2 * j) * plane);
-            ka[nk][j] = *(const double2 *)(kp + (size_t)(2 * j + 1) * plane);
+            kb[j] = ld_stream2(kp + (size_t)(2 * j) * plane);
+            ka[j] = ld_stream2(kp + (size_t)(2 * j + 1) * plane);
         }
-        ++nk;
     }
-    for (int e = 0; e < ch.y; ++e) {
-        const int job = job_list[ch.x + e];
-        const IpJob J = jobs[job];
-        double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
-        double c0x = 0.0, c0y = 0.0, c1x = 0.0, c1y = 0.0;
-        int ki = 0;
-        for (int t = 0; t < J.nt; ++t) {
-            const IpTerm tm = terms[J.t0 + t];
-            double2 mv = make_double2(1.0, 1.0);
-            if (tm.mask >= 0) mv = *(const double2 *)(masks[tm.mask] + (size_t)r * N + p);
-            const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
-            const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
-            if (tm.kind != IP_PLAIN) {
-                const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
-                double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
+    for (int e = ch.x; e < ch.x + ch.y; ++e) {
+        const int2 tk = tasks[e];
+        const IpJob J = jobs[tk.x];
+        const IpTerm tm = terms[tk.y];
+        const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
+        const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
+        const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
+        double y0[BETA], y1[BETA];
 #pragma unroll
-                for (int j = 0; j < BETA; ++j) {
-                    const double y0 = ys[(size_t)j * plane + pp0];
-                    const double y1 = ys[(size_t)j * plane + pp1];
-                    const double2 b = ki == 0 ? kb[0][j] : kb[1][j];
-                    const double2 a = ki == 0 ? ka[0][j] : ka[1][j];
-                    s0x += mulm(y0, b.x, q, qi);
-                    s0y += mulm(y1, b.y, q, qi);
-                    s1x += mulm(y0, a.x, q, qi);
-                    s1y += mulm(y1, a.y, q, qi);
-                }
-                ++ki;
-                s0x = redm(s0x, q, qi);
-                s0y = redm(s0y, q, qi);
-                s1x = redm(s1x, q, qi);
-                s1y = redm(s1y, q, qi);
-                if (tm.mask >= 0) {
-                    s0x = mulm(s0x, mv.x, q, qi);
-                    s0y = mulm(s0y, mv.y, q, qi);
-                    s1x = mulm(s1x, mv.x, q, qi);
-                    s1y = mulm(s1y, mv.y, q, qi);
-                }
-                a0x = redm(a0x + s0x, q, qi);
-                a0y = redm(a0y + s0y, q, qi);
-                a1x = redm(a1x + s1x, q, qi);
-                a1y = redm(a1y + s1y, q, qi);
-            }
-            if (qrow && tm.kind != IP_RELIN) {
-                double x0 = J.c0[(size_t)r * N + pp0], x1 = J.c0[(size_t)r * N + pp1];
-                if (tm.mask >= 0) {
-                    x0 = mulm(x0, mv.x, q, qi);
-                    x1 = mulm(x1, mv.y, q, qi);
-                }
-                c0x = redm(c0x + x0, q, qi);
-                c0y = redm(c0y + x1, q, qi);
-                if (tm.g == 1) {
-                    const double2 w = *(const double2 *)(J.c1 + (size_t)r * N + p);
-                    double z0 = w.x, z1 = w.y;
-                    if (tm.mask >= 0) {
-                        z0 = mulm(z0, mv.x, q, qi);
-                        z1 = mulm(z1, mv.y, q, qi);
+        for (int j = 0; j < BETA; ++j) {
+            y0[j] = ys[(size_t)j * plane + pp0];
+            y1[j] = ys[(size_t)j * plane + pp1];
+        }
+        double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
+#pragma unroll
+        for (int j = 0; j < BETA; ++j) {
+            a0x += mulm(y0[j], kb[j].x, q, qi);
+            a0y += mulm(y1[j], kb[j].y, q, qi);
+            a1x += mulm(y0[j], ka[j].x, q, qi);
+            a1y += mulm(y1[j], ka[j].y, q, qi);
+        }
+        a0x = redm(a0x, q, qi);
+        a0y = redm(a0y, q, qi);
+        a1x = redm(a1x, q, qi);
+        a1y = redm(a1y, q, qi);
+        if (tm.mask >= 0) {
+            const double2 mv = ld_stream2(masks[tm.mask] + (size_t)r * N + p);
+            a0x = mulm(a0x, mv.x, q, qi);
+            a0y = mulm(a0y, mv.y, q, qi);
+            a1x = mulm(a1x, mv.x, q, qi);
+            a1y = mulm(a1y, mv.y, q, qi);
+        }
+        double *u = U + (size_t)tk.x * 2 * plane + (size_t)r * N + p;
+        if (first_round) {
+            if (qrow) {
+                // unswitched part of the whole job
+                double c0x = 0.0, c0y = 0.0, c1x = 0.0, c1y = 0.0;
+                for (int t = J.t0; t < J.t0 + J.nt; ++t) {
+                    const IpTerm pt = terms[t];
+                    if (pt.kind == IP_RELIN) continue;
+                    double2 mv = make_double2(1.0, 1.0);
+                    if (pt.mask >= 0) mv = *(const double2 *)(masks[pt.mask] + (size_t)r * N + p);
+                    const int qq0 = pt.g == 1 ? p : perm_index(p, pt.g, T.logN);
+                    const int qq1 = pt.g == 1 ? p + 1 : perm_index(p + 1, pt.g, T.logN);
+                    double x0 = J.c0[(size_t)r * N + qq0], x1 = J.c0[(size_t)r * N + qq1];
+                    if (pt.mask >= 0) {
+                        x0 = mulm(x0, mv.x, q, qi);
+                        x1 = mulm(x1, mv.y, q, qi);
                     }
-                    c1x = redm(c1x + z0, q, qi);
-                    c1y = redm(c1y + z1, q, qi);
+                    c0x = redm(c0x + x0, q, qi);
+                    c0y = redm(c0y + x1, q, qi);
+                    if (pt.g == 1) {
+                        const double2 w = *(const double2 *)(J.c1 + (size_t)r * N + p);
+                        double z0 = w.x, z1 = w.y;
+                        if (pt.mask >= 0) {
+                            z0 = mulm(z0, mv.x, q, qi);
+                            z1 = mulm(z1, mv.y, q, qi);
+                        }
+                        c1x = redm(c1x + z0, q, qi);
+                        c1y = redm(c1y + z1, q, qi);
+                    }
                 }
+                const double P = T.pmod[r];
+                a0x = redm(a0x + mulm(c0x, P, q, qi), q, qi);
+                a0y = redm(a0y + mulm(c0y, P, q, qi), q, qi);
+                a1x = redm(a1x + mulm(c1x, P, q, qi), q, qi);
+                a1y = redm(a1y + mulm(c1y, P, q, qi), q, qi);
             }
+        } else {
+            const double2 u0 = *(const double2 *)u;
+            const double2 u1 = *(const double2 *)(u + plane);
+            a0x = redm(a0x + u0.x, q, qi);
+            a0y = redm(a0y + u0.y, q, qi);
+            a1x = redm(a1x + u1.x, q, qi);
+            a1y = redm(a1y + u1.y, q, qi);
         }
-        if (qrow) {
-            const double P = T.pmod[r];
-            a0x = redm(a0x + mulm(c0x, P, q, qi), q, qi);
-            a0y = redm(a0y + mulm(c0y, P, q, qi), q, qi);
-            a1x = redm(a1x + mulm(c1x, P, q, qi), q, qi);
-            a1y = redm(a1y + mulm(c1y, P, q, qi), q, qi);
-        }
-        double *u = U + (size_t)job * 2 * plane + (size_t)r * N + p;
         *(double2 *)u = make_double2(a0x, a0y);
         *(double2 *)(u + plane) = make_double2(a1x, a1y);
     }
@@ -514,6 +520,13 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, bool transform_pass,
                hipStream_t s) {
     if (njobs <= 0) return;
+    if (njobs > MAX_GRID_Z) {   // the z extent of a launch is limited: split
+        const size_t plane = (size_t)T.nExt * T.N;
+        for (int o = 0; o < njobs; o += MAX_GRID_Z)
+            ip_launch(T, U + (size_t)o * 2 * plane, y, keys, masks, jobs + o, terms, std::min(MAX_GRID_Z, njobs - o),
+                      transform_pass, s);
+        return;
+    }
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, njobs);
     switch (T.beta) {
 #define HG_IP_CASE(B)                                                                                        \
@@ -530,20 +543,31 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
     }
 }
 
-void ip_grouped_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-                       const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
-                       const int *job_list, int nchunks, hipStream_t s) {
+void ip_keyed_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+                     const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
+                     const int2 *tasks, int nchunks, bool first_round, bool transform_pass, hipStream_t s) {
     if (nchunks <= 0) return;
+    if (nchunks > MAX_GRID_Z) {
+        for (int o = 0; o < nchunks; o += MAX_GRID_Z)
+            ip_keyed_launch(T, U, y, keys, masks, jobs, terms, chunks + o, tasks, std::min(MAX_GRID_Z, nchunks - o),
+                            first_round, transform_pass, s);
+        return;
+    }
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, nchunks);
+    const int fr = first_round ? 1 : 0;
     switch (T.beta) {
-#define HG_IPG_CASE(B)                                                                                          \
-    case B:                                                                                                    \
-        hipLaunchKernelGGL(k_ip_grouped<B>, grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms, chunks, \
-                           job_list);                                                                          \
+#define HG_IPK_CASE(B)                                                                                        \
+    case B:                                                                                                  \
+        if (transform_pass)                                                                                  \
+            hipLaunchKernelGGL((k_ip_keyed<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, \
+                               terms, chunks, tasks, fr);                                                    \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_ip_keyed<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, \
+                               terms, chunks, tasks, fr);                                                    \
         break;
-        HG_IPG_CASE(1) HG_IPG_CASE(2) HG_IPG_CASE(3) HG_IPG_CASE(4) HG_IPG_CASE(5) HG_IPG_CASE(6)
-        HG_IPG_CASE(7) HG_IPG_CASE(8)
-#undef HG_IPG_CASE
+        HG_IPK_CASE(1) HG_IPK_CASE(2) HG_IPK_CASE(3) HG_IPK_CASE(4) HG_IPK_CASE(5) HG_IPK_CASE(6)
+        HG_IPK_CASE(7) HG_IPK_CASE(8) HG_IPK_CASE(9) HG_IPK_CASE(10) HG_IPK_CASE(11) HG_IPK_CASE(12)
+#undef HG_IPK_CASE
         default: break;
     }
 }
@@ -552,6 +576,11 @@ void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
                        const double *const *masks, const int2 *req_pairs, double *const *acc, int nreq,
                        hipStream_t s) {
     if (nreq <= 0) return;
+    if (nreq > MAX_GRID_Z) {
+        for (int o = 0; o < nreq; o += MAX_GRID_Z)
+            fin_tensor_launch(T, jobs, terms, E, masks, req_pairs + o, acc + o, std::min(MAX_GRID_Z, nreq - o), s);
+        return;
+    }
     dim3 grid((T.N + FT_P - 1) / FT_P, T.L, nreq);
     hipLaunchKernelGGL(k_fin_tensor, grid, dim3(FT_P, FT_C), 0, s, T, jobs, terms, E, masks, req_pairs, acc);
 }
@@ -559,6 +588,11 @@ void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
 void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,
                        const double *const *masks, double *const *out, int njobs, hipStream_t s) {
     if (njobs <= 0) return;
+    if (njobs > MAX_GRID_Z) {
+        for (int o = 0; o < njobs; o += MAX_GRID_Z)
+            fin_rotsum_launch(T, jobs + o, terms, E, masks, out + o, std::min(MAX_GRID_Z, njobs - o), s);
+        return;
+    }
     hipLaunchKernelGGL(k_fin_rotsum, ew_grid(T.N, T.L, njobs), dim3(EW_THREADS), 0, s, T, jobs, terms, E, masks,
                        out);
 }

@@ -28,7 +28,7 @@ namespace hg {
 namespace {
 
 constexpr int NTT_THREADS_MAX = 1024;
-constexpr int SPLIT_ELEMS = 1024;            // elements per workgroup in the split transform
+constexpr int SPLIT_ELEMS = 4096;            // elements per workgroup in the split transform
 constexpr int SPLIT_THREADS = SPLIT_ELEMS / 16;
 
 __device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
@@ -731,7 +731,7 @@ int ntt_threads(int N) {
 
 size_t ntt_lds_bytes(int N) { return (size_t)(N + N / 16) * sizeof(double); }
 
-int g_split_rows = 0;     // row counts below this use the split transform (N >= 2048); 0: only N > 16384
+int g_split_rows = 0;     // row counts below this use the split transform (N >= 8192); 0: only N > 16384
 
 bool use_split(const DevTables &T, int rows) {
     if (T.N > 16384) return true;

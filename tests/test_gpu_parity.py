@@ -294,3 +294,30 @@ def test_large_operands_and_product():
     for i, v in g["result_samples"].items():
         assert int(w[int(i)]) == v, i
     assert _sha(w) == g["result_sha256"]
+
+
+@pytest.mark.parametrize("alpha", [1, 2])
+def test_keyed_inner_products_bit_identical(alpha):
+    """The key-stationary schedule (terms grouped by key, one launch per
+    round of terms) gives the same bits as the plain inner products, on a
+    batch with repeated shapes, folds, transposition and blocking."""
+    c = workloads.TINY
+    # every shape three times, so that keys repeat (the schedule is used when
+    # a pass's keys are used at least twice on average)
+    shapes = [(2, 5, 7), (5, 4, 2), (3, 11, 6), (4, 3, 5), (7, 7, 7), (2, 9, 3)] * 3
+    ctx = hg.Context(c.N, c.t, 4 if alpha == 2 else c.L, alpha)
+    ctx.keygen(c.seed, shapes)
+    rng = np.random.default_rng(40 + alpha)
+    mats = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    As = [ctx.encrypt(0, A, *s, nonce=i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    Bs = [ctx.encrypt(1, B, *s, nonce=i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    ctx.tune("ip_chunk", 0)
+    plain = [o.export() for o in ctx.hegmm_batch(As, Bs, shapes)]
+    for chunk in (1, 3, 64):
+        ctx.tune("ip_chunk", chunk)
+        got = ctx.hegmm_batch(As, Bs, shapes)
+        for i, s in enumerate(shapes):
+            assert np.array_equal(got[i].export(), plain[i]), (chunk, s)
+    ctx.tune("ip_chunk", 0)
+    for i, (s, (A, B)) in enumerate(zip(shapes, mats)):
+        assert np.array_equal(ctx.decrypt(ctx.import_ct(plain[i], 1, 2), *s), workloads.plain_matmul_mod(A, B, c.t))
