@@ -33,6 +33,18 @@ constexpr int SPLIT_THREADS = SPLIT_ELEMS / 16;
 
 __device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
 
+// log2 of the radix of the whole-row transforms: each thread owns 2^RK
+// elements per round, so a row uses N / 2^RK threads.  Radix 8 for 4096- and
+// 8192-point rows (more waves per row to hide FP64 and LDS latency), radix
+// 16 otherwise.
+__host__ __device__ constexpr int rk_of(int logn) { return (logn == 12 || logn == 13) ? 3 : 4; }
+
+// Minimum waves per SIMD asked of the compiler for the row kernels: with
+// 1024-thread rows (8192 points) two rows fit a CU (LDS 2 x 70 KB) when each
+// thread keeps to 64 VGPRs, i.e. 8 waves per SIMD; other sizes keep the
+// default.
+__host__ __device__ constexpr int waves_of(int logn) { return logn == 13 ? 8 : 1; }
+
 // ---- whole rows with the size known at compile time ----
 // Round R of a 2^LOGN-point forward transform covers stages [S0, S0 + K).
 // Each thread owns a group of 2^K elements; all twiddles of the round are
@@ -84,7 +96,8 @@ __device__ __forceinline__ void fwd_round_c(double *sh, const double *__restrict
 template <int LOGN, int S0>
 __device__ __forceinline__ void fwd_rows_c(double *sh, const double *tw, double q, double qi) {
     if constexpr (S0 < LOGN) {
-        constexpr int K = (LOGN - S0) < 4 ? (LOGN - S0) : 4;
+        constexpr int RK = rk_of(LOGN);
+        constexpr int K = (LOGN - S0) < RK ? (LOGN - S0) : RK;
         fwd_round_c<LOGN, S0, K>(sh, tw, q, qi);
         __syncthreads();
         fwd_rows_c<LOGN, S0 + K>(sh, tw, q, qi);
@@ -134,18 +147,19 @@ __device__ __forceinline__ void inv_round_c(double *sh, const double *__restrict
 template <int LOGN, int LTS>
 __device__ __forceinline__ void inv_rows_c(double *sh, const double *tw, double q, double qi) {
     if constexpr (LTS < LOGN) {
-        constexpr int K = (LOGN - LTS) < 4 ? (LOGN - LTS) : 4;
+        constexpr int RK = rk_of(LOGN);
+        constexpr int K = (LOGN - LTS) < RK ? (LOGN - LTS) : RK;
         inv_round_c<LOGN, LTS, K>(sh, tw, q, qi);
         __syncthreads();
         inv_rows_c<LOGN, LTS + K>(sh, tw, q, qi);
     }
 }
 
-// Prefetching variant for one group per thread (blockDim = N / 16): the
+// Prefetching variant for one group per thread (blockDim = N / 2^RK): the
 // twiddles of round R+1 are loaded while round R computes.
 template <int LOGN, int S0>
 struct FwdRound {
-    static constexpr int K = (LOGN - S0) < 4 ? (LOGN - S0) : 4;
+    static constexpr int K = (LOGN - S0) < rk_of(LOGN) ? (LOGN - S0) : rk_of(LOGN);
     static constexpr int LTS = LOGN - S0 - K;
     static constexpr int NW = (1 << K) - 1;
     __device__ static __forceinline__ void load_tw(double *w, const double *__restrict__ tw, int grp) {
@@ -160,7 +174,7 @@ struct FwdRound {
 template <int LOGN, int S0>
 __device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict__ tw, double q, double qi, int grp,
                                             const double *wcur) {
-    if constexpr (S0 < LOGN && FwdRound<LOGN, S0>::K < 4) {
+    if constexpr (S0 < LOGN && FwdRound<LOGN, S0>::K < rk_of(LOGN)) {
         // a short tail round has more groups than threads: plain loop
         fwd_round_c<LOGN, S0, FwdRound<LOGN, S0>::K>(sh, tw, q, qi);
         __syncthreads();
@@ -174,7 +188,7 @@ __device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
         constexpr int S1 = S0 + K;
-        constexpr bool PF = S1 < LOGN && FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::K == 4;
+        constexpr bool PF = S1 < LOGN && FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::K == rk_of(LOGN);
         constexpr int NWN = PF ? FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::NW : 1;
         double wnext[NWN];
         if constexpr (PF) FwdRound<LOGN, S1>::load_tw(wnext, tw, grp);
@@ -205,7 +219,7 @@ __device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict
 
 template <int LOGN, int LTS0>
 struct InvRound {
-    static constexpr int K = (LOGN - LTS0) < 4 ? (LOGN - LTS0) : 4;
+    static constexpr int K = (LOGN - LTS0) < rk_of(LOGN) ? (LOGN - LTS0) : rk_of(LOGN);
     static constexpr int NW = (1 << K) - 1;
     __device__ static __forceinline__ void load_tw(double *w, const double *__restrict__ tw, int grp) {
         constexpr int N = 1 << LOGN;
@@ -223,7 +237,7 @@ struct InvRound {
 template <int LOGN, int LTS0>
 __device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict__ tw, double q, double qi, int grp,
                                             const double *wcur) {
-    if constexpr (LTS0 < LOGN && InvRound<LOGN, LTS0>::K < 4) {
+    if constexpr (LTS0 < LOGN && InvRound<LOGN, LTS0>::K < rk_of(LOGN)) {
         inv_round_c<LOGN, LTS0, InvRound<LOGN, LTS0>::K>(sh, tw, q, qi);
         __syncthreads();
     } else if constexpr (LTS0 < LOGN) {
@@ -236,7 +250,7 @@ __device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
         constexpr int L1 = LTS0 + K;
-        constexpr bool PF = L1 < LOGN && InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::K == 4;
+        constexpr bool PF = L1 < LOGN && InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::K == rk_of(LOGN);
         constexpr int NWN = PF ? InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::NW : 1;
         double wnext[NWN];
         if constexpr (PF) InvRound<LOGN, L1>::load_tw(wnext, tw, grp);
@@ -265,13 +279,13 @@ __device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict
 // completes (w0 filled by the caller).
 template <int LOGN>
 __device__ __forceinline__ void fwd_row_stages(double *sh, const double *tw, double q, double qi, const double *w0) {
-    if (blockDim.x == (1 << LOGN) / 16) fwd_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
+    if (blockDim.x == (1 << LOGN) >> rk_of(LOGN)) fwd_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
     else fwd_rows_c<LOGN, 0>(sh, tw, q, qi);
 }
 
 template <int LOGN>
 __device__ __forceinline__ void inv_row_stages(double *sh, const double *tw, double q, double qi, const double *w0) {
-    if (blockDim.x == (1 << LOGN) / 16) inv_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
+    if (blockDim.x == (1 << LOGN) >> rk_of(LOGN)) inv_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
     else inv_rows_c<LOGN, 0>(sh, tw, q, qi);
 }
 
@@ -506,14 +520,14 @@ __device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, i
 // ---- one workgroup per row ----
 
 template <int LOAD, int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX)
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
 k_ntt_fwd(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
     const FwdRow R = fwd_row<LOAD>(T, a, blockIdx.x);
     const double *tw = T.twf + (size_t)R.prime * N;
     double w0[FwdRound<LOGN, 0>::NW];
-    if (blockDim.x == N / 16 && FwdRound<LOGN, 0>::K == 4) FwdRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
+    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
@@ -522,14 +536,14 @@ k_ntt_fwd(DevTables T, NttArgs a) {
 }
 
 template <int STORE, int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX)
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
 k_ntt_inv(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
     const InvRow R = inv_row(T, a, blockIdx.x);
     const double *tw = T.twi + (size_t)R.prime * N;
     double w0[InvRound<LOGN, 0>::NW];
-    if (blockDim.x == N / 16 && InvRound<LOGN, 0>::K == 4) InvRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
+    if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = R.in[i];
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
@@ -649,7 +663,7 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
 // (the digit lift of a one-prime digit) and forward-transformed under prime
 // r, all in LDS.  Row r = j is the source row itself.
 template <int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX)
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
 k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
@@ -665,14 +679,14 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     }
     const double *twj = T.twi + (size_t)j * N;
     double wi[InvRound<LOGN, 0>::NW];
-    if (blockDim.x == N / 16 && InvRound<LOGN, 0>::K == 4) InvRound<LOGN, 0>::load_tw(wi, twj, threadIdx.x);
+    if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(wi, twj, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = c[i];
     __syncthreads();
     const double qj = T.qt[j].x, qij = T.qt[j].y;
     inv_row_stages<LOGN>(sh, twj, qj, qij, wi);
     const double *twr = T.twf + (size_t)r * N;
     double wf[FwdRound<LOGN, 0>::NW];
-    if (blockDim.x == N / 16 && FwdRound<LOGN, 0>::K == 4) FwdRound<LOGN, 0>::load_tw(wf, twr, threadIdx.x);
+    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(wf, twr, threadIdx.x);
     const double nj = T.ninv[j];
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int x = lds_ix(i);
@@ -688,7 +702,7 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
 // (slot, i): inverse transform of U's special row, exact centered r,
 // delta_i = t (P/p) r mod q_i, forward transform, E_i = (U_i - delta_i) P^-1.
 template <int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX)
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
 k_moddown_fused(DevTables T, double *E, const double *U) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
@@ -699,14 +713,14 @@ k_moddown_fused(DevTables T, double *E, const double *U) {
     const int pk = T.L;   // the special prime's index
     const double *twp = T.twi + (size_t)pk * N;
     double wi[InvRound<LOGN, 0>::NW];
-    if (blockDim.x == N / 16 && InvRound<LOGN, 0>::K == 4) InvRound<LOGN, 0>::load_tw(wi, twp, threadIdx.x);
+    if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(wi, twp, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
     __syncthreads();
     const double qp = T.qt[pk].x, qip = T.qt[pk].y;
     inv_row_stages<LOGN>(sh, twp, qp, qip, wi);
     const double *twq = T.twf + (size_t)iq * N;
     double wf[FwdRound<LOGN, 0>::NW];
-    if (blockDim.x == N / 16 && FwdRound<LOGN, 0>::K == 4) FwdRound<LOGN, 0>::load_tw(wf, twq, threadIdx.x);
+    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(wf, twq, threadIdx.x);
     const double q = T.qt[iq].x, qi = T.qt[iq].y;
     const double cf = T.md_coef[0], h = T.md_hat[iq];
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -723,7 +737,9 @@ k_moddown_fused(DevTables T, double *E, const double *U) {
 }
 
 int ntt_threads(int N) {
-    int t = N / 16;
+    int logn = 0;
+    while ((1 << logn) < N) ++logn;
+    int t = N >> rk_of(logn);
     if (t < 64) t = 64;
     if (t > NTT_THREADS_MAX) t = NTT_THREADS_MAX;
     return t;
