@@ -51,6 +51,7 @@ struct Arena {
     size_t cap = 0;
     size_t used = 0;
     void *pinned = nullptr;      // host staging for descriptor tables
+    void *pinned_dev = nullptr;  // the same memory as the device addresses it
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr; // completion of the last copy out of `pinned`
 };

@@ -240,6 +240,7 @@ struct Exec {
             if (A.pinned) HGCHK(hipHostFree(A.pinned));
             A.pinned_cap = align_up(tl.total * 2, 1 << 16);
             HGCHK(hipHostMalloc(&A.pinned, A.pinned_cap, hipHostMallocDefault));
+            HGCHK(hipHostGetDevicePointer(&A.pinned_dev, A.pinned, 0));
         }
         HGCHK(hipEventSynchronize(A.staged));   // the previous copy out of staging is done
         char *h = (char *)A.pinned;
@@ -284,7 +285,9 @@ struct Exec {
             dv.rk = (double *)(base + lay.add((size_t)dv.nks * 2 * alpha * N * 8));
             dv.E = (double *)(base + lay.add((size_t)dv.nks * 2 * L * N * 8));
         }
-        HGCHK(hipMemcpyAsync(tab, h, tl.total, hipMemcpyHostToDevice, st));
+        // a kernel reads the tables straight out of the pinned buffer: cheaper
+        // on the stream than a copy-engine transfer and its barrier
+        copy_from_host(tab, A.pinned_dev, tl.total, st);
         HGCHK(hipEventRecord(A.staged, st));
     }
 

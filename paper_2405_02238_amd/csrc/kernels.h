@@ -144,6 +144,8 @@ void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
 void kernels_init();
 
 // ---- utilities ----
+// Copy `bytes` (a multiple of 16) from device-mapped pinned host memory.
+void copy_from_host(void *dst, const void *src_host_mapped, size_t bytes, hipStream_t s);
 void u64_to_dbl(const uint64_t *in, double *out, size_t n, hipStream_t s);
 void dbl_to_u64(const double *in, uint64_t *out, size_t n, hipStream_t s);
 void mul_rows(const DevTables &T, double *out, const double *a, const double *b, int rows,

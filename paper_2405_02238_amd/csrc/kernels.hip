@@ -318,6 +318,11 @@ k_fin_rotsum(DevTables T, const FinJob *jobs, const FinTerm *terms, const double
     o[(size_t)T.L * N] = e1;
 }
 
+__global__ void k_copy16(uint4 *dst, const uint4 *src, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 __global__ void k_u64_to_dbl(const uint64_t *in, double *out, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (double)in[i];
@@ -595,6 +600,13 @@ void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
     }
     hipLaunchKernelGGL(k_fin_rotsum, ew_grid(T.N, T.L, njobs), dim3(EW_THREADS), 0, s, T, jobs, terms, E, masks,
                        out);
+}
+
+void copy_from_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    const size_t n = bytes / 16;
+    if (!n) return;
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint4 *)dst,
+                       (const uint4 *)src, n);
 }
 
 void u64_to_dbl(const uint64_t *in, double *out, size_t n, hipStream_t s) {
