@@ -92,8 +92,9 @@ def copy_probe(mib):
 def ip_kernel_bytes(ctx, plan_info, N, L, alpha, nsrc, launches=1):
     """Algorithmic HBM bytes of one transform-pass inner-product launch of one
     matmul whose key-switched transforms are split evenly over `launches`
-    launches: its share of the rotation keys (2 beta (L+alpha) N words each),
-    of the masks ((L+alpha) N words each) and of the U output (2 (L+alpha) N
+    launches: its share of the rotation keys (the stored b half, beta (L+alpha)
+    N words each; the a half is regenerated from its stream in registers), of
+    the masks ((L+alpha) N words each) and of the U output (2 (L+alpha) N
     words per transform), plus the hoisted digits of every source
     (beta (L+alpha) N words each), which every launch gathers from."""
     nExt = L + alpha
@@ -101,7 +102,7 @@ def ip_kernel_bytes(ctx, plan_info, N, L, alpha, nsrc, launches=1):
     ks_rot = plan_info["ks_terms"]           # rotation terms (without relin)
     masks = plan_info["masks"]
     jobs = 2 * (plan_info["K"] - 1) * plan_info["nb"]  # transforms that key-switch (k >= 1)
-    shared = (ks_rot * 2 * beta * nExt * N + masks * nExt * N + jobs * 2 * nExt * N) / launches
+    shared = (ks_rot * beta * nExt * N + masks * nExt * N + jobs * 2 * nExt * N) / launches
     return int(8 * (shared + nsrc * beta * nExt * N))
 
 

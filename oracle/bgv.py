@@ -36,7 +36,15 @@ class SecretKey:
 
 class SwitchKey:
     """Key switching from s' to s: per digit j a pair (b_j, a_j) over the
-    extended basis, kept in the oracle's evaluation form."""
+    extended basis, kept in the oracle's evaluation form.
+
+    a_j is sampled directly in the evaluation domain: its value at
+    psi_r^(2i+1) (prime r of the extended basis, natural index i, psi_r the
+    root of ring.primitive_2n_root) is the uniform draw r*N + i of the digit's
+    stream.  The evaluations of a uniform polynomial are uniform, so this is
+    the same distribution as sampling coefficients; it lets an evaluator
+    regenerate a_j from the stream instead of storing it.  The error e_j is
+    sampled in coefficient form (draws from nExt*N on) as before."""
 
     def __init__(self, P: Params, sk: SecretKey, s_prime_ext: np.ndarray, tag: int, idx_base: int):
         self.digits = []
@@ -46,9 +54,8 @@ class SwitchKey:
         nrow = P.L + P.alpha
         for j, (d0, d1) in enumerate(P.digits):
             s0 = ring.stream_seed(sk.master, tag, idx_base + j)
-            a = ring.sample_uniform(s0, 0, mod, P.N)
+            a_eval = ring.sample_uniform(s0, 0, mod, P.N)   # evaluation form, natural order
             e = ring.sample_gauss(P, s0, nrow * P.N)
-            a_eval = ring.ntt(a, mod, psi)
             # gadget factor: [P]_{q_i} on the digit's own primes, 0 elsewhere
             gadget = [(P.P % P.ext[r]) if d0 <= r < d1 else 0 for r in range(nrow)]
             te = ring.reduce_signed(e * P.t, mod)

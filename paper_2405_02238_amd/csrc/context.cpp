@@ -332,24 +332,27 @@ void Ctx::keygen(uint64_t seed_, const std::vector<int> &galois) {
     double *e_rows = dev_alloc((size_t)nExt * N);
     double *sp = dev_alloc((size_t)nExt * N);
 
+    // b_j = t e_j - a_j s + [P] s' (the last term on the digit's primes);
+    // a_j is the digit stream's uniform draws taken as evaluations (draw
+    // r N + i is the value at the i-th evaluation point, natural order), so
+    // it is never stored: the key-switching kernels regenerate it.
     auto make_key = [&](uint64_t tag, uint64_t idx_base, const double *sprime) -> double * {
         double *key = dev_alloc(key_words());
         const size_t plane = (size_t)nExt * N;
+        std::vector<uint64_t> streams(beta);
         for (int j = 0; j < beta; ++j) {
             const uint64_t s0 = stream_state(seed, tag, idx_base + (uint64_t)j);
-            double *b = key + (size_t)(2 * j) * plane;
-            double *a = key + (size_t)(2 * j + 1) * plane;
-            sample_uniform(T, a, s0, 0, nExt, 0, st);      // coefficient form, rows q..., p...
+            streams[j] = s0;
+            double *b = key + (size_t)j * plane;
             sample_small(e_small, s0, (uint64_t)nExt * N, N, 1, st);
             broadcast_rows(e_small, e_rows, N, nExt, st);
             NttArgs na;
             na.rows = nExt; na.per = nExt; na.out_stride = na.in_stride = (long long)plane;
-            na.out = a; na.in = a;
-            ntt_fwd(T, LOAD_PLAIN, na, st);
             na.out = e_rows; na.in = e_rows;
             ntt_fwd(T, LOAD_PLAIN, na, st);
-            keygen_combine(T, b, a, e_rows, s_eval, sprime, dgad + (size_t)j * nExt, st);
+            keygen_combine(T, b, s0, e_rows, s_eval, sprime, dgad + (size_t)j * nExt, st);
         }
+        key_streams[key] = streams;
         return key;
     };
     if (!relin_key) {

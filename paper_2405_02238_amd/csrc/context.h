@@ -83,9 +83,12 @@ struct Ctx {
     uint64_t seed = 0;
     double *s_eval = nullptr;     // nExt x N, evaluation form
     double *s2_eval = nullptr;    // L x N (s^2 over Q)
+    // A switching key keeps only b_j (beta planes of nExt x N, evaluation
+    // form); a_j is regenerated from its stream wherever it is needed.
     double *relin_key = nullptr;
+    std::map<const double *, std::vector<uint64_t>> key_streams;   // key -> beta stream states
     std::map<int, double *> rot_keys;   // Galois element -> key
-    size_t key_words() const { return (size_t)beta * 2 * nExt * N; }
+    size_t key_words() const { return (size_t)beta * nExt * N; }
 
     // plans and masks
     std::map<std::tuple<int, int, int>, std::unique_ptr<PlanEntry>> plans;

@@ -130,7 +130,7 @@ struct Exec {
         char *extra = nullptr;   // caller-requested table space
         // internal
         char *tab = nullptr;
-        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_srcs = 0, t_chunks = 0, t_tasks = 0;
+        size_t t_ipj = 0, t_ipt = 0, t_keys = 0, t_streams = 0, t_srcs = 0, t_chunks = 0, t_tasks = 0;
         int nchunks = 0;          // > 0: key-stationary inner products
         std::vector<int> rounds;  // first chunk of each round, then the chunk count
         double *coef = nullptr, *y = nullptr, *rk = nullptr;
@@ -194,7 +194,13 @@ struct Exec {
         size_t scratch = 0;
         std::vector<size_t> toff(sp.size());
         Layout tl;
-        struct Off { size_t ipj, ipt, fj, ft, keys, masks, extra, srcs, chunks, jlist; };
+        struct Off { size_t ipj, ipt, fj, ft, keys, streams, masks, extra, srcs, chunks, jlist; };
+        std::vector<std::vector<uint64_t>> streams(sp.size());
+        for (size_t i = 0; i < sp.size(); ++i)
+            for (const double *k : sp[i].ps->keys) {
+                const auto &ks = C.key_streams.at(k);
+                streams[i].insert(streams[i].end(), ks.begin(), ks.end());
+            }
         std::vector<Off> off(sp.size());
         std::vector<std::vector<int2>> chunks(sp.size());
         std::vector<std::vector<int2>> tasks(sp.size());
@@ -221,6 +227,7 @@ struct Exec {
             o.fj = tl.add(ps.fin_jobs.size() * sizeof(FinJob));
             o.ft = tl.add(ps.fin_terms.size() * sizeof(FinTerm));
             o.keys = tl.add(ps.keys.size() * sizeof(void *));
+            o.streams = tl.add(streams[i].size() * sizeof(uint64_t));
             o.masks = tl.add(ps.masks.size() * sizeof(void *));
             o.extra = tl.add(sp[i].extra_bytes);
             o.srcs = tl.add(ps.srcs.size() * sizeof(void *));
@@ -257,6 +264,7 @@ struct Exec {
             put(o.fj, ps.fin_jobs.data(), ps.fin_jobs.size() * sizeof(FinJob));
             put(o.ft, ps.fin_terms.data(), ps.fin_terms.size() * sizeof(FinTerm));
             put(o.keys, ps.keys.data(), ps.keys.size() * sizeof(void *));
+            put(o.streams, streams[i].data(), streams[i].size() * sizeof(uint64_t));
             put(o.masks, ps.masks.data(), ps.masks.size() * sizeof(void *));
             put(o.extra, sp[i].extra, sp[i].extra_bytes);
             put(o.srcs, ps.srcs.data(), ps.srcs.size() * sizeof(void *));
@@ -275,6 +283,7 @@ struct Exec {
             dv.t_ipj = o.ipj;
             dv.t_ipt = o.ipt;
             dv.t_keys = o.keys;
+            dv.t_streams = o.streams;
             dv.t_srcs = o.srcs;
             dv.nsrc = (int)ps.srcs.size();
             dv.nks = (int)ps.ip_jobs.size();
@@ -357,6 +366,7 @@ struct Exec {
         }
         if (tev) HGCHK(hipEventRecord(tev[0], st));
         const double *const *keys = (const double *const *)(dv.tab + dv.t_keys);
+        const uint64_t *streams = (const uint64_t *)(dv.tab + dv.t_streams);
         const IpJob *jobs = (const IpJob *)(dv.tab + dv.t_ipj);
         const IpTerm *terms = (const IpTerm *)(dv.tab + dv.t_ipt);
         // 2. inner products
@@ -369,7 +379,7 @@ struct Exec {
                     t1 = C.event(st, true);
                     HGCHK(hipEventRecord(t0, st));
                 }
-                ip_keyed_launch(T, dv.U, dv.y, keys, dv.masks, jobs, terms, chunks + dv.rounds[s],
+                ip_keyed_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs, terms, chunks + dv.rounds[s],
                                 (const int2 *)(dv.tab + dv.t_tasks), dv.rounds[s + 1] - dv.rounds[s], s == 0,
                                 transform_pass, st);
                 if (tm) {
@@ -395,7 +405,7 @@ struct Exec {
                 t1 = C.event(st, true);
                 HGCHK(hipEventRecord(t0, st));
             }
-            ip_launch(T, dv.U + (size_t)j0 * 2 * nExt * N, dv.y, keys, dv.masks, jobs + j0, terms, j1 - j0,
+            ip_launch(T, dv.U + (size_t)j0 * 2 * nExt * N, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0,
                       transform_pass, st);
             if (tm) {
                 HGCHK(hipEventRecord(t1, st));

@@ -70,10 +70,12 @@ inline std::vector<u64> find_ntt_primes(u64 N, int count, int bits = 50) {
 }
 
 // A primitive 2N-th root of unity mod prime p (p = 1 mod 2N): x^((p-1)/2N)
-// for the first x >= 3 whose power has order exactly 2N.
+// for the first x >= 2 whose power has order exactly 2N.  The root fixes the
+// evaluation points, and key a_j values are drawn directly as evaluations,
+// so this rule is part of the key convention.
 inline u64 find_psi(u64 p, u64 N) {
     u64 e = (p - 1) / (2 * N);
-    for (u64 x = 3;; ++x) {
+    for (u64 x = 2;; ++x) {
         u64 w = hpow(x, e, p);
         if (hpow(w, N, p) == p - 1) return w;
     }

@@ -117,7 +117,7 @@ void ntt_set_split_rows(int rows);
 // Inner products: U[job][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
 // the unswitched part on the ciphertext primes (see IpTerm).
-void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
                bool transform_pass, hipStream_t s);
 
@@ -126,8 +126,9 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
 // chunk share one key and no job appears twice in a round.  The first round
 // writes U (adding each job's unswitched part), later rounds add to it.
 void ip_keyed_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-                     const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
-                     const int2 *tasks, int nchunks, bool first_round, bool transform_pass, hipStream_t s);
+                     const uint64_t *streams, const double *const *masks, const IpJob *jobs, const IpTerm *terms,
+                     const int2 *chunks, const int2 *tasks, int nchunks, bool first_round, bool transform_pass,
+                     hipStream_t s);
 
 // Tensor-accumulate: per request, sum over its (eps job, omega job) pairs of
 // the tensor product of the two finished transforms (E slots or plain terms).
@@ -175,7 +176,7 @@ void automorph_rows(const DevTables &T, double *out, const double *in, int rows,
 void center_rows(const DevTables &T, double *x, int rows, int prime_base, int per, hipStream_t s);
 // Switching-key digit, evaluation form over the extended basis:
 // b[r] = t e[r] - a[r] s[r] + gadget[r] s'[r].
-void keygen_combine(const DevTables &T, double *b, const double *a, const double *e, const double *s_,
+void keygen_combine(const DevTables &T, double *b, uint64_t a_stream, const double *e, const double *s_,
                     const double *sp, const double *gadget, hipStream_t s);
 // Encryption: noisy = t e + mu (small integers, N values), then
 // c0[r] = noisy_eval[r] - a[r] s[r] over the L ciphertext primes.

@@ -18,6 +18,24 @@ constexpr int IP_THREADS = 256;
 
 constexpr int MAX_GRID_Z = 65535;   // launches with more z blocks are split
 
+__device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t sm_draw(uint64_t s0, uint64_t k) {
+    return sm_mix(s0 + (k + 1) * 0x9E3779B97F4A7C15ULL);
+}
+
+// A switching key's a_j at evaluation position p of prime row r: the digit
+// stream's draw r N + i, i = bitrev(p) the natural index of the evaluation
+// point at position p, scaled into [0, q) by the high word of draw * q.
+__device__ __forceinline__ double key_a(uint64_t stream, int r, int p, int logN, double q) {
+    const uint64_t k = ((uint64_t)r << logN) + (uint64_t)brev_bits(p, logN);
+    return (double)__umul64hi(sm_draw(stream, k), (uint64_t)q);
+}
+
 // Two consecutive words read once per launch (key and mask streams): a
 // non-temporal load, so that the stream does not evict the hoisted digits
 // and ciphertext rows that every job gathers from L2.
@@ -35,8 +53,8 @@ __device__ __forceinline__ double2 ld_stream2(const double *p) {
 // 1: relinearisation, fold and single-ciphertext passes); the code is the same.
 template <int BETA, int TAG>
 __global__ void __launch_bounds__(IP_THREADS)
-k_ip(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
-     const IpJob *jobs, const IpTerm *terms) {
+k_ip(DevTables T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
+     const double *const *masks, const IpJob *jobs, const IpTerm *terms) {
     const int N = 1 << T.logN;
     const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     const int r = blockIdx.y;
@@ -57,15 +75,18 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const d
         if (tm.kind != IP_PLAIN) {
             const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
             const double *kb = keys[tm.key] + (size_t)r * N + p;
+            const uint64_t *ks = streams + (size_t)tm.key * BETA;
             double y0[BETA], y1[BETA];
             double2 kbv[BETA], kav[BETA];
 #pragma unroll
             for (int j = 0; j < BETA; ++j) {
                 y0[j] = ys[(size_t)j * plane + pp0];
                 y1[j] = ys[(size_t)j * plane + pp1];
-                kbv[j] = ld_stream2(kb + (size_t)(2 * j) * plane);
-                kav[j] = ld_stream2(kb + (size_t)(2 * j + 1) * plane);
+                kbv[j] = ld_stream2(kb + (size_t)j * plane);
             }
+#pragma unroll
+            for (int j = 0; j < BETA; ++j)
+                kav[j] = make_double2(key_a(ks[j], r, p, T.logN, q), key_a(ks[j], r, p + 1, T.logN, q));
             double s0x = 0.0, s0y = 0.0, s1x = 0.0, s1y = 0.0;
 #pragma unroll
             for (int j = 0; j < BETA; ++j) {
@@ -133,8 +154,9 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const d
 // chunks[c] = (first task, count), all of one key.
 template <int BETA, int TAG>
 __global__ void __launch_bounds__(IP_THREADS)
-k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, const double *const *masks,
-           const IpJob *jobs, const IpTerm *terms, const int2 *chunks, const int2 *tasks, int first_round) {
+k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
+           const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks, const int2 *tasks,
+           int first_round) {
     const int N = 1 << T.logN;
     const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     const int r = blockIdx.y;
@@ -145,11 +167,13 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
     const int2 ch = chunks[blockIdx.z];
     double2 kb[BETA], ka[BETA];
     {
-        const double *kp = keys[terms[tasks[ch.x].y].key] + (size_t)r * N + p;
+        const int key = terms[tasks[ch.x].y].key;
+        const double *kp = keys[key] + (size_t)r * N + p;
+        const uint64_t *ks = streams + (size_t)key * BETA;
 #pragma unroll
         for (int j = 0; j < BETA; ++j) {
-            kb[j] = ld_stream2(kp + (size_t)(2 * j) * plane);
-            ka[j] = ld_stream2(kp + (size_t)(2 * j + 1) * plane);
+            kb[j] = ld_stream2(kp + (size_t)j * plane);
+            ka[j] = make_double2(key_a(ks[j], r, p, T.logN, q), key_a(ks[j], r, p + 1, T.logN, q));
         }
     }
     for (int e = ch.x; e < ch.x + ch.y; ++e) {
@@ -369,15 +393,6 @@ __global__ void k_center_rows(DevTables T, double *x, int prime_base, int per) {
 
 // SplitMix64 (Steele, Lea, Flood 2014): the k-th output of the stream that
 // starts in state s0 is mix(s0 + (k+1) * golden_gamma).
-__device__ __forceinline__ uint64_t sm_mix(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ uint64_t sm_draw(uint64_t s0, uint64_t k) {
-    return sm_mix(s0 + (k + 1) * 0x9E3779B97F4A7C15ULL);
-}
 
 __global__ void k_sample_uniform(DevTables T, double *out, uint64_t s0, uint64_t first, int prime_base) {
     const int N = 1 << T.logN;
@@ -466,7 +481,7 @@ __global__ void k_automorph_rows(int logN, double *out, const double *in, int g)
     out[off + p] = in[off + perm_index(p, g, logN)];
 }
 
-__global__ void k_keygen_combine(DevTables T, double *b, const double *a, const double *e, const double *s_,
+__global__ void k_keygen_combine(DevTables T, double *b, uint64_t a_stream, const double *e, const double *s_,
                                  const double *sp, const double *gadget) {
     const int N = 1 << T.logN;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -474,7 +489,8 @@ __global__ void k_keygen_combine(DevTables T, double *b, const double *a, const 
     if (p >= N) return;
     const double q = T.qt[r].x, qi = T.qt[r].y;
     const size_t ix = (size_t)r * N + p;
-    double v = mulm(e[ix], T.t, q, qi) - mulm(a[ix], s_[ix], q, qi);
+    const double a = key_a(a_stream, r, p, T.logN, q);
+    double v = mulm(e[ix], T.t, q, qi) - mulm(a, s_[ix], q, qi);
     v += mulm(sp[ix], gadget[r], q, qi);
     b[ix] = redm(v, q, qi);
 }
@@ -521,15 +537,15 @@ bool g_cdt_uploaded[64] = {false};
 
 static dim3 ew_grid(int N, int y, int z = 1) { return dim3((N + EW_THREADS - 1) / EW_THREADS, y, z); }
 
-void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
+void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, bool transform_pass,
                hipStream_t s) {
     if (njobs <= 0) return;
     if (njobs > MAX_GRID_Z) {   // the z extent of a launch is limited: split
         const size_t plane = (size_t)T.nExt * T.N;
         for (int o = 0; o < njobs; o += MAX_GRID_Z)
-            ip_launch(T, U + (size_t)o * 2 * plane, y, keys, masks, jobs + o, terms, std::min(MAX_GRID_Z, njobs - o),
-                      transform_pass, s);
+            ip_launch(T, U + (size_t)o * 2 * plane, y, keys, streams, masks, jobs + o, terms,
+                      std::min(MAX_GRID_Z, njobs - o), transform_pass, s);
         return;
     }
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, njobs);
@@ -537,9 +553,9 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
 #define HG_IP_CASE(B)                                                                                        \
     case B:                                                                                                  \
         if (transform_pass)                                                                                  \
-            hipLaunchKernelGGL((k_ip<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms); \
+            hipLaunchKernelGGL((k_ip<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, terms); \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_ip<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, terms); \
+            hipLaunchKernelGGL((k_ip<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, terms); \
         break;
         HG_IP_CASE(1) HG_IP_CASE(2) HG_IP_CASE(3) HG_IP_CASE(4) HG_IP_CASE(5) HG_IP_CASE(6)
         HG_IP_CASE(7) HG_IP_CASE(8) HG_IP_CASE(9) HG_IP_CASE(10) HG_IP_CASE(11) HG_IP_CASE(12)
@@ -549,13 +565,14 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
 }
 
 void ip_keyed_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
-                     const double *const *masks, const IpJob *jobs, const IpTerm *terms, const int2 *chunks,
-                     const int2 *tasks, int nchunks, bool first_round, bool transform_pass, hipStream_t s) {
+                     const uint64_t *streams, const double *const *masks, const IpJob *jobs, const IpTerm *terms,
+                     const int2 *chunks, const int2 *tasks, int nchunks, bool first_round, bool transform_pass,
+                     hipStream_t s) {
     if (nchunks <= 0) return;
     if (nchunks > MAX_GRID_Z) {
         for (int o = 0; o < nchunks; o += MAX_GRID_Z)
-            ip_keyed_launch(T, U, y, keys, masks, jobs, terms, chunks + o, tasks, std::min(MAX_GRID_Z, nchunks - o),
-                            first_round, transform_pass, s);
+            ip_keyed_launch(T, U, y, keys, streams, masks, jobs, terms, chunks + o, tasks,
+                            std::min(MAX_GRID_Z, nchunks - o), first_round, transform_pass, s);
         return;
     }
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, nchunks);
@@ -564,10 +581,10 @@ void ip_keyed_launch(const DevTables &T, double *U, const double *y, const doubl
 #define HG_IPK_CASE(B)                                                                                        \
     case B:                                                                                                  \
         if (transform_pass)                                                                                  \
-            hipLaunchKernelGGL((k_ip_keyed<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, \
+            hipLaunchKernelGGL((k_ip_keyed<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, \
                                terms, chunks, tasks, fr);                                                    \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_ip_keyed<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, masks, jobs, \
+            hipLaunchKernelGGL((k_ip_keyed<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, \
                                terms, chunks, tasks, fr);                                                    \
         break;
         HG_IPK_CASE(1) HG_IPK_CASE(2) HG_IPK_CASE(3) HG_IPK_CASE(4) HG_IPK_CASE(5) HG_IPK_CASE(6)
@@ -671,9 +688,10 @@ void gather_slots(const DevTables &T, const double *ev, double *slots, hipStream
     hipLaunchKernelGGL(k_gather_slots, dim3((T.N / 2 + 255) / 256), dim3(256), 0, s, T.logN, ev, slots);
 }
 
-void keygen_combine(const DevTables &T, double *b, const double *a, const double *e, const double *s_,
+void keygen_combine(const DevTables &T, double *b, uint64_t a_stream, const double *e, const double *s_,
                     const double *sp, const double *gadget, hipStream_t s) {
-    hipLaunchKernelGGL(k_keygen_combine, ew_grid(T.N, T.nExt), dim3(EW_THREADS), 0, s, T, b, a, e, s_, sp, gadget);
+    hipLaunchKernelGGL(k_keygen_combine, ew_grid(T.N, T.nExt), dim3(EW_THREADS), 0, s, T, b, a_stream, e, s_, sp,
+                       gadget);
 }
 
 void enc_noisy(const DevTables &T, double *out, const double *e, const double *mu, hipStream_t s) {
