@@ -41,7 +41,7 @@ def parse():
                          "large: one 128x96x128 product per step at N=32768")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
-    ap.add_argument("--max-batch", type=int, default=32, help="serving: products per launch group")
+    ap.add_argument("--max-batch", type=int, default=4, help="serving: products per launch group")
     ap.add_argument("--budget-gib", type=float, default=64.0, help="serving: admitted footprint limit")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB three times with a plain elementwise "

@@ -221,8 +221,8 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
  *                the fused one-workgroup-per-row kernels (alpha = 1 only)
  *   "ip_chunk"   key-switched terms that share a key per workgroup of the
  *                key-stationary inner products (one launch per round of
- *                terms), used for passes whose keys repeat at least twice
- *                on average (batches); 0 disables key grouping
+ *                terms), used for passes whose keys repeat at least four
+ *                times on average (batches); 0 disables key grouping
  *   "split_rows" transforms of fewer rows than this split each row over
  *                N/1024 workgroups (two passes)
  *   "batch_window" products per launch group inside hg_hegmm_batch

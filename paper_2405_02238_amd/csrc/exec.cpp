@@ -149,7 +149,9 @@ struct Exec {
     // tasks (job, term) with the same key form chunks of at most ip_chunk.
     // rounds[s] is the first chunk of round s (rounds.back() = chunk count).
     // Returns false (one plain launch) when key grouping is off or keys would
-    // be used fewer than twice on average.
+    // be used fewer than four times on average (below that, gathering the
+    // hoisted digits of many products costs more than the key reads saved;
+    // measured on MI355X with groups of four 16384-point products).
     bool group_jobs(const Pass &ps, std::vector<int2> &chunks, std::vector<int2> &tasks, std::vector<int> &rounds) {
         const int nj = (int)ps.ip_jobs.size();
         if (C.ip_chunk <= 0 || nj < 2) return false;
@@ -170,7 +172,7 @@ struct Exec {
             groups += rd.size();
             for (auto &kv : rd) ntask += kv.second.size();
         }
-        if (groups * 2 > ntask) return false;   // keys used fewer than twice on average
+        if (groups * 4 > ntask) return false;   // keys used fewer than four times on average
         for (auto &rd : by_round) {
             rounds.push_back((int)chunks.size());
             for (auto &kv : rd) {
@@ -300,14 +302,25 @@ struct Exec {
         HGCHK(hipEventRecord(A.staged, st));
     }
 
-    // Division by P of the key-switched jobs [j0, j1) of a staged pass.
-    void moddown(const Dev &dv, int j0, int j1, bool fuse, hipStream_t s) {
+    // True when a pass's result per job is exactly its division by P (every
+    // job key-switched, job j's output is E slot pair j): the fused division
+    // can then write the job outputs itself.
+    static bool direct_ok(const Pass &ps) {
+        if (ps.fin_jobs.size() != ps.ip_jobs.size()) return false;
+        for (size_t j = 0; j < ps.fin_jobs.size(); ++j)
+            if (ps.fin_jobs[j].ks != (int)j) return false;
+        return true;
+    }
+
+    // Division by P of the key-switched jobs [j0, j1) of a staged pass; with
+    // `outs` (fused only) the results go straight to the jobs' outputs.
+    void moddown(const Dev &dv, int j0, int j1, bool fuse, hipStream_t s, double *const *outs = nullptr) {
         const int nj = j1 - j0;
         if (nj <= 0) return;
         double *U = dv.U + (size_t)j0 * 2 * nExt * N;
         double *E = dv.E + (size_t)j0 * 2 * L * N;
         if (fuse) {
-            moddown_fused(T, E, U, nj * 2, s);
+            moddown_fused(T, E, U, nj * 2, s, outs ? outs + j0 : nullptr);
             return;
         }
         double *rk = dv.rk + (size_t)j0 * 2 * alpha * N;
@@ -336,7 +349,10 @@ struct Exec {
     // P of chunk c (transform bound) on a second stream; `st` then waits for
     // the last division.  Timing events (tev) bracket the phases on `st`;
     // ip_ms accumulates the duration of each inner-product launch.
-    void launch(const Dev &dv, hipEvent_t *tev = nullptr, bool transform_pass = false, Timing *tm = nullptr) {
+    // Returns true when the division by P wrote the job outputs (`direct`
+    // given and the fused path taken): no finishing kernel is needed then.
+    bool launch(const Dev &dv, hipEvent_t *tev = nullptr, bool transform_pass = false, Timing *tm = nullptr,
+                double *const *direct = nullptr) {
         // few rows: one fused launch per chain (latency bound); many rows:
         // separate launches (throughput bound)
         const bool fuse_hoist = fused_ok(T) && dv.nsrc * beta * nExt <= C.fuse_rows;
@@ -346,7 +362,7 @@ struct Exec {
         if (dv.nks <= 0) {
             if (tev)
                 for (int i = 0; i < 3; ++i) HGCHK(hipEventRecord(tev[i], st));
-            return;
+            return false;
         }
         if (!fuse_hoist) {
             // 1. hoist every source once: c1 -> coefficient form -> lifted digits
@@ -388,9 +404,10 @@ struct Exec {
                 }
             }
             if (tev) HGCHK(hipEventRecord(tev[1], st));
-            moddown(dv, 0, dv.nks, fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows, st);
+            const bool fz = fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows;
+            moddown(dv, 0, dv.nks, fz, st, fz ? direct : nullptr);
             if (tev) HGCHK(hipEventRecord(tev[2], st));
-            return;
+            return fz && direct;
         }
         const int nch = std::max(1, std::min(C.pipeline, dv.nks));
         // a chunk's division by P is fused when the chunk is small enough
@@ -417,7 +434,7 @@ struct Exec {
                 HGCHK(hipEventRecord(ev, st));
                 HGCHK(hipStreamWaitEvent(s2, ev, 0));
             }
-            moddown(dv, j0, j1, fuse_md, s2);
+            moddown(dv, j0, j1, fuse_md, s2, fuse_md ? direct : nullptr);
         }
         if (s2 != st) {
             hipEvent_t ev = C.event(st, false);
@@ -425,6 +442,7 @@ struct Exec {
             HGCHK(hipStreamWaitEvent(st, ev, 0));
         }
         if (tev) HGCHK(hipEventRecord(tev[2], st));
+        return fuse_md && direct;
     }
 
     // Stage and launch a single pass.
@@ -563,13 +581,13 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
                       (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
     const Exec::Dev &d2 = sp[1].dv;
-    ex.launch(d2);
-    fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, nreq, st);
+    if (!ex.launch(d2, nullptr, false, nullptr, Exec::direct_ok(pr) ? (double *const *)d2.extra : nullptr))
+        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, nreq, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[4], st));
     if (nfold) {
         const Exec::Dev &d3 = sp[2].dv;
-        ex.launch(d3);
-        fin_rotsum_launch(T, d3.jobs, d3.terms, d3.E, d3.masks, (double *const *)d3.extra, (int)outs.size(), st);
+        if (!ex.launch(d3, nullptr, false, nullptr, Exec::direct_ok(pf) ? (double *const *)d3.extra : nullptr))
+            fin_rotsum_launch(T, d3.jobs, d3.terms, d3.E, d3.masks, (double *const *)d3.extra, (int)outs.size(), st);
     }
     HGCHK(hipFreeAsync(acc, st));
     if (timing.enabled) {

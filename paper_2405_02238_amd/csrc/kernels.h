@@ -107,7 +107,8 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
 //  moddown_fused: E[slot][i] = (U_i - NTT_i(t (P/p) center(INTT_p(U_p) ...))) P^-1
 bool fused_ok(const DevTables &T);
 void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s);
-void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s);
+void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s,
+                   double *const *outs = nullptr);
 
 // Row count below which a transform is split into a column pass and a block
 // pass of 1024-element workgroups (spreading each row over N/1024 CUs);

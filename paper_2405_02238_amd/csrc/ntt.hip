@@ -706,7 +706,7 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
 // inverse transforms when there are enough slots to fill the chip.
 template <int LOGN, int G>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
-k_moddown_fused(DevTables T, double *E, const double *U) {
+k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
     const int ng = T.L / G;
@@ -743,7 +743,9 @@ k_moddown_fused(DevTables T, double *E, const double *U) {
         fwd_row_stages<LOGN>(sh, twq, q, qi, wf);
         const double pinv = T.pinv[iq];
         const double *ui = u + (size_t)iq * N;
-        double *out = E + ((size_t)slot * T.L + iq) * N;
+        // E row, or (outs given) straight into the job's output ciphertext
+        double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N
+                           : E + ((size_t)slot * T.L + iq) * N;
         for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = mulm(ui[i] - sh[lds_ix(i)], pinv, q, qi);
     }
 }
@@ -867,7 +869,7 @@ void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int n
 #undef HG_HF
 }
 
-void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s) {
+void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s, double *const *outs) {
     if (nslots <= 0) return;
     // Two primes per workgroup (half the repeated inverse transforms) was
     // measured slower on MI355X at 8192 points (one 135 KB workgroup per CU
@@ -877,9 +879,9 @@ void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, h
     const size_t lds = ntt_lds_bytes(T.N) + (two ? (size_t)T.N * sizeof(double) : 0);
 #define HG_MF(LN)                                                                                          \
     if (two)                                                                                               \
-        hipLaunchKernelGGL((k_moddown_fused<LN, 2>), dim3(nslots * T.L / 2), dim3(ntt_threads(T.N)), lds, s, T, E, U); \
+        hipLaunchKernelGGL((k_moddown_fused<LN, 2>), dim3(nslots * T.L / 2), dim3(ntt_threads(T.N)), lds, s, T, E, U, outs); \
     else                                                                                                   \
-        hipLaunchKernelGGL((k_moddown_fused<LN, 1>), dim3(nslots * T.L), dim3(ntt_threads(T.N)), lds, s, T, E, U);
+        hipLaunchKernelGGL((k_moddown_fused<LN, 1>), dim3(nslots * T.L), dim3(ntt_threads(T.N)), lds, s, T, E, U, outs);
     HG_LOGN_SWITCH(T.logN, HG_MF)
 #undef HG_MF
 }

@@ -47,8 +47,6 @@ Server::~Server() {
     (void)hipSetDevice(C.device);
     for (auto &ln : lanes) {
         if (ln.st) (void)hipStreamSynchronize(ln.st);
-        if (ln.pin_in) (void)hipHostFree(ln.pin_in);
-        if (ln.pin_out) (void)hipHostFree(ln.pin_out);
         if (ln.done) (void)hipEventDestroy(ln.done);
         // the executor's scratch arena of this stream goes with the stream
         auto it = C.arenas.find(ln.st);
@@ -68,6 +66,35 @@ Server::~Server() {
         }
         if (ln.st) (void)hipStreamDestroy(ln.st);
     }
+    for (auto &kv : reqs)
+        if (kv.second->pin) (void)hipHostFree(kv.second->pin);
+    for (auto &kv : pool) (void)hipHostFree(kv.second);
+}
+
+uint64_t *Server::pin_get(size_t words, size_t &cap) {
+    {
+        std::lock_guard<std::mutex> g(pool_mu);
+        auto it = pool.lower_bound(words);
+        if (it != pool.end() && it->first <= 2 * words) {
+            uint64_t *p = it->second;
+            cap = it->first;
+            pool.erase(it);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    HGCHK(hipHostMalloc(&p, words * sizeof(uint64_t), hipHostMallocDefault));
+    cap = words;
+    return (uint64_t *)p;
+}
+
+void Server::pin_put(uint64_t *p, size_t cap) {
+    std::lock_guard<std::mutex> g(pool_mu);
+    if (pool.size() < 256) {
+        pool.emplace(cap, p);
+        return;
+    }
+    (void)hipHostFree(p);
 }
 
 double Server::now() const {
@@ -100,8 +127,12 @@ uint64_t Server::submit(const uint64_t *a, size_t na, const uint64_t *b, size_t 
     rq->l = l;
     rq->n = n;
     rq->pe = pe;
-    rq->a.assign(a, a + na);
-    rq->b.assign(b, b + nbw);
+    rq->na = na;
+    rq->nb = nbw;
+    rq->nc = ctw;
+    rq->pin = pin_get(na + nbw + ctw, rq->pin_cap);
+    std::memcpy(rq->pin, a, na * sizeof(uint64_t));
+    std::memcpy(rq->pin + na, b, nbw * sizeof(uint64_t));
     rq->footprint = request_footprint(C, pe->plan);
     uint64_t id;
     {
@@ -127,6 +158,11 @@ void Server::wait(uint64_t id, uint64_t *c, size_t nc, double *times) {
         rq = std::move(it->second);
         reqs.erase(it);
     }
+    struct Release {   // the pinned buffer goes back to the pool on every path
+        Server *s;
+        Req *r;
+        ~Release() { s->pin_put(r->pin, r->pin_cap); }
+    } release{this, rq.get()};
     if (rq->status < 0) throw Error(rq->status, rq->err);
     if (times) {
         times[0] = rq->t_submit;
@@ -134,8 +170,8 @@ void Server::wait(uint64_t id, uint64_t *c, size_t nc, double *times) {
         times[2] = rq->t_done;
     }
     if (c) {
-        if (nc < rq->c.size()) throw Error(-1, "result buffer too small");
-        std::memcpy(c, rq->c.data(), rq->c.size() * sizeof(uint64_t));
+        if (nc < rq->nc) throw Error(-1, "result buffer too small");
+        std::memcpy(c, rq->pin + rq->na + rq->nb, rq->nc * sizeof(uint64_t));
     }
 }
 
@@ -156,27 +192,8 @@ void Server::launch(Lane &ln, std::vector<Req *> &batch) {
     const size_t N = C.N, L = C.L;
     const size_t ctw = 2 * L * N;
     size_t in_words = 0;
-    for (Req *r : batch) in_words += r->a.size() + r->b.size();
+    for (Req *r : batch) in_words += r->na + r->nb;
     const size_t out_words = batch.size() * ctw;
-    // the lane is idle (its last group completed), so its staging can be replaced
-    if (in_words * 8 > ln.pin_in_cap) {
-        if (ln.pin_in) HGCHK(hipHostFree(ln.pin_in));
-        ln.pin_in_cap = in_words * 8 + in_words * 4;
-        HGCHK(hipHostMalloc(&ln.pin_in, ln.pin_in_cap, hipHostMallocDefault));
-    }
-    if (out_words * 8 > ln.pin_out_cap) {
-        if (ln.pin_out) HGCHK(hipHostFree(ln.pin_out));
-        ln.pin_out_cap = out_words * 8 + out_words * 4;
-        HGCHK(hipHostMalloc(&ln.pin_out, ln.pin_out_cap, hipHostMallocDefault));
-    }
-    uint64_t *pin = (uint64_t *)ln.pin_in;
-    size_t o = 0;
-    for (Req *r : batch) {
-        std::memcpy(pin + o, r->a.data(), r->a.size() * 8);
-        o += r->a.size();
-        std::memcpy(pin + o, r->b.data(), r->b.size() * 8);
-        o += r->b.size();
-    }
     // device buffer: operands (in_words doubles), results (out_words
     // doubles), canonical staging (in_words words; in_words >= 2 out_words)
     char *dbuf = nullptr;
@@ -184,7 +201,11 @@ void Server::launch(Lane &ln, std::vector<Req *> &batch) {
     double *ops = (double *)dbuf;
     double *outs = ops + in_words;
     uint64_t *stage = (uint64_t *)(outs + out_words);
-    HGCHK(hipMemcpyAsync(stage, pin, in_words * 8, hipMemcpyHostToDevice, st));
+    size_t o = 0;
+    for (Req *r : batch) {   // straight from each request's pinned buffer
+        HGCHK(hipMemcpyAsync(stage + o, r->pin, (r->na + r->nb) * 8, hipMemcpyHostToDevice, st));
+        o += r->na + r->nb;
+    }
     u64_to_dbl(stage, ops, in_words, st);
     NttArgs a;
     a.out = ops;
@@ -215,9 +236,9 @@ void Server::launch(Lane &ln, std::vector<Req *> &batch) {
             return ln.cts.back().get();
         };
         Ct *A = mk(ops + o, side_of_role(p, 0), p.nb);
-        o += r->a.size();
+        o += r->na;
         Ct *B = mk(ops + o, side_of_role(p, 1), p.nb);
-        o += r->b.size();
+        o += r->nb;
         Ct *Cc = mk(outs + i * ctw, 2, 1);
         rq.push_back({A, B, r->m, r->l, r->n, Cc});
     }
@@ -231,36 +252,27 @@ void Server::launch(Lane &ln, std::vector<Req *> &batch) {
     e.out_stride = e.in_stride = (long long)(L * N);
     ntt_inv(C.T, STORE_CANON, e, st);
     dbl_to_u64(ops, stage, out_words, st);
-    HGCHK(hipMemcpyAsync(ln.pin_out, stage, out_words * 8, hipMemcpyDeviceToHost, st));
+    for (size_t i = 0; i < batch.size(); ++i)
+        HGCHK(hipMemcpyAsync(batch[i]->pin + batch[i]->na + batch[i]->nb, stage + i * ctw, ctw * 8,
+                             hipMemcpyDeviceToHost, st));
     HGCHK(hipFreeAsync(dbuf, st));
     HGCHK(hipEventRecord(ln.done, st));
 }
 
 void Server::finish(Lane &ln, int code, const std::string &msg) {
-    const size_t ctw = 2 * (size_t)C.L * C.N;
     const double t = now();
-    std::vector<std::vector<uint64_t>> res(ln.batch.size());
-    if (code == 0) {
-        const uint64_t *po = (const uint64_t *)ln.pin_out;
-        for (size_t i = 0; i < ln.batch.size(); ++i) res[i].assign(po + i * ctw, po + (i + 1) * ctw);
-    }
     {
         std::lock_guard<std::mutex> g(mu);
         for (size_t i = 0; i < ln.batch.size(); ++i) {
             Req *r = ln.batch[i];
             r->t_done = t;
             if (code == 0) {
-                r->c = std::move(res[i]);
                 r->status = 2;
                 ++n_done;
             } else {
                 r->status = code;
                 r->err = msg;
             }
-            r->a.clear();
-            r->a.shrink_to_fit();
-            r->b.clear();
-            r->b.shrink_to_fit();
         }
         inflight -= ln.footprint;
     }

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -35,7 +36,10 @@ struct Server {
         uint64_t id = 0;
         int m = 0, l = 0, n = 0;
         const PlanEntry *pe = nullptr;
-        std::vector<uint64_t> a, b, c;   // canonical words: operands in, result out
+        // pinned host buffer: operand words a then b (copied in by submit),
+        // then the result's words (copied out of the device by the lane)
+        uint64_t *pin = nullptr;
+        size_t pin_cap = 0, na = 0, nb = 0, nc = 0;
         uint64_t footprint = 0;
         double t_submit = 0, t_start = 0, t_done = 0;
         int status = 0;                  // 0 queued, 1 running, 2 done, < 0 error code
@@ -47,8 +51,6 @@ struct Server {
         bool busy = false;
         std::vector<Req *> batch;
         std::vector<std::unique_ptr<Ct>> cts;   // non-owning views of the lane's device buffer
-        void *pin_in = nullptr, *pin_out = nullptr;
-        size_t pin_in_cap = 0, pin_out_cap = 0;
         uint64_t footprint = 0;
     };
 
@@ -64,6 +66,11 @@ struct Server {
     bool stop = false;
     uint64_t inflight = 0;
     std::chrono::steady_clock::time_point origin;
+    // pool of pinned request buffers, reused by size (guarded by pool_mu)
+    std::mutex pool_mu;
+    std::multimap<size_t, uint64_t *> pool;
+    uint64_t *pin_get(size_t words, size_t &cap);
+    void pin_put(uint64_t *p, size_t cap);
     // statistics (guarded by mu)
     uint64_t n_done = 0, n_batches = 0, max_inflight = 0, max_overlap = 0;
     double sum_batch = 0;

@@ -302,9 +302,9 @@ def test_keyed_inner_products_bit_identical(alpha):
     round of terms) gives the same bits as the plain inner products, on a
     batch with repeated shapes, folds, transposition and blocking."""
     c = workloads.TINY
-    # every shape three times, so that keys repeat (the schedule is used when
-    # a pass's keys are used at least twice on average)
-    shapes = [(2, 5, 7), (5, 4, 2), (3, 11, 6), (4, 3, 5), (7, 7, 7), (2, 9, 3)] * 3
+    # every shape five times, so that keys repeat (the schedule is used when
+    # a pass's keys are used at least four times on average)
+    shapes = [(2, 5, 7), (5, 4, 2), (3, 11, 6), (4, 3, 5), (7, 7, 7), (2, 9, 3)] * 5
     ctx = hg.Context(c.N, c.t, 4 if alpha == 2 else c.L, alpha)
     ctx.keygen(c.seed, shapes)
     rng = np.random.default_rng(40 + alpha)
