@@ -108,6 +108,27 @@ hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l
 hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B,
                          const int32_t *mln, hg_ct **C, void *stream);
 
+/* Record a batch (the launches hg_hegmm_batch would make for it) once as a
+ * HIP graph with private workspaces, for replay with no host work.  The
+ * graph binds the operand handles and the new result handles C[i]: every
+ * hg_graph_launch recomputes C[i] from the current contents of A[i], B[i]
+ * (refresh them with hg_ct_load).  Bound handles must stay alive until
+ * hg_graph_destroy.  Recording runs the batch once eagerly first (C[i] then
+ * already hold the products).  Errors as hg_hegmm_batch. */
+typedef struct hg_graph hg_graph;
+hg_status hg_graph_create(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B,
+                          const int32_t *mln, hg_ct **C, hg_graph **out);
+/* Enqueue one replay on `stream`.  Replays of one graph must not overlap:
+ * launch them on one stream, or order them. */
+hg_status hg_graph_launch(hg_graph *g, void *stream);
+void hg_graph_destroy(hg_graph *g);
+
+/* Overwrite a handle's contents with canonical words (the hg_ct_export
+ * layout of a handle of the same size), keeping its shape and role; used to
+ * feed new operands to a recorded graph.  Synchronises `stream`.  Errors:
+ * HG_EINVAL (word count, residue range). */
+hg_status hg_ct_load(hg_ctx *ctx, hg_ct *ct, const uint64_t *buf, size_t nwords, void *stream);
+
 /* Decrypt a result made by hg_hegmm for shape (m, l, n) -- or the
  * hg_ct_import (one ciphertext, two components) of its exported words, such
  * as a served result -- and unpack it into C (row-major m x n, values in

@@ -76,6 +76,9 @@ _SIGS = {
                          ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)],
     "hg_server_wait": [_P, ctypes.c_uint64, _P, ctypes.c_size_t, _P],
     "hg_server_stats": [_P, _f64p],
+    "hg_graph_create": [_P, ctypes.c_size_t, _PP, _PP, _i32p, _PP, _PP],
+    "hg_graph_launch": [_P, _P],
+    "hg_ct_load": [_P, _P, _u64p, ctypes.c_size_t, _P],
 }
 
 
@@ -104,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.hg_ct_free.restype = None
     lib.hg_server_destroy.argtypes = [_P]
     lib.hg_server_destroy.restype = None
+    lib.hg_graph_destroy.argtypes = [_P]
+    lib.hg_graph_destroy.restype = None
     lib.hg_last_error.argtypes = []
     lib.hg_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -283,6 +288,15 @@ class Context:
                 "ip_launches"]
         return dict(zip(keys, (float(x) for x in out)))
 
+    def load_ct(self, ct: "Ciphertext", words: np.ndarray, stream=None):
+        """Overwrite ct's contents with canonical words (export layout)."""
+        w = np.ascontiguousarray(words, dtype=np.uint64)
+        _check(_lib.hg_ct_load(self.ptr, ct.ptr, w, w.size, current_stream() if stream is None else stream))
+
+    def record_batch(self, As, Bs, shapes) -> "Graph":
+        """Record the batch as a replayable graph (see hg_graph_create)."""
+        return Graph(self, As, Bs, shapes)
+
     def request_footprint(self, m: int, l: int, n: int) -> int:
         out = ctypes.c_uint64(0)
         _check(_lib.hg_request_footprint(self.ptr, m, l, n, ctypes.byref(out)))
@@ -334,6 +348,38 @@ class Server:
 
     def __exit__(self, *exc):
         self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """hg_graph: a recorded batch.  Keeps its operand and result handles alive."""
+
+    def __init__(self, ctx: Context, As, Bs, shapes):
+        cnt = len(As)
+        pa = (ctypes.c_void_p * cnt)(*[a.ptr for a in As])
+        pb = (ctypes.c_void_p * cnt)(*[b.ptr for b in Bs])
+        pc = (ctypes.c_void_p * cnt)()
+        mln = np.ascontiguousarray(np.array(list(shapes), dtype=np.int32).reshape(-1))
+        out = ctypes.c_void_p()
+        _check(_lib.hg_graph_create(ctx.ptr, cnt, ctypes.cast(pa, _PP), ctypes.cast(pb, _PP), mln,
+                                    ctypes.cast(pc, _PP), ctypes.byref(out)))
+        self.ptr = out.value
+        self.ctx = ctx
+        self.inputs = (list(As), list(Bs))
+        self.outputs = [Ciphertext(ctx, pc[i]) for i in range(cnt)]
+
+    def launch(self, stream=None):
+        _check(_lib.hg_graph_launch(self.ptr, current_stream() if stream is None else stream))
+
+    def close(self):
+        if getattr(self, "ptr", None):
+            _lib.hg_graph_destroy(self.ptr)
+            self.ptr = None
 
     def __del__(self):
         try:

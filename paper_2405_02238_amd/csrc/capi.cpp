@@ -17,6 +17,9 @@ struct hg_ct {
 struct hg_server {
     hg::Server *s;
 };
+struct hg_graph {
+    hg::Graph *g;
+};
 
 namespace {
 
@@ -147,6 +150,65 @@ hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const h
     }
     for (size_t i = 0; i < cnt; ++i) C[i] = wrap(made[i]);
     return HG_OK;
+}
+
+hg_status hg_graph_create(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B, const int32_t *mln,
+                          hg_ct **C, hg_graph **out) {
+    std::vector<hg::Ct *> made;
+    hg::Graph *gr = nullptr;
+    hg_status st = guard([&] {
+        need(ctx && A && B && mln && C && out, "null argument");
+        need(cnt > 0, "empty batch");
+        *out = nullptr;
+        hg::Ctx &X = *ctx->c;
+        HGCHK(hipSetDevice(X.device));
+        std::vector<hg::Ctx::Request> reqs;
+        for (size_t i = 0; i < cnt; ++i) {
+            need(A[i] && B[i], "null operand");
+            need(A[i]->c->ctx == &X && B[i]->c->ctx == &X, "operand from another context");
+            need(mln[3 * i] > 0 && mln[3 * i + 1] > 0 && mln[3 * i + 2] > 0, "dimensions must be positive");
+            hg::Ct *o = new hg::Ct();
+            o->ctx = &X;
+            o->ncts = 1;
+            o->comps = 2;
+            o->m = mln[3 * i]; o->l = mln[3 * i + 1]; o->n = mln[3 * i + 2];
+            o->side = 2;
+            made.push_back(o);
+            o->d = X.dev_alloc(o->words());
+            reqs.push_back({A[i]->c, B[i]->c, mln[3 * i], mln[3 * i + 1], mln[3 * i + 2], o});
+        }
+        gr = new hg::Graph(X, reqs);
+    });
+    if (st != HG_OK) {
+        for (auto *o : made) delete o;
+        return st;
+    }
+    for (size_t i = 0; i < cnt; ++i) C[i] = wrap(made[i]);
+    *out = new hg_graph{gr};
+    return HG_OK;
+}
+
+hg_status hg_graph_launch(hg_graph *g, void *stream) {
+    return guard([&] {
+        need(g, "null graph");
+        g->g->launch(as_stream(stream));
+    });
+}
+
+void hg_graph_destroy(hg_graph *g) {
+    if (!g) return;
+    delete g->g;
+    delete g;
+}
+
+hg_status hg_ct_load(hg_ctx *ctx, hg_ct *ct, const uint64_t *buf, size_t nwords, void *stream) {
+    return guard([&] {
+        need(ctx && ct && buf, "null argument");
+        hg::Ctx &X = *ctx->c;
+        need(ct->c->ctx == &X, "handle from another context");
+        HGCHK(hipSetDevice(X.device));
+        X.load_ct(*ct->c, buf, nwords, as_stream(stream));
+    });
 }
 
 hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n, hg_ct **ctC, void *stream) {

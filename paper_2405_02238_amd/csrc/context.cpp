@@ -172,11 +172,7 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_) {
 Ctx::~Ctx() {
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
-    for (auto &kv : arenas) {
-        if (kv.second.base) (void)hipFree(kv.second.base);
-        if (kv.second.pinned) (void)hipHostFree(kv.second.pinned);
-        if (kv.second.staged) (void)hipEventDestroy(kv.second.staged);
-    }
+    for (auto &kv : arenas) kv.second.release();
     for (auto &kv : aux) {
         for (auto &ring : kv.second.ev)
             for (hipEvent_t e : ring) (void)hipEventDestroy(e);
@@ -219,6 +215,27 @@ hipEvent_t Ctx::event(hipStream_t st, bool timing) {
     hipEvent_t e = ring[nx];
     nx = (nx + 1) % RING;
     return e;
+}
+
+void Arena::release() {
+    if (base) (void)hipFree(base);
+    if (pinned) (void)hipHostFree(pinned);
+    if (staged) (void)hipEventDestroy(staged);
+    if (acc) (void)hipFree(acc);
+    base = pinned = pinned_dev = acc = nullptr;
+    staged = nullptr;
+    cap = pinned_cap = acc_cap = 0;
+}
+
+Arena &Ctx::arena_for(hipStream_t st) {
+    if (!capture_arenas) return arena(st);
+    auto &v = *capture_arenas;
+    if (capture_next == v.size()) {
+        if (capturing) throw Error(-5, "graph recording needs a workspace the first pass did not make");
+        v.push_back(std::make_unique<Arena>());
+        HGCHK(hipEventCreateWithFlags(&v.back()->staged, hipEventDisableTiming));
+    }
+    return *v[capture_next++];
 }
 
 Arena &Ctx::arena(hipStream_t st) {
@@ -547,26 +564,33 @@ Ct *Ctx::import_ct(const uint64_t *buf, int ncts, int comps, hipStream_t st) {
     c->ncts = ncts;
     c->comps = comps;
     c->d = dev_alloc(c->words());
-    const size_t n = c->words();
+    try {
+        load_ct(*c, buf, c->words(), st);
+    } catch (...) {
+        delete c;
+        throw;
+    }
+    return c;
+}
+
+void Ctx::load_ct(Ct &c, const uint64_t *buf, size_t nwords, hipStream_t st) {
+    const size_t n = c.words();
+    if (nwords != n) throw Error(-1, "word count does not match the handle");
     for (size_t r = 0; r < n / N; ++r) {
         const uint64_t q = qs[r % L];
         for (int i = 0; i < N; ++i)
-            if (buf[r * N + i] >= q) {
-                delete c;
-                throw Error(-1, "residue out of range in import");
-            }
+            if (buf[r * N + i] >= q) throw Error(-1, "residue out of range in import");
     }
     uint64_t *u = nullptr;
     HGCHK(hipMalloc(&u, n * sizeof(uint64_t)));
     HGCHK(hipMemcpyAsync(u, buf, n * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-    u64_to_dbl(u, c->d, n, st);
+    u64_to_dbl(u, c.d, n, st);
     NttArgs a;
-    a.out = c->d; a.in = c->d; a.rows = (int)(n / N); a.per = L;
+    a.out = c.d; a.in = c.d; a.rows = (int)(n / N); a.per = L;
     a.out_stride = a.in_stride = (long long)L * N;
     ntt_fwd(T, LOAD_PLAIN, a, st);
     HGCHK(hipStreamSynchronize(st));
     (void)hipFree(u);
-    return c;
 }
 
 }  // namespace hg

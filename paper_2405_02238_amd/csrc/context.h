@@ -54,6 +54,9 @@ struct Arena {
     void *pinned_dev = nullptr;  // the same memory as the device addresses it
     size_t pinned_cap = 0;
     hipEvent_t staged = nullptr; // completion of the last copy out of `pinned`
+    void *acc = nullptr;         // per-call accumulators (3 x L x N per product, R for folds)
+    size_t acc_cap = 0;
+    void release();              // free everything (device must be idle)
 };
 
 struct Timing {
@@ -95,6 +98,14 @@ struct Ctx {
     std::map<std::string, double *> mask_cache;   // slot bitmap -> device mask (nExt x N)
 
     std::map<hipStream_t, Arena> arenas;
+    // Graph recording: while `capture_arenas` is set, every launch window
+    // takes the next arena of that list (private to the graph, kept for its
+    // replays) instead of the stream's; while `capturing`, nothing may
+    // synchronise or allocate.
+    std::vector<std::unique_ptr<Arena>> *capture_arenas = nullptr;
+    size_t capture_next = 0;
+    bool capturing = false;
+    Arena &arena_for(hipStream_t st);
     Timing timing;
     int fuse_rows = 512;  // passes with at most this many rows per chain use the fused kernels
     int ip_chunk = 16;    // terms sharing a key per workgroup in the key-stationary inner products (0: off)
@@ -141,11 +152,28 @@ struct Ctx {
 
     void export_ct(const Ct &c, uint64_t *buf, hipStream_t st);
     Ct *import_ct(const uint64_t *buf, int ncts, int comps, hipStream_t st);
+    // overwrite a handle's contents with canonical words (same layout as export)
+    void load_ct(Ct &c, const uint64_t *buf, size_t nwords, hipStream_t st);
 
     // canonical (coefficient form, [0,q)) residues of an L-row polynomial
     std::vector<uint64_t> to_host_canonical(const double *eval_rows, int rows, hipStream_t st);
 
     Arena &arena(hipStream_t st);
+};
+
+// A batch of products recorded once as a HIP graph (every launch of its
+// windows, with private workspaces and descriptor tables) and replayed with
+// no host work: each replay recomputes the bound outputs from the current
+// contents of the bound operands.
+struct Graph {
+    Ctx *C = nullptr;
+    hipStream_t gs = nullptr;                    // recording stream
+    std::vector<std::unique_ptr<Arena>> arenas;  // one per launch window, kept for the replays
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ge = nullptr;
+    Graph(Ctx &c, std::vector<Ctx::Request> &reqs);
+    void launch(hipStream_t st);
+    ~Graph();
 };
 
 }  // namespace hg

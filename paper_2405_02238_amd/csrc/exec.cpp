@@ -71,10 +71,24 @@ namespace {
 struct Exec {
     Ctx &C;
     hipStream_t st;
+    Arena &A;
     const DevTables &T;
     int N, L, nExt, beta, alpha;
     Exec(Ctx &c, hipStream_t s)
-        : C(c), st(s), T(c.T), N(c.N), L(c.L), nExt(c.nExt), beta(c.beta), alpha(c.alpha) {}
+        : C(c), st(s), A(c.arena_for(s)), T(c.T), N(c.N), L(c.L), nExt(c.nExt), beta(c.beta), alpha(c.alpha) {}
+
+    // Accumulator space for this call (stream-ordered reuse of one buffer per
+    // arena; grown with the stream drained, never while recording a graph).
+    double *acc(size_t bytes) {
+        if (bytes > A.acc_cap) {
+            if (C.capturing) throw Error(-5, "graph recording needs a workspace the first pass did not make");
+            HGCHK(hipStreamSynchronize(st));
+            if (A.acc) HGCHK(hipFree(A.acc));
+            A.acc_cap = align_up(bytes + bytes / 4, 1 << 20);
+            HGCHK(hipMalloc(&A.acc, A.acc_cap));
+        }
+        return (double *)A.acc;
+    }
 
     // Adds a job to `ps`: the rotation sum sum_z mask_z (.) Rot(ct, z) over
     // `terms` (z, mask pointer or null), plus the key switch of the hoisted
@@ -192,7 +206,6 @@ struct Exec {
     // the stream (one scratch region sized for the largest, one descriptor
     // table block per pass) and copy every table with a single transfer.
     void stage(std::vector<Staged> &sp) {
-        Arena &A = C.arena(st);
         size_t scratch = 0;
         std::vector<size_t> toff(sp.size());
         Layout tl;
@@ -238,6 +251,8 @@ struct Exec {
         }
         tl.add(256);   // never empty
         const size_t total = scratch + tl.total;
+        if ((total > A.cap || tl.total > A.pinned_cap) && C.capturing)
+            throw Error(-5, "graph recording needs a workspace the first pass did not make");
         if (total > A.cap) {
             HGCHK(hipStreamSynchronize(st));
             if (A.base) HGCHK(hipFree(A.base));
@@ -251,7 +266,9 @@ struct Exec {
             HGCHK(hipHostMalloc(&A.pinned, A.pinned_cap, hipHostMallocDefault));
             HGCHK(hipHostGetDevicePointer(&A.pinned_dev, A.pinned, 0));
         }
-        HGCHK(hipEventSynchronize(A.staged));   // the previous copy out of staging is done
+        // the previous copy out of staging is done (a graph's arenas are
+        // private and were drained before recording)
+        if (!C.capturing) HGCHK(hipEventSynchronize(A.staged));
         char *h = (char *)A.pinned;
         char *base = (char *)A.base;
         char *tab = base + scratch;
@@ -299,7 +316,7 @@ struct Exec {
         // a kernel reads the tables straight out of the pinned buffer: cheaper
         // on the stream than a copy-engine transfer and its barrier
         copy_from_host(tab, A.pinned_dev, tl.total, st);
-        HGCHK(hipEventRecord(A.staged, st));
+        if (!C.capturing) HGCHK(hipEventRecord(A.staged, st));
     }
 
     // True when a pass's result per job is exactly its division by P (every
@@ -409,7 +426,7 @@ struct Exec {
             if (tev) HGCHK(hipEventRecord(tev[2], st));
             return fz && direct;
         }
-        const int nch = std::max(1, std::min(C.pipeline, dv.nks));
+        const int nch = C.capturing ? 1 : std::max(1, std::min(C.pipeline, dv.nks));
         // a chunk's division by P is fused when the chunk is small enough
         const int per_chunk = (dv.nks + nch - 1) / nch;
         const bool fuse_md = fused_ok(T) && per_chunk * 2 * L <= C.fuse_rows;
@@ -455,6 +472,62 @@ struct Exec {
 };
 
 }  // namespace
+
+Graph::Graph(Ctx &c, std::vector<Ctx::Request> &reqs) : C(&c) {
+    HGCHK(hipSetDevice(c.device));
+    HGCHK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
+    const bool timing = c.timing.enabled;
+    c.timing.enabled = false;
+    c.capture_arenas = &arenas;
+    c.capture_next = 0;
+    bool recording = false;
+    try {
+        // a first, eager pass makes and sizes every workspace and descriptor
+        // table, so that the recorded pass neither allocates nor waits
+        c.hegmm_batch(reqs, gs);
+        HGCHK(hipStreamSynchronize(gs));
+        c.capture_next = 0;
+        c.capturing = true;
+        HGCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeRelaxed));
+        recording = true;
+        c.hegmm_batch(reqs, gs);
+        recording = false;
+        HGCHK(hipStreamEndCapture(gs, &g));
+        HGCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    } catch (...) {
+        if (recording) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(gs, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+        }
+        c.capturing = false;
+        c.capture_arenas = nullptr;
+        c.timing.enabled = timing;
+        (void)hipStreamSynchronize(gs);
+        for (auto &a : arenas) a->release();
+        (void)hipStreamDestroy(gs);
+        gs = nullptr;
+        throw;
+    }
+    c.capturing = false;
+    c.capture_arenas = nullptr;
+    c.timing.enabled = timing;
+}
+
+void Graph::launch(hipStream_t st) {
+    HGCHK(hipSetDevice(C->device));
+    HGCHK(hipGraphLaunch(ge, st));
+}
+
+Graph::~Graph() {
+    if (!C) return;
+    (void)hipSetDevice(C->device);
+    (void)hipDeviceSynchronize();
+    if (ge) (void)hipGraphExecDestroy(ge);
+    if (g) (void)hipGraphDestroy(g);
+    for (auto &a : arenas) a->release();
+    if (gs) (void)hipStreamDestroy(gs);
+}
 
 void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
     HGCHK(hipSetDevice(device));
@@ -533,8 +606,7 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     // request-lifetime buffers: accumulators (3 x L x N) and relinearised R (2 x L x N, fold only)
     int nfold = 0;
     for (int ri = 0; ri < nreq; ++ri) nfold += info[ri].pe->plan.d > 1;
-    double *acc = nullptr;
-    HGCHK(hipMallocAsync((void **)&acc, ((size_t)nreq * 3 + (size_t)nfold * 2) * ctw * sizeof(double), st));
+    double *acc = ex.acc(((size_t)nreq * 3 + (size_t)nfold * 2) * ctw * sizeof(double));
     double *rbuf = acc + (size_t)nreq * 3 * ctw;
     std::vector<double *> acc_ptrs(nreq);
     for (int ri = 0; ri < nreq; ++ri) acc_ptrs[ri] = acc + (size_t)ri * 3 * ctw;
@@ -589,7 +661,6 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
         if (!ex.launch(d3, nullptr, false, nullptr, Exec::direct_ok(pf) ? (double *const *)d3.extra : nullptr))
             fin_rotsum_launch(T, d3.jobs, d3.terms, d3.E, d3.masks, (double *const *)d3.extra, (int)outs.size(), st);
     }
-    HGCHK(hipFreeAsync(acc, st));
     if (timing.enabled) {
         HGCHK(hipEventRecord(ev[5], st));
         HGCHK(hipEventSynchronize(ev[5]));
@@ -644,8 +715,7 @@ Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
     o->d = dev_alloc(o->words());
     try {
         Exec ex(*this, st);
-        double *acc = nullptr;
-        HGCHK(hipMallocAsync((void **)&acc, 3 * ctw * sizeof(double), st));
+        double *acc = ex.acc(3 * ctw * sizeof(double));
         Pass ps;
         ex.add_job(ps, a.d, {{0, nullptr}}, -1, nullptr);
         ex.add_job(ps, b.d, {{0, nullptr}}, -1, nullptr);
@@ -660,7 +730,6 @@ Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
         double *outp = o->d;
         Exec::Dev d2 = ex.run(pr, &outp, sizeof(void *));
         fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, 1, st);
-        HGCHK(hipFreeAsync(acc, st));
     } catch (...) {
         delete o;
         throw;

@@ -51,9 +51,7 @@ Server::~Server() {
         // the executor's scratch arena of this stream goes with the stream
         auto it = C.arenas.find(ln.st);
         if (it != C.arenas.end()) {
-            if (it->second.base) (void)hipFree(it->second.base);
-            if (it->second.pinned) (void)hipHostFree(it->second.pinned);
-            if (it->second.staged) (void)hipEventDestroy(it->second.staged);
+            it->second.release();
             C.arenas.erase(it);
         }
         auto ax = C.aux.find(ln.st);

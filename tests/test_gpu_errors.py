@@ -1,0 +1,136 @@
+"""GPU: error paths of the C ABI and the client/server roles."""
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2405_02238_amd as hg  # noqa: E402
+
+
+@pytest.fixture()
+def ctx():
+    c = workloads.TINY
+    x = hg.Context(c.N, c.t, c.L, c.alpha)
+    x.keygen(c.seed, [(4, 3, 5)])
+    return x
+
+
+def test_bad_parameters():
+    with pytest.raises(hg.HGError) as e:
+        hg.Context(1000, 12289, 3, 1)          # N not a power of two
+    assert e.value.code == hg.HG_EINVAL
+    with pytest.raises(hg.HGError) as e:
+        hg.Context(1024, 12288, 3, 1)          # t not prime
+    assert e.value.code == hg.HG_EINVAL
+    with pytest.raises(hg.HGError) as e:
+        hg.Context(1024, 65539, 3, 1)          # t prime but not 1 mod 2N
+    assert e.value.code == hg.HG_EINVAL
+
+
+def test_dimensions_and_fit(ctx):
+    A, B = workloads.tiny_operands()
+    with pytest.raises(hg.HGError) as e:
+        ctx.encrypt(0, A, 0, 3, 5)
+    assert e.value.code == hg.HG_EINVAL
+    # m * n alone exceeds the 512 slots: no inner blocking can fit it
+    with pytest.raises(hg.HGError) as e:
+        ctx.plan_info(30, 4, 30)
+    assert e.value.code == hg.HG_ENOFIT
+
+
+def test_missing_rotation_keys(ctx):
+    rng = np.random.default_rng(0)
+    m, l, n = 3, 7, 5                            # not listed in keygen
+    A = rng.integers(-8, 9, size=(m, l))
+    B = rng.integers(-8, 9, size=(l, n))
+    ca, cb = ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1)
+    with pytest.raises(hg.HGError) as e:
+        ctx.hegmm(ca, cb, m, l, n)
+    assert e.value.code == hg.HG_ENOKEY
+    ctx.keygen(workloads.TINY.seed, [(m, l, n)])  # adding keys later under the same seed
+    C = ctx.decrypt(ctx.hegmm(ca, cb, m, l, n), m, l, n)
+    assert np.array_equal(C, workloads.plain_matmul_mod(A, B, workloads.TINY.t))
+    with pytest.raises(hg.HGError) as e:
+        ctx.keygen(workloads.TINY.seed + 1, [(m, l, n)])   # another seed
+    assert e.value.code == hg.HG_ESTATE
+
+
+def test_mismatched_operands(ctx):
+    A, B = workloads.tiny_operands()
+    ca, cb = ctx.encrypt(0, A, 4, 3, 5, nonce=2), ctx.encrypt(1, B, 4, 3, 5, nonce=2)
+    with pytest.raises(hg.HGError) as e:
+        ctx.hegmm(cb, ca, 4, 3, 5)               # roles swapped
+    assert e.value.code == hg.HG_EINVAL
+    with pytest.raises(hg.HGError) as e:
+        ctx.hegmm(ca, cb, 4, 3, 6)               # other shape
+    assert e.value.code in (hg.HG_EINVAL, hg.HG_ENOKEY)
+    cc = ctx.hegmm(ca, cb, 4, 3, 5)
+    with pytest.raises(hg.HGError) as e:
+        ctx.decrypt(cc, 5, 3, 4)                 # result of another shape
+    assert e.value.code == hg.HG_EINVAL
+    with pytest.raises(hg.HGError) as e:
+        ctx.decrypt(ca, 4, 3, 5)                 # a packed operand, not a result
+    assert e.value.code == hg.HG_EINVAL
+
+
+def test_server_role_after_drop_secret(ctx):
+    """The cloud keeps only evaluation keys: products still run, encryption
+    and decryption are refused, and the client (who keeps the secret in its
+    own context) decrypts the exported result."""
+    A, B = workloads.tiny_operands()
+    c = workloads.TINY
+    client = hg.Context(c.N, c.t, c.L, c.alpha)
+    client.keygen(c.seed, [(4, 3, 5)])
+    wa = client.encrypt(0, A, 4, 3, 5, nonce=3).export()
+    wb = client.encrypt(1, B, 4, 3, 5, nonce=3).export()
+    ctx.drop_secret()
+    with pytest.raises(hg.HGError) as e:
+        ctx.encrypt(0, A, 4, 3, 5, nonce=4)
+    assert e.value.code == hg.HG_ESTATE
+    ca, cb = ctx.import_ct(wa, 1, 2), ctx.import_ct(wb, 1, 2)
+    # imported operands carry no shape: the product refuses them until they
+    # come from hg_encrypt for that shape
+    with pytest.raises(hg.HGError):
+        ctx.hegmm(ca, cb, 4, 3, 5)
+    with pytest.raises(hg.HGError) as e:
+        ctx.decrypt_slots(ca)
+    assert e.value.code == hg.HG_ESTATE
+    # the evaluation path through the server accepts serialised operands
+    with hg.Server(ctx, max_batch=2, lanes=1) as srv:
+        words, _ = srv.wait(srv.submit(wa, wb, 4, 3, 5))
+    C = client.decrypt(client.import_ct(words, 1, 2), 4, 3, 5)
+    assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t))
+
+
+def test_export_buffer_and_import_checks(ctx):
+    A, B = workloads.tiny_operands()
+    ca = ctx.encrypt(0, A, 4, 3, 5, nonce=5)
+    w = ca.export()
+    bad = w.copy()
+    bad[0] = np.uint64(2 ** 62)                  # residue out of range
+    with pytest.raises(hg.HGError) as e:
+        ctx.import_ct(bad, 1, 2)
+    assert e.value.code == hg.HG_EINVAL
+    with pytest.raises(hg.HGError) as e:
+        ctx.import_ct(w[:-1], 1, 2)              # wrong length
+    assert e.value.code == hg.HG_EINVAL
+
+
+def test_repeat_and_stream_determinism(ctx):
+    """The same product twice, on the null stream and on a second stream,
+    gives the same bits."""
+    A, B = workloads.tiny_operands()
+    ca, cb = ctx.encrypt(0, A, 4, 3, 5, nonce=6), ctx.encrypt(1, B, 4, 3, 5, nonce=6)
+    first = ctx.hegmm(ca, cb, 4, 3, 5).export()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        other = ctx.hegmm(ca, cb, 4, 3, 5)
+    s.synchronize()
+    assert np.array_equal(other.export(), first)
+    assert np.array_equal(ctx.hegmm(ca, cb, 4, 3, 5).export(), first)

@@ -321,3 +321,42 @@ def test_keyed_inner_products_bit_identical(alpha):
     ctx.tune("ip_chunk", 0)
     for i, (s, (A, B)) in enumerate(zip(shapes, mats)):
         assert np.array_equal(ctx.decrypt(ctx.import_ct(plain[i], 1, 2), *s), workloads.plain_matmul_mod(A, B, c.t))
+
+
+def test_graph_replay_matches_eager(tiny):
+    """A recorded batch (several launch windows) replays with the eager
+    results, with other eager work and synchronisations between replays, and
+    recomputes from operands refreshed in place."""
+    ctx = tiny.ctx
+    shapes = [(2, 5, 7), (5, 4, 2), (3, 11, 6), (4, 3, 5), (7, 7, 7)]
+    rng = np.random.default_rng(77)
+    mats = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    As = [ctx.encrypt(0, A, *s, nonce=200 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    Bs = [ctx.encrypt(1, B, *s, nonce=200 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    eager = [o.export() for o in ctx.hegmm_batch(As, Bs, shapes)]
+    ctx.tune("batch_window", 2)       # three launch windows, three private workspaces
+    try:
+        g = ctx.record_batch(As, Bs, shapes)
+    finally:
+        ctx.tune("batch_window", 64)
+    zero = np.zeros_like(eager[0])
+    for rep in range(3):
+        for o in g.outputs:
+            ctx.load_ct(o, zero)
+        ctx.hegmm(As[rep], Bs[rep], *shapes[rep])     # eager work between replays
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, s in enumerate(shapes):
+            assert np.array_equal(g.outputs[i].export(), eager[i]), (rep, s)
+    mats2 = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    for i, (s, (A, B)) in enumerate(zip(shapes, mats2)):
+        ctx.load_ct(As[i], ctx.encrypt(0, A, *s, nonce=300 + i).export())
+        ctx.load_ct(Bs[i], ctx.encrypt(1, B, *s, nonce=300 + i).export())
+    g.launch()
+    torch.cuda.synchronize()
+    again = [o.export() for o in ctx.hegmm_batch(As, Bs, shapes)]
+    for i, (s, (A, B)) in enumerate(zip(shapes, mats2)):
+        assert np.array_equal(g.outputs[i].export(), again[i]), s
+        assert np.array_equal(ctx.decrypt(g.outputs[i], *s), workloads.plain_matmul_mod(A, B, tiny.P.t)), s
+    g.close()
