@@ -406,6 +406,121 @@ __device__ __forceinline__ void inv_stages(double *sh, const double *tw, int ls,
     }
 }
 
+// Compile-time forms of the rounds above for the split transforms of a
+// known size: shapes, reduction pattern and twiddle offsets are constants and
+// each group's twiddles are loaded before its butterflies.
+template <int K, int LS, int NSUB, int S0, int SG0, int LOGN, bool FL>
+__device__ __forceinline__ void fwd_round_t(double *sh, const double *__restrict__ tw, int cb, int cs, double q,
+                                            double qi) {
+    constexpr int LTS = LS - S0 - K;
+    constexpr int TS = 1 << LTS;
+    constexpr int LGPS = LS - K;
+    constexpr int NG = NSUB << LGPS;
+    for (int grp = threadIdx.x; grp < NG; grp += blockDim.x) {
+        const int sb = grp >> LGPS;
+        const int lg = grp & ((1 << LGPS) - 1);
+        const int low = lg & (TS - 1);
+        const int blk = lg >> LTS;
+        const int base = (sb << LS) + (blk << (LTS + K)) + low;
+        const int C = cb + sb * cs;
+        double w[(1 << K) - 1];
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+            for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(C << (S0 + u)) + (blk << u) + c];
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            constexpr int dummy = 0;
+            (void)dummy;
+            const int s = S0 + u;
+            const int sg = SG0 + s;
+            const bool red = (sg & 1) || (sg == LOGN - 1) || (FL && s == LS - 1);
+            const int half = 1 << (K - 1 - u);
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & half) continue;
+                const double t = mulm(x[b + half], w[(1 << u) - 1 + (b >> (K - u))], q, qi);
+                const double X = x[b];
+                if (red) {
+                    x[b] = redm(X + t, q, qi);
+                    x[b + half] = redm(X - t, q, qi);
+                } else {
+                    x[b] = X + t;
+                    x[b + half] = X - t;
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+    }
+}
+
+template <int LS, int NSUB, int S0, int SG0, int LOGN, bool FL>
+__device__ __forceinline__ void fwd_stages_t(double *sh, const double *tw, int cb, int cs, double q, double qi) {
+    if constexpr (S0 < LS) {
+        constexpr int K = (LS - S0) < 4 ? (LS - S0) : 4;
+        fwd_round_t<K, LS, NSUB, S0, SG0, LOGN, FL>(sh, tw, cb, cs, q, qi);
+        __syncthreads();
+        fwd_stages_t<LS, NSUB, S0 + K, SG0, LOGN, FL>(sh, tw, cb, cs, q, qi);
+    }
+}
+
+template <int K, int LS, int NSUB, int LTS>
+__device__ __forceinline__ void inv_round_t(double *sh, const double *__restrict__ tw, int cb, int cs, double q,
+                                            double qi) {
+    constexpr int TS = 1 << LTS;
+    constexpr int LGPS = LS - K;
+    constexpr int NG = NSUB << LGPS;
+    for (int grp = threadIdx.x; grp < NG; grp += blockDim.x) {
+        const int sb = grp >> LGPS;
+        const int lg = grp & ((1 << LGPS) - 1);
+        const int low = lg & (TS - 1);
+        const int blk = lg >> LTS;
+        const int base = (sb << LS) + (blk << (LTS + K)) + low;
+        const int C = cb + sb * cs;
+        double w[(1 << K) - 1];
+        int wo = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+#pragma unroll
+            for (int c = 0; c < (1 << (K - u - 1)); ++c)
+                w[wo + c] = tw[((1 << LS) >> (LTS + u + 1)) * C + (blk << (K - u - 1)) + c];
+            wo += 1 << (K - u - 1);
+        }
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        wo = 0;
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int d = 1 << u;
+#pragma unroll
+            for (int b = 0; b < (1 << K); ++b) {
+                if (b & d) continue;
+                const double X = x[b], Y = x[b + d];
+                x[b] = redm(X + Y, q, qi);
+                x[b + d] = mulm(X - Y, w[wo + (b >> (u + 1))], q, qi);
+            }
+            wo += 1 << (K - u - 1);
+        }
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+    }
+}
+
+template <int LS, int NSUB, int LTS>
+__device__ __forceinline__ void inv_stages_t(double *sh, const double *tw, int cb, int cs, double q, double qi) {
+    if constexpr (LTS < LS) {
+        constexpr int K = (LS - LTS) < 4 ? (LS - LTS) : 4;
+        inv_round_t<K, LS, NSUB, LTS>(sh, tw, cb, cs, q, qi);
+        __syncthreads();
+        inv_stages_t<LS, NSUB, LTS + K>(sh, tw, cb, cs, q, qi);
+    }
+}
+
 // ---- per-row addressing and the fused load / store steps ----
 
 struct FwdRow {
@@ -563,11 +678,13 @@ __device__ __forceinline__ void split_dims(int logN, int &a, int &b) {
     b = logN - a;
 }
 
-template <int LOAD>
+// LOGN > 0: a size known at compile time (rounds fully unrolled, twiddles
+// preloaded); LOGN = 0: any size, runtime rounds.
+template <int LOAD, int LOGN>
 __global__ void __launch_bounds__(SPLIT_THREADS)
 k_ntt_fwd_cols(DevTables T, NttArgs a) {
     __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
-    const int logN = T.logN;
+    const int logN = LOGN > 0 ? LOGN : T.logN;
     int la, lb;
     split_dims(logN, la, lb);
     const int N2 = 1 << lb;
@@ -582,18 +699,24 @@ k_ntt_fwd_cols(DevTables T, NttArgs a) {
     }
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    fwd_stages(sh, T.twf + (size_t)R.prime * (1 << logN), la, cw, 0, 1, 0, 0, logN, true, q, qi);
+    const double *tw = T.twf + (size_t)R.prime * (1 << logN);
+    if constexpr (LOGN > 0) {
+        constexpr int LA = (LOGN + 1) >> 1;
+        fwd_stages_t<LA, (SPLIT_ELEMS >> LA), 0, 0, LOGN, true>(sh, tw, 1, 0, q, qi);
+    } else {
+        fwd_stages(sh, tw, la, cw, 0, 1, 0, 0, logN, true, q, qi);
+    }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
         R.out[c0 + cc + (j << lb)] = sh[lds_ix((cc << la) + j)];
     }
 }
 
-template <int LOAD>
+template <int LOAD, int LOGN>
 __global__ void __launch_bounds__(SPLIT_THREADS)
 k_ntt_fwd_blocks(DevTables T, NttArgs a) {
     __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
-    const int logN = T.logN;
+    const int logN = LOGN > 0 ? LOGN : T.logN;
     int la, lb;
     split_dims(logN, la, lb);
     const int N = 1 << logN;
@@ -606,14 +729,21 @@ k_ntt_fwd_blocks(DevTables T, NttArgs a) {
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     const int B0 = off >> lb;
-    fwd_stages(sh, T.twf + (size_t)R.prime * N, lb, bw, 0, (1 << la) + B0, 1, la, logN, false, q, qi);
+    const double *tw = T.twf + (size_t)R.prime * N;
+    if constexpr (LOGN > 0) {
+        constexpr int LA = (LOGN + 1) >> 1, LB = LOGN - LA;
+        fwd_stages_t<LB, (SPLIT_ELEMS >> LB), 0, LA, LOGN, false>(sh, tw, (1 << LA) + B0, 1, q, qi);
+    } else {
+        fwd_stages(sh, tw, lb, bw, 0, (1 << la) + B0, 1, la, logN, false, q, qi);
+    }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) fwd_store<LOAD>(T, R, off + e, sh[lds_ix(e)], q, qi);
 }
 
+template <int LOGN>
 __global__ void __launch_bounds__(SPLIT_THREADS)
 k_ntt_inv_blocks(DevTables T, NttArgs a) {
     __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
-    const int logN = T.logN;
+    const int logN = LOGN > 0 ? LOGN : T.logN;
     int la, lb;
     split_dims(logN, la, lb);
     const int N = 1 << logN;
@@ -626,15 +756,21 @@ k_ntt_inv_blocks(DevTables T, NttArgs a) {
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     const int B0 = off >> lb;
-    inv_stages(sh, T.twi + (size_t)R.prime * N, lb, bw, (1 << la) + B0, 1, q, qi);
+    const double *tw = T.twi + (size_t)R.prime * N;
+    if constexpr (LOGN > 0) {
+        constexpr int LA = (LOGN + 1) >> 1, LB = LOGN - LA;
+        inv_stages_t<LB, (SPLIT_ELEMS >> LB), 0>(sh, tw, (1 << LA) + B0, 1, q, qi);
+    } else {
+        inv_stages(sh, tw, lb, bw, (1 << la) + B0, 1, q, qi);
+    }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) R.out[off + e] = sh[lds_ix(e)];
 }
 
-template <int STORE>
+template <int STORE, int LOGN>
 __global__ void __launch_bounds__(SPLIT_THREADS)
 k_ntt_inv_cols(DevTables T, NttArgs a) {
     __shared__ double sh[SPLIT_ELEMS + SPLIT_ELEMS / 16];
-    const int logN = T.logN;
+    const int logN = LOGN > 0 ? LOGN : T.logN;
     int la, lb;
     split_dims(logN, la, lb);
     const int N2 = 1 << lb;
@@ -649,7 +785,13 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
     }
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    inv_stages(sh, T.twi + (size_t)R.prime * (1 << logN), la, cw, 1, 0, q, qi);
+    const double *tw = T.twi + (size_t)R.prime * (1 << logN);
+    if constexpr (LOGN > 0) {
+        constexpr int LA = (LOGN + 1) >> 1;
+        inv_stages_t<LA, (SPLIT_ELEMS >> LA), 0>(sh, tw, 1, 0, q, qi);
+    } else {
+        inv_stages(sh, tw, la, cw, 1, 0, q, qi);
+    }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
         inv_store<STORE>(T, R, c0 + cc + (j << lb), sh[lds_ix((cc << la) + j)], q, qi);
@@ -811,16 +953,17 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) 
     if (a.rows <= 0) return;
     if (use_split(T, a.rows)) {
         dim3 grid((unsigned)(a.rows * (T.N / SPLIT_ELEMS))), block(SPLIT_THREADS);
-        switch (mode) {
-            case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd_cols<LOAD_MODUP>, grid, block, 0, s, T, a); break;
-            case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd_cols<LOAD_DELTA>, grid, block, 0, s, T, a); break;
-            default: hipLaunchKernelGGL(k_ntt_fwd_cols<LOAD_PLAIN>, grid, block, 0, s, T, a); break;
-        }
-        switch (mode) {
-            case LOAD_MODUP: hipLaunchKernelGGL(k_ntt_fwd_blocks<LOAD_MODUP>, grid, block, 0, s, T, a); break;
-            case LOAD_DELTA: hipLaunchKernelGGL(k_ntt_fwd_blocks<LOAD_DELTA>, grid, block, 0, s, T, a); break;
-            default: hipLaunchKernelGGL(k_ntt_fwd_blocks<LOAD_PLAIN>, grid, block, 0, s, T, a); break;
-        }
+#define HG_SPLIT_FWD(LN)                                                                                             \
+    switch (mode) {                                                                                                 \
+        case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd_cols<LOAD_MODUP, LN>), grid, block, 0, s, T, a);             \
+                         hipLaunchKernelGGL((k_ntt_fwd_blocks<LOAD_MODUP, LN>), grid, block, 0, s, T, a); break;    \
+        case LOAD_DELTA: hipLaunchKernelGGL((k_ntt_fwd_cols<LOAD_DELTA, LN>), grid, block, 0, s, T, a);             \
+                         hipLaunchKernelGGL((k_ntt_fwd_blocks<LOAD_DELTA, LN>), grid, block, 0, s, T, a); break;    \
+        default: hipLaunchKernelGGL((k_ntt_fwd_cols<LOAD_PLAIN, LN>), grid, block, 0, s, T, a);                     \
+                 hipLaunchKernelGGL((k_ntt_fwd_blocks<LOAD_PLAIN, LN>), grid, block, 0, s, T, a); break;            \
+    }
+        if (T.logN == 15) { HG_SPLIT_FWD(15) } else { HG_SPLIT_FWD(0) }
+#undef HG_SPLIT_FWD
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
@@ -839,12 +982,15 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
     if (a.rows <= 0) return;
     if (use_split(T, a.rows)) {
         dim3 grid((unsigned)(a.rows * (T.N / SPLIT_ELEMS))), block(SPLIT_THREADS);
-        hipLaunchKernelGGL(k_ntt_inv_blocks, grid, block, 0, s, T, a);
-        switch (mode) {
-            case STORE_MDR: hipLaunchKernelGGL(k_ntt_inv_cols<STORE_MDR>, grid, block, 0, s, T, a); break;
-            case STORE_CANON: hipLaunchKernelGGL(k_ntt_inv_cols<STORE_CANON>, grid, block, 0, s, T, a); break;
-            default: hipLaunchKernelGGL(k_ntt_inv_cols<STORE_PLAIN>, grid, block, 0, s, T, a); break;
-        }
+#define HG_SPLIT_INV(LN)                                                                                          \
+    hipLaunchKernelGGL((k_ntt_inv_blocks<LN>), grid, block, 0, s, T, a);                                          \
+    switch (mode) {                                                                                              \
+        case STORE_MDR: hipLaunchKernelGGL((k_ntt_inv_cols<STORE_MDR, LN>), grid, block, 0, s, T, a); break;     \
+        case STORE_CANON: hipLaunchKernelGGL((k_ntt_inv_cols<STORE_CANON, LN>), grid, block, 0, s, T, a); break; \
+        default: hipLaunchKernelGGL((k_ntt_inv_cols<STORE_PLAIN, LN>), grid, block, 0, s, T, a); break;          \
+    }
+        if (T.logN == 15) { HG_SPLIT_INV(15) } else { HG_SPLIT_INV(0) }
+#undef HG_SPLIT_INV
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
