@@ -46,6 +46,7 @@ class Plan:
     eps: List[List[Tuple[int, Optional[frozenset]]]]    # per k: (z, mask slots or None)
     omega: List[List[Tuple[int, Optional[frozenset]]]]
     fold: List[int]        # rotation amounts summed after relinearisation (0 first)
+    method: int = 2        # 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1)
 
     def rotations(self, S: int) -> List[int]:
         zs = set()
@@ -76,9 +77,11 @@ def orientation(m: int, l: int, n: int) -> bool:
     return p == n
 
 
-def plan(m: int, l: int, n: int, S: int) -> Plan:
+def plan(m: int, l: int, n: int, S: int, method: int = 2) -> Plan:
     if min(m, l, n) <= 0:
         raise ValueError("dimensions must be positive")
+    if method == 1:
+        return plan_alg1(m, l, n, S)
     tr = orientation(m, l, n)
     mo, no = (n, m) if tr else (m, n)
 
@@ -103,6 +106,60 @@ def plan(m: int, l: int, n: int, S: int) -> Plan:
         omega.append(_terms(omega_diagonals(lb, no, M, k), region, [k, k - lb]))
     fold = [h * mo for h in range(d)]
     return Plan(m, l, n, tr, mo, no, nb, lb, d, M, K, W, eps, omega, fold)
+
+
+def alg1_eps_diagonals(mo: int, l: int, no: int, k: int) -> Dict[int, set]:
+    """Algorithm 1's eps^k_{mo x no} on sigma(X) flattened column-major
+    (mo x l, column stride mo): output (i, j) reads column (j + k) mod l,
+    i.e. slot i + ((j + k) mod l) mo, a left rotation by the difference."""
+    cand: Dict[int, set] = {}
+    for i in range(mo):
+        for j in range(no):
+            src = i + ((j + k) % l) * mo
+            cand.setdefault(src - (i + j * mo), set()).add(i + j * mo)
+    return cand
+
+
+def alg1_omega_diagonals(mo: int, l: int, no: int, k: int) -> Dict[int, set]:
+    """Algorithm 1's omega^k_{mo x no} on tau(Y) flattened column-major
+    (l x no, column stride l): output (i, j) reads row (i + k) mod l of
+    column j, i.e. slot ((i + k) mod l) + j l."""
+    cand: Dict[int, set] = {}
+    for i in range(mo):
+        for j in range(no):
+            src = ((i + k) % l) + j * l
+            cand.setdefault(src - (i + j * mo), set()).add(i + j * mo)
+    return cand
+
+
+def _alg1_count(mo: int, l: int, no: int, S: int) -> int:
+    c = 0
+    for k in range(l):
+        for cand in (alg1_eps_diagonals(mo, l, no, k), alg1_omega_diagonals(mo, l, no, k)):
+            c += sum(1 for z in cand if z % S)
+    return c
+
+
+def plan_alg1(m: int, l: int, n: int, S: int) -> Plan:
+    """Algorithm 1 (HEGMM): C = sum_{k<l} eps^k(sigma(A)) (.) omega^k(tau(B)),
+    sigma and tau applied by the client while packing (as in the paper's
+    experiments), matrices flattened column-major -- or row-major, i.e. the
+    transposed problem B^T A^T column-major, when that needs fewer
+    key-switched diagonals in total (ties: column-major).  No duplication, so
+    d = 1 and no fold; the result sits at slot i + j m (j + i n transposed).
+    Needs max(m l, l n, m n) <= S."""
+    if max(m * l, l * n, m * n) > S:
+        raise ValueError("shape does not fit one ciphertext")
+    tr = _alg1_count(n, l, m, S) < _alg1_count(m, l, n, S)
+    mo, no = (n, m) if tr else (m, n)
+    region = frozenset(i + j * mo for i in range(mo) for j in range(no))
+    eps, omega = [], []
+    for k in range(l):
+        ce = alg1_eps_diagonals(mo, l, no, k)
+        cw = alg1_omega_diagonals(mo, l, no, k)
+        eps.append(_terms(ce, region, sorted(ce)))
+        omega.append(_terms(cw, region, sorted(cw)))
+    return Plan(m, l, n, tr, mo, no, 1, l, 1, mo, l, l, eps, omega, [0], method=1)
 
 
 def eps_diagonals(mo: int, lb: int, no: int, M: int, W: int, k: int) -> Dict[int, set]:
@@ -160,9 +217,16 @@ def oriented_operands(pl: Plan, A: np.ndarray, B: np.ndarray):
 
 
 def pack_left(pl: Plan, X: np.ndarray, block: int, t: int, S: int) -> List[int]:
-    """x[i + c*M] = Xb[i mod mo][(i + c) mod lb] for i < M, c < W: the
+    """Algorithm 1: x[i + c*mo] = X[i][(i + c) mod l], sigma(X) column-major.
+    Algorithm 2: x[i + c*M] = Xb[i mod mo][(i + c) mod lb] for i < M, c < W: the
     client-side eps^0_{M x W}(sigma(Xbar)) of Algorithm 2, with Xbar the d
     stacked copies of the block Xb, flattened column-major."""
+    if pl.method == 1:
+        x = [0] * S
+        for i in range(pl.mo):
+            for c in range(pl.l):
+                x[i + c * pl.mo] = int(X[i][(i + c) % pl.l]) % t
+        return x
     Xb = np.zeros((pl.mo, pl.lb), dtype=np.int64)
     lo = block * pl.lb
     hi = min(pl.l, lo + pl.lb)
@@ -175,8 +239,15 @@ def pack_left(pl: Plan, X: np.ndarray, block: int, t: int, S: int) -> List[int]:
 
 
 def pack_right(pl: Plan, Y: np.ndarray, block: int, t: int, S: int) -> List[int]:
-    """y[r + j*M] = Yb[(r + j) mod lb][j] for r < M, j < no: the client-side
-    omega^0_{M x no}(tau(Yb)), flattened column-major."""
+    """Algorithm 1: y[r + j*l] = Y[(r + j) mod l][j], tau(Y) column-major.
+    Algorithm 2: y[r + j*M] = Yb[(r + j) mod lb][j] for r < M, j < no: the
+    client-side omega^0_{M x no}(tau(Yb)), flattened column-major."""
+    if pl.method == 1:
+        y = [0] * S
+        for r in range(pl.l):
+            for j in range(pl.no):
+                y[r + j * pl.l] = int(Y[(r + j) % pl.l][j]) % t
+        return y
     Yb = np.zeros((pl.lb, pl.no), dtype=np.int64)
     lo = block * pl.lb
     hi = min(pl.l, lo + pl.lb)
@@ -254,10 +325,10 @@ class MaskCache:
         return m
 
 
-def galois_elements(P: Params, shapes: Sequence[Tuple[int, int, int]]) -> List[int]:
+def galois_elements(P: Params, shapes: Sequence[Tuple[int, int, int]], method: int = 2) -> List[int]:
     gs = set()
     for (m, l, n) in shapes:
-        pl = plan(m, l, n, P.S)
+        pl = plan(m, l, n, P.S, method)
         for z in pl.rotations(P.S):
             gs.add(P.galois(z))
     return sorted(gs)

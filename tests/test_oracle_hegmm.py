@@ -215,3 +215,68 @@ def test_tiny_config_end_to_end():
     assert (H.decrypt_result(ks, pl, C) == workloads.plain_matmul_mod(A, B, P.t)).all()
     mu = bgv.decrypt_poly(ks, C)
     assert bgv.noise_bits(ks, C, mu) < np.log2(float(P.Q)) - 2
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 (HEGMM) variant
+# ---------------------------------------------------------------------------
+
+def test_alg1_figure_diagonals():
+    """The eps^1 / omega^1 examples of the transform figure (Section III-B):
+    Algorithm 1 flattens column-major without duplication, so its diagonals
+    are exactly the captioned ones."""
+    g = GOLDEN["eps1_5x3"]
+    got = {z: sorted(s) for z, s in H.alg1_eps_diagonals(5, 3, 3, 1).items()}
+    assert got == {int(z): v for z, v in g["diagonals"].items()}
+    g = GOLDEN["omega1_3x5"]
+    got = {z: len(s) for z, s in H.alg1_omega_diagonals(3, 3, 5, 1).items()}
+    assert got == {int(z): v for z, v in g["diagonal_sizes"].items()}
+
+
+def test_alg1_iterations_and_eps_bound():
+    """l iterations (the mm-example figure: 5x3 times 3x4 takes 3), and at
+    most ceil(n/l) + 1 diagonals per eps^k in column-major (corrected
+    Theorem 3)."""
+    g = GOLDEN["alg1_5x3x4"]
+    assert H.plan(g["m"], g["l"], g["n"], 4096, method=1).K == g["iterations"]
+    for m in range(1, 9):
+        for l in range(1, 9):
+            for n in range(1, 9):
+                for k in range(l):
+                    assert len(H.alg1_eps_diagonals(m, l, n, k)) <= -(-n // l) + 1
+
+
+@pytest.mark.parametrize("shape", [(5, 3, 3), (3, 3, 5), (4, 3, 5), (2, 5, 7), (7, 3, 2), (6, 4, 9), (1, 6, 1), (9, 1, 4)])
+def test_alg1_cleartext_twin(shape):
+    m, l, n = shape
+    rng = np.random.default_rng(m * 100 + l * 10 + n)
+    A = rng.integers(-8, 9, size=(m, l))
+    B = rng.integers(-8, 9, size=(l, n))
+    pl = H.plan(m, l, n, 512, method=1)
+    assert pl.method == 1 and pl.d == 1 and pl.nb == 1 and pl.K == l
+    assert np.array_equal(H.hegmm_cleartext(pl, A, B, 12289, 512), workloads.plain_matmul_mod(A, B, 12289))
+
+
+def test_alg1_needs_more_rotations_than_en():
+    """The point of Algorithm 2: on the headline shape HEGMM-En needs far
+    fewer key-switched rotations than Algorithm 1."""
+    en = H.plan(64, 32, 48, 4096)
+    a1 = H.plan(64, 32, 48, 4096, method=1)
+    count = lambda pl: sum(1 for ts in pl.eps + pl.omega for z, _ in ts if z % 4096)
+    assert count(a1) > 2 * count(en)
+
+
+def test_alg1_encrypted_small():
+    c = workloads.TINY
+    P = Params(c.N, c.t, c.L, c.alpha)
+    shapes = [(4, 3, 5), (3, 5, 2)]
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, shapes, method=1))
+    rng = np.random.default_rng(8)
+    for (m, l, n) in shapes:
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        pl = H.plan(m, l, n, P.S, method=1)
+        ox = H.encrypt_operand(ks, pl, 0, A, B, 3)
+        oy = H.encrypt_operand(ks, pl, 1, A, B, 3)
+        C = H.decrypt_result(ks, pl, H.hegmm(ks, pl, ox, oy))
+        assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t)), (m, l, n)
