@@ -35,10 +35,11 @@ def parse():
                     help="bounded CPU-oracle sample: run whole oracle matmuls until this much time passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "serving", "large"],
+    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "serving", "large", "alg1"],
                     help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step; "
                          "serving: 512 Poisson arrivals at N=16384 through the continuous-batching server; "
-                         "large: one 128x96x128 product per step at N=32768")
+                         "large: one 128x96x128 product per step at N=32768; "
+                         "alg1: the headline product with the paper's Algorithm 1 instead of HEGMM-En")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
     ap.add_argument("--max-batch", type=int, default=4, help="serving: products per launch group")
@@ -301,6 +302,46 @@ def run_large(args):
                      "algorithmic_bytes_per_launch": ip_bytes, "avg_launch_ms": phases["ip_kernel"]}}), flush=True)
 
 
+def run_alg1(args):
+    """The headline product (64x32x48, N=8192) computed with the paper's
+    Algorithm 1 (no duplication, l iterations, more diagonals) beside
+    HEGMM-En, both on resident operands and decrypt-checked: the GPU view of
+    the op-count gap Algorithm 2 was designed to close."""
+    import torch
+    import paper_2405_02238_amd as hg
+    import workloads
+
+    cfg = workloads.HEADLINE
+    m, l, n = 64, 32, 48
+    A, B = workloads.headline_operands()
+    want = workloads.plain_matmul_mod(A, B, cfg.t)
+    res = {}
+    for method in (1, 2):
+        ctx = hg.Context(cfg.N, cfg.t, cfg.L, cfg.alpha, method=method)
+        ctx.keygen(cfg.seed, [(m, l, n)])
+        ca, cb = ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1)
+        info = ctx.plan_info(m, l, n)
+        outs = [ctx.hegmm(ca, cb, m, l, n) for _ in range(args.warmup)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = [ctx.hegmm(ca, cb, m, l, n) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        ok = bool(np.array_equal(ctx.decrypt(outs[-1], m, l, n), want))
+        res[method] = {"ms_per_matmul": ms, "matmuls_per_s": 1000.0 / ms if ok else 0.0, "decrypt_ok": ok,
+                       "key_switched_rotations": info["ks_terms"], "rotation_keys": info["rotations"],
+                       "iterations": info["K"], "transposed": bool(info["transposed"])}
+        del outs, ctx
+    v = res[1]["matmuls_per_s"]
+    print(json.dumps({
+        "metric": "HE matmuls/s at N=8192 64x32x48 with Algorithm 1 (HEGMM)", "value": v, "unit": "HE matmuls/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[1]["ms_per_matmul"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "HEGMM A(64x32) x B(32x48), Algorithm 1, BGV N=8192 t=65537 L=4 alpha=1"},
+        "algorithm1": res[1], "hegmm_en": res[2],
+        "en_speedup_over_alg1": res[2]["matmuls_per_s"] / v if v else None}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -314,6 +355,8 @@ def main():
         return run_serving(args)
     if args.workload == "large":
         return run_large(args)
+    if args.workload == "alg1":
+        return run_alg1(args)
     import torch
     import paper_2405_02238_amd as hg
     import workloads

@@ -64,6 +64,8 @@ typedef struct {
     uint64_t t;
     uint32_t L;
     uint32_t alpha;
+    uint32_t method;   /* 0 or 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1, column- or
+                          row-major, no duplication or blocking; for comparison) */
 } hg_params;
 
 /* Create a context on HIP device `hip_device` (must be gfx950).

@@ -37,7 +37,7 @@ class _ServerConfig(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_uint32),
-                ("alpha", ctypes.c_uint32)]
+                ("alpha", ctypes.c_uint32), ("method", ctypes.c_uint32)]
 
 
 _lib = None
@@ -161,13 +161,14 @@ class Ciphertext:
 class Context:
     """hg_ctx: one BGV parameter set on one GPU."""
 
-    def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0):
+    def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0, method: int = 2):
+        """method 2: HEGMM-En (Algorithm 2); method 1: Algorithm 1, for comparison."""
         load()
-        p = _Params(N, t, L, alpha)
+        p = _Params(N, t, L, alpha, method)
         out = ctypes.c_void_p()
         _check(_lib.hg_ctx_create(ctypes.byref(p), device, ctypes.byref(out)))
         self.ptr = out.value
-        self.N, self.t, self.L, self.alpha = N, t, L, alpha
+        self.N, self.t, self.L, self.alpha, self.method = N, t, L, alpha, method
         self.S = N // 2
 
     def close(self):

@@ -59,7 +59,9 @@ Ct::~Ct() {
 // set-up
 // ---------------------------------------------------------------------------
 
-Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_) {
+Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, int method_) {
+    if (method_ != 1 && method_ != 2) throw Error(-1, "method must be 1 or 2");
+    method = method_;
     if (N_ < 64 || N_ > 32768 || (N_ & (N_ - 1))) throw Error(-1, "N must be a power of two in [64, 32768]");
     if (L_ < 1 || L_ > 12 || alpha_ < 1 || alpha_ > 4 || L_ + alpha_ > 16)
         throw Error(-1, "need 1 <= L <= 12, 1 <= alpha <= 4, L + alpha <= 16");
@@ -255,7 +257,7 @@ const PlanEntry &Ctx::plan_for(int m, int l, int n) {
     if (it != plans.end()) return *it->second;
     auto pe = std::make_unique<PlanEntry>();
     try {
-        pe->plan = make_plan(m, l, n, S);
+        pe->plan = make_plan(m, l, n, S, method);
     } catch (std::invalid_argument &e) {
         throw Error(-1, e.what());
     } catch (std::range_error &e) {

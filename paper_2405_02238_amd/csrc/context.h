@@ -115,7 +115,8 @@ struct Ctx {
     hipStream_t side_stream(hipStream_t st);
     hipEvent_t event(hipStream_t st, bool timing);
 
-    Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device);
+    int method = 2;        // 2: HEGMM-En; 1: the paper's Algorithm 1
+    Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device, int method = 2);
     ~Ctx();
 
     double *dev_alloc(size_t words);

@@ -42,10 +42,82 @@ void add_terms(Plan &p, std::vector<Term> &out, std::map<int, std::vector<int>> 
     }
 }
 
+// Every diagonal found, in increasing z; a lone diagonal covering the whole
+// region needs no mask.
+void add_all_terms(Plan &p, std::vector<Term> &out, const std::map<int, std::vector<int>> &cand, int S,
+                   size_t region) {
+    if (cand.size() == 1 && cand.begin()->second.size() == region) {
+        out.push_back({cand.begin()->first, -1});
+        return;
+    }
+    for (auto &kv : cand) {
+        std::vector<uint8_t> bm(S, 0);
+        for (int s : kv.second) bm[s] = 1;
+        p.masks.push_back(std::move(bm));
+        out.push_back({kv.first, (int)p.masks.size() - 1});
+    }
+}
+
+// Algorithm 1's transforms on column-major sigma(X) (mo x l) and tau(Y)
+// (l x no): output (i, j) reads slot i + ((j + k) mod l) mo, resp.
+// ((i + k) mod l) + j l; the diagonal is the difference of the slots.
+std::map<int, std::vector<int>> alg1_eps(int mo, int l, int no, int k) {
+    std::map<int, std::vector<int>> cand;
+    for (int j = 0; j < no; ++j)
+        for (int i = 0; i < mo; ++i) {
+            const int dst = i + j * mo;
+            cand[i + ((j + k) % l) * mo - dst].push_back(dst);
+        }
+    return cand;
+}
+
+std::map<int, std::vector<int>> alg1_omega(int mo, int l, int no, int k) {
+    std::map<int, std::vector<int>> cand;
+    for (int j = 0; j < no; ++j)
+        for (int i = 0; i < mo; ++i) {
+            const int dst = i + j * mo;
+            cand[((i + k) % l) + j * l - dst].push_back(dst);
+        }
+    return cand;
+}
+
+long long alg1_switched(int mo, int l, int no, int S) {
+    long long c = 0;
+    for (int k = 0; k < l; ++k) {
+        for (auto &kv : alg1_eps(mo, l, no, k)) c += (((kv.first % S) + S) % S) != 0;
+        for (auto &kv : alg1_omega(mo, l, no, k)) c += (((kv.first % S) + S) % S) != 0;
+    }
+    return c;
+}
+
+Plan make_plan_alg1(int m, int l, int n, int S) {
+    if ((long long)m * l > S || (long long)l * n > S || (long long)m * n > S)
+        throw std::range_error("shape does not fit one ciphertext row");
+    Plan p;
+    p.method = 1;
+    p.m = m; p.l = l; p.n = n;
+    p.transposed = alg1_switched(n, l, m, S) < alg1_switched(m, l, n, S);
+    p.mo = p.transposed ? n : m;
+    p.no = p.transposed ? m : n;
+    p.nb = 1; p.lb = l; p.d = 1; p.M = p.mo; p.K = l; p.W = l;
+    const size_t region = (size_t)p.mo * p.no;
+    for (int k = 0; k < l; ++k) {
+        std::vector<Term> e, w;
+        add_all_terms(p, e, alg1_eps(p.mo, l, p.no, k), S, region);
+        add_all_terms(p, w, alg1_omega(p.mo, l, p.no, k), S, region);
+        p.eps.push_back(e);
+        p.omega.push_back(w);
+    }
+    p.fold.push_back(0);
+    return p;
+}
+
 }  // namespace
 
-Plan make_plan(int m, int l, int n, int S) {
+Plan make_plan(int m, int l, int n, int S, int method) {
     if (m <= 0 || l <= 0 || n <= 0) throw std::invalid_argument("dimensions must be positive");
+    if (method == 1) return make_plan_alg1(m, l, n, S);
+    if (method != 2) throw std::invalid_argument("method must be 1 or 2");
     Plan p;
     p.m = m; p.l = l; p.n = n;
     // Orientation in Algorithm 2's order: p == m duplicates A; else p == n
@@ -141,6 +213,23 @@ std::vector<uint64_t> pack_operand(const Plan &p, int side, const int64_t *X, in
         return (uint64_t)(r < 0 ? r + (int64_t)t : r);
     };
     const int lo = block * p.lb;
+    if (p.method == 1) {
+        // Algorithm 1: sigma(Xo) (mo x l) and tau(Yo) (l x no), column-major
+        if (side == 0) {
+            for (int i = 0; i < p.mo; ++i)
+                for (int c = 0; c < p.l; ++c) {
+                    const int cc = (i + c) % p.l;
+                    v[i + (size_t)c * p.mo] = modt(p.transposed ? X[(size_t)cc * p.n + i] : X[(size_t)i * p.l + cc]);
+                }
+        } else {
+            for (int r = 0; r < p.l; ++r)
+                for (int j = 0; j < p.no; ++j) {
+                    const int rr = (r + j) % p.l;
+                    v[r + (size_t)j * p.l] = modt(p.transposed ? X[(size_t)j * p.l + rr] : X[(size_t)rr * p.n + j]);
+                }
+        }
+        return v;
+    }
     // entries of the oriented operands, zero outside the block
     if (side == 0) {
         // left operand Xo (mo x l): A itself, or B^T when transposed (X = B, l x n)

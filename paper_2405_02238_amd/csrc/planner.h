@@ -28,13 +28,17 @@ struct Plan {
     std::vector<std::vector<Term>> eps, omega;  // per k
     std::vector<int> fold;                      // h * mo, h = 0..d-1
     std::vector<std::vector<uint8_t>> masks;    // S bytes each, 1 = slot kept
+    int method = 2;                             // 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1)
     std::vector<int> rotations(int S) const;    // distinct nonzero z mod S
     int key_switched_terms(int S) const;        // terms that need a key switch
 };
 
 // Throws std::invalid_argument when a dimension is not positive and
 // std::range_error when the shape cannot be planned into S slots.
-Plan make_plan(int m, int l, int n, int S);
+// method 2: HEGMM-En; method 1: the paper's Algorithm 1 (HEGMM), sigma and
+// tau applied by the client, column-major or (when that needs fewer
+// key-switched diagonals) row-major flattening, no duplication, no blocking.
+Plan make_plan(int m, int l, int n, int S, int method = 2);
 
 // Client packing: the slot vector (length S, values in [0, t)) of the left
 // (side 0) or right (side 1) operand of the oriented problem for inner block

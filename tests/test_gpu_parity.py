@@ -360,3 +360,30 @@ def test_graph_replay_matches_eager(tiny):
         assert np.array_equal(g.outputs[i].export(), again[i]), s
         assert np.array_equal(ctx.decrypt(g.outputs[i], *s), workloads.plain_matmul_mod(A, B, tiny.P.t)), s
     g.close()
+
+
+@pytest.mark.parametrize("shape", [(4, 3, 5), (3, 5, 2), (5, 3, 3), (2, 7, 6)])
+def test_algorithm1_variant(shape):
+    """Algorithm 1 (HEGMM, no duplication; column- or row-major whichever
+    needs fewer key switches) against the oracle's Algorithm 1, bit for bit."""
+    c = workloads.TINY
+    m, l, n = shape
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, method=1)
+    ctx.keygen(c.seed, [shape])
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [shape], method=1))
+    pl = H.plan(m, l, n, P.S, method=1)
+    info = ctx.plan_info(m, l, n)
+    assert info["transposed"] == int(pl.transposed) and info["K"] == l and info["d"] == 1
+    rng = np.random.default_rng(m + 10 * l + 100 * n)
+    A = rng.integers(-8, 9, size=(m, l))
+    B = rng.integers(-8, 9, size=(l, n))
+    ca, cb = ctx.encrypt(0, A, m, l, n, nonce=4), ctx.encrypt(1, B, m, l, n, nonce=4)
+    ox = H.encrypt_operand(ks, pl, 0, A, B, 4)
+    oy = H.encrypt_operand(ks, pl, 1, A, B, 4)
+    left, right = (cb, ca) if pl.transposed else (ca, cb)
+    assert np.array_equal(left.export(), np.concatenate([flat(x) for x in ox]))
+    assert np.array_equal(right.export(), np.concatenate([flat(y) for y in oy]))
+    cc = ctx.hegmm(ca, cb, m, l, n)
+    assert np.array_equal(cc.export(), flat(H.hegmm(ks, pl, ox, oy))), shape
+    assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
