@@ -33,6 +33,15 @@ constexpr int SPLIT_THREADS = SPLIT_ELEMS / 16;
 
 __device__ __forceinline__ int lds_ix(int i) { return i + (i >> 4); }
 
+// LDS index of element base + b * TS.  When TS is a multiple of 16 the
+// padding term splits, so every element sits at a constant offset from the
+// first (immediate offsets in the LDS instructions instead of index math).
+template <int TS>
+__device__ __forceinline__ int lds_ix_step(int base, int b) {
+    if constexpr (TS % 16 == 0) return lds_ix(base) + b * (TS + TS / 16);
+    else return lds_ix(base + b * TS);
+}
+
 // log2 of the radix of the whole-row transforms: each thread owns 2^RK
 // elements per round, so a row uses N / 2^RK threads.  Radix 8 for 4096- and
 // 8192-point rows (more waves per row to hide FP64 and LDS latency), radix
@@ -67,7 +76,7 @@ __device__ __forceinline__ void fwd_round_c(double *sh, const double *__restrict
             for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (S0 + u)) + (blk << u) + c];
         double x[1 << K];
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
 #pragma unroll
         for (int u = 0; u < K; ++u) {
             constexpr int dummy = 0;
@@ -89,7 +98,7 @@ __device__ __forceinline__ void fwd_round_c(double *sh, const double *__restrict
             }
         }
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
     }
 }
 
@@ -125,7 +134,7 @@ __device__ __forceinline__ void inv_round_c(double *sh, const double *__restrict
         }
         double x[1 << K];
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         wo = 0;
 #pragma unroll
         for (int u = 0; u < K; ++u) {
@@ -140,7 +149,7 @@ __device__ __forceinline__ void inv_round_c(double *sh, const double *__restrict
             wo += 1 << (K - u - 1);
         }
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
     }
 }
 
@@ -186,7 +195,7 @@ __device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict
         const int base = (blk << (LTS + K)) + low;
         double x[1 << K];
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         constexpr int S1 = S0 + K;
         constexpr bool PF = S1 < LOGN && FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::K == rk_of(LOGN);
         constexpr int NWN = PF ? FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::NW : 1;
@@ -211,7 +220,7 @@ __device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict
             }
         }
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
         if constexpr (S1 < LOGN) fwd_rows_pf<LOGN, S1>(sh, tw, q, qi, grp, wnext);
     }
@@ -248,7 +257,7 @@ __device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict
         const int base = (blk << (LTS0 + K)) + low;
         double x[1 << K];
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         constexpr int L1 = LTS0 + K;
         constexpr bool PF = L1 < LOGN && InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::K == rk_of(LOGN);
         constexpr int NWN = PF ? InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::NW : 1;
@@ -268,7 +277,7 @@ __device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict
             wo += 1 << (K - u - 1);
         }
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
         if constexpr (L1 < LOGN) inv_rows_pf<LOGN, L1>(sh, tw, q, qi, grp, wnext);
     }
@@ -430,7 +439,7 @@ __device__ __forceinline__ void fwd_round_t(double *sh, const double *__restrict
             for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(C << (S0 + u)) + (blk << u) + c];
         double x[1 << K];
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
 #pragma unroll
         for (int u = 0; u < K; ++u) {
             constexpr int dummy = 0;
@@ -454,7 +463,7 @@ __device__ __forceinline__ void fwd_round_t(double *sh, const double *__restrict
             }
         }
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
     }
 }
 
@@ -492,7 +501,7 @@ __device__ __forceinline__ void inv_round_t(double *sh, const double *__restrict
         }
         double x[1 << K];
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix(base + b * TS)];
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         wo = 0;
 #pragma unroll
         for (int u = 0; u < K; ++u) {
@@ -507,7 +516,7 @@ __device__ __forceinline__ void inv_round_t(double *sh, const double *__restrict
             wo += 1 << (K - u - 1);
         }
 #pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix(base + b * TS)] = x[b];
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
     }
 }
 
