@@ -107,7 +107,7 @@ struct Ctx {
     bool capturing = false;
     Arena &arena_for(hipStream_t st);
     Timing timing;
-    int fuse_rows = 512;  // passes with at most this many rows per chain use the fused kernels
+    int fuse_rows = 256;  // passes with at most this many rows per chain use the fused kernels
     int ip_chunk = 16;    // terms sharing a key per workgroup in the key-stationary inner products (0: off)
     int batch_window = 64; // products per launch group in hegmm_batch (0: all)
     int pipeline = 1;      // chunks of a pass whose inner products and division by P overlap (1: off)

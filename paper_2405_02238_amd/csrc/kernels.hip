@@ -286,32 +286,63 @@ __device__ __forceinline__ void finish_one(const DevTables &T, const FinJob &J, 
     }
 }
 
-constexpr int FT_P = 64;  // positions per block of the tensor accumulation
-constexpr int FT_C = 4;   // pair chunks per block, reduced through LDS
+// finish_one for the two positions p, p + 1 (p even), 16-byte loads.
+__device__ __forceinline__ void finish_two(const DevTables &T, const FinJob &J, const FinTerm *terms,
+                                           const double *E, const double *const *masks, int i, int p, double q,
+                                           double qi, double2 &e0, double2 &e1) {
+    const int N = 1 << T.logN;
+    const size_t off = (size_t)i * N + p;
+    if (J.ks >= 0) {
+        const size_t plane = (size_t)T.L * N;
+        const double *e = E + (size_t)J.ks * 2 * plane + off;
+        e0 = *(const double2 *)e;
+        e1 = *(const double2 *)(e + plane);
+        return;
+    }
+    e0 = make_double2(0.0, 0.0);
+    e1 = make_double2(0.0, 0.0);
+    for (int t = J.t0; t < J.t0 + J.nt; ++t) {
+        const FinTerm ft = terms[t];
+        double2 x0 = *(const double2 *)(J.c0 + off), x1 = *(const double2 *)(J.c1 + off);
+        if (ft.mask >= 0) {
+            const double2 mv = *(const double2 *)(masks[ft.mask] + off);
+            x0 = make_double2(mulm(x0.x, mv.x, q, qi), mulm(x0.y, mv.y, q, qi));
+            x1 = make_double2(mulm(x1.x, mv.x, q, qi), mulm(x1.y, mv.y, q, qi));
+        }
+        e0 = make_double2(redm(e0.x + x0.x, q, qi), redm(e0.y + x0.y, q, qi));
+        e1 = make_double2(redm(e1.x + x1.x, q, qi), redm(e1.y + x1.y, q, qi));
+    }
+}
 
-// Tensor accumulation: block (64 positions x 4 pair chunks) per (prime i,
-// request); each thread sums a strided quarter of the request's (eps, omega)
-// pairs, then the four partial sums are added in LDS.
+constexpr int FT_P = 64;  // threads along positions per block (two positions each)
+constexpr int FT_C = 8;   // pair chunks per block, reduced through LDS
+
+// Tensor accumulation: block (128 positions x 8 pair chunks) per (prime i,
+// request); each thread takes two adjacent positions and a strided eighth of
+// the request's (eps, omega) pairs, then the partial sums are added in LDS.
 __global__ void __launch_bounds__(FT_P * FT_C)
 k_fin_tensor(DevTables T, const FinJob *jobs, const FinTerm *terms, const double *E, const double *const *masks,
              const int2 *req_pairs, double *const *acc) {
-    __shared__ double part[3][FT_C][FT_P];
+    __shared__ double2 part[3][FT_C][FT_P];
     const int N = 1 << T.logN;
-    const int p = blockIdx.x * FT_P + threadIdx.x;
+    const int p = 2 * (blockIdx.x * FT_P + threadIdx.x);
     const int c = threadIdx.y;
     const int i = blockIdx.y;
     const int req = blockIdx.z;
     const double q = T.qt[i].x, qi = T.qt[i].y;
     const int2 pr = req_pairs[req];
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    double2 a0 = make_double2(0.0, 0.0), a1 = a0, a2 = a0;
     if (p < N) {
         for (int pi = pr.x + c; pi < pr.x + pr.y; pi += FT_C) {
-            double e0, e1, f0, f1;
-            finish_one(T, jobs[2 * pi], terms, E, masks, i, p, q, qi, e0, e1);
-            finish_one(T, jobs[2 * pi + 1], terms, E, masks, i, p, q, qi, f0, f1);
-            a0 = redm(a0 + mulm(e0, f0, q, qi), q, qi);
-            a1 = redm(a1 + mulm(e0, f1, q, qi) + mulm(e1, f0, q, qi), q, qi);
-            a2 = redm(a2 + mulm(e1, f1, q, qi), q, qi);
+            double2 e0, e1, f0, f1;
+            finish_two(T, jobs[2 * pi], terms, E, masks, i, p, q, qi, e0, e1);
+            finish_two(T, jobs[2 * pi + 1], terms, E, masks, i, p, q, qi, f0, f1);
+            a0.x = redm(a0.x + mulm(e0.x, f0.x, q, qi), q, qi);
+            a0.y = redm(a0.y + mulm(e0.y, f0.y, q, qi), q, qi);
+            a1.x = redm(a1.x + mulm(e0.x, f1.x, q, qi) + mulm(e1.x, f0.x, q, qi), q, qi);
+            a1.y = redm(a1.y + mulm(e0.y, f1.y, q, qi) + mulm(e1.y, f0.y, q, qi), q, qi);
+            a2.x = redm(a2.x + mulm(e1.x, f1.x, q, qi), q, qi);
+            a2.y = redm(a2.y + mulm(e1.y, f1.y, q, qi), q, qi);
         }
     }
     part[0][c][threadIdx.x] = a0;
@@ -319,10 +350,13 @@ k_fin_tensor(DevTables T, const FinJob *jobs, const FinTerm *terms, const double
     part[2][c][threadIdx.x] = a2;
     __syncthreads();
     if (c < 3 && p < N) {
-        double s = 0.0;
+        double sx = 0.0, sy = 0.0;
 #pragma unroll
-        for (int k = 0; k < FT_C; ++k) s += part[c][k][threadIdx.x];
-        acc[req][(size_t)c * T.L * N + (size_t)i * N + p] = redm(s, q, qi);
+        for (int k = 0; k < FT_C; ++k) {
+            sx += part[c][k][threadIdx.x].x;
+            sy += part[c][k][threadIdx.x].y;
+        }
+        *(double2 *)(acc[req] + (size_t)c * T.L * N + (size_t)i * N + p) = make_double2(redm(sx, q, qi), redm(sy, q, qi));
     }
 }
 
@@ -603,7 +637,7 @@ void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
             fin_tensor_launch(T, jobs, terms, E, masks, req_pairs + o, acc + o, std::min(MAX_GRID_Z, nreq - o), s);
         return;
     }
-    dim3 grid((T.N + FT_P - 1) / FT_P, T.L, nreq);
+    dim3 grid((T.N + 2 * FT_P - 1) / (2 * FT_P), T.L, nreq);
     hipLaunchKernelGGL(k_fin_tensor, grid, dim3(FT_P, FT_C), 0, s, T, jobs, terms, E, masks, req_pairs, acc);
 }
 
