@@ -849,20 +849,21 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = sh[lds_ix(i)];
 }
 
-// Division by P for one special prime.  A workgroup takes G output rows of
-// one slot: inverse transform of U's special row, exact centered r (kept in
-// a second LDS buffer when G > 1), then for each of its primes q_i:
-// delta_i = t (P/p) r mod q_i, forward transform, E_i = (U_i - delta_i) P^-1.
-// G = 1 gives the most workgroups (few slots); G = 2 halves the repeated
-// inverse transforms when there are enough slots to fill the chip.
-template <int LOGN, int G>
+// Division by P for one special prime, one workgroup per output row
+// (slot, i): inverse transform of U's special row, exact centered r,
+// delta_i = t (P/p) r mod q_i, forward transform, E_i = (U_i - delta_i) P^-1,
+// written to E or (outs given) straight into the job's output ciphertext.
+// (Giving a workgroup several primes of a slot, to share the inverse
+// transform, was measured slower at 8192 points: one 135 KB workgroup per CU
+// running three transforms against two 70 KB workgroups running two.)
+template <int LOGN>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
 k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    const int ng = T.L / G;
-    const int slot = blockIdx.x / ng;
-    const int i0 = (blockIdx.x % ng) * G;
+    const int row = blockIdx.x;
+    const int iq = row % T.L;
+    const int slot = row / T.L;
     const double *u = U + (size_t)slot * T.nExt * N;
     const int pk = T.L;   // the special prime's index
     const double *twp = T.twi + (size_t)pk * N;
@@ -872,33 +873,22 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     __syncthreads();
     const double qp = T.qt[pk].x, qip = T.qt[pk].y;
     inv_row_stages<LOGN>(sh, twp, qp, qip, wi);
-    const double cf = T.md_coef[0];
-    double *rks = sh + (N + N / 16);
-    if (G > 1)
-        for (int i = threadIdx.x; i < N; i += blockDim.x) rks[i] = centerm(mulm(sh[lds_ix(i)], cf, qp, qip), qp, qip);
-    for (int g = 0; g < G; ++g) {
-        const int iq = i0 + g;
-        const double *twq = T.twf + (size_t)iq * N;
-        double wf[FwdRound<LOGN, 0>::NW];
-        if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(wf, twq, threadIdx.x);
-        const double q = T.qt[iq].x, qi = T.qt[iq].y;
-        const double h = T.md_hat[iq];
-        // each thread rewrites only the elements it reads, and every
-        // transform ends with a barrier, so no barrier is needed here
-        for (int i = threadIdx.x; i < N; i += blockDim.x) {
-            const int x = lds_ix(i);
-            const double rk = G > 1 ? rks[i] : centerm(mulm(sh[x], cf, qp, qip), qp, qip);
-            sh[x] = mulm(rk, h, q, qi);
-        }
-        __syncthreads();
-        fwd_row_stages<LOGN>(sh, twq, q, qi, wf);
-        const double pinv = T.pinv[iq];
-        const double *ui = u + (size_t)iq * N;
-        // E row, or (outs given) straight into the job's output ciphertext
-        double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N
-                           : E + ((size_t)slot * T.L + iq) * N;
-        for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = mulm(ui[i] - sh[lds_ix(i)], pinv, q, qi);
+    const double *twq = T.twf + (size_t)iq * N;
+    double wf[FwdRound<LOGN, 0>::NW];
+    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(wf, twq, threadIdx.x);
+    const double q = T.qt[iq].x, qi = T.qt[iq].y;
+    const double cf = T.md_coef[0], h = T.md_hat[iq];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int x = lds_ix(i);
+        const double rk = centerm(mulm(sh[x], cf, qp, qip), qp, qip);
+        sh[x] = mulm(rk, h, q, qi);
     }
+    __syncthreads();
+    fwd_row_stages<LOGN>(sh, twq, q, qi, wf);
+    const double pinv = T.pinv[iq];
+    const double *ui = u + (size_t)iq * N;
+    double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = mulm(ui[i] - sh[lds_ix(i)], pinv, q, qi);
 }
 
 int ntt_threads(int N) {
@@ -944,8 +934,7 @@ void set_lds_attrs() {
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 }  // namespace
@@ -1026,17 +1015,9 @@ void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int n
 
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s, double *const *outs) {
     if (nslots <= 0) return;
-    // Two primes per workgroup (half the repeated inverse transforms) was
-    // measured slower on MI355X at 8192 points (one 135 KB workgroup per CU
-    // running three transforms against two 70 KB workgroups running two), so
-    // one prime per workgroup is used.
-    const bool two = false;
-    const size_t lds = ntt_lds_bytes(T.N) + (two ? (size_t)T.N * sizeof(double) : 0);
 #define HG_MF(LN)                                                                                          \
-    if (two)                                                                                               \
-        hipLaunchKernelGGL((k_moddown_fused<LN, 2>), dim3(nslots * T.L / 2), dim3(ntt_threads(T.N)), lds, s, T, E, U, outs); \
-    else                                                                                                   \
-        hipLaunchKernelGGL((k_moddown_fused<LN, 1>), dim3(nslots * T.L), dim3(ntt_threads(T.N)), lds, s, T, E, U, outs);
+    hipLaunchKernelGGL(k_moddown_fused<LN>, dim3(nslots * T.L), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, \
+                       E, U, outs)
     HG_LOGN_SWITCH(T.logN, HG_MF)
 #undef HG_MF
 }

@@ -387,3 +387,34 @@ def test_algorithm1_variant(shape):
     cc = ctx.hegmm(ca, cb, m, l, n)
     assert np.array_equal(cc.export(), flat(H.hegmm(ks, pl, ox, oy))), shape
     assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
+
+
+def test_execution_knobs_bit_identical():
+    """Every execution knob changes only the schedule: pipelined passes on a
+    second stream, split-row transforms, fused or unfused chains, launch
+    windows -- the 64x32x48 product and a small batch keep their bits."""
+    c = workloads.HEADLINE
+    m, l, n = 64, 32, 48
+    A, B = workloads.headline_operands()
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    shapes = [(m, l, n), (8, 24, 16), (40, 8, 8)]
+    ctx.keygen(c.seed, shapes)
+    ca, cb = ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1)
+    rng = np.random.default_rng(5)
+    mats = [(rng.integers(-8, 9, size=(a, b)), rng.integers(-8, 9, size=(b, d))) for (a, b, d) in shapes[1:]]
+    As = [ca] + [ctx.encrypt(0, X, *s, nonce=2 + i) for i, (s, (X, Y)) in enumerate(zip(shapes[1:], mats))]
+    Bs = [cb] + [ctx.encrypt(1, Y, *s, nonce=2 + i) for i, (s, (X, Y)) in enumerate(zip(shapes[1:], mats))]
+    ref_one = ctx.hegmm(ca, cb, m, l, n).export()
+    ref_batch = [o.export() for o in ctx.hegmm_batch(As, Bs, shapes)]
+    settings = [{"pipeline": 2}, {"pipeline": 3, "fuse_rows": 0}, {"split_rows": 64, "fuse_rows": 0},
+                {"fuse_rows": 4096}, {"batch_window": 1}, {"ip_chunk": 0}]
+    defaults = {"pipeline": 1, "fuse_rows": 256, "split_rows": 0, "batch_window": 64, "ip_chunk": 16}
+    for st in settings:
+        for k, v in st.items():
+            ctx.tune(k, v)
+        assert np.array_equal(ctx.hegmm(ca, cb, m, l, n).export(), ref_one), st
+        got = ctx.hegmm_batch(As, Bs, shapes)
+        for i, s in enumerate(shapes):
+            assert np.array_equal(got[i].export(), ref_batch[i]), (st, s)
+        for k in st:
+            ctx.tune(k, defaults[k])
