@@ -106,7 +106,9 @@ hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l
  * mln holds cnt triples.  The products share the launches of each phase
  * (one hoisting launch, one key-switching launch, ...), and rotations that
  * several products need read each key once per launch.  C[i] receives new
- * handles.  Errors as hg_hegmm; on error no handle is returned. */
+ * handles.  Errors as hg_hegmm; every request is checked before any work
+ * is enqueued, so on an error no handle is returned and nothing of this
+ * call runs on the stream. */
 hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B,
                          const int32_t *mln, hg_ct **C, void *stream);
 

@@ -144,6 +144,7 @@ struct Ctx {
         int m, l, n;
         Ct *out;
     };
+    const PlanEntry &check_request(const Request &r);   // throws on any invalid request
     void hegmm_batch(std::vector<Request> &reqs, hipStream_t st);
     void hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st);
     Ct *rotate(const Ct &c, int z, hipStream_t st);

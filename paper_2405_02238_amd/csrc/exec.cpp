@@ -529,8 +529,25 @@ Graph::~Graph() {
     if (gs) (void)hipStreamDestroy(gs);
 }
 
+const PlanEntry &Ctx::check_request(const Request &r) {
+    if (!r.A || !r.B) throw Error(-1, "null operand");
+    const PlanEntry &pe = plan_for(r.m, r.l, r.n);
+    const Ct *A = r.A, *B = r.B;
+    if (A->m != r.m || A->l != r.l || A->n != r.n || B->m != r.m || B->l != r.l || B->n != r.n)
+        throw Error(-1, "operand shape differs from (m, l, n)");
+    if (A->side != side_of_role(pe.plan, 0) || B->side != side_of_role(pe.plan, 1))
+        throw Error(-1, "operands must be hg_encrypt outputs for roles 0 (A) and 1 (B)");
+    if (A->ncts != pe.plan.nb || B->ncts != pe.plan.nb) throw Error(-1, "block count mismatch");
+    for (auto &rz : pe.plan.rotations(S))
+        if (!rot_keys.count(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
+    return pe;
+}
+
 void Ctx::hegmm_batch(std::vector<Request> &reqs, hipStream_t st) {
     HGCHK(hipSetDevice(device));
+    // every request is checked before any launch, so an error leaves no
+    // work of this call on the stream
+    for (auto &r : reqs) check_request(r);
     if (batch_window > 0 && (int)reqs.size() > batch_window) {
         for (size_t o = 0; o < reqs.size(); o += batch_window) {
             std::vector<Request> part(reqs.begin() + o,
@@ -553,19 +570,10 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     };
     std::vector<RInfo> info;
     for (auto &r : reqs) {
-        if (!r.A || !r.B) throw Error(-1, "null operand");
-        const PlanEntry &pe = plan_for(r.m, r.l, r.n);
-        const Ct *A = r.A, *B = r.B;
-        if (A->m != r.m || A->l != r.l || A->n != r.n || B->m != r.m || B->l != r.l || B->n != r.n)
-            throw Error(-1, "operand shape differs from (m, l, n)");
-        if (A->side != side_of_role(pe.plan, 0) || B->side != side_of_role(pe.plan, 1))
-            throw Error(-1, "operands must be hg_encrypt outputs for roles 0 (A) and 1 (B)");
-        if (A->ncts != pe.plan.nb || B->ncts != pe.plan.nb) throw Error(-1, "block count mismatch");
-        const Ct *X = A->side == 0 ? A : B;
-        const Ct *Y = A->side == 0 ? B : A;
+        const PlanEntry &pe = check_request(r);
+        const Ct *X = r.A->side == 0 ? r.A : r.B;
+        const Ct *Y = r.A->side == 0 ? r.B : r.A;
         info.push_back({&pe, X, Y});
-        for (auto &rz : pe.plan.rotations(S))
-            if (!rot_keys.count(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
     }
     const int nreq = (int)reqs.size();
     hipEvent_t ev[10] = {nullptr};

@@ -196,6 +196,20 @@ void Server::launch(Lane &ln, std::vector<Req *> &batch) {
     // doubles), canonical staging (in_words words; in_words >= 2 out_words)
     char *dbuf = nullptr;
     HGCHK(hipMallocAsync((void **)&dbuf, (2 * in_words + out_words) * 8, st));
+    try {
+        launch_group(ln, batch, dbuf, in_words, out_words);
+    } catch (...) {
+        (void)hipFreeAsync(dbuf, st);
+        throw;
+    }
+    HGCHK(hipFreeAsync(dbuf, st));
+    HGCHK(hipEventRecord(ln.done, st));
+}
+
+void Server::launch_group(Lane &ln, std::vector<Req *> &batch, char *dbuf, size_t in_words, size_t out_words) {
+    const hipStream_t st = ln.st;
+    const size_t N = C.N, L = C.L;
+    const size_t ctw = 2 * L * N;
     double *ops = (double *)dbuf;
     double *outs = ops + in_words;
     uint64_t *stage = (uint64_t *)(outs + out_words);
@@ -253,8 +267,6 @@ void Server::launch(Lane &ln, std::vector<Req *> &batch) {
     for (size_t i = 0; i < batch.size(); ++i)
         HGCHK(hipMemcpyAsync(batch[i]->pin + batch[i]->na + batch[i]->nb, stage + i * ctw, ctw * 8,
                              hipMemcpyDeviceToHost, st));
-    HGCHK(hipFreeAsync(dbuf, st));
-    HGCHK(hipEventRecord(ln.done, st));
 }
 
 void Server::finish(Lane &ln, int code, const std::string &msg) {

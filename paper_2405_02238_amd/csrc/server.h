@@ -88,6 +88,7 @@ struct Server {
     double now() const;
     void loop();
     void launch(Lane &ln, std::vector<Req *> &batch);
+    void launch_group(Lane &ln, std::vector<Req *> &batch, char *dbuf, size_t in_words, size_t out_words);
     void finish(Lane &ln, int code, const std::string &msg);
 };
 

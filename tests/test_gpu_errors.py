@@ -134,3 +134,25 @@ def test_repeat_and_stream_determinism(ctx):
     s.synchronize()
     assert np.array_equal(other.export(), first)
     assert np.array_equal(ctx.hegmm(ca, cb, 4, 3, 5).export(), first)
+
+
+def test_batch_rejects_before_any_work(ctx):
+    """A batch with one request that cannot run (no rotation keys for its
+    shape) is refused as a whole before anything is enqueued; the same
+    batch without it then gives the bits of each product alone."""
+    A, B = workloads.tiny_operands()
+    rng = np.random.default_rng(1)
+    A2, B2 = rng.integers(-8, 9, size=(3, 7)), rng.integers(-8, 9, size=(7, 5))
+    ca, cb = ctx.encrypt(0, A, 4, 3, 5, nonce=7), ctx.encrypt(1, B, 4, 3, 5, nonce=7)
+    ca2, cb2 = ctx.encrypt(0, A2, 3, 7, 5, nonce=7), ctx.encrypt(1, B2, 3, 7, 5, nonce=7)
+    alone = ctx.hegmm(ca, cb, 4, 3, 5).export()
+    torch.cuda.synchronize()
+    with pytest.raises(hg.HGError) as e:
+        ctx.hegmm_batch([ca, ca2], [cb, cb2], [(4, 3, 5), (3, 7, 5)])
+    assert e.value.code == hg.HG_ENOKEY
+    with pytest.raises(hg.HGError) as e:
+        ctx.hegmm_batch([ca, cb], [cb, ca], [(4, 3, 5), (4, 3, 5)])   # roles swapped in the second
+    assert e.value.code == hg.HG_EINVAL
+    out = ctx.hegmm_batch([ca, ca], [cb, cb], [(4, 3, 5), (4, 3, 5)])
+    for c in out:
+        assert np.array_equal(c.export(), alone)
