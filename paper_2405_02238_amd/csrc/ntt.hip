@@ -298,6 +298,211 @@ __device__ __forceinline__ void inv_row_stages(double *sh, const double *tw, dou
     else inv_rows_c<LOGN, 0>(sh, tw, q, qi);
 }
 
+// ---- whole rows with both ends in registers (2^10 .. 2^14 points) ----
+// A row of N = 2^LOGN points runs on NT = N / 2^RK threads.  The forward
+// transform takes the 2^RK elements t + b NT of thread t straight from the
+// caller (global memory, or the registers an inverse transform left) into
+// its first round, and hands the outputs of its last round to a store
+// functor; the inverse transform reads global memory in its first round and
+// leaves the outputs of its last round, again elements t + b NT, in
+// registers.  Against staging the row through LDS at both ends, this saves
+// two LDS round trips and two barriers per transform, and a chain inverse ->
+// elementwise step -> forward keeps the row in registers in between.
+// Forward rounds: RK, ..., RK, KT; inverse rounds: KT, RK, ..., RK
+// (KT = the remainder of LOGN over RK, or RK).
+template <int LOGN>
+struct Rows {
+    static constexpr int N = 1 << LOGN;
+    static constexpr int RK = rk_of(LOGN);
+    static constexpr int NT = N >> RK;                          // threads per row
+    static constexpr int KT = LOGN % RK == 0 ? RK : LOGN % RK;  // stages of the short round
+    static constexpr int SL = LOGN - KT;                        // forward: first stage of the short round
+    static constexpr int GPT = 1 << (RK - KT);                  // short-round groups per thread
+};
+
+template <int LOGN>
+__host__ __device__ constexpr bool direct_rows() { return LOGN >= 10 && LOGN <= 14; }
+
+// Twiddles of forward stages [S0, S0 + K) for group blk.
+template <int S0, int K>
+__device__ __forceinline__ void fwd_tw(double *w, const double *__restrict__ tw, int blk) {
+#pragma unroll
+    for (int u = 0; u < K; ++u)
+#pragma unroll
+        for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (S0 + u)) + (blk << u) + c];
+}
+
+// Forward stages [S0, S0 + K) on the 2^K elements of one group; odd global
+// stages and the last one reduce.
+template <int LOGN, int S0, int K>
+__device__ __forceinline__ void fwd_bfly(double *x, const double *w, double q, double qi) {
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const bool red = ((S0 + u) & 1) || (S0 + u == LOGN - 1);
+        const int half = 1 << (K - 1 - u);
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) {
+            if (b & half) continue;
+            const double t = mulm(x[b + half], w[(1 << u) - 1 + (b >> (K - u))], q, qi);
+            const double X = x[b];
+            if (red) {
+                x[b] = redm(X + t, q, qi);
+                x[b + half] = redm(X - t, q, qi);
+            } else {
+                x[b] = X + t;
+                x[b + half] = X - t;
+            }
+        }
+    }
+}
+
+// Twiddles of the inverse round whose first stage has half-size 2^LTS0.
+template <int LOGN, int LTS0, int K>
+__device__ __forceinline__ void inv_tw(double *w, const double *__restrict__ tw, int blk) {
+    constexpr int N = 1 << LOGN;
+    int wo = 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+#pragma unroll
+        for (int c = 0; c < (1 << (K - u - 1)); ++c) w[wo + c] = tw[(N >> (LTS0 + u + 1)) + (blk << (K - u - 1)) + c];
+        wo += 1 << (K - u - 1);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void inv_bfly(double *x, const double *w, double q, double qi) {
+    int wo = 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int d = 1 << u;
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) {
+            if (b & d) continue;
+            const double X = x[b], Y = x[b + d];
+            x[b] = redm(X + Y, q, qi);
+            x[b + d] = mulm(X - Y, w[wo + (b >> (u + 1))], q, qi);
+        }
+        wo += 1 << (K - u - 1);
+    }
+}
+
+// Full forward rounds from stage S0 up to the short round, one group per
+// thread, the next round's twiddles loaded while this one computes.
+template <int LOGN, int S0>
+__device__ __forceinline__ void fwd_mid(double *sh, const double *__restrict__ tw, double q, double qi, int t,
+                                        const double *wcur) {
+    using R = Rows<LOGN>;
+    if constexpr (S0 < R::SL) {
+        constexpr int K = R::RK, LTS = LOGN - S0 - K, TS = 1 << LTS;
+        constexpr int S1 = S0 + K;
+        const int low = t & (TS - 1);
+        const int base = ((t >> LTS) << (LTS + K)) + low;
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
+        double wnext[(1 << K) - 1];
+        if constexpr (S1 < R::SL) fwd_tw<S1, K>(wnext, tw, t >> (LOGN - S1 - K));
+        fwd_bfly<LOGN, S0, K>(x, wcur, q, qi);
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
+        __syncthreads();
+        fwd_mid<LOGN, S1>(sh, tw, q, qi, t, wnext);
+    }
+}
+
+// Forward transform of a row of which thread t holds elements t + b NT in
+// x (|x| < q); st(i, v) receives output position i (bit-reversed order).
+// Uses sh as scratch; the caller must not touch sh concurrently.
+template <int LOGN, class Store>
+__device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restrict__ tw, double q, double qi,
+                                             double *x, Store st) {
+    using R = Rows<LOGN>;
+    constexpr int K = R::RK, NT = R::NT, KT = R::KT, SL = R::SL;
+    const int t = threadIdx.x;
+    double w0[(1 << K) - 1], w1[(1 << K) - 1];
+    fwd_tw<0, K>(w0, tw, 0);
+    fwd_tw<K, K>(w1, tw, t >> (LOGN - 2 * K));
+    fwd_bfly<LOGN, 0, K>(x, w0, q, qi);
+#pragma unroll
+    for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<NT>(t, b)] = x[b];
+    __syncthreads();
+    fwd_mid<LOGN, K>(sh, tw, q, qi, t, w1);
+#pragma unroll
+    for (int g = 0; g < R::GPT; ++g) {
+        const int grp = t + g * NT;
+        double w[(1 << KT) - 1], y[1 << KT];
+        fwd_tw<SL, KT>(w, tw, grp);
+#pragma unroll
+        for (int b = 0; b < (1 << KT); ++b) y[b] = sh[lds_ix((grp << KT) + b)];
+        fwd_bfly<LOGN, SL, KT>(y, w, q, qi);
+#pragma unroll
+        for (int b = 0; b < (1 << KT); ++b) st((grp << KT) + b, y[b]);
+    }
+}
+
+template <int LOGN, class Load, class Store>
+__device__ __forceinline__ void fwd_row_direct(double *sh, const double *__restrict__ tw, double q, double qi,
+                                               Load ld, Store st) {
+    using R = Rows<LOGN>;
+    double x[1 << R::RK];
+#pragma unroll
+    for (int b = 0; b < (1 << R::RK); ++b) x[b] = ld((int)threadIdx.x + b * R::NT);
+    fwd_row_regs<LOGN>(sh, tw, q, qi, x, st);
+}
+
+// Full inverse rounds from half-size 2^LTS0 up to the last round.
+template <int LOGN, int LTS0>
+__device__ __forceinline__ void inv_mid(double *sh, const double *__restrict__ tw, double q, double qi, int t,
+                                        const double *wcur) {
+    using R = Rows<LOGN>;
+    if constexpr (LTS0 < LOGN - R::RK) {
+        constexpr int K = R::RK, TS = 1 << LTS0, L1 = LTS0 + K;
+        const int low = t & (TS - 1);
+        const int base = ((t >> LTS0) << (LTS0 + K)) + low;
+        double x[1 << K];
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
+        double wnext[(1 << K) - 1];
+        if constexpr (L1 < LOGN - K) inv_tw<LOGN, L1, K>(wnext, tw, t >> L1);
+        inv_bfly<K>(x, wcur, q, qi);
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
+        __syncthreads();
+        inv_mid<LOGN, L1>(sh, tw, q, qi, t, wnext);
+    }
+}
+
+// Inverse transform (without the N^-1 scaling) of the row read through
+// ld(i) (bit-reversed order); on return thread t holds output positions
+// t + b NT in x, |x| < q.  sh is scratch.
+template <int LOGN, class Load>
+__device__ __forceinline__ void inv_row_direct(double *sh, const double *__restrict__ tw, double q, double qi, Load ld,
+                                               double *x) {
+    using R = Rows<LOGN>;
+    constexpr int K = R::RK, NT = R::NT, KT = R::KT;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int g = 0; g < R::GPT; ++g) {
+        const int grp = t + g * NT;
+        double w[(1 << KT) - 1], y[1 << KT];
+        inv_tw<LOGN, 0, KT>(w, tw, grp);
+#pragma unroll
+        for (int b = 0; b < (1 << KT); ++b) y[b] = ld((grp << KT) + b);
+        inv_bfly<KT>(y, w, q, qi);
+#pragma unroll
+        for (int b = 0; b < (1 << KT); ++b) sh[lds_ix((grp << KT) + b)] = y[b];
+    }
+    double w1[(1 << K) - 1];
+    if constexpr (KT < LOGN - K) inv_tw<LOGN, KT, K>(w1, tw, t >> KT);
+    __syncthreads();
+    inv_mid<LOGN, KT>(sh, tw, q, qi, t, w1);
+    double w[(1 << K) - 1];
+    inv_tw<LOGN, LOGN - K, K>(w, tw, 0);
+#pragma unroll
+    for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<NT>(t, b)];
+    inv_bfly<K>(x, w, q, qi);
+}
+
 // K forward stages [s0, s0 + K) of nsub independent 2^ls-point transforms
 // stored one after another in LDS.  Sub-transform sb takes its stage-s
 // twiddles from tw[C * 2^s + local], C = cb + sb * cs (C = 1 for a whole row
@@ -650,6 +855,13 @@ k_ntt_fwd(DevTables T, NttArgs a) {
     constexpr int N = 1 << LOGN;
     const FwdRow R = fwd_row<LOAD>(T, a, blockIdx.x);
     const double *tw = T.twf + (size_t)R.prime * N;
+    if constexpr (direct_rows<LOGN>()) {
+        const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+        fwd_row_direct<LOGN>(
+            sh, tw, q, qi, [&](int i) { return fwd_load<LOAD>(T, R, i); },
+            [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
+        return;
+    }
     double w0[FwdRound<LOGN, 0>::NW];
     if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
@@ -666,6 +878,15 @@ k_ntt_inv(DevTables T, NttArgs a) {
     constexpr int N = 1 << LOGN;
     const InvRow R = inv_row(T, a, blockIdx.x);
     const double *tw = T.twi + (size_t)R.prime * N;
+    if constexpr (direct_rows<LOGN>()) {
+        using RW = Rows<LOGN>;
+        const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+        double x[1 << RW::RK];
+        inv_row_direct<LOGN>(sh, tw, q, qi, [&](int i) { return R.in[i]; }, x);
+#pragma unroll
+        for (int b = 0; b < (1 << RW::RK); ++b) inv_store<STORE>(T, R, (int)threadIdx.x + b * RW::NT, x[b], q, qi);
+        return;
+    }
     double w0[InvRound<LOGN, 0>::NW];
     if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = R.in[i];
@@ -829,6 +1050,17 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
         return;
     }
     const double *twj = T.twi + (size_t)j * N;
+    if constexpr (direct_rows<LOGN>()) {
+        using RW = Rows<LOGN>;
+        const double qj = T.qt[j].x, qij = T.qt[j].y, nj = T.ninv[j];
+        double x[1 << RW::RK];
+        inv_row_direct<LOGN>(sh, twj, qj, qij, [&](int i) { return c[i]; }, x);
+#pragma unroll
+        for (int b = 0; b < (1 << RW::RK); ++b) x[b] = centerm(mulm(x[b], nj, qj, qij), qj, qij);
+        const double q = T.qt[r].x, qi = T.qt[r].y;
+        fwd_row_regs<LOGN>(sh, T.twf + (size_t)r * N, q, qi, x, [&](int i, double v) { out[i] = v; });
+        return;
+    }
     double wi[InvRound<LOGN, 0>::NW];
     if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(wi, twj, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = c[i];
@@ -867,6 +1099,21 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     const double *u = U + (size_t)slot * T.nExt * N;
     const int pk = T.L;   // the special prime's index
     const double *twp = T.twi + (size_t)pk * N;
+    if constexpr (direct_rows<LOGN>()) {
+        using RW = Rows<LOGN>;
+        const double qp = T.qt[pk].x, qip = T.qt[pk].y;
+        const double q = T.qt[iq].x, qi = T.qt[iq].y;
+        const double cf = T.md_coef[0], h = T.md_hat[iq], pinv = T.pinv[iq];
+        double x[1 << RW::RK];
+        inv_row_direct<LOGN>(sh, twp, qp, qip, [&](int i) { return u[(size_t)pk * N + i]; }, x);
+#pragma unroll
+        for (int b = 0; b < (1 << RW::RK); ++b) x[b] = mulm(centerm(mulm(x[b], cf, qp, qip), qp, qip), h, q, qi);
+        const double *ui = u + (size_t)iq * N;
+        double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
+        fwd_row_regs<LOGN>(sh, T.twf + (size_t)iq * N, q, qi, x,
+                           [&](int i, double v) { out[i] = mulm(ui[i] - v, pinv, q, qi); });
+        return;
+    }
     double wi[InvRound<LOGN, 0>::NW];
     if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(wi, twp, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
