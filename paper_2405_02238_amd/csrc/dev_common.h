@@ -20,4 +20,18 @@ __device__ __forceinline__ int perm_index(int p, int g, int logN) {
     return brev_bits((e - 1) >> 1, logN);
 }
 
+// Every buffer the kernels touch lives in global memory, but a pointer read
+// out of a descriptor table is generic to the compiler, which then emits
+// flat loads and stores; those also count as scalar-memory operations, so a
+// wait for a scalar load (the next table entry) stalls until they land.
+// Accessing through these casts gives plain global instructions.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gld(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gst(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 }  // namespace hg

@@ -41,8 +41,20 @@ __device__ __forceinline__ double key_a(uint64_t stream, int r, int p, int logN,
 // and ciphertext rows that every job gathers from L2.
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ double2 ld_stream2(const double *p) {
-    const dvec2 v = __builtin_nontemporal_load((const dvec2 *)p);
+    const dvec2 v = __builtin_nontemporal_load(gld((const dvec2 *)p));
     return make_double2(v.x, v.y);
+}
+
+// Two consecutive words through global (not flat) instructions.
+__device__ __forceinline__ double2 ld2(const double *p) {
+    const dvec2 v = *gld((const dvec2 *)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st2(double *p, double2 v) {
+    dvec2 w;
+    w.x = v.x;
+    w.y = v.y;
+    *gst((dvec2 *)p) = w;
 }
 
 // Key-switching inner products with the automorphism folded into the gather
@@ -111,7 +123,7 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
             a1y = redm(a1y + s1y, q, qi);
         }
         if (qrow && tm.kind != IP_RELIN) {
-            double x0 = J.c0[(size_t)r * N + pp0], x1 = J.c0[(size_t)r * N + pp1];
+            double x0 = gld(J.c0)[(size_t)r * N + pp0], x1 = gld(J.c0)[(size_t)r * N + pp1];
             if (tm.mask >= 0) {
                 x0 = mulm(x0, mv.x, q, qi);
                 x1 = mulm(x1, mv.y, q, qi);
@@ -119,7 +131,7 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
             c0x = redm(c0x + x0, q, qi);
             c0y = redm(c0y + x1, q, qi);
             if (tm.g == 1) {
-                const double2 w = *(const double2 *)(J.c1 + (size_t)r * N + p);
+                const double2 w = ld2(J.c1 + (size_t)r * N + p);
                 double z0 = w.x, z1 = w.y;
                 if (tm.mask >= 0) {
                     z0 = mulm(z0, mv.x, q, qi);
@@ -217,10 +229,10 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
                     const IpTerm pt = terms[t];
                     if (pt.kind == IP_RELIN) continue;
                     double2 mv = make_double2(1.0, 1.0);
-                    if (pt.mask >= 0) mv = *(const double2 *)(masks[pt.mask] + (size_t)r * N + p);
+                    if (pt.mask >= 0) mv = ld2(masks[pt.mask] + (size_t)r * N + p);
                     const int qq0 = pt.g == 1 ? p : perm_index(p, pt.g, T.logN);
                     const int qq1 = pt.g == 1 ? p + 1 : perm_index(p + 1, pt.g, T.logN);
-                    double x0 = J.c0[(size_t)r * N + qq0], x1 = J.c0[(size_t)r * N + qq1];
+                    double x0 = gld(J.c0)[(size_t)r * N + qq0], x1 = gld(J.c0)[(size_t)r * N + qq1];
                     if (pt.mask >= 0) {
                         x0 = mulm(x0, mv.x, q, qi);
                         x1 = mulm(x1, mv.y, q, qi);
@@ -228,7 +240,7 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
                     c0x = redm(c0x + x0, q, qi);
                     c0y = redm(c0y + x1, q, qi);
                     if (pt.g == 1) {
-                        const double2 w = *(const double2 *)(J.c1 + (size_t)r * N + p);
+                        const double2 w = ld2(J.c1 + (size_t)r * N + p);
                         double z0 = w.x, z1 = w.y;
                         if (pt.mask >= 0) {
                             z0 = mulm(z0, mv.x, q, qi);
@@ -275,9 +287,9 @@ __device__ __forceinline__ void finish_one(const DevTables &T, const FinJob &J, 
     e1 = 0.0;
     for (int t = J.t0; t < J.t0 + J.nt; ++t) {
         const FinTerm ft = terms[t];
-        double x0 = J.c0[off + p], x1 = J.c1[off + p];
+        double x0 = gld(J.c0)[off + p], x1 = gld(J.c1)[off + p];
         if (ft.mask >= 0) {
-            const double mv = masks[ft.mask][off + p];
+            const double mv = gld(masks[ft.mask])[off + p];
             x0 = mulm(x0, mv, q, qi);
             x1 = mulm(x1, mv, q, qi);
         }
@@ -303,9 +315,9 @@ __device__ __forceinline__ void finish_two(const DevTables &T, const FinJob &J, 
     e1 = make_double2(0.0, 0.0);
     for (int t = J.t0; t < J.t0 + J.nt; ++t) {
         const FinTerm ft = terms[t];
-        double2 x0 = *(const double2 *)(J.c0 + off), x1 = *(const double2 *)(J.c1 + off);
+        double2 x0 = ld2(J.c0 + off), x1 = ld2(J.c1 + off);
         if (ft.mask >= 0) {
-            const double2 mv = *(const double2 *)(masks[ft.mask] + off);
+            const double2 mv = ld2(masks[ft.mask] + off);
             x0 = make_double2(mulm(x0.x, mv.x, q, qi), mulm(x0.y, mv.y, q, qi));
             x1 = make_double2(mulm(x1.x, mv.x, q, qi), mulm(x1.y, mv.y, q, qi));
         }
@@ -356,7 +368,7 @@ k_fin_tensor(DevTables T, const FinJob *jobs, const FinTerm *terms, const double
             sx += part[c][k][threadIdx.x].x;
             sy += part[c][k][threadIdx.x].y;
         }
-        *(double2 *)(acc[req] + (size_t)c * T.L * N + (size_t)i * N + p) = make_double2(redm(sx, q, qi), redm(sy, q, qi));
+        st2(acc[req] + (size_t)c * T.L * N + (size_t)i * N + p, make_double2(redm(sx, q, qi), redm(sy, q, qi)));
     }
 }
 
@@ -371,7 +383,7 @@ k_fin_rotsum(DevTables T, const FinJob *jobs, const FinTerm *terms, const double
     const double q = T.qt[i].x, qi = T.qt[i].y;
     double e0, e1;
     finish_one(T, jobs[job], terms, E, masks, i, p, q, qi, e0, e1);
-    double *o = out[job] + (size_t)i * N + p;
+    auto o = gst(out[job] + (size_t)i * N + p);
     o[0] = e0;
     o[(size_t)T.L * N] = e1;
 }

@@ -8,11 +8,13 @@
 //
 // One workgroup owns one row (one prime of one polynomial); the row lives in
 // LDS, padded by one double every 16 so that the strided accesses of the late
-// rounds hit distinct banks.  Each round runs up to four radix-2 stages in
-// registers on groups of 16 elements (one group per thread), so an 8192-point
-// row takes four LDS round trips.  Reductions are lazy: a forward stage whose
-// outputs feed another multiplication keeps them unreduced (|x| < 2q), every
-// second stage reduces.
+// rounds hit distinct banks.  Each round runs three or four radix-2 stages in
+// registers on the 8 or 16 elements of one group per thread; the first round
+// of a forward transform takes its inputs from registers and its last round
+// writes the outputs, and the inverse mirrors this, so an 8192-point row
+// (13 stages: 3+3+3+3+1) makes three full LDS round trips.  Reductions are
+// lazy: a forward stage whose outputs feed another multiplication keeps them
+// unreduced (|x| < 2q), every second stage reduces.
 //
 // The load and store steps fuse the neighbouring work of key switching:
 // LOAD_MODUP lifts one digit of a coefficient-form polynomial to the prime of
@@ -162,140 +164,6 @@ __device__ __forceinline__ void inv_rows_c(double *sh, const double *tw, double 
         __syncthreads();
         inv_rows_c<LOGN, LTS + K>(sh, tw, q, qi);
     }
-}
-
-// Prefetching variant for one group per thread (blockDim = N / 2^RK): the
-// twiddles of round R+1 are loaded while round R computes.
-template <int LOGN, int S0>
-struct FwdRound {
-    static constexpr int K = (LOGN - S0) < rk_of(LOGN) ? (LOGN - S0) : rk_of(LOGN);
-    static constexpr int LTS = LOGN - S0 - K;
-    static constexpr int NW = (1 << K) - 1;
-    __device__ static __forceinline__ void load_tw(double *w, const double *__restrict__ tw, int grp) {
-        const int blk = grp >> LTS;
-#pragma unroll
-        for (int u = 0; u < K; ++u)
-#pragma unroll
-            for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (S0 + u)) + (blk << u) + c];
-    }
-};
-
-template <int LOGN, int S0>
-__device__ __forceinline__ void fwd_rows_pf(double *sh, const double *__restrict__ tw, double q, double qi, int grp,
-                                            const double *wcur) {
-    if constexpr (S0 < LOGN && FwdRound<LOGN, S0>::K < rk_of(LOGN)) {
-        // a short tail round has more groups than threads: plain loop
-        fwd_round_c<LOGN, S0, FwdRound<LOGN, S0>::K>(sh, tw, q, qi);
-        __syncthreads();
-    } else if constexpr (S0 < LOGN) {
-        using RD = FwdRound<LOGN, S0>;
-        constexpr int K = RD::K, LTS = RD::LTS, TS = 1 << LTS;
-        const int low = grp & (TS - 1);
-        const int blk = grp >> LTS;
-        const int base = (blk << (LTS + K)) + low;
-        double x[1 << K];
-#pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
-        constexpr int S1 = S0 + K;
-        constexpr bool PF = S1 < LOGN && FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::K == rk_of(LOGN);
-        constexpr int NWN = PF ? FwdRound<LOGN, (S1 < LOGN ? S1 : 0)>::NW : 1;
-        double wnext[NWN];
-        if constexpr (PF) FwdRound<LOGN, S1>::load_tw(wnext, tw, grp);
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            const bool red = ((S0 + u) & 1) || (S0 + u == LOGN - 1);
-            const int half = 1 << (K - 1 - u);
-#pragma unroll
-            for (int b = 0; b < (1 << K); ++b) {
-                if (b & half) continue;
-                const double t = mulm(x[b + half], wcur[(1 << u) - 1 + (b >> (K - u))], q, qi);
-                const double X = x[b];
-                if (red) {
-                    x[b] = redm(X + t, q, qi);
-                    x[b + half] = redm(X - t, q, qi);
-                } else {
-                    x[b] = X + t;
-                    x[b + half] = X - t;
-                }
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
-        __syncthreads();
-        if constexpr (S1 < LOGN) fwd_rows_pf<LOGN, S1>(sh, tw, q, qi, grp, wnext);
-    }
-}
-
-template <int LOGN, int LTS0>
-struct InvRound {
-    static constexpr int K = (LOGN - LTS0) < rk_of(LOGN) ? (LOGN - LTS0) : rk_of(LOGN);
-    static constexpr int NW = (1 << K) - 1;
-    __device__ static __forceinline__ void load_tw(double *w, const double *__restrict__ tw, int grp) {
-        constexpr int N = 1 << LOGN;
-        const int blk = grp >> LTS0;
-        int wo = 0;
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-#pragma unroll
-            for (int c = 0; c < (1 << (K - u - 1)); ++c) w[wo + c] = tw[(N >> (LTS0 + u + 1)) + (blk << (K - u - 1)) + c];
-            wo += 1 << (K - u - 1);
-        }
-    }
-};
-
-template <int LOGN, int LTS0>
-__device__ __forceinline__ void inv_rows_pf(double *sh, const double *__restrict__ tw, double q, double qi, int grp,
-                                            const double *wcur) {
-    if constexpr (LTS0 < LOGN && InvRound<LOGN, LTS0>::K < rk_of(LOGN)) {
-        inv_round_c<LOGN, LTS0, InvRound<LOGN, LTS0>::K>(sh, tw, q, qi);
-        __syncthreads();
-    } else if constexpr (LTS0 < LOGN) {
-        using RD = InvRound<LOGN, LTS0>;
-        constexpr int K = RD::K, TS = 1 << LTS0;
-        const int low = grp & (TS - 1);
-        const int blk = grp >> LTS0;
-        const int base = (blk << (LTS0 + K)) + low;
-        double x[1 << K];
-#pragma unroll
-        for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
-        constexpr int L1 = LTS0 + K;
-        constexpr bool PF = L1 < LOGN && InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::K == rk_of(LOGN);
-        constexpr int NWN = PF ? InvRound<LOGN, (L1 < LOGN ? L1 : 0)>::NW : 1;
-        double wnext[NWN];
-        if constexpr (PF) InvRound<LOGN, L1>::load_tw(wnext, tw, grp);
-        int wo = 0;
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            const int d = 1 << u;
-#pragma unroll
-            for (int b = 0; b < (1 << K); ++b) {
-                if (b & d) continue;
-                const double X = x[b], Y = x[b + d];
-                x[b] = redm(X + Y, q, qi);
-                x[b + d] = mulm(X - Y, wcur[wo + (b >> (u + 1))], q, qi);
-            }
-            wo += 1 << (K - u - 1);
-        }
-#pragma unroll
-        for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
-        __syncthreads();
-        if constexpr (L1 < LOGN) inv_rows_pf<LOGN, L1>(sh, tw, q, qi, grp, wnext);
-    }
-}
-
-// Whole-row stages with twiddle prefetch when every thread owns exactly one
-// group; the first round's twiddles are loaded before the caller's row load
-// completes (w0 filled by the caller).
-template <int LOGN>
-__device__ __forceinline__ void fwd_row_stages(double *sh, const double *tw, double q, double qi, const double *w0) {
-    if (blockDim.x == (1 << LOGN) >> rk_of(LOGN)) fwd_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
-    else fwd_rows_c<LOGN, 0>(sh, tw, q, qi);
-}
-
-template <int LOGN>
-__device__ __forceinline__ void inv_row_stages(double *sh, const double *tw, double q, double qi, const double *w0) {
-    if (blockDim.x == (1 << LOGN) >> rk_of(LOGN)) inv_rows_pf<LOGN, 0>(sh, tw, q, qi, threadIdx.x, w0);
-    else inv_rows_c<LOGN, 0>(sh, tw, q, qi);
 }
 
 // ---- whole rows with both ends in registers (2^10 .. 2^14 points) ----
@@ -782,28 +650,28 @@ __device__ __forceinline__ double fwd_load(const DevTables &T, const FwdRow &R, 
     const int N = 1 << T.logN;
     if (LOAD == LOAD_MODUP) {
         const int r = R.prime;
-        if (r >= R.d0 && r < R.d1) return R.in[(size_t)r * N + i];
+        if (r >= R.d0 && r < R.d1) return gld(R.in)[(size_t)r * N + i];
         if (R.d1 - R.d0 == 1) {
             // one-prime digit: the centered residue itself is the lift
-            return centerm(R.in[(size_t)R.d0 * N + i], T.qt[R.d0].x, T.qt[R.d0].y);
+            return centerm(gld(R.in)[(size_t)R.d0 * N + i], T.qt[R.d0].x, T.qt[R.d0].y);
         }
         const double qr = T.qt[r].x, qir = T.qt[r].y;
         double acc = 0.0;
         for (int s = R.d0; s < R.d1; ++s) {
             const double qs = T.qt[s].x, qis = T.qt[s].y;
-            const double ct = centerm(mulm(R.in[(size_t)s * N + i], T.mu_invhat[s], qs, qis), qs, qis);
+            const double ct = centerm(mulm(gld(R.in)[(size_t)s * N + i], T.mu_invhat[s], qs, qis), qs, qis);
             acc += mulm(ct, T.mu_hat[s * T.nExt + r], qr, qir);
         }
         return redm(acc, qr, qir);
     } else if (LOAD == LOAD_DELTA) {
         const int iq = R.prime;
         const double qr = T.qt[iq].x, qir = T.qt[iq].y;
-        if (T.alpha == 1) return mulm(R.in[i], T.md_hat[iq], qr, qir);
+        if (T.alpha == 1) return mulm(gld(R.in)[i], T.md_hat[iq], qr, qir);
         double acc = 0.0;
-        for (int k = 0; k < T.alpha; ++k) acc += mulm(R.in[(size_t)k * N + i], T.md_hat[k * T.L + iq], qr, qir);
+        for (int k = 0; k < T.alpha; ++k) acc += mulm(gld(R.in)[(size_t)k * N + i], T.md_hat[k * T.L + iq], qr, qir);
         return redm(acc, qr, qir);
     } else {
-        return R.in[i];
+        return gld(R.in)[i];
     }
 }
 
@@ -812,9 +680,9 @@ template <int LOAD>
 __device__ __forceinline__ void fwd_store(const DevTables &T, const FwdRow &R, int i, double v, double q, double qi) {
     if (LOAD == LOAD_DELTA) {
         // E = (U - delta) * P^-1: the finished, divided output of the job
-        R.out[i] = mulm(R.aux[i] - v, T.pinv[R.prime], q, qi);
+        gst(R.out)[i] = mulm(gld(R.aux)[i] - v, T.pinv[R.prime], q, qi);
     } else {
-        R.out[i] = v;
+        gst(R.out)[i] = v;
     }
 }
 
@@ -838,11 +706,11 @@ __device__ __forceinline__ InvRow inv_row(const DevTables &T, const NttArgs &a, 
 template <int STORE>
 __device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, int i, double v, double q, double qi) {
     if (STORE == STORE_MDR) {
-        R.out[i] = centerm(mulm(v, T.md_coef[R.rr], q, qi), q, qi);
+        gst(R.out)[i] = centerm(mulm(v, T.md_coef[R.rr], q, qi), q, qi);
     } else {
         double x = mulm(v, T.ninv[R.prime], q, qi);
         if (STORE == STORE_CANON) x = canonm(centerm(x, q, qi), q);
-        R.out[i] = x;
+        gst(R.out)[i] = x;
     }
 }
 
@@ -862,12 +730,10 @@ k_ntt_fwd(DevTables T, NttArgs a) {
             [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
         return;
     }
-    double w0[FwdRound<LOGN, 0>::NW];
-    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    fwd_row_stages<LOGN>(sh, tw, q, qi, w0);
+    fwd_rows_c<LOGN, 0>(sh, tw, q, qi);
     for (int i = threadIdx.x; i < N; i += blockDim.x) fwd_store<LOAD>(T, R, i, sh[lds_ix(i)], q, qi);
 }
 
@@ -882,17 +748,15 @@ k_ntt_inv(DevTables T, NttArgs a) {
         using RW = Rows<LOGN>;
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
         double x[1 << RW::RK];
-        inv_row_direct<LOGN>(sh, tw, q, qi, [&](int i) { return R.in[i]; }, x);
+        inv_row_direct<LOGN>(sh, tw, q, qi, [&](int i) { return gld(R.in)[i]; }, x);
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) inv_store<STORE>(T, R, (int)threadIdx.x + b * RW::NT, x[b], q, qi);
         return;
     }
-    double w0[InvRound<LOGN, 0>::NW];
-    if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(w0, tw, threadIdx.x);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = R.in[i];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = gld(R.in)[i];
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    inv_row_stages<LOGN>(sh, tw, q, qi, w0);
+    inv_rows_c<LOGN, 0>(sh, tw, q, qi);
     for (int i = threadIdx.x; i < N; i += blockDim.x) inv_store<STORE>(T, R, i, sh[lds_ix(i)], q, qi);
 }
 
@@ -938,7 +802,7 @@ k_ntt_fwd_cols(DevTables T, NttArgs a) {
     }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
-        R.out[c0 + cc + (j << lb)] = sh[lds_ix((cc << la) + j)];
+        gst(R.out)[c0 + cc + (j << lb)] = sh[lds_ix((cc << la) + j)];
     }
 }
 
@@ -955,7 +819,7 @@ k_ntt_fwd_blocks(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int off = (blockIdx.x % wpr) * SPLIT_ELEMS;
     const FwdRow R = fwd_row<LOAD>(T, a, row);
-    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = R.out[off + e];
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = gld(R.out)[off + e];
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     const int B0 = off >> lb;
@@ -982,7 +846,7 @@ k_ntt_inv_blocks(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int off = (blockIdx.x % wpr) * SPLIT_ELEMS;
     const InvRow R = inv_row(T, a, row);
-    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = R.in[off + e];
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = gld(R.in)[off + e];
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     const int B0 = off >> lb;
@@ -993,7 +857,7 @@ k_ntt_inv_blocks(DevTables T, NttArgs a) {
     } else {
         inv_stages(sh, tw, lb, bw, (1 << la) + B0, 1, q, qi);
     }
-    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) R.out[off + e] = sh[lds_ix(e)];
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) gst(R.out)[off + e] = sh[lds_ix(e)];
 }
 
 template <int STORE, int LOGN>
@@ -1011,7 +875,7 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
     const InvRow R = inv_row(T, a, row);
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
-        sh[lds_ix((cc << la) + j)] = R.out[c0 + cc + (j << lb)];
+        sh[lds_ix((cc << la) + j)] = gld(R.out)[c0 + cc + (j << lb)];
     }
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
@@ -1046,7 +910,7 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     const double *c = srcs[src] + (size_t)j * N;
     double *out = y + (size_t)row * N;
     if (r == j) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = c[i];
+        for (int i = threadIdx.x; i < N; i += blockDim.x) gst(out)[i] = gld(c)[i];
         return;
     }
     const double *twj = T.twi + (size_t)j * N;
@@ -1054,22 +918,18 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
         using RW = Rows<LOGN>;
         const double qj = T.qt[j].x, qij = T.qt[j].y, nj = T.ninv[j];
         double x[1 << RW::RK];
-        inv_row_direct<LOGN>(sh, twj, qj, qij, [&](int i) { return c[i]; }, x);
+        inv_row_direct<LOGN>(sh, twj, qj, qij, [&](int i) { return gld(c)[i]; }, x);
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = centerm(mulm(x[b], nj, qj, qij), qj, qij);
         const double q = T.qt[r].x, qi = T.qt[r].y;
-        fwd_row_regs<LOGN>(sh, T.twf + (size_t)r * N, q, qi, x, [&](int i, double v) { out[i] = v; });
+        fwd_row_regs<LOGN>(sh, T.twf + (size_t)r * N, q, qi, x, [&](int i, double v) { gst(out)[i] = v; });
         return;
     }
-    double wi[InvRound<LOGN, 0>::NW];
-    if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(wi, twj, threadIdx.x);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = c[i];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = gld(c)[i];
     __syncthreads();
     const double qj = T.qt[j].x, qij = T.qt[j].y;
-    inv_row_stages<LOGN>(sh, twj, qj, qij, wi);
+    inv_rows_c<LOGN, 0>(sh, twj, qj, qij);
     const double *twr = T.twf + (size_t)r * N;
-    double wf[FwdRound<LOGN, 0>::NW];
-    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(wf, twr, threadIdx.x);
     const double nj = T.ninv[j];
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int x = lds_ix(i);
@@ -1077,8 +937,8 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     }
     __syncthreads();
     const double q = T.qt[r].x, qi = T.qt[r].y;
-    fwd_row_stages<LOGN>(sh, twr, q, qi, wf);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = sh[lds_ix(i)];
+    fwd_rows_c<LOGN, 0>(sh, twr, q, qi);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) gst(out)[i] = sh[lds_ix(i)];
 }
 
 // Division by P for one special prime, one workgroup per output row
@@ -1105,24 +965,20 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
         const double q = T.qt[iq].x, qi = T.qt[iq].y;
         const double cf = T.md_coef[0], h = T.md_hat[iq], pinv = T.pinv[iq];
         double x[1 << RW::RK];
-        inv_row_direct<LOGN>(sh, twp, qp, qip, [&](int i) { return u[(size_t)pk * N + i]; }, x);
+        inv_row_direct<LOGN>(sh, twp, qp, qip, [&](int i) { return gld(u)[(size_t)pk * N + i]; }, x);
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = mulm(centerm(mulm(x[b], cf, qp, qip), qp, qip), h, q, qi);
         const double *ui = u + (size_t)iq * N;
         double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
         fwd_row_regs<LOGN>(sh, T.twf + (size_t)iq * N, q, qi, x,
-                           [&](int i, double v) { out[i] = mulm(ui[i] - v, pinv, q, qi); });
+                           [&](int i, double v) { gst(out)[i] = mulm(gld(ui)[i] - v, pinv, q, qi); });
         return;
     }
-    double wi[InvRound<LOGN, 0>::NW];
-    if (blockDim.x == (N >> rk_of(LOGN)) && InvRound<LOGN, 0>::K == rk_of(LOGN)) InvRound<LOGN, 0>::load_tw(wi, twp, threadIdx.x);
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
     __syncthreads();
     const double qp = T.qt[pk].x, qip = T.qt[pk].y;
-    inv_row_stages<LOGN>(sh, twp, qp, qip, wi);
+    inv_rows_c<LOGN, 0>(sh, twp, qp, qip);
     const double *twq = T.twf + (size_t)iq * N;
-    double wf[FwdRound<LOGN, 0>::NW];
-    if (blockDim.x == (N >> rk_of(LOGN)) && FwdRound<LOGN, 0>::K == rk_of(LOGN)) FwdRound<LOGN, 0>::load_tw(wf, twq, threadIdx.x);
     const double q = T.qt[iq].x, qi = T.qt[iq].y;
     const double cf = T.md_coef[0], h = T.md_hat[iq];
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -1131,11 +987,11 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
         sh[x] = mulm(rk, h, q, qi);
     }
     __syncthreads();
-    fwd_row_stages<LOGN>(sh, twq, q, qi, wf);
+    fwd_rows_c<LOGN, 0>(sh, twq, q, qi);
     const double pinv = T.pinv[iq];
     const double *ui = u + (size_t)iq * N;
     double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) out[i] = mulm(ui[i] - sh[lds_ix(i)], pinv, q, qi);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) gst(out)[i] = mulm(gld(ui)[i] - sh[lds_ix(i)], pinv, q, qi);
 }
 
 int ntt_threads(int N) {
