@@ -410,15 +410,11 @@ struct Exec {
                 if (tm) {
                     t0 = C.event(st, true);
                     t1 = C.event(st, true);
-                    HGCHK(hipEventRecord(t0, st));
                 }
                 ip_keyed_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs, terms, chunks + dv.rounds[s],
                                 (const int2 *)(dv.tab + dv.t_tasks), dv.rounds[s + 1] - dv.rounds[s], s == 0,
-                                transform_pass, st);
-                if (tm) {
-                    HGCHK(hipEventRecord(t1, st));
-                    tm->ip_pairs.push_back({t0, t1});
-                }
+                                transform_pass, st, t0, t1);
+                if (tm) tm->ip_pairs.push_back({t0, t1});
             }
             if (tev) HGCHK(hipEventRecord(tev[1], st));
             const bool fz = fused_ok(T) && dv.nks * 2 * L <= C.fuse_rows;
@@ -437,14 +433,10 @@ struct Exec {
             if (tm) {
                 t0 = C.event(st, true);
                 t1 = C.event(st, true);
-                HGCHK(hipEventRecord(t0, st));
             }
             ip_launch(T, dv.U + (size_t)j0 * 2 * nExt * N, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0,
-                      transform_pass, st);
-            if (tm) {
-                HGCHK(hipEventRecord(t1, st));
-                tm->ip_pairs.push_back({t0, t1});
-            }
+                      transform_pass, st, t0, t1);
+            if (tm) tm->ip_pairs.push_back({t0, t1});
             if (tev && c == nch - 1) HGCHK(hipEventRecord(tev[1], st));
             if (s2 != st) {
                 hipEvent_t ev = C.event(st, false);

@@ -118,9 +118,10 @@ void ntt_set_split_rows(int rows);
 // Inner products: U[job][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
 // the unswitched part on the ciphertext primes (see IpTerm).
+// ev0 / ev1 (optional) receive the start and end of the launch.
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
-               bool transform_pass, hipStream_t s);
+               bool transform_pass, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Key-stationary variant, one launch per round of key-switched terms:
 // tasks[i] = (job, term); chunks[c] = (first task, count), all tasks of a
@@ -129,7 +130,7 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
 void ip_keyed_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
                      const uint64_t *streams, const double *const *masks, const IpJob *jobs, const IpTerm *terms,
                      const int2 *chunks, const int2 *tasks, int nchunks, bool first_round, bool transform_pass,
-                     hipStream_t s);
+                     hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Tensor-accumulate: per request, sum over its (eps job, omega job) pairs of
 // the tensor product of the two finished transforms (E slots or plain terms).

@@ -2,6 +2,8 @@
 // inner products, the division by P, tensor accumulation, sampling.
 #include "kernels.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "arith.h"
@@ -583,15 +585,27 @@ bool g_cdt_uploaded[64] = {false};
 
 static dim3 ew_grid(int N, int y, int z = 1) { return dim3((N + EW_THREADS - 1) / EW_THREADS, y, z); }
 
+// A launch whose start and stop timestamps land in ev0 / ev1 (taken by the
+// dispatch itself, so they bracket exactly the kernel), or a plain launch.
+template <typename... Args, typename F = void (*)(Args...)>
+static void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                         Args... args) {
+    if (ev0) hipExtLaunchKernelGGL(kernel, grid, block, 0, s, ev0, ev1, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
+
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, bool transform_pass,
-               hipStream_t s) {
-    if (njobs <= 0) return;
-    if (njobs > MAX_GRID_Z) {   // the z extent of a launch is limited: split
+               hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (njobs <= 0 || njobs > MAX_GRID_Z) {
+        // nothing to launch, or the z extent of a launch is limited: split,
+        // timed by events around the launches
+        if (ev0) (void)hipEventRecord(ev0, s);   // a failed record surfaces when the timing is read
         const size_t plane = (size_t)T.nExt * T.N;
         for (int o = 0; o < njobs; o += MAX_GRID_Z)
             ip_launch(T, U + (size_t)o * 2 * plane, y, keys, streams, masks, jobs + o, terms,
                       std::min(MAX_GRID_Z, njobs - o), transform_pass, s);
+        if (ev1) (void)hipEventRecord(ev1, s);
         return;
     }
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, njobs);
@@ -599,9 +613,9 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
 #define HG_IP_CASE(B)                                                                                        \
     case B:                                                                                                  \
         if (transform_pass)                                                                                  \
-            hipLaunchKernelGGL((k_ip<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, terms); \
+            launch_timed(k_ip<B, 0>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, terms); \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_ip<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, terms); \
+            launch_timed(k_ip<B, 1>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, terms); \
         break;
         HG_IP_CASE(1) HG_IP_CASE(2) HG_IP_CASE(3) HG_IP_CASE(4) HG_IP_CASE(5) HG_IP_CASE(6)
         HG_IP_CASE(7) HG_IP_CASE(8) HG_IP_CASE(9) HG_IP_CASE(10) HG_IP_CASE(11) HG_IP_CASE(12)
@@ -613,12 +627,13 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
 void ip_keyed_launch(const DevTables &T, double *U, const double *y, const double *const *keys,
                      const uint64_t *streams, const double *const *masks, const IpJob *jobs, const IpTerm *terms,
                      const int2 *chunks, const int2 *tasks, int nchunks, bool first_round, bool transform_pass,
-                     hipStream_t s) {
-    if (nchunks <= 0) return;
-    if (nchunks > MAX_GRID_Z) {
+                     hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (nchunks <= 0 || nchunks > MAX_GRID_Z) {
+        if (ev0) (void)hipEventRecord(ev0, s);   // a failed record surfaces when the timing is read
         for (int o = 0; o < nchunks; o += MAX_GRID_Z)
             ip_keyed_launch(T, U, y, keys, streams, masks, jobs, terms, chunks + o, tasks,
                             std::min(MAX_GRID_Z, nchunks - o), first_round, transform_pass, s);
+        if (ev1) (void)hipEventRecord(ev1, s);
         return;
     }
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, nchunks);
@@ -627,11 +642,11 @@ void ip_keyed_launch(const DevTables &T, double *U, const double *y, const doubl
 #define HG_IPK_CASE(B)                                                                                        \
     case B:                                                                                                  \
         if (transform_pass)                                                                                  \
-            hipLaunchKernelGGL((k_ip_keyed<B, 0>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, \
-                               terms, chunks, tasks, fr);                                                    \
+            launch_timed(k_ip_keyed<B, 0>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, \
+                         terms, chunks, tasks, fr);                                                          \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_ip_keyed<B, 1>), grid, dim3(IP_THREADS), 0, s, T, U, y, keys, streams, masks, jobs, \
-                               terms, chunks, tasks, fr);                                                    \
+            launch_timed(k_ip_keyed<B, 1>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, \
+                         terms, chunks, tasks, fr);                                                          \
         break;
         HG_IPK_CASE(1) HG_IPK_CASE(2) HG_IPK_CASE(3) HG_IPK_CASE(4) HG_IPK_CASE(5) HG_IPK_CASE(6)
         HG_IPK_CASE(7) HG_IPK_CASE(8) HG_IPK_CASE(9) HG_IPK_CASE(10) HG_IPK_CASE(11) HG_IPK_CASE(12)
