@@ -247,7 +247,10 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
  *   "ip_chunk"   key-switched terms that share a key per workgroup of the
  *                key-stationary inner products (one launch per round of
  *                terms), used for passes whose keys repeat at least four
- *                times on average (batches); 0 disables key grouping
+ *                times on average; 0 (the default) disables key grouping
+ *   "ip_order"   1: the plain (one launch) inner products start their jobs
+ *                ordered by their keys, so jobs that read the same keys run
+ *                together; 0: in pass order
  *   "split_rows" transforms of fewer rows than this split each row over
  *                N/1024 workgroups (two passes)
  *   "batch_window" products per launch group inside hg_hegmm_batch

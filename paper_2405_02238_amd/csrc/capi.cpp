@@ -369,6 +369,7 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
         const std::string n(name);
         if (n == "fuse_rows") X.fuse_rows = (int)value;
         else if (n == "ip_chunk") X.ip_chunk = (int)value;
+        else if (n == "ip_order") X.ip_order = (int)value;
         else if (n == "split_rows") hg::ntt_set_split_rows((int)value);
         else if (n == "batch_window") X.batch_window = (int)value;
         else if (n == "pipeline") {

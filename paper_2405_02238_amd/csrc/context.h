@@ -108,7 +108,8 @@ struct Ctx {
     Arena &arena_for(hipStream_t st);
     Timing timing;
     int fuse_rows = 256;  // passes with at most this many rows per chain use the fused kernels
-    int ip_chunk = 16;    // terms sharing a key per workgroup in the key-stationary inner products (0: off)
+    int ip_chunk = 0;     // terms sharing a key per workgroup in the key-stationary inner products (0: off)
+    int ip_order = 1;     // plain inner products launch their jobs ordered by key (0: pass order)
     int batch_window = 64; // products per launch group in hegmm_batch (0: all)
     int pipeline = 1;      // chunks of a pass whose inner products and division by P overlap (1: off)
     std::map<hipStream_t, StreamAux> aux;

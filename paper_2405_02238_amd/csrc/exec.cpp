@@ -113,7 +113,7 @@ struct Exec {
             ij.c1 = fj.c1;
             ij.src = src;
             ij.t0 = (int)ps.ip_terms.size();
-            ij.pad = 0;
+            ij.slot = (int)ps.ip_jobs.size();
             for (auto &tm : terms) {
                 const int g = C.galois_of(tm.first);
                 const int mid = ps.mask_id(tm.second);
@@ -202,6 +202,23 @@ struct Exec {
         return true;
     }
 
+    // The pass's jobs ordered by the keys of their key-switched terms
+    // (stable: ties keep their order).
+    static std::vector<IpJob> key_order(const Pass &ps) {
+        std::vector<std::pair<std::vector<int>, int>> ks(ps.ip_jobs.size());
+        for (size_t j = 0; j < ps.ip_jobs.size(); ++j) {
+            const IpJob &J = ps.ip_jobs[j];
+            for (int t = J.t0; t < J.t0 + J.nt; ++t)
+                if (ps.ip_terms[t].kind != IP_PLAIN) ks[j].first.push_back(ps.ip_terms[t].key);
+            ks[j].second = (int)j;
+        }
+        std::stable_sort(ks.begin(), ks.end());
+        std::vector<IpJob> out;
+        out.reserve(ks.size());
+        for (auto &k : ks) out.push_back(ps.ip_jobs[k.second]);
+        return out;
+    }
+
     // Lay out the scratch of several passes that run one after another on
     // the stream (one scratch region sized for the largest, one descriptor
     // table block per pass) and copy every table with a single transfer.
@@ -278,7 +295,15 @@ struct Exec {
         for (size_t i = 0; i < sp.size(); ++i) {
             Pass &ps = *sp[i].ps;
             const Off &o = off[i];
-            put(o.ipj, ps.ip_jobs.data(), ps.ip_jobs.size() * sizeof(IpJob));
+            if (chunks[i].empty() && C.ip_order && C.pipeline <= 1) {
+                // one plain launch: jobs ordered by their key sequence, so that
+                // jobs reading the same keys run side by side and find them in
+                // cache (bit-neutral: each job writes its own slot)
+                const std::vector<IpJob> sorted = key_order(ps);
+                put(o.ipj, sorted.data(), sorted.size() * sizeof(IpJob));
+            } else {
+                put(o.ipj, ps.ip_jobs.data(), ps.ip_jobs.size() * sizeof(IpJob));
+            }
             put(o.ipt, ps.ip_terms.data(), ps.ip_terms.size() * sizeof(IpTerm));
             put(o.fj, ps.fin_jobs.data(), ps.fin_jobs.size() * sizeof(FinJob));
             put(o.ft, ps.fin_terms.data(), ps.fin_terms.size() * sizeof(FinTerm));
@@ -434,8 +459,7 @@ struct Exec {
                 t0 = C.event(st, true);
                 t1 = C.event(st, true);
             }
-            ip_launch(T, dv.U + (size_t)j0 * 2 * nExt * N, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0,
-                      transform_pass, st, t0, t1);
+            ip_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0, transform_pass, st, t0, t1);
             if (tm) tm->ip_pairs.push_back({t0, t1});
             if (tev && c == nch - 1) HGCHK(hipEventRecord(tev[1], st));
             if (s2 != st) {

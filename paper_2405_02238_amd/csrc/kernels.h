@@ -50,7 +50,8 @@ struct IpJob {
     const double *c1;
     int src;            // hoisted digit set for the key-switched terms
     int t0, nt;         // terms [t0, t0 + nt)
-    int pad;
+    int slot;           // output slot of U (the job's index in its pass; the
+                        // launch order of the jobs may differ)
 };
 
 // One term of a finishing job without key switching (the identity transforms).
@@ -115,7 +116,7 @@ void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, h
 // rows longer than 16384 always use the split form.
 void ntt_set_split_rows(int rows);
 
-// Inner products: U[job][c][r][p] = sum over the job's key-switched terms of
+// Inner products: U[slot][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
 // the unswitched part on the ciphertext primes (see IpTerm).
 // ev0 / ev1 (optional) receive the start and end of the launch.

@@ -151,7 +151,7 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
         a1x = redm(a1x + mulm(c1x, P, q, qi), q, qi);
         a1y = redm(a1y + mulm(c1y, P, q, qi), q, qi);
     }
-    double *u = U + (size_t)job * 2 * plane + (size_t)r * N + p;
+    double *u = U + (size_t)J.slot * 2 * plane + (size_t)r * N + p;
     *(double2 *)u = make_double2(a0x, a0y);
     *(double2 *)(u + plane) = make_double2(a1x, a1y);
 }
@@ -222,7 +222,7 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
             a1x = mulm(a1x, mv.x, q, qi);
             a1y = mulm(a1y, mv.y, q, qi);
         }
-        double *u = U + (size_t)tk.x * 2 * plane + (size_t)r * N + p;
+        double *u = U + (size_t)J.slot * 2 * plane + (size_t)r * N + p;
         if (first_round) {
             if (qrow) {
                 // unswitched part of the whole job
@@ -601,10 +601,9 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
         // nothing to launch, or the z extent of a launch is limited: split,
         // timed by events around the launches
         if (ev0) (void)hipEventRecord(ev0, s);   // a failed record surfaces when the timing is read
-        const size_t plane = (size_t)T.nExt * T.N;
         for (int o = 0; o < njobs; o += MAX_GRID_Z)
-            ip_launch(T, U + (size_t)o * 2 * plane, y, keys, streams, masks, jobs + o, terms,
-                      std::min(MAX_GRID_Z, njobs - o), transform_pass, s);
+            ip_launch(T, U, y, keys, streams, masks, jobs + o, terms, std::min(MAX_GRID_Z, njobs - o),
+                      transform_pass, s);
         if (ev1) (void)hipEventRecord(ev1, s);
         return;
     }
