@@ -24,6 +24,7 @@ import numpy as np
 DEFAULT_SPACE = {
     "fuse_rows": [0, 64, 256],
     "ip_chunk": [0, 16, 64],
+    "ip_order": [0, 1],
     "batch_window": [0, 64, 128],
 }
 
