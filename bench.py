@@ -35,11 +35,14 @@ def parse():
                     help="bounded CPU-oracle sample: run whole oracle matmuls until this much time passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batched", "serving", "large", "alg1"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "batched", "serving", "large", "alg1", "blocked"],
                     help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step; "
                          "serving: 512 Poisson arrivals at N=16384 through the continuous-batching server; "
                          "large: one 128x96x128 product per step at N=32768; "
-                         "alg1: the headline product with the paper's Algorithm 1 instead of HEGMM-En")
+                         "alg1: the headline product with the paper's Algorithm 1 instead of HEGMM-En; "
+                         "blocked: a 100x100x100 product split into output blocks (partitions P1/P2)")
+    ap.add_argument("--partition", default="P2", choices=["P1", "P2"], help="blocked: the reported partition")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
     ap.add_argument("--max-batch", type=int, default=4, help="serving: products per launch group")
@@ -342,11 +345,68 @@ def run_alg1(args):
         "en_speedup_over_alg1": res[2]["matmuls_per_s"] / v if v else None}), flush=True)
 
 
+def run_blocked(args):
+    """A 100x100 by 100x100 product, whose 10000-entry result does not fit
+    one ciphertext of the headline ring, as a blocked product: A split into
+    row blocks and B into column blocks (P1: 50+50, P2: 64+36 each way), the
+    block products (each with its inner dimension split as it needs) run as
+    one batch per step, the client assembles C.  Each step's results are
+    decrypt-checked against the brute-force product."""
+    import torch
+    import paper_2405_02238_amd as hg
+    import workloads
+
+    cfg = workloads.HEADLINE
+    D = workloads.BLOCKED_DIM
+    A, B = workloads.blocked_operands()
+    want = workloads.plain_matmul_mod(A, B, cfg.t)
+    res = {}
+    for part, (rows, cols) in workloads.PARTITIONS.items():
+        r0 = [int(x) for x in np.cumsum((0,) + rows)[:-1]]
+        c0 = [int(x) for x in np.cumsum((0,) + cols)[:-1]]
+        grid = [(i, j) for i in range(len(rows)) for j in range(len(cols))]
+        shapes = [(rows[i], D, cols[j]) for (i, j) in grid]
+        ctx = hg.Context(cfg.N, cfg.t, cfg.L, cfg.alpha)
+        ctx.keygen(cfg.seed, shapes)
+        As = [ctx.encrypt(0, A[r0[i]:r0[i] + rows[i], :], *shapes[k], nonce=k) for k, (i, j) in enumerate(grid)]
+        Bs = [ctx.encrypt(1, B[:, c0[j]:c0[j] + cols[j]], *shapes[k], nonce=k) for k, (i, j) in enumerate(grid)]
+        for _ in range(args.warmup):
+            outs = ctx.hegmm_batch(As, Bs, shapes)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            outs = ctx.hegmm_batch(As, Bs, shapes)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        C = np.zeros((D, D), dtype=np.int64)
+        for k, (i, j) in enumerate(grid):
+            C[r0[i]:r0[i] + rows[i], c0[j]:c0[j] + cols[j]] = ctx.decrypt(outs[k], *shapes[k])
+        ok = bool(np.array_equal(C, want))
+        ks = sum(ctx.plan_info(*s)["ks_terms"] for s in shapes)
+        res[part] = {"ms_per_product": ms, "products_per_s": 1000.0 / ms if ok else 0.0, "decrypt_ok": ok,
+                     "block_shapes": shapes, "inner_blocks": [ctx.plan_info(*s)["nb"] for s in shapes],
+                     "key_switched_rotations": ks}
+        del outs, As, Bs, ctx
+    r = res[args.partition]
+    print(json.dumps({
+        "metric": "100x100x100 blocked HE matmuls/s at N=8192", "value": r["products_per_s"],
+        "unit": "HE matmuls/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_product"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"HEGMM-En A(100x100) x B(100x100) as output blocks, partition {args.partition}, "
+                               "BGV N=8192 t=65537 L=4 alpha=1, entries in [-8,8]"},
+        "partitions": res,
+        "paper_table_iv_seconds_context": {"P1": 39.15, "P2": 26.23,
+                                            "platform": "Pyfhel BFV N=4096, Xeon Silver 4114 (10 cores)"}}),
+          flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); "
-              "the hot path shards across GPUs as described in DESIGN.md but no multi-GPU run is made.",
+              "independent products shard by request and one large product by its k-loop, but no multi-GPU "
+              "run is made.",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
@@ -357,6 +417,8 @@ def main():
         return run_large(args)
     if args.workload == "alg1":
         return run_alg1(args)
+    if args.workload == "blocked":
+        return run_blocked(args)
     import torch
     import paper_2405_02238_amd as hg
     import workloads

@@ -66,6 +66,12 @@ typedef struct {
     uint32_t alpha;
     uint32_t method;   /* 0 or 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1, column- or
                           row-major, no duplication or blocking; for comparison) */
+    uint32_t min_blocks; /* 0 or 1: every product splits its inner dimension into as few
+                            blocks as fit one ciphertext (usually one); k > 1: into at
+                            least k blocks (at most l), each accumulated into the same
+                            result (the blockwise product of Section IV-D, forced; the
+                            result decrypts to the same A B, its bits differ).  HEGMM-En
+                            only (HG_EINVAL with method 1). */
 } hg_params;
 
 /* Create a context on HIP device `hip_device` (must be gfx950).

@@ -77,10 +77,12 @@ def orientation(m: int, l: int, n: int) -> bool:
     return p == n
 
 
-def plan(m: int, l: int, n: int, S: int, method: int = 2) -> Plan:
+def plan(m: int, l: int, n: int, S: int, method: int = 2, min_blocks: int = 1) -> Plan:
     if min(m, l, n) <= 0:
         raise ValueError("dimensions must be positive")
     if method == 1:
+        if min_blocks > 1:
+            raise ValueError("forced blocking needs HEGMM-En")
         return plan_alg1(m, l, n, S)
     tr = orientation(m, l, n)
     mo, no = (n, m) if tr else (m, n)
@@ -89,14 +91,16 @@ def plan(m: int, l: int, n: int, S: int, method: int = 2) -> Plan:
         d, M, K, W = _constants(mo, lb, no)
         return M * W <= S
 
-    nb, lb = 1, l
-    if not fits(l):
-        nb = 2
-        while nb <= l and not fits(-(-l // nb)):
-            nb += 1
-        if nb > l:
-            raise ValueError("shape does not fit one ciphertext even with inner blocking")
-        lb = -(-l // nb)
+    # Section IV-D: when the operands do not fit one ciphertext, split the
+    # inner dimension into the fewest blocks that fit (at least min_blocks,
+    # to force the blockwise product on shapes that would fit whole), each
+    # block product accumulated into the same result
+    nb = min(max(min_blocks, 1), l)
+    while nb <= l and not fits(-(-l // nb)):
+        nb += 1
+    if nb > l:
+        raise ValueError("shape does not fit one ciphertext even with inner blocking")
+    lb = -(-l // nb)
     d, M, K, W = _constants(mo, lb, no)
     region = frozenset(i + j * M for i in range(M) for j in range(no))
 
@@ -325,10 +329,11 @@ class MaskCache:
         return m
 
 
-def galois_elements(P: Params, shapes: Sequence[Tuple[int, int, int]], method: int = 2) -> List[int]:
+def galois_elements(P: Params, shapes: Sequence[Tuple[int, int, int]], method: int = 2,
+                    min_blocks: int = 1) -> List[int]:
     gs = set()
     for (m, l, n) in shapes:
-        pl = plan(m, l, n, P.S, method)
+        pl = plan(m, l, n, P.S, method, min_blocks)
         for z in pl.rotations(P.S):
             gs.add(P.galois(z))
     return sorted(gs)

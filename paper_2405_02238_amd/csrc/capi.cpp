@@ -64,7 +64,10 @@ hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
     return guard([&] {
         need(p && out, "null argument");
         *out = nullptr;
+        need(p->min_blocks <= 4096, "min_blocks out of range");
+        need(p->min_blocks <= 1 || p->method != 1, "forced blocking needs HEGMM-En (method 2)");
         hg::Ctx *c = new hg::Ctx(p->N, p->t, p->L, p->alpha, dev, p->method == 0 ? 2 : (int)p->method);
+        c->min_blocks = p->min_blocks > 1 ? (int)p->min_blocks : 1;
         hg_ctx *h = new hg_ctx;
         h->c = c;
         *out = h;
@@ -335,7 +338,7 @@ hg_status hg_plan_info(hg_ctx *ctx, int m, int l, int n, int64_t *out) {
         hg::Ctx &X = *ctx->c;
         hg::Plan p;
         try {
-            p = hg::make_plan(m, l, n, X.S, X.method);
+            p = hg::make_plan(m, l, n, X.S, X.method, X.min_blocks);
         } catch (std::invalid_argument &e) {
             throw hg::Error(HG_EINVAL, e.what());
         } catch (std::range_error &e) {
@@ -400,7 +403,7 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
         hg::Ctx &X = *ctx->c;
         hg::Plan p;
         try {
-            p = hg::make_plan(m, l, n, X.S, X.method);
+            p = hg::make_plan(m, l, n, X.S, X.method, X.min_blocks);
         } catch (std::invalid_argument &e) {
             throw hg::Error(HG_EINVAL, e.what());
         } catch (std::range_error &e) {

@@ -257,7 +257,7 @@ const PlanEntry &Ctx::plan_for(int m, int l, int n) {
     if (it != plans.end()) return *it->second;
     auto pe = std::make_unique<PlanEntry>();
     try {
-        pe->plan = make_plan(m, l, n, S, method);
+        pe->plan = make_plan(m, l, n, S, method, min_blocks);
     } catch (std::invalid_argument &e) {
         throw Error(-1, e.what());
     } catch (std::range_error &e) {

@@ -107,6 +107,7 @@ struct Ctx {
     bool capturing = false;
     Arena &arena_for(hipStream_t st);
     Timing timing;
+    int min_blocks = 1;   // inner blocks of every plan at least this many (fixed at creation)
     int fuse_rows = 256;  // passes with at most this many rows per chain use the fused kernels
     int ip_chunk = 0;     // terms sharing a key per workgroup in the key-stationary inner products (0: off)
     int ip_order = 1;     // plain inner products launch their jobs ordered by key (0: pass order)

@@ -114,8 +114,9 @@ Plan make_plan_alg1(int m, int l, int n, int S) {
 
 }  // namespace
 
-Plan make_plan(int m, int l, int n, int S, int method) {
+Plan make_plan(int m, int l, int n, int S, int method, int min_blocks) {
     if (m <= 0 || l <= 0 || n <= 0) throw std::invalid_argument("dimensions must be positive");
+    if (min_blocks > 1 && method == 1) throw std::invalid_argument("forced blocking needs HEGMM-En");
     if (method == 1) return make_plan_alg1(m, l, n, S);
     if (method != 2) throw std::invalid_argument("method must be 1 or 2");
     Plan p;
@@ -132,15 +133,13 @@ Plan make_plan(int m, int l, int n, int S, int method) {
         Consts c = constants(p.mo, lb, p.no);
         return (long long)c.M * c.W <= S;
     };
-    p.nb = 1;
-    p.lb = l;
-    if (!fits(l)) {
-        int nb = 2;
-        while (nb <= l && !fits((l + nb - 1) / nb)) ++nb;
-        if (nb > l) throw std::range_error("shape does not fit one ciphertext row");
-        p.nb = nb;
-        p.lb = (l + nb - 1) / nb;
-    }
+    // the fewest inner blocks (at least min_blocks, at most l) whose block
+    // length fits
+    int nb = std::min(std::max(min_blocks, 1), l);
+    while (nb <= l && !fits((l + nb - 1) / nb)) ++nb;
+    if (nb > l) throw std::range_error("shape does not fit one ciphertext row");
+    p.nb = nb;
+    p.lb = (l + nb - 1) / nb;
     Consts c = constants(p.mo, p.lb, p.no);
     p.d = c.d; p.M = c.M; p.K = c.K; p.W = c.W;
     const int M = p.M, mo = p.mo, no = p.no, lb = p.lb, W = p.W;

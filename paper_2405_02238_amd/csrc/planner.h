@@ -35,10 +35,12 @@ struct Plan {
 
 // Throws std::invalid_argument when a dimension is not positive and
 // std::range_error when the shape cannot be planned into S slots.
+// min_blocks > 1 splits the inner dimension into at least that many blocks
+// (capped at l) even when fewer would fit (method 2 only).
 // method 2: HEGMM-En; method 1: the paper's Algorithm 1 (HEGMM), sigma and
 // tau applied by the client, column-major or (when that needs fewer
 // key-switched diagonals) row-major flattening, no duplication, no blocking.
-Plan make_plan(int m, int l, int n, int S, int method = 2);
+Plan make_plan(int m, int l, int n, int S, int method = 2, int min_blocks = 1);
 
 // Client packing: the slot vector (length S, values in [0, t)) of the left
 // (side 0) or right (side 1) operand of the oriented problem for inner block

@@ -26,13 +26,14 @@ def flat(ct):
 class Pair:
     """A library context and the oracle's key set for the same parameters and seed."""
 
-    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=()):
+    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=(), min_blocks=1):
         self.P = Params(N, t, L, alpha)
-        self.ctx = hg.Context(N, t, L, alpha)
+        self.min_blocks = min_blocks
+        self.ctx = hg.Context(N, t, L, alpha, min_blocks=min_blocks)
         self.ctx.keygen(seed, shapes)
         if zs:
             self.ctx.keygen_rotations(zs)
-        gal = H.galois_elements(self.P, shapes) + [self.P.galois(z) for z in zs]
+        gal = H.galois_elements(self.P, shapes, min_blocks=min_blocks) + [self.P.galois(z) for z in zs]
         self.ks = bgv.KeySet(self.P, seed, gal)
         self.masks = H.MaskCache(self.P)
 
@@ -95,7 +96,7 @@ def run_pair(pair, m, l, n, A, B, nonce):
     ctx, P, ks = pair.ctx, pair.P, pair.ks
     ca = ctx.encrypt(0, A, m, l, n, nonce=nonce)
     cb = ctx.encrypt(1, B, m, l, n, nonce=nonce)
-    pl = H.plan(m, l, n, P.S)
+    pl = H.plan(m, l, n, P.S, min_blocks=pair.min_blocks)
     ox = H.encrypt_operand(ks, pl, 0, A, B, nonce)
     oy = H.encrypt_operand(ks, pl, 1, A, B, nonce)
     # operands: bit-identical packing + encryption
@@ -123,6 +124,22 @@ def test_hegmm_shapes(tiny, shape):
     A = rng.integers(-8, 9, size=(m, l))
     B = rng.integers(-8, 9, size=(l, n))
     run_pair(tiny, m, l, n, A, B, nonce=7)
+
+
+@pytest.mark.parametrize("min_blocks", [2, 3])
+def test_hegmm_forced_blocks(min_blocks):
+    """The blockwise product (inner dimension split into at least k blocks,
+    one accumulator) forced on shapes that fit whole: bits equal the oracle's
+    with the same plan, and the result decrypts to A.B mod t."""
+    c = workloads.TINY
+    shapes = [(4, 3, 5), (2, 5, 7), (5, 4, 2), (7, 7, 7)]
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=shapes, min_blocks=min_blocks)
+    rng = np.random.default_rng(60 + min_blocks)
+    for i, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        assert pair.ctx.plan_info(m, l, n)["nb"] == min(min_blocks, l)
+        run_pair(pair, m, l, n, A, B, nonce=11 + i)
 
 
 def test_hegmm_alpha2():
@@ -259,6 +276,79 @@ def test_serving_errors_and_budget():
 def _sha(words):
     import hashlib
     return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
+
+
+def _offsets(sizes):
+    return [int(x) for x in np.cumsum((0,) + tuple(sizes))[:-1]]
+
+
+@pytest.mark.parametrize("part", ["P1", "P2"])
+def test_blocked_100x100(part):
+    """A 100x100 by 100x100 product whose result does not fit one ciphertext
+    (10000 > 4096 slots), computed as the paper's blocked product: the client
+    splits A into row blocks and B into column blocks, the cloud runs the
+    block products in one batch (each splits its inner dimension itself), the
+    client assembles C.  One block is checked against the oracle bit for bit.
+    For P1 the paper's own split of the inner dimension too (eight 50x50x50
+    products, partial results added with HE-Add) gives the same C."""
+    c = workloads.HEADLINE
+    D = workloads.BLOCKED_DIM
+    A, B = workloads.blocked_operands()
+    rows, cols = workloads.PARTITIONS[part]
+    r0, c0 = _offsets(rows), _offsets(cols)
+    grid = [(i, j) for i in range(len(rows)) for j in range(len(cols))]
+    shapes = [(rows[i], D, cols[j]) for (i, j) in grid]
+    extra = [(50, 50, 50)] if part == "P1" else []
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=shapes[:1] + extra)
+    ctx = pair.ctx
+    ctx.keygen(c.seed, shapes)
+    As = [ctx.encrypt(0, A[r0[i]:r0[i] + rows[i], :], *shapes[k], nonce=20 + k) for k, (i, j) in enumerate(grid)]
+    Bs = [ctx.encrypt(1, B[:, c0[j]:c0[j] + cols[j]], *shapes[k], nonce=20 + k) for k, (i, j) in enumerate(grid)]
+    outs = ctx.hegmm_batch(As, Bs, shapes)
+    C = np.zeros((D, D), dtype=np.int64)
+    for k, (i, j) in enumerate(grid):
+        C[r0[i]:r0[i] + rows[i], c0[j]:c0[j] + cols[j]] = ctx.decrypt(outs[k], *shapes[k])
+    assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t))
+    # the first block product against the oracle
+    m, l, n = shapes[0]
+    pl = H.plan(m, l, n, pair.P.S)
+    assert pl.nb > 1
+    Ab, Bb = A[:m, :], B[:, :n]
+    ox = H.encrypt_operand(pair.ks, pl, 0, Ab, Bb, 20)
+    oy = H.encrypt_operand(pair.ks, pl, 1, Ab, Bb, 20)
+    assert np.array_equal(outs[0].export(), flat(H.hegmm(pair.ks, pl, ox, oy, pair.masks)))
+    if part == "P1":
+        # inner dimension split as well: C_ij = A_i1 B_1j + A_i2 B_2j
+        k0 = _offsets((50, 50))
+        s = (50, 50, 50)
+        pa, pb = [], []
+        for (i, j) in grid:
+            for h in range(2):
+                pa.append(ctx.encrypt(0, A[r0[i]:r0[i] + 50, k0[h]:k0[h] + 50], *s, nonce=40 + len(pa)))
+                pb.append(ctx.encrypt(1, B[k0[h]:k0[h] + 50, c0[j]:c0[j] + 50], *s, nonce=40 + len(pb)))
+        prods = ctx.hegmm_batch(pa, pb, [s] * len(pa))
+        for g, (i, j) in enumerate(grid):
+            blk = ctx.add(prods[2 * g], prods[2 * g + 1])
+            assert np.array_equal(ctx.decrypt(blk, *s), C[r0[i]:r0[i] + 50, c0[j]:c0[j] + 50])
+
+
+def test_large_forced_two_blocks():
+    """The large configuration's blockwise run: 128x96x128 at N = 32768 with
+    the inner dimension forced into two blocks of 48 (two ciphertexts per
+    operand, one accumulator); its bits differ from the one-block product by
+    design, its decryption must not."""
+    c = workloads.LARGE
+    m, l, n = 128, 96, 128
+    A, B = workloads.large_operands()
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, min_blocks=2)
+    info = ctx.plan_info(m, l, n)
+    assert (info["nb"], info["lb"]) == (2, 48)
+    ctx.keygen(c.seed, [(m, l, n)])
+    ca = ctx.encrypt(0, A, m, l, n, nonce=2)
+    cb = ctx.encrypt(1, B, m, l, n, nonce=2)
+    assert ca.export().size == 2 * 2 * c.L * c.N
+    cc = ctx.hegmm(ca, cb, m, l, n)
+    assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
 
 
 def test_large_operands_and_product():

@@ -156,6 +156,26 @@ def test_cleartext_twin_blocked_shapes():
     assert count > 10
 
 
+def test_forced_blocking_plans():
+    """Section IV-D's blockwise product forced on shapes that fit whole: the
+    large configuration splits its inner dimension 96 into two blocks of 48;
+    blocks never exceed l; the blocked plan is still exact on cleartext."""
+    large = H.plan(128, 96, 128, 16384, min_blocks=2)
+    assert (large.nb, large.lb, large.M, large.W) == (2, 48, 128, 128)
+    assert H.plan(4, 3, 5, 512, min_blocks=9).nb == 3          # capped at l
+    assert H.plan(64, 32, 48, 4096, min_blocks=1).nb == 1
+    with pytest.raises(ValueError):
+        H.plan(4, 3, 5, 512, method=1, min_blocks=2)
+    rng = np.random.default_rng(13)
+    for (m, l, n) in workloads.random_shapes(rng, 60, 2, 12):
+        for k in (2, 3):
+            pl = H.plan(m, l, n, 256, min_blocks=k)
+            assert pl.nb == min(k, l) and pl.lb == -(-l // pl.nb)
+            A = rng.integers(-8, 9, size=(m, l))
+            B = rng.integers(-8, 9, size=(l, n))
+            assert (H.hegmm_cleartext(pl, A, B, 12289, 256) == workloads.plain_matmul_mod(A, B, 12289)).all(), (m, l, n, k)
+
+
 def test_headline_plan_counts():
     pl = H.plan(64, 32, 48, 4096)
     assert (pl.transposed, pl.d, pl.M, pl.K, pl.W, pl.nb) == (False, 1, 64, 32, 48, 1)
@@ -176,14 +196,14 @@ def test_batched_grid_fit_counts():
 # encrypted end to end
 # ---------------------------------------------------------------------------
 
-def run_encrypted(P, shapes, seed):
-    ks = bgv.KeySet(P, seed, H.galois_elements(P, shapes))
+def run_encrypted(P, shapes, seed, min_blocks=1):
+    ks = bgv.KeySet(P, seed, H.galois_elements(P, shapes, min_blocks=min_blocks))
     rng = np.random.default_rng(seed)
     masks = H.MaskCache(P)
     for idx, (m, l, n) in enumerate(shapes):
         A = rng.integers(-8, 9, size=(m, l))
         B = rng.integers(-8, 9, size=(l, n))
-        pl = H.plan(m, l, n, P.S)
+        pl = H.plan(m, l, n, P.S, min_blocks=min_blocks)
         cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=idx)
         cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=idx)
         C = H.hegmm(ks, pl, cx, cy, masks)
@@ -196,6 +216,13 @@ def test_encrypted_small_shapes_alpha1():
     P = Params(128, 12289, 3, 1)
     # d > 1 (fold), transposed, l-min, square, blocked (M*W > 64)
     run_encrypted(P, [(2, 5, 7), (5, 4, 2), (6, 3, 5), (4, 4, 4), (3, 11, 6), (1, 6, 1)], 77)
+
+
+def test_encrypted_forced_blocks():
+    """Forced inner blocks (one accumulator over the block products) decrypt
+    to A B mod t."""
+    P = Params(128, 12289, 3, 1)
+    run_encrypted(P, [(2, 5, 7), (5, 4, 2), (4, 4, 4)], 79, min_blocks=2)
 
 
 def test_encrypted_small_shapes_alpha2():

@@ -85,6 +85,18 @@ def large_operands() -> Tuple[np.ndarray, np.ndarray]:
     return operands(LARGE, 128, 96, 128, -4, 4)
 
 
+# Blocked 100 x 100 product (the partitions of the paper's large-matrix
+# experiment, Section IV-D): the row blocks of A and the column blocks of B.
+# P1: 50 + 50 each way; P2: 64 + 36 each way.  On the headline ring.
+BLOCKED_DIM = 100
+PARTITIONS = {"P1": ((50, 50), (50, 50)), "P2": ((64, 36), (64, 36))}
+
+
+def blocked_operands() -> Tuple[np.ndarray, np.ndarray]:
+    """A and B, 100 x 100, entries in [-8, 8]."""
+    return operands(HEADLINE, BLOCKED_DIM, BLOCKED_DIM, BLOCKED_DIM, -8, 8, seed_offset=100)
+
+
 def batched_shapes(count: int = 256, seed_offset: int = 0) -> List[Tuple[int, int, int]]:
     """(m, l, n) i.i.d. uniform over {8, 16, ..., 64}^3 (the products never exceed 4096)."""
     rng = np.random.default_rng(BATCHED.seed + seed_offset)
