@@ -79,6 +79,27 @@ typedef struct {
 hg_status hg_ctx_create(const hg_params *params, int hip_device, hg_ctx **out);
 void hg_ctx_destroy(hg_ctx *ctx);
 
+/* Device memory of ciphertext handles.  By default every handle the library
+ * creates (hg_encrypt, hg_hegmm, hg_hegmm_batch and graph results,
+ * hg_ct_import, the primitives) takes its own hipMalloc, and hg_ct_free
+ * returns it with hipFree, which waits for the whole device.  A caller can
+ * supply the memory instead, for instance from a framework's caching
+ * allocator: alloc(bytes, stream, user) returns device memory of at least
+ * `bytes` for use on `stream` (the stream of the call that creates the
+ * handle; NULL for hg_encrypt, hg_ct_import and graph results), or NULL on
+ * failure (the call then fails with HG_ENOMEM); release(ptr, user) takes it
+ * back when the handle is freed.  release may be called while work that
+ * reads or writes the memory is still queued on that stream, so the
+ * allocator must not reuse the memory for work on another stream before that
+ * work has finished (stream-ordered caching allocators guarantee this).
+ * A handle always goes back to the release function in force when it was
+ * created.  Both NULL: back to hipMalloc / hipFree.  Internal workspaces,
+ * keys and tables always use the library's own allocations.
+ * Errors: HG_EINVAL (only one of alloc, release given). */
+typedef void *(*hg_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*hg_release_fn)(void *ptr, void *user);
+hg_status hg_set_allocator(hg_ctx *ctx, hg_alloc_fn alloc, hg_release_fn release, void *user);
+
 /* Key generation (client role).  Samples the secret key from `seed` and
  * generates, on the device, the relinearisation key and every rotation key
  * that the HEGMM-En plans of the given shapes need.  `shapes` holds nshapes

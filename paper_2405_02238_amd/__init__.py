@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import List, Optional, Sequence, Tuple
+from typing import Callable, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -48,8 +48,12 @@ _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _SIGS = {
     "hg_ctx_create": [ctypes.POINTER(_Params), ctypes.c_int, _PP],
+    "hg_set_allocator": [_P, _ALLOC_FN, _RELEASE_FN, _P],
     "hg_keygen": [_P, ctypes.c_uint64, _i32p, ctypes.c_size_t],
     "hg_keygen_rotations": [_P, _i32p, ctypes.c_size_t],
     "hg_drop_secret": [_P],
@@ -170,6 +174,7 @@ class Context:
         _check(_lib.hg_ctx_create(ctypes.byref(p), device, ctypes.byref(out)))
         self.ptr = out.value
         self.N, self.t, self.L, self.alpha, self.method, self.min_blocks = N, t, L, alpha, method, min_blocks
+        self.device = device
         self.S = N // 2
 
     def close(self):
@@ -185,6 +190,33 @@ class Context:
 
     def _ct(self, out: ctypes.c_void_p) -> Ciphertext:
         return Ciphertext(self, out.value)
+
+    def set_allocator(self, alloc: Optional[Callable[[int, Optional[int]], int]],
+                      release: Optional[Callable[[int], None]]):
+        """hg_set_allocator: alloc(nbytes, stream) -> device pointer (0 on
+        failure), release(ptr); both None restores hipMalloc / hipFree."""
+        if alloc is None and release is None:
+            _check(_lib.hg_set_allocator(self.ptr, _ALLOC_FN(), _RELEASE_FN(), None))
+            self._alloc_cbs = None
+            return
+        a = _ALLOC_FN(lambda nbytes, stream, user: alloc(nbytes, stream) or None)
+        r = _RELEASE_FN(lambda ptr, user: release(ptr))
+        _check(_lib.hg_set_allocator(self.ptr, a, r, None))
+        # every callback object stays alive as long as the context: handles made
+        # while it was in force still return their memory through it
+        self._alloc_cbs_all = getattr(self, "_alloc_cbs_all", []) + [(a, r)]
+        self._alloc_cbs = (a, r)
+
+    def use_torch_allocator(self):
+        """Route ciphertext handles through torch's caching allocator (stream
+        ordered; freeing a handle then does not wait for the device)."""
+        import torch
+        dev = self.device
+
+        def alloc(nbytes, stream):
+            return torch.cuda.caching_allocator_alloc(nbytes, device=dev, stream=stream or 0)
+
+        self.set_allocator(alloc, torch.cuda.caching_allocator_delete)
 
     def keygen(self, seed: int, shapes: Sequence[Tuple[int, int, int]] = ()):
         arr = np.ascontiguousarray(np.array(list(shapes), dtype=np.int32).reshape(-1))

@@ -60,6 +60,17 @@ extern "C" {
 
 const char *hg_last_error(void) { return g_err.c_str(); }
 
+hg_status hg_set_allocator(hg_ctx *ctx, hg_alloc_fn alloc, hg_release_fn release, void *user) {
+    return guard([&] {
+        need(ctx, "null argument");
+        need((alloc == nullptr) == (release == nullptr), "alloc and release must be given together");
+        hg::Ctx &X = *ctx->c;
+        X.ct_alloc_fn = alloc;
+        X.ct_release_fn = release;
+        X.ct_alloc_user = alloc ? user : nullptr;
+    });
+}
+
 hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
     return guard([&] {
         need(p && out, "null argument");
@@ -142,7 +153,7 @@ hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const h
             o->m = mln[3 * i]; o->l = mln[3 * i + 1]; o->n = mln[3 * i + 2];
             o->side = 2;
             made.push_back(o);
-            o->d = X.dev_alloc(o->words());
+            X.ct_alloc(o, as_stream(stream));
             reqs.push_back({A[i]->c, B[i]->c, mln[3 * i], mln[3 * i + 1], mln[3 * i + 2], o});
         }
         X.hegmm_batch(reqs, as_stream(stream));
@@ -177,7 +188,7 @@ hg_status hg_graph_create(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const 
             o->m = mln[3 * i]; o->l = mln[3 * i + 1]; o->n = mln[3 * i + 2];
             o->side = 2;
             made.push_back(o);
-            o->d = X.dev_alloc(o->words());
+            X.ct_alloc(o, nullptr);
             reqs.push_back({A[i]->c, B[i]->c, mln[3 * i], mln[3 * i + 1], mln[3 * i + 2], o});
         }
         gr = new hg::Graph(X, reqs);

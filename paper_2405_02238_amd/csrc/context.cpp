@@ -52,7 +52,21 @@ double centered_d(uint64_t x, uint64_t m) { return (double)centered_of(x, m); }
 size_t Ct::words() const { return (size_t)ncts * comps * ctx->L * ctx->N; }
 double *Ct::ct(int i) const { return d + (size_t)i * comps * ctx->L * ctx->N; }
 Ct::~Ct() {
-    if (d && owns) (void)hipFree(d);
+    if (!d || !owns) return;
+    if (release) release(d, release_user);
+    else (void)hipFree(d);
+}
+
+void Ctx::ct_alloc(Ct *c, hipStream_t st) {
+    if (!ct_alloc_fn) {
+        c->d = dev_alloc(c->words());
+        return;
+    }
+    void *p = ct_alloc_fn(std::max<size_t>(c->words(), 32) * sizeof(double), (void *)st, ct_alloc_user);
+    if (!p) throw Error(-4, "the caller's allocator returned no memory");
+    c->d = (double *)p;
+    c->release = ct_release_fn;
+    c->release_user = ct_alloc_user;
 }
 
 // ---------------------------------------------------------------------------
@@ -415,7 +429,7 @@ Ct *Ctx::encrypt_slots(const std::vector<uint64_t> &slots, int side, int block, 
         c->ctx = this;
         c->ncts = 1;
         c->comps = 2;
-        c->d = dev_alloc(c->words());
+        ct_alloc(c, st);
     }
     double *c0 = c->ct(into_index);
     double *c1 = c0 + (size_t)L * N;
@@ -452,7 +466,7 @@ Ct *Ctx::encrypt_matrix(int role, const int64_t *X, int m, int l, int n, uint64_
     c->comps = 2;
     c->m = m; c->l = l; c->n = n;
     c->side = side;
-    c->d = dev_alloc(c->words());
+    ct_alloc(c, nullptr);
     try {
         for (int b = 0; b < p.nb; ++b) {
             std::vector<uint64_t> v = pack_operand(p, side, X, b, t, S);
@@ -565,7 +579,7 @@ Ct *Ctx::import_ct(const uint64_t *buf, int ncts, int comps, hipStream_t st) {
     c->ctx = this;
     c->ncts = ncts;
     c->comps = comps;
-    c->d = dev_alloc(c->words());
+    ct_alloc(c, st);
     try {
         load_ct(*c, buf, c->words(), st);
     } catch (...) {

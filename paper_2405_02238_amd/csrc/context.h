@@ -26,6 +26,11 @@ void hip_check(hipError_t e, const char *what);
 
 struct Ctx;
 
+// Caller-supplied device memory for ciphertext handles (hg_set_allocator):
+// alloc(bytes, stream, user) -> device memory or null; release(ptr, user).
+typedef void *(*CtAllocFn)(size_t bytes, void *stream, void *user);
+typedef void (*CtReleaseFn)(void *ptr, void *user);
+
 // A packed operand/result: ncts ciphertexts of `comps` components, each
 // comps x L x N doubles in evaluation form, one device allocation.
 struct Ct {
@@ -35,6 +40,8 @@ struct Ct {
     int side = -1;             // packed side (0 left, 1 right, 2 result, -1 raw)
     double *d = nullptr;
     bool owns = true;          // false: a view into memory owned elsewhere
+    CtReleaseFn release = nullptr;   // d came from the caller's allocator: give it back here
+    void *release_user = nullptr;
     size_t words() const;      // doubles in total
     double *ct(int i) const;   // start of ciphertext i
     ~Ct();
@@ -108,6 +115,12 @@ struct Ctx {
     Arena &arena_for(hipStream_t st);
     Timing timing;
     int min_blocks = 1;   // inner blocks of every plan at least this many (fixed at creation)
+    // the caller's allocator for ciphertext handles (null: hipMalloc / hipFree)
+    CtAllocFn ct_alloc_fn = nullptr;
+    CtReleaseFn ct_release_fn = nullptr;
+    void *ct_alloc_user = nullptr;
+    // device memory for the words of handle c, to be used on stream st
+    void ct_alloc(Ct *c, hipStream_t st);
     int fuse_rows = 256;  // passes with at most this many rows per chain use the fused kernels
     int ip_chunk = 0;     // terms sharing a key per workgroup in the key-stationary inner products (0: off)
     int ip_order = 1;     // plain inner products launch their jobs ordered by key (0: pass order)

@@ -714,7 +714,7 @@ Ct *Ctx::rotate(const Ct &c, int z, hipStream_t st) {
     if (c.comps != 2 || c.ncts != 1) throw Error(-1, "rotate takes one two-component ciphertext");
     Ct *o = new Ct();
     o->ctx = this;
-    o->d = dev_alloc(o->words());
+    ct_alloc(o, st);
     try {
         Exec ex(*this, st);
         Pass ps;
@@ -736,7 +736,7 @@ Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
     const size_t ctw = (size_t)L * N;
     Ct *o = new Ct();
     o->ctx = this;
-    o->d = dev_alloc(o->words());
+    ct_alloc(o, st);
     try {
         Exec ex(*this, st);
         double *acc = ex.acc(3 * ctw * sizeof(double));
@@ -767,7 +767,7 @@ Ct *Ctx::add(const Ct &a, const Ct &b, hipStream_t st) {
     o->ctx = this;
     o->ncts = a.ncts;
     o->comps = a.comps;
-    o->d = dev_alloc(o->words());
+    ct_alloc(o, st);
     add_rows(T, o->d, a.d, b.d, a.ncts * a.comps * L, 0, L, st);
     return o;
 }
@@ -802,7 +802,7 @@ Ct *Ctx::cmul(const Ct &a, const std::vector<uint64_t> &slots, hipStream_t st) {
     o->ctx = this;
     o->ncts = a.ncts;
     o->comps = a.comps;
-    o->d = dev_alloc(o->words());
+    ct_alloc(o, st);
     for (int c = 0; c < a.ncts * a.comps; ++c)
         mul_rows(T, o->d + (size_t)c * L * N, a.d + (size_t)c * L * N, m, L, 0, L, st);
     if (own) {

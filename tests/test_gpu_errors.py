@@ -156,3 +156,40 @@ def test_batch_rejects_before_any_work(ctx):
     out = ctx.hegmm_batch([ca, ca], [cb, cb], [(4, 3, 5), (4, 3, 5)])
     for c in out:
         assert np.array_equal(c.export(), alone)
+
+
+def test_caller_allocator():
+    """Handles from the caller's allocator (torch's caching allocator) hold
+    the same bits as library-allocated ones, on any stream; their memory is
+    torch's and returns to it when they are freed, also after the allocator
+    was switched back to hipMalloc."""
+    import gc
+    c = workloads.TINY
+    A, B = workloads.tiny_operands()
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, [(4, 3, 5)])
+    ref = ctx.hegmm(ctx.encrypt(0, A, 4, 3, 5, nonce=1), ctx.encrypt(1, B, 4, 3, 5, nonce=1), 4, 3, 5).export()
+    torch.cuda.synchronize()
+    gc.collect()
+    before = torch.cuda.memory_allocated()
+    ctx.use_torch_allocator()
+    ca, cb = ctx.encrypt(0, A, 4, 3, 5, nonce=1), ctx.encrypt(1, B, 4, 3, 5, nonce=1)
+    outs = [ctx.hegmm(ca, cb, 4, 3, 5) for _ in range(4)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        outs.append(ctx.hegmm(ca, cb, 4, 3, 5))
+    s.synchronize()
+    assert torch.cuda.memory_allocated() > before
+    assert all(np.array_equal(o.export(), ref) for o in outs)
+    kept = outs.pop()
+    del outs
+    ctx.set_allocator(None, None)
+    plain = ctx.hegmm(ca, cb, 4, 3, 5)
+    assert np.array_equal(plain.export(), ref)
+    del kept, ca, cb, plain
+    gc.collect()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+    with pytest.raises(hg.HGError) as e:   # alloc without release
+        hg._check(hg._lib.hg_set_allocator(ctx.ptr, hg._ALLOC_FN(lambda n, s, u: None), hg._RELEASE_FN(), None))
+    assert e.value.code == hg.HG_EINVAL
