@@ -84,8 +84,12 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
         const IpTerm tm = terms[tix];
         double2 mv = make_double2(1.0, 1.0);
         if (tm.mask >= 0) mv = ld_stream2(masks[tm.mask] + (size_t)r * N + p);
-        const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
-        const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
+        // positions p, p + 1 (p even) gather from the aligned pair {pb, pb + 1}
+        // (the automorphism flips bit 0 of the source with bit 0 of p), in
+        // swapped order when sw
+        const int pp = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
+        const int pb = pp & ~1;
+        const bool sw = pp & 1;
         if (tm.kind != IP_PLAIN) {
             const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
             const double *kb = keys[tm.key] + (size_t)r * N + p;
@@ -94,8 +98,9 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
             double2 kbv[BETA], kav[BETA];
 #pragma unroll
             for (int j = 0; j < BETA; ++j) {
-                y0[j] = ys[(size_t)j * plane + pp0];
-                y1[j] = ys[(size_t)j * plane + pp1];
+                const double2 v = ld2(ys + (size_t)j * plane + pb);
+                y0[j] = sw ? v.y : v.x;
+                y1[j] = sw ? v.x : v.y;
                 kbv[j] = ld_stream2(kb + (size_t)j * plane);
             }
 #pragma unroll
@@ -125,7 +130,8 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
             a1y = redm(a1y + s1y, q, qi);
         }
         if (qrow && tm.kind != IP_RELIN) {
-            double x0 = gld(J.c0)[(size_t)r * N + pp0], x1 = gld(J.c0)[(size_t)r * N + pp1];
+            const double2 cv = ld2(J.c0 + (size_t)r * N + pb);
+            double x0 = sw ? cv.y : cv.x, x1 = sw ? cv.x : cv.y;
             if (tm.mask >= 0) {
                 x0 = mulm(x0, mv.x, q, qi);
                 x1 = mulm(x1, mv.y, q, qi);
@@ -194,14 +200,16 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
         const int2 tk = tasks[e];
         const IpJob J = jobs[tk.x];
         const IpTerm tm = terms[tk.y];
-        const int pp0 = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
-        const int pp1 = tm.g == 1 ? p + 1 : perm_index(p + 1, tm.g, T.logN);
+        const int pp = tm.g == 1 ? p : perm_index(p, tm.g, T.logN);
+        const int pb = pp & ~1;
+        const bool sw = pp & 1;
         const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
         double y0[BETA], y1[BETA];
 #pragma unroll
         for (int j = 0; j < BETA; ++j) {
-            y0[j] = ys[(size_t)j * plane + pp0];
-            y1[j] = ys[(size_t)j * plane + pp1];
+            const double2 v = ld2(ys + (size_t)j * plane + pb);
+            y0[j] = sw ? v.y : v.x;
+            y1[j] = sw ? v.x : v.y;
         }
         double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;
 #pragma unroll
@@ -232,9 +240,10 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
                     if (pt.kind == IP_RELIN) continue;
                     double2 mv = make_double2(1.0, 1.0);
                     if (pt.mask >= 0) mv = ld2(masks[pt.mask] + (size_t)r * N + p);
-                    const int qq0 = pt.g == 1 ? p : perm_index(p, pt.g, T.logN);
-                    const int qq1 = pt.g == 1 ? p + 1 : perm_index(p + 1, pt.g, T.logN);
-                    double x0 = gld(J.c0)[(size_t)r * N + qq0], x1 = gld(J.c0)[(size_t)r * N + qq1];
+                    const int qq = pt.g == 1 ? p : perm_index(p, pt.g, T.logN);
+                    const bool qs = qq & 1;
+                    const double2 cv = ld2(J.c0 + (size_t)r * N + (qq & ~1));
+                    double x0 = qs ? cv.y : cv.x, x1 = qs ? cv.x : cv.y;
                     if (pt.mask >= 0) {
                         x0 = mulm(x0, mv.x, q, qi);
                         x1 = mulm(x1, mv.y, q, qi);
