@@ -280,9 +280,13 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
  *                together; 0: in pass order
  *   "split_rows" transforms of fewer rows than this split each row over
  *                N/1024 workgroups (two passes)
+ *   "ntt_radix"  radix of the one-workgroup row transforms of 4096- and
+ *                8192-point rows: 8, 16, or 0 for the built-in choice (8);
+ *                like "split_rows" it holds for every context of the process
  *   "batch_window" products per launch group inside hg_hegmm_batch
  *                (0: all at once)
- * Errors: HG_EINVAL (unknown name or negative value). */
+ * Errors: HG_EINVAL (unknown name, negative value, "pipeline" outside
+ * [1, 16], "ntt_radix" other than 0, 8, 16). */
 hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value);
 
 /* ---- introspection ---------------------------------------------------- */

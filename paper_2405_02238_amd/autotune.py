@@ -25,6 +25,7 @@ DEFAULT_SPACE = {
     "fuse_rows": [0, 64, 256],
     "ip_chunk": [0, 16, 64],
     "ip_order": [0, 1],
+    "ntt_radix": [8, 16],
     "batch_window": [0, 64, 128],
 }
 

@@ -385,6 +385,10 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
         else if (n == "ip_chunk") X.ip_chunk = (int)value;
         else if (n == "ip_order") X.ip_order = (int)value;
         else if (n == "split_rows") hg::ntt_set_split_rows((int)value);
+        else if (n == "ntt_radix") {
+            need(value == 0 || value == 8 || value == 16, "ntt_radix must be 0, 8 or 16");
+            hg::ntt_set_radix((int)value);
+        }
         else if (n == "batch_window") X.batch_window = (int)value;
         else if (n == "pipeline") {
             need(value >= 1 && value <= 16, "pipeline must be in [1, 16]");

@@ -116,6 +116,11 @@ void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, h
 // rows longer than 16384 always use the split form.
 void ntt_set_split_rows(int rows);
 
+// Radix of the row transforms of 4096- and 8192-point rows: 8 or 16, or 0
+// for the built-in choice (8); other lengths have one radix.  Results are
+// the same for every radix.  Throws std::invalid_argument for other values.
+void ntt_set_radix(int radix);
+
 // Inner products: U[slot][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
 // the unswitched part on the ciphertext primes (see IpTerm).

@@ -21,6 +21,8 @@
 // the row (ModUp), LOAD_DELTA forms the correction delta of the division by P
 // from the centered r_k rows, STORE_MDR turns an inverse-transformed special
 // prime row into the exact centered r_k.
+#include <stdexcept>
+
 #include "arith.h"
 #include "dev_common.h"
 #include "kernels.h"
@@ -54,7 +56,7 @@ __host__ __device__ constexpr int rk_of(int logn) { return (logn == 12 || logn =
 // 1024-thread rows (8192 points) two rows fit a CU (LDS 2 x 70 KB) when each
 // thread keeps to 64 VGPRs, i.e. 8 waves per SIMD; other sizes keep the
 // default.
-__host__ __device__ constexpr int waves_of(int logn) { return logn == 13 ? 8 : 1; }
+__host__ __device__ constexpr int waves_of(int logn, int rk) { return logn == 13 ? (rk == 3 ? 8 : 4) : 1; }
 
 // ---- whole rows with the size known at compile time ----
 // Round R of a 2^LOGN-point forward transform covers stages [S0, S0 + K).
@@ -178,10 +180,10 @@ __device__ __forceinline__ void inv_rows_c(double *sh, const double *tw, double 
 // elementwise step -> forward keeps the row in registers in between.
 // Forward rounds: RK, ..., RK, KT; inverse rounds: KT, RK, ..., RK
 // (KT = the remainder of LOGN over RK, or RK).
-template <int LOGN>
+template <int LOGN, int RK_ = rk_of(LOGN)>
 struct Rows {
     static constexpr int N = 1 << LOGN;
-    static constexpr int RK = rk_of(LOGN);
+    static constexpr int RK = RK_;
     static constexpr int NT = N >> RK;                          // threads per row
     static constexpr int KT = LOGN % RK == 0 ? RK : LOGN % RK;  // stages of the short round
     static constexpr int SL = LOGN - KT;                        // forward: first stage of the short round
@@ -256,10 +258,10 @@ __device__ __forceinline__ void inv_bfly(double *x, const double *w, double q, d
 
 // Full forward rounds from stage S0 up to the short round, one group per
 // thread, the next round's twiddles loaded while this one computes.
-template <int LOGN, int S0>
+template <int LOGN, int RKX, int S0>
 __device__ __forceinline__ void fwd_mid(double *sh, const double *__restrict__ tw, double q, double qi, int t,
                                         const double *wcur) {
-    using R = Rows<LOGN>;
+    using R = Rows<LOGN, RKX>;
     if constexpr (S0 < R::SL) {
         constexpr int K = R::RK, LTS = LOGN - S0 - K, TS = 1 << LTS;
         constexpr int S1 = S0 + K;
@@ -274,17 +276,17 @@ __device__ __forceinline__ void fwd_mid(double *sh, const double *__restrict__ t
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
-        fwd_mid<LOGN, S1>(sh, tw, q, qi, t, wnext);
+        fwd_mid<LOGN, RKX, S1>(sh, tw, q, qi, t, wnext);
     }
 }
 
 // Forward transform of a row of which thread t holds elements t + b NT in
 // x (|x| < q); st(i, v) receives output position i (bit-reversed order).
 // Uses sh as scratch; the caller must not touch sh concurrently.
-template <int LOGN, class Store>
+template <int LOGN, int RKX, class Store>
 __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restrict__ tw, double q, double qi,
                                              double *x, Store st) {
-    using R = Rows<LOGN>;
+    using R = Rows<LOGN, RKX>;
     constexpr int K = R::RK, NT = R::NT, KT = R::KT, SL = R::SL;
     const int t = threadIdx.x;
     double w0[(1 << K) - 1], w1[(1 << K) - 1];
@@ -294,7 +296,7 @@ __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restric
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<NT>(t, b)] = x[b];
     __syncthreads();
-    fwd_mid<LOGN, K>(sh, tw, q, qi, t, w1);
+    fwd_mid<LOGN, RKX, K>(sh, tw, q, qi, t, w1);
 #pragma unroll
     for (int g = 0; g < R::GPT; ++g) {
         const int grp = t + g * NT;
@@ -308,21 +310,21 @@ __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restric
     }
 }
 
-template <int LOGN, class Load, class Store>
+template <int LOGN, int RKX, class Load, class Store>
 __device__ __forceinline__ void fwd_row_direct(double *sh, const double *__restrict__ tw, double q, double qi,
                                                Load ld, Store st) {
-    using R = Rows<LOGN>;
+    using R = Rows<LOGN, RKX>;
     double x[1 << R::RK];
 #pragma unroll
     for (int b = 0; b < (1 << R::RK); ++b) x[b] = ld((int)threadIdx.x + b * R::NT);
-    fwd_row_regs<LOGN>(sh, tw, q, qi, x, st);
+    fwd_row_regs<LOGN, RKX>(sh, tw, q, qi, x, st);
 }
 
 // Full inverse rounds from half-size 2^LTS0 up to the last round.
-template <int LOGN, int LTS0>
+template <int LOGN, int RKX, int LTS0>
 __device__ __forceinline__ void inv_mid(double *sh, const double *__restrict__ tw, double q, double qi, int t,
                                         const double *wcur) {
-    using R = Rows<LOGN>;
+    using R = Rows<LOGN, RKX>;
     if constexpr (LTS0 < LOGN - R::RK) {
         constexpr int K = R::RK, TS = 1 << LTS0, L1 = LTS0 + K;
         const int low = t & (TS - 1);
@@ -336,17 +338,17 @@ __device__ __forceinline__ void inv_mid(double *sh, const double *__restrict__ t
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
-        inv_mid<LOGN, L1>(sh, tw, q, qi, t, wnext);
+        inv_mid<LOGN, RKX, L1>(sh, tw, q, qi, t, wnext);
     }
 }
 
 // Inverse transform (without the N^-1 scaling) of the row read through
 // ld(i) (bit-reversed order); on return thread t holds output positions
 // t + b NT in x, |x| < q.  sh is scratch.
-template <int LOGN, class Load>
+template <int LOGN, int RKX, class Load>
 __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restrict__ tw, double q, double qi, Load ld,
                                                double *x) {
-    using R = Rows<LOGN>;
+    using R = Rows<LOGN, RKX>;
     constexpr int K = R::RK, NT = R::NT, KT = R::KT;
     const int t = threadIdx.x;
 #pragma unroll
@@ -363,7 +365,7 @@ __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restr
     double w1[(1 << K) - 1];
     if constexpr (KT < LOGN - K) inv_tw<LOGN, KT, K>(w1, tw, t >> KT);
     __syncthreads();
-    inv_mid<LOGN, KT>(sh, tw, q, qi, t, w1);
+    inv_mid<LOGN, RKX, KT>(sh, tw, q, qi, t, w1);
     double w[(1 << K) - 1];
     inv_tw<LOGN, LOGN - K, K>(w, tw, 0);
 #pragma unroll
@@ -716,8 +718,8 @@ __device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, i
 
 // ---- one workgroup per row ----
 
-template <int LOAD, int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
+template <int LOAD, int LOGN, int RK = rk_of(LOGN)>
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
 k_ntt_fwd(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
@@ -725,7 +727,7 @@ k_ntt_fwd(DevTables T, NttArgs a) {
     const double *tw = T.twf + (size_t)R.prime * N;
     if constexpr (direct_rows<LOGN>()) {
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-        fwd_row_direct<LOGN>(
+        fwd_row_direct<LOGN, RK>(
             sh, tw, q, qi, [&](int i) { return fwd_load<LOAD>(T, R, i); },
             [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
         return;
@@ -737,18 +739,18 @@ k_ntt_fwd(DevTables T, NttArgs a) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) fwd_store<LOAD>(T, R, i, sh[lds_ix(i)], q, qi);
 }
 
-template <int STORE, int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
+template <int STORE, int LOGN, int RK = rk_of(LOGN)>
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
 k_ntt_inv(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
     const InvRow R = inv_row(T, a, blockIdx.x);
     const double *tw = T.twi + (size_t)R.prime * N;
     if constexpr (direct_rows<LOGN>()) {
-        using RW = Rows<LOGN>;
+        using RW = Rows<LOGN, RK>;
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
         double x[1 << RW::RK];
-        inv_row_direct<LOGN>(sh, tw, q, qi, [&](int i) { return gld(R.in)[i]; }, x);
+        inv_row_direct<LOGN, RK>(sh, tw, q, qi, [&](int i) { return gld(R.in)[i]; }, x);
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) inv_store<STORE>(T, R, (int)threadIdx.x + b * RW::NT, x[b], q, qi);
         return;
@@ -898,8 +900,8 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
 // evaluation-form row j of the source's c1 is inverse-transformed, centered
 // (the digit lift of a one-prime digit) and forward-transformed under prime
 // r, all in LDS.  Row r = j is the source row itself.
-template <int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
+template <int LOGN, int RK = rk_of(LOGN)>
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
 k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
@@ -915,14 +917,14 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     }
     const double *twj = T.twi + (size_t)j * N;
     if constexpr (direct_rows<LOGN>()) {
-        using RW = Rows<LOGN>;
+        using RW = Rows<LOGN, RK>;
         const double qj = T.qt[j].x, qij = T.qt[j].y, nj = T.ninv[j];
         double x[1 << RW::RK];
-        inv_row_direct<LOGN>(sh, twj, qj, qij, [&](int i) { return gld(c)[i]; }, x);
+        inv_row_direct<LOGN, RK>(sh, twj, qj, qij, [&](int i) { return gld(c)[i]; }, x);
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = centerm(mulm(x[b], nj, qj, qij), qj, qij);
         const double q = T.qt[r].x, qi = T.qt[r].y;
-        fwd_row_regs<LOGN>(sh, T.twf + (size_t)r * N, q, qi, x, [&](int i, double v) { gst(out)[i] = v; });
+        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, [&](int i, double v) { gst(out)[i] = v; });
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = gld(c)[i];
@@ -948,8 +950,8 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
 // (Giving a workgroup several primes of a slot, to share the inverse
 // transform, was measured slower at 8192 points: one 135 KB workgroup per CU
 // running three transforms against two 70 KB workgroups running two.)
-template <int LOGN>
-__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN))))
+template <int LOGN, int RK = rk_of(LOGN)>
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
 k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
@@ -960,17 +962,17 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     const int pk = T.L;   // the special prime's index
     const double *twp = T.twi + (size_t)pk * N;
     if constexpr (direct_rows<LOGN>()) {
-        using RW = Rows<LOGN>;
+        using RW = Rows<LOGN, RK>;
         const double qp = T.qt[pk].x, qip = T.qt[pk].y;
         const double q = T.qt[iq].x, qi = T.qt[iq].y;
         const double cf = T.md_coef[0], h = T.md_hat[iq], pinv = T.pinv[iq];
         double x[1 << RW::RK];
-        inv_row_direct<LOGN>(sh, twp, qp, qip, [&](int i) { return gld(u)[(size_t)pk * N + i]; }, x);
+        inv_row_direct<LOGN, RK>(sh, twp, qp, qip, [&](int i) { return gld(u)[(size_t)pk * N + i]; }, x);
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = mulm(centerm(mulm(x[b], cf, qp, qip), qp, qip), h, q, qi);
         const double *ui = u + (size_t)iq * N;
         double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
-        fwd_row_regs<LOGN>(sh, T.twf + (size_t)iq * N, q, qi, x,
+        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x,
                            [&](int i, double v) { gst(out)[i] = mulm(gld(ui)[i] - v, pinv, q, qi); });
         return;
     }
@@ -994,10 +996,15 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) gst(out)[i] = mulm(gld(ui)[i] - sh[lds_ix(i)], pinv, q, qi);
 }
 
+int g_radix = 0;   // radix exponent of 4096- and 8192-point rows (0: rk_of)
+
+// Radix exponent the row kernels of 2^logn points run with.
+int row_rk(int logn) { return (logn == 12 || logn == 13) && g_radix ? g_radix : rk_of(logn); }
+
 int ntt_threads(int N) {
     int logn = 0;
     while ((1 << logn) < N) ++logn;
-    int t = N >> rk_of(logn);
+    int t = N >> row_rk(logn);
     if (t < 64) t = 64;
     if (t > NTT_THREADS_MAX) t = NTT_THREADS_MAX;
     return t;
@@ -1027,28 +1034,50 @@ bool use_split(const DevTables &T, int rows) {
         default: break;           \
     }
 
-template <int LN>
+// The same with the row radix: CALL(LN, RK) for the radix row_rk(LN).
+#define HG_LOGN_RK_SWITCH(LN, CALL)                                  \
+    switch (LN) {                                                    \
+        case 6: CALL(6, rk_of(6)); break;                            \
+        case 7: CALL(7, rk_of(7)); break;                            \
+        case 8: CALL(8, rk_of(8)); break;                            \
+        case 9: CALL(9, rk_of(9)); break;                            \
+        case 10: CALL(10, rk_of(10)); break;                         \
+        case 11: CALL(11, rk_of(11)); break;                         \
+        case 12: if (row_rk(12) == 4) { CALL(12, 4); } else { CALL(12, 3); } break; \
+        case 13: if (row_rk(13) == 4) { CALL(13, 4); } else { CALL(13, 3); } break; \
+        case 14: CALL(14, rk_of(14)); break;                         \
+        default: break;                                              \
+    }
+
+template <int LN, int RK>
 void set_lds_attrs() {
     const int lds = 160 * 1024;
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_PLAIN, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_MODUP, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON, LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_PLAIN, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_MODUP, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 }  // namespace
 
 void kernels_init() {
-#define HG_INIT(LN) set_lds_attrs<LN>()
+#define HG_INIT(LN) set_lds_attrs<LN, rk_of(LN)>()
     for (int ln = 6; ln <= 14; ++ln) HG_LOGN_SWITCH(ln, HG_INIT)
 #undef HG_INIT
+    set_lds_attrs<12, 4>();
+    set_lds_attrs<13, 4>();
 }
 
 void ntt_set_split_rows(int rows) { g_split_rows = rows; }
+
+void ntt_set_radix(int radix) {
+    if (radix != 0 && radix != 8 && radix != 16) throw std::invalid_argument("row radix must be 0, 8 or 16");
+    g_radix = radix == 8 ? 3 : radix == 16 ? 4 : 0;
+}
 
 void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) {
     if (a.rows <= 0) return;
@@ -1069,13 +1098,13 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) 
     }
     const size_t lds = ntt_lds_bytes(T.N);
     dim3 grid(a.rows), block(ntt_threads(T.N));
-#define HG_FWD(LN)                                                                                        \
-    switch (mode) {                                                                                      \
-        case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd<LOAD_MODUP, LN>), grid, block, lds, s, T, a); break; \
-        case LOAD_DELTA: hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA, LN>), grid, block, lds, s, T, a); break; \
-        default: hipLaunchKernelGGL((k_ntt_fwd<LOAD_PLAIN, LN>), grid, block, lds, s, T, a); break;         \
+#define HG_FWD(LN, RK)                                                                                        \
+    switch (mode) {                                                                                          \
+        case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd<LOAD_MODUP, LN, RK>), grid, block, lds, s, T, a); break; \
+        case LOAD_DELTA: hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA, LN, RK>), grid, block, lds, s, T, a); break; \
+        default: hipLaunchKernelGGL((k_ntt_fwd<LOAD_PLAIN, LN, RK>), grid, block, lds, s, T, a); break;         \
     }
-    HG_LOGN_SWITCH(T.logN, HG_FWD)
+    HG_LOGN_RK_SWITCH(T.logN, HG_FWD)
 #undef HG_FWD
 }
 
@@ -1096,13 +1125,13 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
     }
     const size_t lds = ntt_lds_bytes(T.N);
     dim3 grid(a.rows), block(ntt_threads(T.N));
-#define HG_INV(LN)                                                                                          \
-    switch (mode) {                                                                                        \
-        case STORE_MDR: hipLaunchKernelGGL((k_ntt_inv<STORE_MDR, LN>), grid, block, lds, s, T, a); break;     \
-        case STORE_CANON: hipLaunchKernelGGL((k_ntt_inv<STORE_CANON, LN>), grid, block, lds, s, T, a); break; \
-        default: hipLaunchKernelGGL((k_ntt_inv<STORE_PLAIN, LN>), grid, block, lds, s, T, a); break;         \
+#define HG_INV(LN, RK)                                                                                          \
+    switch (mode) {                                                                                            \
+        case STORE_MDR: hipLaunchKernelGGL((k_ntt_inv<STORE_MDR, LN, RK>), grid, block, lds, s, T, a); break;     \
+        case STORE_CANON: hipLaunchKernelGGL((k_ntt_inv<STORE_CANON, LN, RK>), grid, block, lds, s, T, a); break; \
+        default: hipLaunchKernelGGL((k_ntt_inv<STORE_PLAIN, LN, RK>), grid, block, lds, s, T, a); break;         \
     }
-    HG_LOGN_SWITCH(T.logN, HG_INV)
+    HG_LOGN_RK_SWITCH(T.logN, HG_INV)
 #undef HG_INV
 }
 
@@ -1110,18 +1139,19 @@ bool fused_ok(const DevTables &T) { return T.alpha == 1 && T.N <= 16384; }
 
 void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s) {
     if (nsrc <= 0) return;
-#define HG_HF(LN) \
-    hipLaunchKernelGGL(k_hoist_fused<LN>, dim3(nsrc * T.beta * T.nExt), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, y, srcs)
-    HG_LOGN_SWITCH(T.logN, HG_HF)
+#define HG_HF(LN, RK)                                                                                           \
+    hipLaunchKernelGGL((k_hoist_fused<LN, RK>), dim3(nsrc * T.beta * T.nExt), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
+                       s, T, y, srcs)
+    HG_LOGN_RK_SWITCH(T.logN, HG_HF)
 #undef HG_HF
 }
 
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s, double *const *outs) {
     if (nslots <= 0) return;
-#define HG_MF(LN)                                                                                          \
-    hipLaunchKernelGGL(k_moddown_fused<LN>, dim3(nslots * T.L), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, \
-                       E, U, outs)
-    HG_LOGN_SWITCH(T.logN, HG_MF)
+#define HG_MF(LN, RK)                                                                                           \
+    hipLaunchKernelGGL((k_moddown_fused<LN, RK>), dim3(nslots * T.L), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, \
+                       T, E, U, outs)
+    HG_LOGN_RK_SWITCH(T.logN, HG_MF)
 #undef HG_MF
 }
 

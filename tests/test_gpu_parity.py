@@ -151,6 +151,24 @@ def test_hegmm_alpha2():
         run_pair(pair, m, l, n, A, B, nonce=5)
 
 
+@pytest.mark.parametrize("N", [4096, 8192])
+@pytest.mark.parametrize("radix", [8, 16])
+def test_hegmm_row_radix(N, radix):
+    """Both radices of the 4096- and 8192-point row transforms (radix 8 is
+    the built-in choice, radix 16 the tuning alternative): bits equal the
+    oracle's, and the result decrypts to A.B mod t."""
+    shapes = [(6, 5, 9)]
+    pair = Pair(N, 65537, 3, 1, 70 + N // 4096, shapes=shapes)
+    rng = np.random.default_rng(N + radix)
+    A = rng.integers(-8, 9, size=(6, 5))
+    B = rng.integers(-8, 9, size=(5, 9))
+    pair.ctx.tune("ntt_radix", radix)
+    try:
+        run_pair(pair, 6, 5, 9, A, B, nonce=3)
+    finally:
+        pair.ctx.tune("ntt_radix", 0)
+
+
 def test_hegmm_headline_full_size():
     """64x32x48 at N = 8192: the whole output ciphertext against the oracle."""
     c = workloads.HEADLINE
@@ -498,8 +516,9 @@ def test_execution_knobs_bit_identical():
     ref_batch = [o.export() for o in ctx.hegmm_batch(As, Bs, shapes)]
     settings = [{"pipeline": 2}, {"pipeline": 3, "fuse_rows": 0}, {"split_rows": 64, "fuse_rows": 0},
                 {"fuse_rows": 4096}, {"batch_window": 1}, {"ip_chunk": 16}, {"ip_chunk": 4, "batch_window": 0},
-                {"ip_order": 0}]
-    defaults = {"pipeline": 1, "fuse_rows": 256, "split_rows": 0, "batch_window": 64, "ip_chunk": 0, "ip_order": 1}
+                {"ip_order": 0}, {"ntt_radix": 16}, {"ntt_radix": 16, "fuse_rows": 0, "pipeline": 2}]
+    defaults = {"pipeline": 1, "fuse_rows": 256, "split_rows": 0, "batch_window": 64, "ip_chunk": 0, "ip_order": 1,
+                "ntt_radix": 0}
     for st in settings:
         for k, v in st.items():
             ctx.tune(k, v)
