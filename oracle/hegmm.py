@@ -352,10 +352,16 @@ def encrypt_operand(ks: bgv.KeySet, pl: Plan, role: int, A, B, nonce: int) -> Li
 
 
 def hegmm(ks: bgv.KeySet, pl: Plan, ctX: List[bgv.Ct], ctY: List[bgv.Ct],
-          masks: Optional[MaskCache] = None) -> bgv.Ct:
+          masks: Optional[MaskCache] = None, eager: bool = False) -> bgv.Ct:
     """Cloud side of Algorithm 2:  Acc = sum_{blocks, k < K} eps^k(ctX) x omega^k(ctY),
     one relinearisation, then the fold sum_h Rot(R, h*mo) that gathers the d
-    row blocks (the extraction of Theorem 5's partial products)."""
+    row blocks (the extraction of Theorem 5's partial products).
+
+    eager=True takes each product of the loop as a full HE-Mult (tensor, then
+    relinearisation, the HE-Mult of Section II-A) and sums the relinearised
+    two-component ciphertexts; the default relinearises the three-component
+    sum once.  Both decrypt to the same matrix; their bits differ (the key
+    switch lifts and rounds each input on its own)."""
     P = ks.P
     masks = masks or MaskCache(P)
     acc = None
@@ -363,9 +369,9 @@ def hegmm(ks: bgv.KeySet, pl: Plan, ctX: List[bgv.Ct], ctY: List[bgv.Ct],
         for k in range(pl.K):
             e = bgv.rot_sum(P, ks, ctX[b], [(z, None if s is None else masks.get(s)) for z, s in pl.eps[k]])
             f = bgv.rot_sum(P, ks, ctY[b], [(z, None if s is None else masks.get(s)) for z, s in pl.omega[k]])
-            prod = bgv.tensor(P, e, f)
+            prod = bgv.he_mult(P, ks, e, f) if eager else bgv.tensor(P, e, f)
             acc = prod if acc is None else bgv.he_add(P, acc, prod)
-    R = bgv.relinearize(P, ks, acc)
+    R = acc if eager else bgv.relinearize(P, ks, acc)
     if pl.d == 1:
         return R
     return bgv.rot_sum(P, ks, R, [(z, None) for z in pl.fold])

@@ -307,3 +307,54 @@ def test_alg1_encrypted_small():
         oy = H.encrypt_operand(ks, pl, 1, A, B, 3)
         C = H.decrypt_result(ks, pl, H.hegmm(ks, pl, ox, oy))
         assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t)), (m, l, n)
+
+
+# ---------------------------------------------------------------------------
+# eager relinearisation (HE-Mult per loop product)
+# ---------------------------------------------------------------------------
+
+def test_eager_relin_decrypts():
+    """Each loop product relinearised on its own (HE-Mult as in Section II-A):
+    the sum still decrypts to A B mod t on every plan shape (fold, transposed,
+    blocked, forced blocks), with noise well inside the modulus."""
+    P = Params(128, 12289, 3, 1)
+    shapes = [(2, 5, 7), (5, 4, 2), (4, 4, 4), (3, 11, 6)]
+    ks = bgv.KeySet(P, 81, H.galois_elements(P, shapes) + H.galois_elements(P, shapes[:2], min_blocks=2))
+    rng = np.random.default_rng(81)
+    masks = H.MaskCache(P)
+    for idx, (m, l, n) in enumerate(shapes + [(2, 5, 7)]):
+        mb = 2 if idx == len(shapes) else 1
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        pl = H.plan(m, l, n, P.S, min_blocks=mb)
+        cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=idx)
+        cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=idx)
+        C = H.hegmm(ks, pl, cx, cy, masks, eager=True)
+        assert len(C) == 2
+        assert (H.decrypt_result(ks, pl, C) == workloads.plain_matmul_mod(A, B, P.t)).all(), (m, l, n)
+        mu = bgv.decrypt_poly(ks, C)
+        assert bgv.noise_bits(ks, C, mu) < np.log2(float(P.Q)) - 2
+        if pl.nb * pl.K > 1:
+            # more than one product: relinearising each on its own changes the bits
+            lazy = H.hegmm(ks, pl, cx, cy, masks)
+            assert not np.array_equal(H.export_d7(C), H.export_d7(lazy)), (m, l, n)
+
+
+def test_eager_relin_single_product_equals_lazy():
+    """With one loop product (K = 1, one block) eager and lazy
+    relinearisation are the same computation: bit-identical ciphertexts."""
+    P = Params(128, 12289, 3, 1)
+    shapes = [(1, 4, 3), (5, 1, 2)]
+    ks = bgv.KeySet(P, 82, H.galois_elements(P, shapes))
+    rng = np.random.default_rng(82)
+    for idx, (m, l, n) in enumerate(shapes):
+        pl = H.plan(m, l, n, P.S)
+        assert pl.nb * pl.K == 1
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=idx)
+        cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=idx)
+        e = H.hegmm(ks, pl, cx, cy, eager=True)
+        z = H.hegmm(ks, pl, cx, cy)
+        assert np.array_equal(H.export_d7(e), H.export_d7(z))
+        assert (H.decrypt_result(ks, pl, e) == workloads.plain_matmul_mod(A, B, P.t)).all()
