@@ -36,12 +36,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batched", "serving", "large", "alg1", "blocked"],
+                    choices=["headline", "batched", "serving", "large", "alg1", "blocked", "eager"],
                     help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step; "
                          "serving: 512 Poisson arrivals at N=16384 through the continuous-batching server; "
                          "large: one 128x96x128 product per step at N=32768; "
                          "alg1: the headline product with the paper's Algorithm 1 instead of HEGMM-En; "
-                         "blocked: a 100x100x100 product split into output blocks (partitions P1/P2)")
+                         "blocked: a 100x100x100 product split into output blocks (partitions P1/P2); "
+                         "eager: the headline product with every loop product relinearised on its own")
     ap.add_argument("--partition", default="P2", choices=["P1", "P2"], help="blocked: the reported partition")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
@@ -345,6 +346,61 @@ def run_alg1(args):
         "en_speedup_over_alg1": res[2]["matmuls_per_s"] / v if v else None}), flush=True)
 
 
+def run_eager(args):
+    """The headline product (64x32x48, N=8192) with eager relinearisation
+    (each of the 32 tensor products of the loop relinearised on its own, the
+    HE-Mult of the paper's operation list) beside the default lazy one (one
+    relinearisation of the summed three-component accumulator), both on
+    resident operands, decrypt-checked, and the eager result compared with
+    the oracle's eager mode bit for bit."""
+    import torch
+    import paper_2405_02238_amd as hg
+    import workloads
+
+    cfg = workloads.HEADLINE
+    m, l, n = 64, 32, 48
+    A, B = workloads.headline_operands()
+    want = workloads.plain_matmul_mod(A, B, cfg.t)
+    res = {}
+    last = None
+    for relin in (1, 0):
+        ctx = hg.Context(cfg.N, cfg.t, cfg.L, cfg.alpha, relin=relin)
+        ctx.keygen(cfg.seed, [(m, l, n)])
+        ca, cb = ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1)
+        info = ctx.plan_info(m, l, n)
+        outs = [ctx.hegmm(ca, cb, m, l, n) for _ in range(args.warmup)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = [ctx.hegmm(ca, cb, m, l, n) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        ok = bool(np.array_equal(ctx.decrypt(outs[-1], m, l, n), want))
+        res[relin] = {"ms_per_matmul": ms, "matmuls_per_s": 1000.0 / ms if ok else 0.0, "decrypt_ok": ok,
+                      "key_switches": info["ks_terms"] + (info["nb"] * info["K"] if relin else 1)}
+        if relin:
+            last = outs[-1].export()
+        del outs, ctx
+    bit_exact = None
+    if not args.no_oracle_check:
+        from oracle import bgv, hegmm as H
+        from oracle.ring import Params
+        P = Params(cfg.N, cfg.t, cfg.L, cfg.alpha)
+        ks = bgv.KeySet(P, cfg.seed, H.galois_elements(P, [(m, l, n)]))
+        pl = H.plan(m, l, n, P.S)
+        ref = H.hegmm(ks, pl, H.encrypt_operand(ks, pl, 0, A, B, 1), H.encrypt_operand(ks, pl, 1, A, B, 1),
+                      eager=True)
+        bit_exact = bool(np.array_equal(last, H.export_d7(ref)))
+    v = res[1]["matmuls_per_s"] if bit_exact is not False else 0.0
+    print(json.dumps({
+        "metric": "HE matmuls/s at N=8192 64x32x48 with eager relinearisation", "value": v,
+        "unit": "HE matmuls/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res[1]["ms_per_matmul"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "HEGMM-En A(64x32) x B(32x48), eager relinearisation, BGV N=8192 t=65537 L=4 alpha=1"},
+        "bit_exact": bit_exact, "eager": res[1], "lazy": res[0],
+        "lazy_speedup_over_eager": res[0]["matmuls_per_s"] / v if v else None}), flush=True)
+
+
 def run_blocked(args):
     """A 100x100 by 100x100 product, whose 10000-entry result does not fit
     one ciphertext of the headline ring, as a blocked product: A split into
@@ -419,6 +475,8 @@ def main():
         return run_alg1(args)
     if args.workload == "blocked":
         return run_blocked(args)
+    if args.workload == "eager":
+        return run_eager(args)
     import torch
     import paper_2405_02238_amd as hg
     import workloads

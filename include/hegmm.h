@@ -72,6 +72,13 @@ typedef struct {
                             result (the blockwise product of Section IV-D, forced; the
                             result decrypts to the same A B, its bits differ).  HEGMM-En
                             only (HG_EINVAL with method 1). */
+    uint32_t relin;    /* 0: lazy relinearisation, once per product on the three-component
+                          sum of the loop's tensor products (the default); 1: eager, each
+                          tensor product of the loop relinearised on its own (HE-Mult of
+                          Section II-A) and the two-component results summed: one key
+                          switch per loop product instead of one per product, the same
+                          decrypted result, different bits.  Either method.  HG_EINVAL
+                          for other values. */
 } hg_params;
 
 /* Create a context on HIP device `hip_device` (must be gfx950).

@@ -37,7 +37,8 @@ class _ServerConfig(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_uint32),
-                ("alpha", ctypes.c_uint32), ("method", ctypes.c_uint32), ("min_blocks", ctypes.c_uint32)]
+                ("alpha", ctypes.c_uint32), ("method", ctypes.c_uint32), ("min_blocks", ctypes.c_uint32),
+                ("relin", ctypes.c_uint32)]
 
 
 _lib = None
@@ -165,15 +166,18 @@ class Ciphertext:
 class Context:
     """hg_ctx: one BGV parameter set on one GPU."""
 
-    def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0, method: int = 2, min_blocks: int = 1):
+    def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0, method: int = 2, min_blocks: int = 1,
+                 relin: int = 0):
         """method 2: HEGMM-En (Algorithm 2); method 1: Algorithm 1, for comparison.
-        min_blocks > 1 forces that many inner blocks per product (hg_params)."""
+        min_blocks > 1 forces that many inner blocks per product; relin 1
+        relinearises every loop product on its own (eager; hg_params)."""
         load()
-        p = _Params(N, t, L, alpha, method, min_blocks)
+        p = _Params(N, t, L, alpha, method, min_blocks, relin)
         out = ctypes.c_void_p()
         _check(_lib.hg_ctx_create(ctypes.byref(p), device, ctypes.byref(out)))
         self.ptr = out.value
         self.N, self.t, self.L, self.alpha, self.method, self.min_blocks = N, t, L, alpha, method, min_blocks
+        self.relin = relin
         self.device = device
         self.S = N // 2
 

@@ -77,8 +77,10 @@ hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
         *out = nullptr;
         need(p->min_blocks <= 4096, "min_blocks out of range");
         need(p->min_blocks <= 1 || p->method != 1, "forced blocking needs HEGMM-En (method 2)");
+        need(p->relin <= 1, "relin must be 0 (lazy) or 1 (eager)");
         hg::Ctx *c = new hg::Ctx(p->N, p->t, p->L, p->alpha, dev, p->method == 0 ? 2 : (int)p->method);
         c->min_blocks = p->min_blocks > 1 ? (int)p->min_blocks : 1;
+        c->relin = (int)p->relin;
         hg_ctx *h = new hg_ctx;
         h->c = c;
         *out = h;

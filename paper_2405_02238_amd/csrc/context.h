@@ -131,6 +131,7 @@ struct Ctx {
     hipEvent_t event(hipStream_t st, bool timing);
 
     int method = 2;        // 2: HEGMM-En; 1: the paper's Algorithm 1
+    int relin = 0;         // 0: one relinearisation per product; 1: one per loop product (eager)
     Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device, int method = 2);
     ~Ctx();
 

@@ -627,28 +627,51 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
             }
         }
     }
-    // request-lifetime buffers: accumulators (3 x L x N) and relinearised R (2 x L x N, fold only)
+    // request-lifetime buffers: accumulators (3 x L x N) and relinearised R (2 x L x N, fold only).
+    // Eager relinearisation keeps every loop product apart instead: one
+    // three-component tensor per (eps, omega) pair, then its relinearised
+    // two-component ciphertext, summed per request after the key switches.
+    const bool eager = relin == 1;
     int nfold = 0;
     for (int ri = 0; ri < nreq; ++ri) nfold += info[ri].pe->plan.d > 1;
-    double *acc = ex.acc(((size_t)nreq * 3 + (size_t)nfold * 2) * ctw * sizeof(double));
-    double *rbuf = acc + (size_t)nreq * 3 * ctw;
-    std::vector<double *> acc_ptrs(nreq);
-    for (int ri = 0; ri < nreq; ++ri) acc_ptrs[ri] = acc + (size_t)ri * 3 * ctw;
-    std::vector<char> extra(req_pairs.size() * sizeof(int2) + acc_ptrs.size() * sizeof(void *));
-    std::memcpy(extra.data(), req_pairs.data(), req_pairs.size() * sizeof(int2));
-    std::memcpy(extra.data() + req_pairs.size() * sizeof(int2), acc_ptrs.data(), acc_ptrs.size() * sizeof(void *));
+    const int npairs = (int)ps.fin_jobs.size() / 2;
+    const int nacc = eager ? npairs : nreq;
+    double *acc = ex.acc(((size_t)nacc * 3 + (size_t)nfold * 2 + (eager ? (size_t)npairs * 2 : 0)) * ctw *
+                         sizeof(double));
+    double *rbuf = acc + (size_t)nacc * 3 * ctw;
+    double *ebuf = rbuf + (size_t)nfold * 2 * ctw;   // eager: relinearised products, one after the other
+    std::vector<double *> acc_ptrs(nacc);
+    for (int a = 0; a < nacc; ++a) acc_ptrs[a] = acc + (size_t)a * 3 * ctw;
+    std::vector<int2> tensor_pairs = req_pairs;
+    if (eager) {
+        tensor_pairs.resize(npairs);
+        for (int q = 0; q < npairs; ++q) tensor_pairs[q] = make_int2(q, 1);
+    }
+    std::vector<char> extra(tensor_pairs.size() * sizeof(int2) + acc_ptrs.size() * sizeof(void *));
+    std::memcpy(extra.data(), tensor_pairs.data(), tensor_pairs.size() * sizeof(int2));
+    std::memcpy(extra.data() + tensor_pairs.size() * sizeof(int2), acc_ptrs.data(),
+                acc_ptrs.size() * sizeof(void *));
 
-    // --- relinearisation pass: once per product (lazy) ---
+    // --- relinearisation pass: once per product (lazy) or per loop product (eager) ---
     Pass pr;
     std::vector<double *> R(nreq, nullptr);
+    std::vector<double *> relin_out;   // the pass's job outputs
+    std::vector<char> sums;            // eager: per request (first product, count), then R pointers
     {
         int fi = 0;
-        for (int ri = 0; ri < nreq; ++ri) {
+        for (int ri = 0; ri < nreq; ++ri)
             R[ri] = info[ri].pe->plan.d > 1 ? rbuf + (size_t)(fi++) * 2 * ctw : reqs[ri].out->d;
-            // a job over (Acc0, Acc1) with the unrotated term, plus the key
-            // switch of Acc2 (the hoisted source) under the key for s^2
-            pr.srcs.push_back(acc_ptrs[ri] + 2 * ctw);
-            ex.add_job(pr, acc_ptrs[ri], {{0, nullptr}}, ri, relin_key);
+        // each job: (c0, c1) of its accumulator with the unrotated term, plus
+        // the key switch of c2 (the hoisted source) under the key for s^2
+        for (int a = 0; a < nacc; ++a) {
+            pr.srcs.push_back(acc_ptrs[a] + 2 * ctw);
+            ex.add_job(pr, acc_ptrs[a], {{0, nullptr}}, a, relin_key);
+            relin_out.push_back(eager ? ebuf + (size_t)a * 2 * ctw : R[a]);
+        }
+        if (eager) {
+            sums.resize(nreq * sizeof(int2) + nreq * sizeof(void *));
+            std::memcpy(sums.data(), req_pairs.data(), nreq * sizeof(int2));
+            std::memcpy(sums.data() + nreq * sizeof(int2), R.data(), nreq * sizeof(void *));
         }
     }
     // --- fold pass: C = sum_h Rot(R, h*mo) for the products with d > 1 ---
@@ -664,9 +687,14 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
         ex.add_job(pf, R[ri], terms, src, nullptr);
         outs.push_back(reqs[ri].out->d);
     }
+    // the relinearisation pass's table space: its job outputs, then (eager)
+    // the per-request sums
+    std::vector<char> rextra(relin_out.size() * sizeof(void *) + sums.size());
+    std::memcpy(rextra.data(), relin_out.data(), relin_out.size() * sizeof(void *));
+    if (!sums.empty()) std::memcpy(rextra.data() + relin_out.size() * sizeof(void *), sums.data(), sums.size());
     std::vector<Exec::Staged> sp;
     sp.push_back({&ps, extra.data(), extra.size(), Exec::Dev()});
-    sp.push_back({&pr, R.data(), R.size() * sizeof(void *), Exec::Dev()});
+    sp.push_back({&pr, rextra.data(), rextra.size(), Exec::Dev()});
     if (nfold) sp.push_back({&pf, outs.data(), outs.size() * sizeof(void *), Exec::Dev()});
     ex.stage(sp);
 
@@ -674,11 +702,15 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     timing.ip_pairs.clear();
     ex.launch(dv, timing.enabled ? ev : nullptr, true, timing.enabled ? &timing : nullptr);
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
-                      (double *const *)(dv.extra + req_pairs.size() * sizeof(int2)), nreq, st);
+                      (double *const *)(dv.extra + tensor_pairs.size() * sizeof(int2)), nacc, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
     const Exec::Dev &d2 = sp[1].dv;
     if (!ex.launch(d2, nullptr, false, nullptr, Exec::direct_ok(pr) ? (double *const *)d2.extra : nullptr))
-        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, nreq, st);
+        fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, nacc, st);
+    if (eager) {
+        const char *sm = d2.extra + relin_out.size() * sizeof(void *);
+        sum_cts_launch(T, ebuf, (const int2 *)sm, (double *const *)(sm + nreq * sizeof(int2)), nreq, st);
+    }
     if (timing.enabled) HGCHK(hipEventRecord(ev[4], st));
     if (nfold) {
         const Exec::Dev &d3 = sp[2].dv;

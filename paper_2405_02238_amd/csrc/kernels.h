@@ -148,6 +148,12 @@ void fin_tensor_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
 void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *terms, const double *E,
                        const double *const *masks, double *const *out, int njobs, hipStream_t s);
 
+// Group sums of ciphertexts (2 x L x N each, evaluation form) stored one
+// after the other from `in`: out[g] = sum of ciphertexts groups[g].x ..
+// groups[g].x + groups[g].y - 1 (device tables `groups` and `out`).
+void sum_cts_launch(const DevTables &T, const double *in, const int2 *groups, double *const *out, int ngroups,
+                    hipStream_t s);
+
 // Allow the transform kernels the full LDS of a CDNA4 workgroup (call once
 // per device before the first transform with N > 4096).
 void kernels_init();

@@ -399,6 +399,29 @@ k_fin_rotsum(DevTables T, const FinJob *jobs, const FinTerm *terms, const double
     o[(size_t)T.L * N] = e1;
 }
 
+// Group sums of two-component ciphertexts stored one after the other:
+// out[g] = sum of in[k] over k in [groups[g].x, groups[g].x + groups[g].y).
+// Each thread two adjacent positions of one (component, prime) row.
+__global__ void __launch_bounds__(EW_THREADS)
+k_sum_cts(DevTables T, const double *in, const int2 *groups, double *const *out) {
+    const int N = 1 << T.logN;
+    const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const int r = blockIdx.y;   // component * L + prime
+    const int g = blockIdx.z;
+    if (p >= N) return;
+    const int i = r % T.L;
+    const double q = T.qt[i].x, qi = T.qt[i].y;
+    const int2 gr = groups[g];
+    const size_t ctw = (size_t)2 * T.L * N;
+    double2 a = make_double2(0.0, 0.0);
+    for (int k = gr.x; k < gr.x + gr.y; ++k) {
+        const double2 v = ld2(in + (size_t)k * ctw + (size_t)r * N + p);
+        a.x = redm(a.x + v.x, q, qi);
+        a.y = redm(a.y + v.y, q, qi);
+    }
+    st2(gld(out)[g] + (size_t)r * N + p, a);
+}
+
 __global__ void k_copy16(uint4 *dst, const uint4 *src, size_t n) {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
@@ -686,6 +709,17 @@ void fin_rotsum_launch(const DevTables &T, const FinJob *jobs, const FinTerm *te
     }
     hipLaunchKernelGGL(k_fin_rotsum, ew_grid(T.N, T.L, njobs), dim3(EW_THREADS), 0, s, T, jobs, terms, E, masks,
                        out);
+}
+
+void sum_cts_launch(const DevTables &T, const double *in, const int2 *groups, double *const *out, int ngroups,
+                    hipStream_t s) {
+    if (ngroups <= 0) return;
+    if (ngroups > MAX_GRID_Z) {
+        for (int o = 0; o < ngroups; o += MAX_GRID_Z)
+            sum_cts_launch(T, in, groups + o, out + o, std::min(MAX_GRID_Z, ngroups - o), s);
+        return;
+    }
+    hipLaunchKernelGGL(k_sum_cts, ew_grid(T.N / 2, 2 * T.L, ngroups), dim3(EW_THREADS), 0, s, T, in, groups, out);
 }
 
 void copy_from_host(void *dst, const void *src, size_t bytes, hipStream_t s) {

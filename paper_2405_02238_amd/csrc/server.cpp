@@ -20,8 +20,16 @@ uint64_t request_footprint(const Ctx &C, const Plan &p) {
     const uint64_t nsrc = 2 * (uint64_t)p.nb;
     const uint64_t operands = 2 * (uint64_t)p.nb * ct;
     const uint64_t result = ct;
-    const uint64_t acc = 3 * L * N * w + (p.d > 1 ? ct : 0);
-    const uint64_t scratch = nsrc * (L + beta * nExt) * N * w + nks * 2 * (nExt + alpha + L) * N * w;
+    uint64_t acc = 3 * L * N * w + (p.d > 1 ? ct : 0);
+    uint64_t scratch = nsrc * (L + beta * nExt) * N * w + nks * 2 * (nExt + alpha + L) * N * w;
+    if (C.relin == 1) {
+        // eager relinearisation: a tensor and a relinearised ciphertext per
+        // loop product, and a relinearisation pass with one source and one
+        // key switch per loop product
+        const uint64_t pairs = (uint64_t)p.nb * p.K;
+        acc += pairs * 5 * L * N * w;
+        scratch = std::max(scratch, pairs * (L + beta * nExt) * N * w + pairs * 2 * (nExt + alpha + L) * N * w);
+    }
     const uint64_t staging = operands / 2;   // canonical words of the operands, then of the result
     return operands + result + acc + scratch + staging;
 }

@@ -26,10 +26,11 @@ def flat(ct):
 class Pair:
     """A library context and the oracle's key set for the same parameters and seed."""
 
-    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=(), min_blocks=1):
+    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=(), min_blocks=1, relin=0):
         self.P = Params(N, t, L, alpha)
         self.min_blocks = min_blocks
-        self.ctx = hg.Context(N, t, L, alpha, min_blocks=min_blocks)
+        self.relin = relin
+        self.ctx = hg.Context(N, t, L, alpha, min_blocks=min_blocks, relin=relin)
         self.ctx.keygen(seed, shapes)
         if zs:
             self.ctx.keygen_rotations(zs)
@@ -105,7 +106,7 @@ def run_pair(pair, m, l, n, A, B, nonce):
     assert np.array_equal(right.export(), np.concatenate([flat(c) for c in oy]))
     cc = ctx.hegmm(ca, cb, m, l, n)
     got = cc.export()
-    want = flat(H.hegmm(ks, pl, ox, oy, pair.masks))
+    want = flat(H.hegmm(ks, pl, ox, oy, pair.masks, eager=pair.relin == 1))
     assert np.array_equal(got, want), (m, l, n)
     C = ctx.decrypt(cc, m, l, n)
     assert np.array_equal(C, workloads.plain_matmul_mod(A, B, P.t))
@@ -167,6 +168,72 @@ def test_hegmm_row_radix(N, radix):
         run_pair(pair, 6, 5, 9, A, B, nonce=3)
     finally:
         pair.ctx.tune("ntt_radix", 0)
+
+
+@pytest.mark.parametrize("alpha", [1, 2])
+def test_eager_relin_shapes(alpha):
+    """Eager relinearisation (every loop product relinearised on its own):
+    bits equal the oracle's eager mode on fold, transposed, blocked and
+    forced-block shapes, and each result decrypts to A.B mod t."""
+    c = workloads.TINY
+    L = c.L if alpha == 1 else 4
+    shapes = [(4, 3, 5), (2, 5, 7), (5, 4, 2), (3, 11, 6), (1, 4, 3)]
+    pair = Pair(c.N, c.t, L, alpha, c.seed + alpha, shapes=shapes, relin=1)
+    rng = np.random.default_rng(90 + alpha)
+    for i, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        run_pair(pair, m, l, n, A, B, nonce=20 + i)
+    forced = Pair(c.N, c.t, c.L, 1, c.seed, shapes=[(5, 4, 2)], min_blocks=2, relin=1)
+    A = rng.integers(-8, 9, size=(5, 4))
+    B = rng.integers(-8, 9, size=(4, 2))
+    run_pair(forced, 5, 4, 2, A, B, nonce=30)
+
+
+def test_eager_relin_batch_and_graph():
+    """Eager relinearisation inside a batch and a recorded graph: every
+    result is the bit pattern of the same product run alone; with one loop
+    product (K = 1) eager and lazy contexts give the same bits."""
+    c = workloads.TINY
+    shapes = [(4, 3, 5), (2, 5, 7), (5, 4, 2), (1, 4, 3)]
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, relin=1)
+    lazy = hg.Context(c.N, c.t, c.L, c.alpha)
+    for x in (ctx, lazy):
+        x.keygen(c.seed, shapes)
+    rng = np.random.default_rng(95)
+    mats = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    As = [ctx.encrypt(0, A, *s, nonce=40 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    Bs = [ctx.encrypt(1, B, *s, nonce=40 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    alone = [ctx.hegmm(a, b, *s).export() for a, b, s in zip(As, Bs, shapes)]
+    got = ctx.hegmm_batch(As, Bs, shapes)
+    for i, s in enumerate(shapes):
+        assert np.array_equal(got[i].export(), alone[i]), s
+        assert np.array_equal(ctx.decrypt(got[i], *s), workloads.plain_matmul_mod(*mats[i], c.t)), s
+    g = ctx.record_batch(As, Bs, shapes)
+    zero = np.zeros_like(alone[0])
+    for rep in range(3):
+        for o in g.outputs:
+            ctx.load_ct(o, zero)
+        ctx.hegmm(As[rep], Bs[rep], *shapes[rep])     # eager work between replays
+        torch.cuda.synchronize()
+        g.launch()
+        torch.cuda.synchronize()
+        for i, s in enumerate(shapes):
+            assert np.array_equal(g.outputs[i].export(), alone[i]), (rep, s)
+    g.close()
+    m, l, n = shapes[3]
+    la = lazy.encrypt(0, mats[3][0], m, l, n, nonce=43)
+    lb = lazy.encrypt(1, mats[3][1], m, l, n, nonce=43)
+    assert np.array_equal(lazy.hegmm(la, lb, m, l, n).export(), alone[3])
+
+
+def test_eager_relin_headline_full_size():
+    """64x32x48 at N = 8192 with eager relinearisation (32 key switches of
+    the tensor products instead of one): the whole output against the oracle."""
+    c = workloads.HEADLINE
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(64, 32, 48)], relin=1)
+    A, B = workloads.headline_operands()
+    run_pair(pair, 64, 32, 48, A, B, nonce=1)
 
 
 def test_hegmm_headline_full_size():
