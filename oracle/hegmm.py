@@ -46,11 +46,13 @@ class Plan:
     eps: List[List[Tuple[int, Optional[frozenset]]]]    # per k: (z, mask slots or None)
     omega: List[List[Tuple[int, Optional[frozenset]]]]
     fold: List[int]        # rotation amounts summed after relinearisation (0 first)
-    method: int = 2        # 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1)
+    method: int = 2        # 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1); 3: Algorithm 1, sigma/tau in the cloud
+    sigma: List[Tuple[int, Optional[frozenset]]] = dataclasses.field(default_factory=list)   # method 3
+    tau: List[Tuple[int, Optional[frozenset]]] = dataclasses.field(default_factory=list)
 
     def rotations(self, S: int) -> List[int]:
         zs = set()
-        for terms in self.eps + self.omega:
+        for terms in self.eps + self.omega + [self.sigma, self.tau]:
             for z, _ in terms:
                 if z % S:
                     zs.add(z % S)
@@ -80,10 +82,10 @@ def orientation(m: int, l: int, n: int) -> bool:
 def plan(m: int, l: int, n: int, S: int, method: int = 2, min_blocks: int = 1) -> Plan:
     if min(m, l, n) <= 0:
         raise ValueError("dimensions must be positive")
-    if method == 1:
+    if method in (1, 3):
         if min_blocks > 1:
             raise ValueError("forced blocking needs HEGMM-En")
-        return plan_alg1(m, l, n, S)
+        return plan_alg1(m, l, n, S, cloud=method == 3)
     tr = orientation(m, l, n)
     mo, no = (n, m) if tr else (m, n)
 
@@ -144,14 +146,42 @@ def _alg1_count(mo: int, l: int, no: int, S: int) -> int:
     return c
 
 
-def plan_alg1(m: int, l: int, n: int, S: int) -> Plan:
+def sigma_diagonals(mo: int, l: int) -> Dict[int, set]:
+    """sigma on X (mo x l) flattened column-major (Section III-A definition
+    sigma(X)[i][j] = X[i][(i + j) mod l]): output slot i + j mo reads slot
+    i + ((i + j) mod l) mo, a left rotation by the difference."""
+    cand: Dict[int, set] = {}
+    for i in range(mo):
+        for j in range(l):
+            dst = i + j * mo
+            cand.setdefault(i + ((i + j) % l) * mo - dst, set()).add(dst)
+    return cand
+
+
+def tau_diagonals(l: int, no: int) -> Dict[int, set]:
+    """tau on Y (l x no) flattened column-major (tau(Y)[i][j] =
+    Y[(i + j) mod l][j]): output slot i + j l reads slot ((i + j) mod l) + j l."""
+    cand: Dict[int, set] = {}
+    for i in range(l):
+        for j in range(no):
+            dst = i + j * l
+            cand.setdefault(((i + j) % l) + j * l - dst, set()).add(dst)
+    return cand
+
+
+def plan_alg1(m: int, l: int, n: int, S: int, cloud: bool = False) -> Plan:
     """Algorithm 1 (HEGMM): C = sum_{k<l} eps^k(sigma(A)) (.) omega^k(tau(B)),
     sigma and tau applied by the client while packing (as in the paper's
     experiments), matrices flattened column-major -- or row-major, i.e. the
     transposed problem B^T A^T column-major, when that needs fewer
     key-switched diagonals in total (ties: column-major).  No duplication, so
     d = 1 and no fold; the result sits at slot i + j m (j + i n transposed).
-    Needs max(m l, l n, m n) <= S."""
+    Needs max(m l, l n, m n) <= S.
+
+    cloud=True (method 3): the client packs X and Y as they are (column-major)
+    and the cloud applies sigma and tau to the ciphertexts as linear
+    transforms by the diagonal method, with the 2 min(mo, l) - 1 and
+    2 min(no, l) - 1 diagonals of Theorems 1 and 2, before the loop."""
     if max(m * l, l * n, m * n) > S:
         raise ValueError("shape does not fit one ciphertext")
     tr = _alg1_count(n, l, m, S) < _alg1_count(m, l, n, S)
@@ -163,7 +193,12 @@ def plan_alg1(m: int, l: int, n: int, S: int) -> Plan:
         cw = alg1_omega_diagonals(mo, l, no, k)
         eps.append(_terms(ce, region, sorted(ce)))
         omega.append(_terms(cw, region, sorted(cw)))
-    return Plan(m, l, n, tr, mo, no, 1, l, 1, mo, l, l, eps, omega, [0], method=1)
+    if not cloud:
+        return Plan(m, l, n, tr, mo, no, 1, l, 1, mo, l, l, eps, omega, [0], method=1)
+    cs, ct = sigma_diagonals(mo, l), tau_diagonals(l, no)
+    sigma = _terms(cs, frozenset(range(mo * l)), sorted(cs))
+    tau = _terms(ct, frozenset(range(l * no)), sorted(ct))
+    return Plan(m, l, n, tr, mo, no, 1, l, 1, mo, l, l, eps, omega, [0], method=3, sigma=sigma, tau=tau)
 
 
 def eps_diagonals(mo: int, lb: int, no: int, M: int, W: int, k: int) -> Dict[int, set]:
@@ -231,6 +266,12 @@ def pack_left(pl: Plan, X: np.ndarray, block: int, t: int, S: int) -> List[int]:
             for c in range(pl.l):
                 x[i + c * pl.mo] = int(X[i][(i + c) % pl.l]) % t
         return x
+    if pl.method == 3:   # X itself, column-major; sigma is applied in the cloud
+        x = [0] * S
+        for i in range(pl.mo):
+            for c in range(pl.l):
+                x[i + c * pl.mo] = int(X[i][c]) % t
+        return x
     Xb = np.zeros((pl.mo, pl.lb), dtype=np.int64)
     lo = block * pl.lb
     hi = min(pl.l, lo + pl.lb)
@@ -251,6 +292,12 @@ def pack_right(pl: Plan, Y: np.ndarray, block: int, t: int, S: int) -> List[int]
         for r in range(pl.l):
             for j in range(pl.no):
                 y[r + j * pl.l] = int(Y[(r + j) % pl.l][j]) % t
+        return y
+    if pl.method == 3:   # Y itself, column-major; tau is applied in the cloud
+        y = [0] * S
+        for r in range(pl.l):
+            for j in range(pl.no):
+                y[r + j * pl.l] = int(Y[r][j]) % t
         return y
     Yb = np.zeros((pl.lb, pl.no), dtype=np.int64)
     lo = block * pl.lb
@@ -301,6 +348,9 @@ def hegmm_cleartext(pl: Plan, A, B, t: int, S: int) -> np.ndarray:
     for b in range(pl.nb):
         x = pack_left(pl, X, b, t, S)
         y = pack_right(pl, Y, b, t, S)
+        if pl.method == 3:
+            x = _rot_sum_clear(x, pl.sigma, t)
+            y = _rot_sum_clear(y, pl.tau, t)
         for k in range(pl.K):
             e = _rot_sum_clear(x, pl.eps[k], t)
             f = _rot_sum_clear(y, pl.omega[k], t)
@@ -364,6 +414,9 @@ def hegmm(ks: bgv.KeySet, pl: Plan, ctX: List[bgv.Ct], ctY: List[bgv.Ct],
     switch lifts and rounds each input on its own)."""
     P = ks.P
     masks = masks or MaskCache(P)
+    if pl.method == 3:   # sigma and tau of Algorithm 1 on the ciphertexts (Theorems 1 and 2)
+        ctX = [bgv.rot_sum(P, ks, ctX[0], [(z, None if s is None else masks.get(s)) for z, s in pl.sigma])]
+        ctY = [bgv.rot_sum(P, ks, ctY[0], [(z, None if s is None else masks.get(s)) for z, s in pl.tau])]
     acc = None
     for b in range(pl.nb):
         for k in range(pl.K):

@@ -358,3 +358,68 @@ def test_eager_relin_single_product_equals_lazy():
         z = H.hegmm(ks, pl, cx, cy)
         assert np.array_equal(H.export_d7(e), H.export_d7(z))
         assert (H.decrypt_result(ks, pl, e) == workloads.plain_matmul_mod(A, B, P.t)).all()
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1 with sigma and tau evaluated in the cloud (method 3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(5, 3, 4), (3, 5, 2), (4, 4, 4), (1, 6, 2), (7, 2, 3), (2, 7, 6)])
+def test_cloud_sigma_tau_diagonals(shape):
+    """The sigma / tau rotation sums reproduce the Section III-A definitions
+    sigma(X)[i][j] = X[i][(i+j) mod l], tau(Y)[i][j] = Y[(i+j) mod l][j] on the
+    column-major slot vectors, with 2 min(mo, l) - 1 and 2 min(no, l) - 1
+    diagonals (Theorems 1 and 2; both bounds are met here).  Theorem 1's
+    claim that row-major flattening has the same count is checked from the
+    definition directly."""
+    m, l, n = shape
+    S, t = 64, 257
+    pl = H.plan(m, l, n, S, method=3)
+    assert pl.method == 3
+    rng = np.random.default_rng(sum(shape))
+    X = rng.integers(0, t, size=(pl.mo, l))
+    Y = rng.integers(0, t, size=(l, pl.no))
+    x = [0] * S
+    x[: pl.mo * l] = [int(v) for v in X.flatten(order="F")]
+    y = [0] * S
+    y[: l * pl.no] = [int(v) for v in Y.flatten(order="F")]
+    sx = np.array([[X[i, (i + j) % l] for j in range(l)] for i in range(pl.mo)])
+    ty = np.array([[Y[(i + j) % l, j] for j in range(pl.no)] for i in range(l)])
+    want_x = [0] * S
+    want_x[: pl.mo * l] = [int(v) for v in sx.flatten(order="F")]
+    want_y = [0] * S
+    want_y[: l * pl.no] = [int(v) for v in ty.flatten(order="F")]
+    assert H._rot_sum_clear(x, pl.sigma, t) == want_x
+    assert H._rot_sum_clear(y, pl.tau, t) == want_y
+    assert len(pl.sigma) == 2 * min(pl.mo, l) - 1
+    assert len(pl.tau) == 2 * min(pl.no, l) - 1
+    # row-major: slot i*l + j of sigma(X) reads slot i*l + (i+j) mod l
+    rm = {i * l + (i + j) % l - (i * l + j) for i in range(pl.mo) for j in range(l)}
+    assert len(rm) <= 2 * min(pl.mo, l) - 1
+
+
+def test_cloud_sigma_tau_encrypted():
+    """Method 3 end to end: the sigma / tau passes on the encrypted plain
+    packing decrypt to the client-side sigma / tau packing of Algorithm 1,
+    and the product decrypts to A B mod t."""
+    P = Params(128, 12289, 3, 1)
+    shapes = [(4, 3, 5), (3, 5, 2), (2, 4, 6)]
+    ks = bgv.KeySet(P, 83, H.galois_elements(P, shapes, method=3))
+    rng = np.random.default_rng(83)
+    masks = H.MaskCache(P)
+    for idx, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        pl = H.plan(m, l, n, P.S, method=3)
+        p1 = H.plan(m, l, n, P.S, method=1)
+        assert (pl.transposed, pl.eps, pl.omega) == (p1.transposed, p1.eps, p1.omega)
+        cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=idx)
+        cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=idx)
+        X, Y = H.oriented_operands(pl, A, B)
+        sx = bgv.rot_sum(P, ks, cx[0], [(z, None if s is None else masks.get(s)) for z, s in pl.sigma])
+        ty = bgv.rot_sum(P, ks, cy[0], [(z, None if s is None else masks.get(s)) for z, s in pl.tau])
+        assert bgv.decrypt_slots(ks, sx) == H.pack_left(p1, X, 0, P.t, P.S)
+        assert bgv.decrypt_slots(ks, ty) == H.pack_right(p1, Y, 0, P.t, P.S)
+        C = H.hegmm(ks, pl, cx, cy, masks)
+        assert (H.decrypt_result(ks, pl, C) == workloads.plain_matmul_mod(A, B, P.t)).all(), (m, l, n)
+        assert (H.hegmm_cleartext(pl, A, B, P.t, P.S) == workloads.plain_matmul_mod(A, B, P.t)).all()
