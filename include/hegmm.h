@@ -65,13 +65,17 @@ typedef struct {
     uint32_t L;
     uint32_t alpha;
     uint32_t method;   /* 0 or 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1, column- or
-                          row-major, no duplication or blocking; for comparison) */
+                          row-major, no duplication or blocking; for comparison), sigma and
+                          tau applied by the client while packing; 3: Algorithm 1 with the
+                          operands packed as they are and sigma / tau evaluated on the
+                          ciphertexts by the diagonal method (2 min(m,l) - 1 and
+                          2 min(n,l) - 1 rotations, Theorems 1 and 2).  HG_EINVAL above 3. */
     uint32_t min_blocks; /* 0 or 1: every product splits its inner dimension into as few
                             blocks as fit one ciphertext (usually one); k > 1: into at
                             least k blocks (at most l), each accumulated into the same
                             result (the blockwise product of Section IV-D, forced; the
                             result decrypts to the same A B, its bits differ).  HEGMM-En
-                            only (HG_EINVAL with method 1). */
+                            only (HG_EINVAL with method 1 or 3). */
     uint32_t relin;    /* 0: lazy relinearisation, once per product on the three-component
                           sum of the loop's tensor products (the default); 1: eager, each
                           tensor product of the loop relinearised on its own (HE-Mult of

@@ -168,7 +168,8 @@ class Context:
 
     def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0, method: int = 2, min_blocks: int = 1,
                  relin: int = 0):
-        """method 2: HEGMM-En (Algorithm 2); method 1: Algorithm 1, for comparison.
+        """method 2: HEGMM-En (Algorithm 2); method 1: Algorithm 1, for comparison
+        (method 3: Algorithm 1 with sigma / tau evaluated on the ciphertexts).
         min_blocks > 1 forces that many inner blocks per product; relin 1
         relinearises every loop product on its own (eager; hg_params)."""
         load()

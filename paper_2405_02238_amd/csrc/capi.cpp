@@ -76,7 +76,8 @@ hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
         need(p && out, "null argument");
         *out = nullptr;
         need(p->min_blocks <= 4096, "min_blocks out of range");
-        need(p->min_blocks <= 1 || p->method != 1, "forced blocking needs HEGMM-En (method 2)");
+        need(p->method <= 3, "method must be 0, 1, 2 or 3");
+        need(p->min_blocks <= 1 || p->method == 0 || p->method == 2, "forced blocking needs HEGMM-En (method 2)");
         need(p->relin <= 1, "relin must be 0 (lazy) or 1 (eager)");
         hg::Ctx *c = new hg::Ctx(p->N, p->t, p->L, p->alpha, dev, p->method == 0 ? 2 : (int)p->method);
         c->min_blocks = p->min_blocks > 1 ? (int)p->min_blocks : 1;

@@ -74,7 +74,7 @@ void Ctx::ct_alloc(Ct *c, hipStream_t st) {
 // ---------------------------------------------------------------------------
 
 Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, int method_) {
-    if (method_ != 1 && method_ != 2) throw Error(-1, "method must be 1 or 2");
+    if (method_ < 1 || method_ > 3) throw Error(-1, "method must be 1, 2 or 3");
     method = method_;
     if (N_ < 64 || N_ > 32768 || (N_ & (N_ - 1))) throw Error(-1, "N must be a power of two in [64, 32768]");
     if (L_ < 1 || L_ > 12 || alpha_ < 1 || alpha_ > 4 || L_ + alpha_ > 16)

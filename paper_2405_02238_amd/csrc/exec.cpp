@@ -598,6 +598,57 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
         HGCHK(hipEventRecord(ev[9], st));
     }
 
+    // request-lifetime buffers: accumulators (3 x L x N) and relinearised R
+    // (2 x L x N, fold only).  Eager relinearisation keeps every loop product
+    // apart instead: one three-component tensor per (eps, omega) pair, then
+    // its relinearised two-component ciphertext, summed per request after the
+    // key switches.  Algorithm 1 with sigma / tau in the cloud (method 3)
+    // keeps sigma(X) and tau(Y) of each such request.
+    const bool eager = relin == 1;
+    int nfold = 0, nst = 0, npairs = 0;
+    for (int ri = 0; ri < nreq; ++ri) {
+        const Plan &p = info[ri].pe->plan;
+        nfold += p.d > 1;
+        nst += p.method == 3;
+        npairs += p.nb * p.K;
+    }
+    const int nacc = eager ? npairs : nreq;
+    double *acc = ex.acc(((size_t)nacc * 3 + (size_t)nfold * 2 + (eager ? (size_t)npairs * 2 : 0) +
+                          (size_t)nst * 4) * ctw * sizeof(double));
+    double *rbuf = acc + (size_t)nacc * 3 * ctw;
+    double *ebuf = rbuf + (size_t)nfold * 2 * ctw;                  // eager: relinearised products
+    double *sbuf = ebuf + (eager ? (size_t)npairs * 2 * ctw : 0);   // method 3: sigma(X), tau(Y)
+
+    // --- method 3: sigma(X) and tau(Y) as rotation sums (Theorems 1 and 2) ---
+    Pass pst;
+    std::vector<double *> st_out;   // the pass's job outputs
+    std::vector<const double *> opX(nreq, nullptr), opY(nreq, nullptr);
+    for (int ri = 0, si = 0; ri < nreq; ++ri) {
+        const Plan &p = info[ri].pe->plan;
+        if (p.method != 3) continue;
+        const auto &mp = info[ri].pe->mask_ptrs;
+        double *xs = sbuf + (size_t)(si++) * 4 * ctw, *ys = xs + 2 * ctw;
+        auto add = [&](const std::vector<Term> &tms, const double *in, double *out) {
+            std::vector<std::pair<int, const double *>> te;
+            bool k = false;
+            for (auto &tm : tms) {
+                te.push_back({tm.z, tm.mask >= 0 ? mp[tm.mask] : nullptr});
+                k |= galois_of(tm.z) != 1;
+            }
+            int src = -1;
+            if (k) {
+                src = (int)pst.srcs.size();
+                pst.srcs.push_back(in + ctw);
+            }
+            ex.add_job(pst, in, te, src, nullptr);
+            st_out.push_back(out);
+        };
+        add(p.sigma, info[ri].X->ct(0), xs);
+        add(p.tau, info[ri].Y->ct(0), ys);
+        opX[ri] = xs;
+        opY[ri] = ys;
+    }
+
     // --- main pass: every eps^k / omega^k transform, then tensor accumulation ---
     Pass ps;
     std::vector<int2> req_pairs(nreq);
@@ -606,8 +657,8 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
         const auto &mp = info[ri].pe->mask_ptrs;
         req_pairs[ri] = make_int2((int)ps.fin_jobs.size() / 2, p.nb * p.K);
         for (int b = 0; b < p.nb; ++b) {
-            const double *xc = info[ri].X->ct(b);
-            const double *yc = info[ri].Y->ct(b);
+            const double *xc = opX[ri] ? opX[ri] : info[ri].X->ct(b);
+            const double *yc = opY[ri] ? opY[ri] : info[ri].Y->ct(b);
             int sx = -1, sy = -1;
             for (int k = 0; k < p.K; ++k) {
                 std::vector<std::pair<int, const double *>> te, tw;
@@ -627,19 +678,6 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
             }
         }
     }
-    // request-lifetime buffers: accumulators (3 x L x N) and relinearised R (2 x L x N, fold only).
-    // Eager relinearisation keeps every loop product apart instead: one
-    // three-component tensor per (eps, omega) pair, then its relinearised
-    // two-component ciphertext, summed per request after the key switches.
-    const bool eager = relin == 1;
-    int nfold = 0;
-    for (int ri = 0; ri < nreq; ++ri) nfold += info[ri].pe->plan.d > 1;
-    const int npairs = (int)ps.fin_jobs.size() / 2;
-    const int nacc = eager ? npairs : nreq;
-    double *acc = ex.acc(((size_t)nacc * 3 + (size_t)nfold * 2 + (eager ? (size_t)npairs * 2 : 0)) * ctw *
-                         sizeof(double));
-    double *rbuf = acc + (size_t)nacc * 3 * ctw;
-    double *ebuf = rbuf + (size_t)nfold * 2 * ctw;   // eager: relinearised products, one after the other
     std::vector<double *> acc_ptrs(nacc);
     for (int a = 0; a < nacc; ++a) acc_ptrs[a] = acc + (size_t)a * 3 * ctw;
     std::vector<int2> tensor_pairs = req_pairs;
@@ -693,18 +731,26 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     std::memcpy(rextra.data(), relin_out.data(), relin_out.size() * sizeof(void *));
     if (!sums.empty()) std::memcpy(rextra.data() + relin_out.size() * sizeof(void *), sums.data(), sums.size());
     std::vector<Exec::Staged> sp;
+    const int i_main = nst ? 1 : 0;
+    if (nst) sp.push_back({&pst, st_out.data(), st_out.size() * sizeof(void *), Exec::Dev()});
     sp.push_back({&ps, extra.data(), extra.size(), Exec::Dev()});
     sp.push_back({&pr, rextra.data(), rextra.size(), Exec::Dev()});
     if (nfold) sp.push_back({&pf, outs.data(), outs.size() * sizeof(void *), Exec::Dev()});
     ex.stage(sp);
 
-    const Exec::Dev &dv = sp[0].dv;
+    if (nst) {
+        const Exec::Dev &d0 = sp[0].dv;
+        if (!ex.launch(d0, nullptr, false, nullptr, Exec::direct_ok(pst) ? (double *const *)d0.extra : nullptr))
+            fin_rotsum_launch(T, d0.jobs, d0.terms, d0.E, d0.masks, (double *const *)d0.extra, (int)st_out.size(),
+                              st);
+    }
+    const Exec::Dev &dv = sp[i_main].dv;
     timing.ip_pairs.clear();
     ex.launch(dv, timing.enabled ? ev : nullptr, true, timing.enabled ? &timing : nullptr);
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
                       (double *const *)(dv.extra + tensor_pairs.size() * sizeof(int2)), nacc, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
-    const Exec::Dev &d2 = sp[1].dv;
+    const Exec::Dev &d2 = sp[i_main + 1].dv;
     if (!ex.launch(d2, nullptr, false, nullptr, Exec::direct_ok(pr) ? (double *const *)d2.extra : nullptr))
         fin_rotsum_launch(T, d2.jobs, d2.terms, d2.E, d2.masks, (double *const *)d2.extra, nacc, st);
     if (eager) {
@@ -713,7 +759,7 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     }
     if (timing.enabled) HGCHK(hipEventRecord(ev[4], st));
     if (nfold) {
-        const Exec::Dev &d3 = sp[2].dv;
+        const Exec::Dev &d3 = sp[i_main + 2].dv;
         if (!ex.launch(d3, nullptr, false, nullptr, Exec::direct_ok(pf) ? (double *const *)d3.extra : nullptr))
             fin_rotsum_launch(T, d3.jobs, d3.terms, d3.E, d3.masks, (double *const *)d3.extra, (int)outs.size(), st);
     }

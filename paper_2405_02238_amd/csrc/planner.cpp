@@ -81,6 +81,29 @@ std::map<int, std::vector<int>> alg1_omega(int mo, int l, int no, int k) {
     return cand;
 }
 
+// sigma on X (mo x l) and tau on Y (l x no), both column-major: output
+// slot i + j mo reads i + ((i + j) mod l) mo, resp. slot i + j l reads
+// ((i + j) mod l) + j l (the Section III-A definitions).
+std::map<int, std::vector<int>> sigma_diags(int mo, int l) {
+    std::map<int, std::vector<int>> cand;
+    for (int j = 0; j < l; ++j)
+        for (int i = 0; i < mo; ++i) {
+            const int dst = i + j * mo;
+            cand[i + ((i + j) % l) * mo - dst].push_back(dst);
+        }
+    return cand;
+}
+
+std::map<int, std::vector<int>> tau_diags(int l, int no) {
+    std::map<int, std::vector<int>> cand;
+    for (int j = 0; j < no; ++j)
+        for (int i = 0; i < l; ++i) {
+            const int dst = i + j * l;
+            cand[((i + j) % l) + j * l - dst].push_back(dst);
+        }
+    return cand;
+}
+
 long long alg1_switched(int mo, int l, int no, int S) {
     long long c = 0;
     for (int k = 0; k < l; ++k) {
@@ -90,7 +113,7 @@ long long alg1_switched(int mo, int l, int no, int S) {
     return c;
 }
 
-Plan make_plan_alg1(int m, int l, int n, int S) {
+Plan make_plan_alg1(int m, int l, int n, int S, bool cloud) {
     if ((long long)m * l > S || (long long)l * n > S || (long long)m * n > S)
         throw std::range_error("shape does not fit one ciphertext row");
     Plan p;
@@ -109,6 +132,11 @@ Plan make_plan_alg1(int m, int l, int n, int S) {
         p.omega.push_back(w);
     }
     p.fold.push_back(0);
+    if (cloud) {
+        p.method = 3;
+        add_all_terms(p, p.sigma, sigma_diags(p.mo, l), S, (size_t)p.mo * l);
+        add_all_terms(p, p.tau, tau_diags(l, p.no), S, (size_t)l * p.no);
+    }
     return p;
 }
 
@@ -116,9 +144,9 @@ Plan make_plan_alg1(int m, int l, int n, int S) {
 
 Plan make_plan(int m, int l, int n, int S, int method, int min_blocks) {
     if (m <= 0 || l <= 0 || n <= 0) throw std::invalid_argument("dimensions must be positive");
-    if (min_blocks > 1 && method == 1) throw std::invalid_argument("forced blocking needs HEGMM-En");
-    if (method == 1) return make_plan_alg1(m, l, n, S);
-    if (method != 2) throw std::invalid_argument("method must be 1 or 2");
+    if (min_blocks > 1 && method != 2) throw std::invalid_argument("forced blocking needs HEGMM-En");
+    if (method == 1 || method == 3) return make_plan_alg1(m, l, n, S, method == 3);
+    if (method != 2) throw std::invalid_argument("method must be 1, 2 or 3");
     Plan p;
     p.m = m; p.l = l; p.n = n;
     // Orientation in Algorithm 2's order: p == m duplicates A; else p == n
@@ -188,6 +216,8 @@ std::vector<int> Plan::rotations(int S) const {
     };
     for (auto &v : eps) for (auto &t : v) addz(t.z);
     for (auto &v : omega) for (auto &t : v) addz(t.z);
+    for (auto &t : sigma) addz(t.z);
+    for (auto &t : tau) addz(t.z);
     for (int z : fold) addz(z);
     return std::vector<int>(zs.begin(), zs.end());
 }
@@ -201,6 +231,8 @@ int Plan::key_switched_terms(int S) const {
         for (auto &v : eps) cnt(v);
         for (auto &v : omega) cnt(v);
     }
+    cnt(sigma);
+    cnt(tau);
     for (int z : fold) c += (((z % S) + S) % S) != 0;
     return c;
 }
@@ -212,6 +244,20 @@ std::vector<uint64_t> pack_operand(const Plan &p, int side, const int64_t *X, in
         return (uint64_t)(r < 0 ? r + (int64_t)t : r);
     };
     const int lo = block * p.lb;
+    if (p.method == 3) {
+        // Xo (mo x l) and Yo (l x no) as they are, column-major: sigma and
+        // tau are applied to the ciphertexts
+        if (side == 0) {
+            for (int i = 0; i < p.mo; ++i)
+                for (int c = 0; c < p.l; ++c)
+                    v[i + (size_t)c * p.mo] = modt(p.transposed ? X[(size_t)c * p.n + i] : X[(size_t)i * p.l + c]);
+        } else {
+            for (int r = 0; r < p.l; ++r)
+                for (int j = 0; j < p.no; ++j)
+                    v[r + (size_t)j * p.l] = modt(p.transposed ? X[(size_t)j * p.l + r] : X[(size_t)r * p.n + j]);
+        }
+        return v;
+    }
     if (p.method == 1) {
         // Algorithm 1: sigma(Xo) (mo x l) and tau(Yo) (l x no), column-major
         if (side == 0) {

@@ -28,7 +28,9 @@ struct Plan {
     std::vector<std::vector<Term>> eps, omega;  // per k
     std::vector<int> fold;                      // h * mo, h = 0..d-1
     std::vector<std::vector<uint8_t>> masks;    // S bytes each, 1 = slot kept
-    int method = 2;                             // 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1)
+    int method = 2;                             // 2: HEGMM-En (Algorithm 2); 1: HEGMM (Algorithm 1);
+                                                // 3: Algorithm 1 with sigma / tau in the cloud
+    std::vector<Term> sigma, tau;               // method 3: the transforms applied to X and Y first
     std::vector<int> rotations(int S) const;    // distinct nonzero z mod S
     int key_switched_terms(int S) const;        // terms that need a key switch
 };
@@ -39,7 +41,10 @@ struct Plan {
 // (capped at l) even when fewer would fit (method 2 only).
 // method 2: HEGMM-En; method 1: the paper's Algorithm 1 (HEGMM), sigma and
 // tau applied by the client, column-major or (when that needs fewer
-// key-switched diagonals) row-major flattening, no duplication, no blocking.
+// key-switched diagonals) row-major flattening, no duplication, no blocking;
+// method 3: Algorithm 1 with the operands packed as they are and sigma / tau
+// applied to the ciphertexts (2 min(mo, l) - 1 and 2 min(no, l) - 1
+// diagonals, Theorems 1 and 2).
 Plan make_plan(int m, int l, int n, int S, int method = 2, int min_blocks = 1);
 
 // Client packing: the slot vector (length S, values in [0, t)) of the left

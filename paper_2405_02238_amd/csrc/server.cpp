@@ -20,7 +20,7 @@ uint64_t request_footprint(const Ctx &C, const Plan &p) {
     const uint64_t nsrc = 2 * (uint64_t)p.nb;
     const uint64_t operands = 2 * (uint64_t)p.nb * ct;
     const uint64_t result = ct;
-    uint64_t acc = 3 * L * N * w + (p.d > 1 ? ct : 0);
+    uint64_t acc = 3 * L * N * w + (p.d > 1 ? ct : 0) + (p.method == 3 ? 2 * ct : 0);
     uint64_t scratch = nsrc * (L + beta * nExt) * N * w + nks * 2 * (nExt + alpha + L) * N * w;
     if (C.relin == 1) {
         // eager relinearisation: a tensor and a relinearised ciphertext per

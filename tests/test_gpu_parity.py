@@ -537,19 +537,24 @@ def test_graph_replay_matches_eager(tiny):
     g.close()
 
 
+@pytest.mark.parametrize("method", [1, 3])
 @pytest.mark.parametrize("shape", [(4, 3, 5), (3, 5, 2), (5, 3, 3), (2, 7, 6)])
-def test_algorithm1_variant(shape):
+def test_algorithm1_variant(shape, method):
     """Algorithm 1 (HEGMM, no duplication; column- or row-major whichever
-    needs fewer key switches) against the oracle's Algorithm 1, bit for bit."""
+    needs fewer key switches) against the oracle's Algorithm 1, bit for bit:
+    sigma / tau applied by the client (method 1) or evaluated on the
+    ciphertexts before the loop (method 3, Theorems 1 and 2)."""
     c = workloads.TINY
     m, l, n = shape
-    ctx = hg.Context(c.N, c.t, c.L, c.alpha, method=1)
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, method=method)
     ctx.keygen(c.seed, [shape])
     P = Params(c.N, c.t, c.L, c.alpha)
-    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [shape], method=1))
-    pl = H.plan(m, l, n, P.S, method=1)
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [shape], method=method))
+    pl = H.plan(m, l, n, P.S, method=method)
     info = ctx.plan_info(m, l, n)
     assert info["transposed"] == int(pl.transposed) and info["K"] == l and info["d"] == 1
+    assert info["rotations"] == len(pl.rotations(P.S))
+    assert info["ks_terms"] == sum(1 for ts in pl.eps + pl.omega + [pl.sigma, pl.tau] for z, _ in ts if z % P.S)
     rng = np.random.default_rng(m + 10 * l + 100 * n)
     A = rng.integers(-8, 9, size=(m, l))
     B = rng.integers(-8, 9, size=(l, n))
