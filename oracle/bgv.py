@@ -111,30 +111,39 @@ def encrypt_slots(ks: KeySet, slots: Sequence[int], role: int = 2, block: int = 
     return encrypt_poly(ks, ring.encode(ks.P, slots), role, block, nonce)
 
 
-def decrypt_poly(ks: KeySet, ct: Ct) -> np.ndarray:
-    """c0 + c1 s (+ c2 s^2) over Q -> exact CRT -> centered -> mod t."""
+def _combine(ks: KeySet, ct: Ct) -> np.ndarray:
+    """c0 + c1 s (+ c2 s^2) over the ciphertext's primes (its level: the
+    first rows of Q; fewer than L after modulus switching)."""
     P = ks.P
-    s_q = ks.sk.s_ext[:P.L]
+    lv = ct[0].shape[0]
+    s_q = ks.sk.s_ext[:lv]
     acc = ct[0]
     spow = s_q
     for comp in ct[1:]:
-        acc = ring.add(acc, ring.polymul(P, comp, spow), P.q_arr)
+        acc = ring.add(acc, ring.polymul(P, comp, spow), P.q_arr[:lv])
         spow = ring.polymul(P, spow, s_q)
-    return crt_centered_mod_t(P, acc)
+    return acc
+
+
+def decrypt_poly(ks: KeySet, ct: Ct) -> np.ndarray:
+    """c0 + c1 s (+ c2 s^2) over Q -> exact CRT -> centered -> mod t."""
+    return crt_centered_mod_t(ks.P, _combine(ks, ct))
 
 
 def crt_centered_mod_t(P: Params, rows: np.ndarray) -> np.ndarray:
-    """Residues over Q -> the integer in (-Q/2, Q/2) -> reduced mod t."""
-    Q = P.Q
+    """Residues over Q (or the first rows of it) -> the integer in (-Q/2, Q/2)
+    -> reduced mod t."""
+    qs = P.q[: rows.shape[0]]
+    Q = math.prod(qs)
     basis = []
-    for qi in P.q:
+    for qi in qs:
         hat = Q // qi
         basis.append(hat * pow(hat % qi, -1, qi))
     out = np.empty(P.N, dtype=np.int64)
-    cols = [[int(v) for v in rows[i]] for i in range(P.L)]
+    cols = [[int(v) for v in rows[i]] for i in range(len(qs))]
     for k in range(P.N):
         x = 0
-        for i in range(P.L):
+        for i in range(len(qs)):
             x += cols[i][k] * basis[i]
         x %= Q
         if x > Q // 2:
@@ -146,18 +155,14 @@ def crt_centered_mod_t(P: Params, rows: np.ndarray) -> np.ndarray:
 def noise_bits(ks: KeySet, ct: Ct, mu: np.ndarray) -> float:
     """log2 of the largest |c0 + c1 s - lift(mu)| over coefficients (a diagnostic)."""
     P = ks.P
-    s_q = ks.sk.s_ext[:P.L]
-    acc = ct[0]
-    spow = s_q
-    for comp in ct[1:]:
-        acc = ring.add(acc, ring.polymul(P, comp, spow), P.q_arr)
-        spow = ring.polymul(P, spow, s_q)
-    Q = P.Q
-    basis = [(Q // qi) * pow((Q // qi) % qi, -1, qi) for qi in P.q]
+    acc = _combine(ks, ct)
+    qs = P.q[: acc.shape[0]]
+    Q = math.prod(qs)
+    basis = [(Q // qi) * pow((Q // qi) % qi, -1, qi) for qi in qs]
     worst = 0
     lifted = ring.lift_centered(mu, P.t)
     for k in range(P.N):
-        x = sum(int(acc[i][k]) * basis[i] for i in range(P.L)) % Q
+        x = sum(int(acc[i][k]) * basis[i] for i in range(len(qs))) % Q
         if x > Q // 2:
             x -= Q
         worst = max(worst, abs(x - int(lifted[k])))
@@ -299,3 +304,46 @@ def he_cmult(P: Params, ct: Ct, mask: Mask) -> Ct:
     """HE-CMult by a plaintext slot vector."""
     return [ring.intt(ring.mul(ring.ntt(c, P.q_arr, P.psi_q), mask.q_eval, P.q_arr), P.q_arr, P.psi_q)
             for c in ct]
+
+
+def mod_switch(P: Params, ct: Ct, drop: int = 1) -> Ct:
+    """BGV modulus switching: drop the last `drop` primes of the ciphertext
+    (coefficient form), one at a time, keeping the plaintext.
+
+    From level l (primes q_0..q_{l-1}) to l - 1, with q = q_{l-1} and
+    k = q mod t: each component, read as the integer x in [0, Q_l), becomes
+    y = k x mod Q_l, then z = (y - delta) / q with delta = t [y t^-1]_q
+    (centered), so that delta = y (mod q) and delta = 0 (mod t) and the
+    division is exact; z is reduced mod q_0..q_{l-2}.  Decryption then gives
+    k mu q^-1 = mu (mod t), and the noise becomes about k/q of what it was
+    plus t (1 + |s|_1) / 2 (the standard rescaling of BGV; the factor k keeps
+    the plaintext unscaled)."""
+    out = [np.ascontiguousarray(c, dtype=np.uint64) for c in ct]
+    if drop < 1 or drop >= out[0].shape[0]:
+        raise ValueError("drop must leave at least one prime")
+    for _ in range(drop):
+        lv = out[0].shape[0]
+        qs = P.q[:lv]
+        q = qs[-1]
+        Q = math.prod(qs)
+        k = q % P.t
+        tinv = pow(P.t, -1, q)
+        basis = [(Q // qi) * pow((Q // qi) % qi, -1, qi) for qi in qs]
+        nxt = []
+        for c in out:
+            cols = [[int(v) for v in c[i]] for i in range(lv)]
+            rows = np.empty((lv - 1, P.N), dtype=np.uint64)
+            for j in range(P.N):
+                x = sum(cols[i][j] * basis[i] for i in range(lv)) % Q
+                y = (k * x) % Q
+                r = (y * tinv) % q
+                if r > q // 2:
+                    r -= q
+                num = y - P.t * r
+                assert num % q == 0
+                z = num // q
+                for i in range(lv - 1):
+                    rows[i, j] = z % qs[i]
+            nxt.append(rows)
+        out = nxt
+    return out

@@ -204,3 +204,63 @@ def test_noise_stays_in_budget(setup):
     r = bgv.rotate(P, ks, ct, 5)
     mu = ring.encode(P, [v[(s + 5) % P.S] for s in range(P.S)])
     assert bgv.noise_bits(ks, r, mu) < math.log2(P.Q) - 2
+
+
+# ---------------------------------------------------------------------------
+# modulus switching
+# ---------------------------------------------------------------------------
+
+def _switch_bound(P, ks, nb_in, lv):
+    """The rescaling bound of BGV modulus switching from level lv to lv - 1:
+    |v'| <= k (|v|) / q + t (1 + |s|_1) / 2, v the centered decryption before
+    reduction mod t (|v| <= 2^nb_in + t / 2), plus t / 2 for the message."""
+    q = P.q[lv - 1]
+    k = q % P.t
+    s1 = int(np.abs(np.asarray(ks.sk.s, dtype=np.int64)).sum())
+    return k * (2.0 ** nb_in + P.t / 2) / q + P.t * (1 + s1) / 2 + P.t / 2
+
+
+def test_mod_switch_keeps_plaintext_and_bounds_noise():
+    """Dropping one and two primes keeps the decrypted slots, leaves L - drop
+    rows, and the noise obeys the closed-form rescaling bound at each step."""
+    P = Params(1024, 12289, 3, 1)
+    ks = bgv.KeySet(P, 5, [])
+    rng = np.random.default_rng(11)
+    for nonce in range(3):
+        v = [int(x) for x in rng.integers(0, P.t, P.S)]
+        c = bgv.encrypt_slots(ks, v, nonce=nonce)
+        mu = bgv.decrypt_poly(ks, c)
+        nb = bgv.noise_bits(ks, c, mu)
+        cur = c
+        for lv in (P.L, P.L - 1):
+            nxt = bgv.mod_switch(P, cur, 1)
+            assert all(x.shape == (lv - 1, P.N) for x in nxt)
+            assert bgv.decrypt_slots(ks, nxt) == v
+            nb2 = bgv.noise_bits(ks, nxt, mu)
+            assert 2.0 ** nb2 <= _switch_bound(P, ks, nb, lv)
+            cur, nb = nxt, nb2
+        two = bgv.mod_switch(P, c, 2)
+        assert all(np.array_equal(a, b) for a, b in zip(two, cur))
+
+
+def test_mod_switch_of_a_product():
+    """A relinearised product (large noise) switched down one prime: the
+    plaintext is kept and the noise shrinks by about q / k."""
+    P = Params(1024, 12289, 3, 1)
+    ks = bgv.KeySet(P, 6, [])
+    rng = np.random.default_rng(12)
+    a = [int(x) for x in rng.integers(0, P.t, P.S)]
+    b = [int(x) for x in rng.integers(0, P.t, P.S)]
+    ca, cb = bgv.encrypt_slots(ks, a, nonce=1), bgv.encrypt_slots(ks, b, nonce=2)
+    prod = bgv.he_mult(P, ks, ca, cb)
+    want = [(x * y) % P.t for x, y in zip(a, b)]
+    assert bgv.decrypt_slots(ks, prod) == want
+    mu = bgv.decrypt_poly(ks, prod)
+    nb = bgv.noise_bits(ks, prod, mu)
+    sw = bgv.mod_switch(P, prod, 1)
+    assert bgv.decrypt_slots(ks, sw) == want
+    nb2 = bgv.noise_bits(ks, sw, mu)
+    assert 2.0 ** nb2 <= _switch_bound(P, ks, nb, P.L)
+    assert nb2 < nb
+    with pytest.raises(ValueError):
+        bgv.mod_switch(P, prod, P.L)
