@@ -180,13 +180,15 @@ hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ctC, int m, int l, int n, uint64_
 
 /* Canonical serialisation: coefficient form, residues in [0, q_i), the
  * ciphertexts of the handle in order, each component c0 then c1 (then c2),
- * each limb q_0..q_{L-1}, N little-endian u64 words per limb.  *needed gets
+ * each limb q_0..q_{L-1} (q_0..q_{l-1} for a handle switched to level l by
+ * hg_mod_switch), N little-endian u64 words per limb.  *needed gets
  * the word count; buf may be NULL to query it.  Errors: HG_EINVAL (buffer
  * too small). */
 hg_status hg_ct_export(hg_ctx *ctx, const hg_ct *ct, uint64_t *buf, size_t nwords, size_t *needed);
 
 /* Rebuild a handle from hg_ct_export output (ncts ciphertexts of
- * `components` components each).  Words must be residues in [0, q_i).
+ * `components` components each, all L limbs).  Words must be residues in
+ * [0, q_i).
  * Errors: HG_EINVAL. */
 hg_status hg_ct_import(hg_ctx *ctx, const uint64_t *buf, size_t nwords, int ncts, int components,
                        hg_ct **out);
@@ -216,6 +218,20 @@ hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void 
 
 /* HE-CMult by a 0/1 (or any mod-t) slot vector of length S. */
 hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream);
+
+/* BGV modulus switching of a two-component handle (an hg_hegmm result, any
+ * number of ciphertexts): a new handle at `drop` primes fewer, q_0..q_{l-1}
+ * with l = L - drop (1 <= drop < L), that decrypts to the same plaintext, so
+ * a result goes back to the client in l/L of the words.  Each step from
+ * level l to l - 1 scales the ciphertext by q_{l-1} mod t and divides it by
+ * q_{l-1} with the t-corrected rounding of the division by P (the standard
+ * BGV rescaling; the scaling keeps the plaintext unscaled).  The new handle
+ * can be exported (hg_ct_export writes l limbs per component), loaded
+ * (hg_ct_load) and decrypted (hg_decrypt), but is no operand of any other
+ * call (HG_EINVAL).  Enqueued on `stream`, which it synchronises before it
+ * returns.  Errors: HG_EINVAL (not two components, drop out of range, an
+ * input already switched to fewer than drop + 1 primes), HG_ENOMEM. */
+hg_status hg_mod_switch(hg_ctx *ctx, const hg_ct *ct, int drop, hg_ct **out, void *stream);
 
 /* ---- serving: continuous batching ------------------------------------ */
 

@@ -70,6 +70,7 @@ _SIGS = {
     "hg_mul": [_P, _P, _P, _PP, _P],
     "hg_add": [_P, _P, _P, _PP, _P],
     "hg_cmul": [_P, _P, _i64p, _PP, _P],
+    "hg_mod_switch": [_P, _P, ctypes.c_int, _PP, _P],
     "hg_plan_info": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p],
     "hg_primes": [_P, _u64p],
     "hg_set_timing": [_P, ctypes.c_int],
@@ -300,6 +301,13 @@ class Context:
         v[: len(slots)] = np.asarray(slots, dtype=np.int64)
         out = ctypes.c_void_p()
         _check(_lib.hg_cmul(self.ptr, a.ptr, v, ctypes.byref(out), current_stream() if stream is None else stream))
+        return self._ct(out)
+
+    def mod_switch(self, a: Ciphertext, drop: int = 1, stream=None) -> Ciphertext:
+        """hg_mod_switch: the same plaintext at `drop` ciphertext primes fewer."""
+        out = ctypes.c_void_p()
+        _check(_lib.hg_mod_switch(self.ptr, a.ptr, drop, ctypes.byref(out),
+                                  current_stream() if stream is None else stream))
         return self._ct(out)
 
     def plan_info(self, m: int, l: int, n: int) -> dict:

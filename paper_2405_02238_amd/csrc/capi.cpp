@@ -332,6 +332,14 @@ hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void 
     });
 }
 
+hg_status hg_mod_switch(hg_ctx *ctx, const hg_ct *ct, int drop, hg_ct **out, void *stream) {
+    return guard([&] {
+        need(ctx && ct && out, "null argument");
+        *out = nullptr;
+        *out = wrap(ctx->c->mod_switch(*ct->c, drop, as_stream(stream)));
+    });
+}
+
 hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream) {
     return guard([&] {
         need(ctx && a && slots && out, "null argument");

@@ -49,8 +49,9 @@ double centered_d(uint64_t x, uint64_t m) { return (double)centered_of(x, m); }
 // Ct
 // ---------------------------------------------------------------------------
 
-size_t Ct::words() const { return (size_t)ncts * comps * ctx->L * ctx->N; }
-double *Ct::ct(int i) const { return d + (size_t)i * comps * ctx->L * ctx->N; }
+int Ct::lv() const { return level > 0 ? level : ctx->L; }
+size_t Ct::words() const { return (size_t)ncts * comps * lv() * ctx->N; }
+double *Ct::ct(int i) const { return d + (size_t)i * comps * lv() * ctx->N; }
 Ct::~Ct() {
     if (!d || !owns) return;
     if (release) release(d, release_user);
@@ -183,6 +184,27 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, in
     T.pmod = (double *)up(pmod.data(), pmod.size() * sizeof(double));
     T.t = (double)t;
     T.tinv = 1.0 / (double)t;
+    // modulus switching from level l to l - 1: P = q_{l-1}, over q_0..q_{l-2}
+    ms_tabs.assign(L + 1, DevTables());
+    std::vector<double> ms_hat(L);
+    for (int i = 0; i < L; ++i) ms_hat[i] = (double)(t % qs[i]);
+    double *ms_hat_d = L > 1 ? (double *)up(ms_hat.data(), ms_hat.size() * sizeof(double)) : nullptr;
+    for (int l = 2; l <= L; ++l) {
+        const uint64_t q = qs[l - 1];
+        std::vector<double> coef(1), pinv_l(l - 1);
+        coef[0] = centered_d(hmul(hinv(t % q, q), hinv((uint64_t)N % q, q), q), q);
+        for (int i = 0; i < l - 1; ++i) pinv_l[i] = centered_d(hinv(q % qs[i], qs[i]), qs[i]);
+        DevTables M = T;
+        M.L = l - 1;          // output primes
+        M.alpha = 1;          // q_{l-1} is the one prime divided out
+        M.nExt = l;           // input rows per component
+        M.beta = 0;
+        M.md_coef = (double *)up(coef.data(), sizeof(double));
+        M.md_hat = ms_hat_d;
+        M.pinv = (double *)up(pinv_l.data(), pinv_l.size() * sizeof(double));
+        M.mu_invhat = M.mu_hat = M.pmod = nullptr;
+        ms_tabs[l] = M;
+    }
 }
 
 Ctx::~Ctx() {
@@ -479,12 +501,13 @@ Ct *Ctx::encrypt_matrix(int role, const int64_t *X, int m, int l, int n, uint64_
     return c;
 }
 
-std::vector<uint64_t> Ctx::to_host_canonical(const double *eval_rows, int rows, hipStream_t st) {
+std::vector<uint64_t> Ctx::to_host_canonical(const double *eval_rows, int rows, hipStream_t st, int per) {
+    if (per <= 0) per = L;
     double *tmp = dev_alloc((size_t)rows * N);
     uint64_t *u = nullptr;
     HGCHK(hipMalloc(&u, (size_t)rows * N * sizeof(uint64_t)));
     NttArgs a;
-    a.out = tmp; a.in = eval_rows; a.rows = rows; a.per = L; a.out_stride = a.in_stride = (long long)L * N;
+    a.out = tmp; a.in = eval_rows; a.rows = rows; a.per = per; a.out_stride = a.in_stride = (long long)per * N;
     ntt_inv(T, STORE_CANON, a, st);
     dbl_to_u64(tmp, u, (size_t)rows * N, st);
     std::vector<uint64_t> h((size_t)rows * N);
@@ -498,9 +521,14 @@ std::vector<uint64_t> Ctx::to_host_canonical(const double *eval_rows, int rows, 
 std::vector<uint64_t> Ctx::decrypt_poly(const Ct &c, int index) {
     if (!has_secret) throw Error(-6, "no secret key");
     hipStream_t st = nullptr;
+    // a ciphertext at a lower level (after modulus switching) holds only the
+    // first primes of Q: everything below runs over those (L = its level)
+    const int L = c.lv();
+    DevTables Tl = T;
+    Tl.L = L;
     double *v = dev_alloc((size_t)L * N);
-    dec_combine(T, v, c.ct(index), c.comps, s_eval, s2_eval, st);
-    std::vector<uint64_t> res = to_host_canonical(v, L, st);
+    dec_combine(Tl, v, c.ct(index), c.comps, s_eval, s2_eval, st);
+    std::vector<uint64_t> res = to_host_canonical(v, L, st, L);
     (void)hipFree(v);
     // Garner mixed-radix reconstruction: x = sum_i a_i R_i, R_i = q_0...q_{i-1}
     std::vector<std::vector<uint64_t>> inv(L, std::vector<uint64_t>(L, 0));
@@ -569,8 +597,8 @@ std::vector<uint64_t> Ctx::decrypt_slot_values(const Ct &c, int index) {
 // ---------------------------------------------------------------------------
 
 void Ctx::export_ct(const Ct &c, uint64_t *buf, hipStream_t st) {
-    const int rows = c.ncts * c.comps * L;
-    std::vector<uint64_t> h = to_host_canonical(c.d, rows, st);
+    const int rows = c.ncts * c.comps * c.lv();
+    std::vector<uint64_t> h = to_host_canonical(c.d, rows, st, c.lv());
     std::memcpy(buf, h.data(), h.size() * sizeof(uint64_t));
 }
 
@@ -591,9 +619,10 @@ Ct *Ctx::import_ct(const uint64_t *buf, int ncts, int comps, hipStream_t st) {
 
 void Ctx::load_ct(Ct &c, const uint64_t *buf, size_t nwords, hipStream_t st) {
     const size_t n = c.words();
+    const int lv = c.lv();
     if (nwords != n) throw Error(-1, "word count does not match the handle");
     for (size_t r = 0; r < n / N; ++r) {
-        const uint64_t q = qs[r % L];
+        const uint64_t q = qs[r % lv];
         for (int i = 0; i < N; ++i)
             if (buf[r * N + i] >= q) throw Error(-1, "residue out of range in import");
     }
@@ -602,8 +631,8 @@ void Ctx::load_ct(Ct &c, const uint64_t *buf, size_t nwords, hipStream_t st) {
     HGCHK(hipMemcpyAsync(u, buf, n * sizeof(uint64_t), hipMemcpyHostToDevice, st));
     u64_to_dbl(u, c.d, n, st);
     NttArgs a;
-    a.out = c.d; a.in = c.d; a.rows = (int)(n / N); a.per = L;
-    a.out_stride = a.in_stride = (long long)L * N;
+    a.out = c.d; a.in = c.d; a.rows = (int)(n / N); a.per = lv;
+    a.out_stride = a.in_stride = (long long)lv * N;
     ntt_fwd(T, LOAD_PLAIN, a, st);
     HGCHK(hipStreamSynchronize(st));
     (void)hipFree(u);

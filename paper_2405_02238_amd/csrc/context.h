@@ -38,10 +38,12 @@ struct Ct {
     int ncts = 1, comps = 2;
     int m = 0, l = 0, n = 0;   // shape (0 for raw slot ciphertexts)
     int side = -1;             // packed side (0 left, 1 right, 2 result, -1 raw)
+    int level = 0;             // ciphertext primes per component (0: all L; fewer after modulus switching)
     double *d = nullptr;
     bool owns = true;          // false: a view into memory owned elsewhere
     CtReleaseFn release = nullptr;   // d came from the caller's allocator: give it back here
     void *release_user = nullptr;
+    int lv() const;            // ciphertext primes per component
     size_t words() const;      // doubles in total
     double *ct(int i) const;   // start of ciphertext i
     ~Ct();
@@ -86,6 +88,9 @@ struct Ctx {
     uint64_t t = 0, zeta = 0;
     std::vector<uint64_t> qs;     // extended basis: q_0..q_{L-1}, p_0..p_{alpha-1}
     DevTables T;                  // device tables (pointers)
+    // Modulus switching from level l to l - 1 (index l = 2..L): the tables of
+    // the division by P with P = q_{l-1} (one special prime) over q_0..q_{l-2}.
+    std::vector<DevTables> ms_tabs;
     std::vector<void *> owned;    // device allocations released at destroy
 
     // keys
@@ -167,6 +172,9 @@ struct Ctx {
     Ct *mul(const Ct &a, const Ct &b, hipStream_t st);
     Ct *add(const Ct &a, const Ct &b, hipStream_t st);
     Ct *cmul(const Ct &a, const std::vector<uint64_t> &slots, hipStream_t st);
+    // BGV modulus switching of a two-component ciphertext: drop its last `drop` primes
+    Ct *mod_switch(const Ct &c, int drop, hipStream_t st);
+    void need_full_level(const Ct &c) const;   // throws unless c has all L primes
 
     void export_ct(const Ct &c, uint64_t *buf, hipStream_t st);
     Ct *import_ct(const uint64_t *buf, int ncts, int comps, hipStream_t st);
@@ -174,7 +182,8 @@ struct Ctx {
     void load_ct(Ct &c, const uint64_t *buf, size_t nwords, hipStream_t st);
 
     // canonical (coefficient form, [0,q)) residues of an L-row polynomial
-    std::vector<uint64_t> to_host_canonical(const double *eval_rows, int rows, hipStream_t st);
+    // (rows cycle over the first `per` primes; 0: L)
+    std::vector<uint64_t> to_host_canonical(const double *eval_rows, int rows, hipStream_t st, int per = 0);
 
     Arena &arena(hipStream_t st);
 };

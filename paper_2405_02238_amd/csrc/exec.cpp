@@ -554,6 +554,8 @@ const PlanEntry &Ctx::check_request(const Request &r) {
     if (A->side != side_of_role(pe.plan, 0) || B->side != side_of_role(pe.plan, 1))
         throw Error(-1, "operands must be hg_encrypt outputs for roles 0 (A) and 1 (B)");
     if (A->ncts != pe.plan.nb || B->ncts != pe.plan.nb) throw Error(-1, "block count mismatch");
+    need_full_level(*A);
+    need_full_level(*B);
     for (auto &rz : pe.plan.rotations(S))
         if (!rot_keys.count(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
     return pe;
@@ -790,6 +792,7 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
 Ct *Ctx::rotate(const Ct &c, int z, hipStream_t st) {
     HGCHK(hipSetDevice(device));
     if (c.comps != 2 || c.ncts != 1) throw Error(-1, "rotate takes one two-component ciphertext");
+    need_full_level(c);
     Ct *o = new Ct();
     o->ctx = this;
     ct_alloc(o, st);
@@ -811,6 +814,8 @@ Ct *Ctx::rotate(const Ct &c, int z, hipStream_t st) {
 Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
     HGCHK(hipSetDevice(device));
     if (a.comps != 2 || b.comps != 2 || a.ncts != 1 || b.ncts != 1) throw Error(-1, "mul takes two-component ciphertexts");
+    need_full_level(a);
+    need_full_level(b);
     const size_t ctw = (size_t)L * N;
     Ct *o = new Ct();
     o->ctx = this;
@@ -841,6 +846,8 @@ Ct *Ctx::mul(const Ct &a, const Ct &b, hipStream_t st) {
 
 Ct *Ctx::add(const Ct &a, const Ct &b, hipStream_t st) {
     if (a.comps != b.comps || a.ncts != b.ncts) throw Error(-1, "add: mismatched ciphertexts");
+    need_full_level(a);
+    need_full_level(b);
     Ct *o = new Ct();
     o->ctx = this;
     o->ncts = a.ncts;
@@ -851,6 +858,7 @@ Ct *Ctx::add(const Ct &a, const Ct &b, hipStream_t st) {
 }
 
 Ct *Ctx::cmul(const Ct &a, const std::vector<uint64_t> &slots, hipStream_t st) {
+    need_full_level(a);
     std::vector<uint8_t> key(S);
     // masks are cached by bitmap; general slot values go through a one-off plaintext
     bool binary = true;
@@ -888,6 +896,73 @@ Ct *Ctx::cmul(const Ct &a, const std::vector<uint64_t> &slots, hipStream_t st) {
         (void)hipFree(m);
     }
     return o;
+}
+
+void Ctx::need_full_level(const Ct &c) const {
+    if (c.lv() != L) throw Error(-1, "the ciphertext was modulus-switched: only export and decryption take it");
+}
+
+// BGV modulus switching, one prime at a time: from level l to l - 1 the
+// input is scaled by k = q_{l-1} mod t (so that the plaintext comes out
+// unscaled) and divided by q_{l-1} with the t-corrected rounding of the
+// division by P, run by the same kernels with the tables of P = q_{l-1}.
+Ct *Ctx::mod_switch(const Ct &c, int drop, hipStream_t st) {
+    HGCHK(hipSetDevice(device));
+    if (c.comps != 2) throw Error(-1, "modulus switching takes two-component ciphertexts");
+    if (drop < 1 || drop >= c.lv()) throw Error(-1, "drop must be at least 1 and leave at least one prime");
+    std::unique_ptr<Ct> cur;
+    const Ct *in = &c;
+    double *scaled = nullptr, *rk = nullptr;
+    try {
+        scaled = dev_alloc(c.words());
+        if (N > 16384) rk = dev_alloc((size_t)c.ncts * 2 * N);
+        for (int s = 0; s < drop; ++s) {
+            const int l = in->lv();
+            const DevTables &M = ms_tabs[l];
+            std::unique_ptr<Ct> o(new Ct());
+            o->ctx = this;
+            o->ncts = in->ncts;
+            o->comps = 2;
+            o->m = in->m; o->l = in->l; o->n = in->n;
+            o->side = in->side;
+            o->level = l - 1;
+            ct_alloc(o.get(), st);
+            const int nslots = in->ncts * 2;
+            scale_rows(T, scaled, in->d, nslots * l, l, (double)(qs[l - 1] % t), st);
+            if (N <= 16384) {
+                moddown_fused(M, o->d, scaled, nslots, st);
+            } else {
+                NttArgs md;
+                md.out = rk;
+                md.in = scaled;
+                md.rows = nslots;
+                md.per = 1;
+                md.prime_base = l - 1;
+                md.out_stride = (long long)N;
+                md.in_stride = (long long)l * N;
+                md.in_offset = (long long)(l - 1) * N;
+                ntt_inv(M, STORE_MDR, md, st);
+                NttArgs dl;
+                dl.out = o->d;
+                dl.in = rk;
+                dl.aux = scaled;
+                dl.rows = nslots * (l - 1);
+                dl.in_stride = (long long)N;
+                ntt_fwd(M, LOAD_DELTA, dl, st);
+            }
+            cur = std::move(o);   // the steps run in stream order on the shared scratch
+            in = cur.get();
+        }
+        HGCHK(hipStreamSynchronize(st));
+    } catch (...) {
+        (void)hipStreamSynchronize(st);
+        if (scaled) (void)hipFree(scaled);
+        if (rk) (void)hipFree(rk);
+        throw;
+    }
+    (void)hipFree(scaled);
+    if (rk) (void)hipFree(rk);
+    return cur.release();
 }
 
 }  // namespace hg

@@ -167,6 +167,8 @@ void mul_rows(const DevTables &T, double *out, const double *a, const double *b,
               int prime_base, int per, hipStream_t s);
 void add_rows(const DevTables &T, double *out, const double *a, const double *b, int rows,
               int prime_base, int per, hipStream_t s);
+// out = c * a row by row; row r is over prime r % per (|c| below every prime).
+void scale_rows(const DevTables &T, double *out, const double *a, int rows, int per, double c, hipStream_t s);
 
 // Sampling (counter-based SplitMix64 streams): rows x N uniform residues
 // (draw first + r*N + i), N ternary or Gaussian integers (draw first + i).

@@ -461,6 +461,17 @@ __global__ void k_add_rows(DevTables T, double *out, const double *a, const doub
     out[x] = redm(a[x] + b[x], q, qi);
 }
 
+__global__ void k_scale_rows(DevTables T, double *out, const double *a, double c, int per) {
+    const int N = 1 << T.logN;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.y;
+    if (p >= N) return;
+    const int pr = r % per;
+    const double q = T.qt[pr].x, qi = T.qt[pr].y;
+    const size_t x = (size_t)r * N + p;
+    out[x] = mulm(a[x], c, q, qi);
+}
+
 __global__ void k_center_rows(DevTables T, double *x, int prime_base, int per) {
     const int N = 1 << T.logN;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -749,6 +760,11 @@ void add_rows(const DevTables &T, double *out, const double *a, const double *b,
               int per, hipStream_t s) {
     if (rows <= 0) return;
     hipLaunchKernelGGL(k_add_rows, ew_grid(T.N, rows), dim3(EW_THREADS), 0, s, T, out, a, b, prime_base, per);
+}
+
+void scale_rows(const DevTables &T, double *out, const double *a, int rows, int per, double c, hipStream_t s) {
+    if (rows <= 0) return;
+    hipLaunchKernelGGL(k_scale_rows, ew_grid(T.N, rows), dim3(EW_THREADS), 0, s, T, out, a, c, per);
 }
 
 void center_rows(const DevTables &T, double *x, int rows, int prime_base, int per, hipStream_t s) {

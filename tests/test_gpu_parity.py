@@ -236,6 +236,60 @@ def test_eager_relin_headline_full_size():
     run_pair(pair, 64, 32, 48, A, B, nonce=1)
 
 
+def test_mod_switch_result(tiny):
+    """Modulus switching of a product result by one and two primes: bits equal
+    the oracle's switching of the oracle's (bit-identical) result, the export
+    shrinks to 2 (L - drop) N words, and the result decrypts to A.B mod t."""
+    ctx, P, ks = tiny.ctx, tiny.P, tiny.ks
+    m, l, n = 4, 3, 5
+    A, B = workloads.tiny_operands()
+    pl = H.plan(m, l, n, P.S)
+    ox = H.encrypt_operand(ks, pl, 0, A, B, 1)
+    oy = H.encrypt_operand(ks, pl, 1, A, B, 1)
+    R = H.hegmm(ks, pl, ox, oy, tiny.masks)
+    cc = ctx.hegmm(ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1), m, l, n)
+    assert np.array_equal(cc.export(), flat(R))
+    for drop in range(1, P.L):
+        sw = ctx.mod_switch(cc, drop)
+        got = sw.export()
+        assert got.size == 2 * (P.L - drop) * P.N
+        assert np.array_equal(got, flat(bgv.mod_switch(P, R, drop))), drop
+        assert np.array_equal(ctx.decrypt(sw, m, l, n), workloads.plain_matmul_mod(A, B, P.t)), drop
+    one = ctx.mod_switch(cc, 1)
+    with pytest.raises(hg.HGError):
+        ctx.mod_switch(cc, P.L)
+    with pytest.raises(hg.HGError):
+        ctx.mod_switch(cc, 0)
+    with pytest.raises(hg.HGError):
+        ctx.mod_switch(one, P.L - 1)
+    with pytest.raises(hg.HGError):
+        ctx.rotate(one, 1)
+    with pytest.raises(hg.HGError):
+        ctx.hegmm(one, cc, m, l, n)
+
+
+@pytest.mark.parametrize("cfg", ["serving", "large"])
+def test_mod_switch_fresh_large_rings(cfg):
+    """Modulus switching at N = 16384 (6 + 2 primes, one-workgroup rows) and
+    N = 32768 (8 + 2 primes, two-pass transforms) on fresh encryptions: bits
+    equal the oracle's switching of the same (bit-identical) encryption, and
+    the slots decrypt unchanged."""
+    c = workloads.CONFIGS[cfg]
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, [])
+    ks = bgv.KeySet(P, c.seed, [], relin=False)
+    rng = np.random.default_rng(c.N)
+    v = rng.integers(0, P.t, P.S)
+    ct = ctx.encrypt_slots(v, nonce=5)
+    ref = bgv.encrypt_slots(ks, [int(x) for x in v], role=2, block=0, nonce=5)
+    assert np.array_equal(ct.export(), flat(ref))
+    for drop in (1, 3):
+        sw = ctx.mod_switch(ct, drop)
+        assert np.array_equal(sw.export(), flat(bgv.mod_switch(P, ref, drop))), drop
+        assert np.array_equal(ctx.decrypt_slots(sw), v.astype(np.int64)), drop
+
+
 def test_hegmm_headline_full_size():
     """64x32x48 at N = 8192: the whole output ciphertext against the oracle."""
     c = workloads.HEADLINE
