@@ -36,13 +36,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batched", "serving", "large", "alg1", "blocked", "eager"],
+                    choices=["headline", "batched", "serving", "large", "alg1", "blocked", "eager", "modswitch"],
                     help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step; "
                          "serving: 512 Poisson arrivals at N=16384 through the continuous-batching server; "
                          "large: one 128x96x128 product per step at N=32768; "
                          "alg1: the headline product with the paper's Algorithm 1 instead of HEGMM-En; "
                          "blocked: a 100x100x100 product split into output blocks (partitions P1/P2); "
-                         "eager: the headline product with every loop product relinearised on its own")
+                         "eager: the headline product with every loop product relinearised on its own; "
+                         "modswitch: the headline product followed by modulus switching of its result")
     ap.add_argument("--partition", default="P2", choices=["P1", "P2"], help="blocked: the reported partition")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
@@ -403,6 +404,61 @@ def run_eager(args):
         "lazy_speedup_over_eager": res[0]["matmuls_per_s"] / v if v else None}), flush=True)
 
 
+def run_modswitch(args):
+    """The headline product (64x32x48, N=8192, L=4) followed by BGV modulus
+    switching of its result down 1, 2 and 3 primes: time per switch, the
+    exported words the client receives, decryption, and the one-prime switch
+    compared with the oracle's bit for bit."""
+    import torch
+    import paper_2405_02238_amd as hg
+    import workloads
+
+    cfg = workloads.HEADLINE
+    m, l, n = 64, 32, 48
+    A, B = workloads.headline_operands()
+    want = workloads.plain_matmul_mod(A, B, cfg.t)
+    ctx = hg.Context(cfg.N, cfg.t, cfg.L, cfg.alpha)
+    ctx.keygen(cfg.seed, [(m, l, n)])
+    ca, cb = ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1)
+    cc = ctx.hegmm(ca, cb, m, l, n)
+    torch.cuda.synchronize()
+    full_words = int(cc.export().size)
+    res = {}
+    for drop in range(1, cfg.L):
+        for _ in range(args.warmup):
+            ctx.mod_switch(cc, drop)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sw = ctx.mod_switch(cc, drop)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        words = sw.export()
+        res[drop] = {"ms_per_switch": ms, "export_words": int(words.size),
+                     "decrypt_ok": bool(np.array_equal(ctx.decrypt(sw, m, l, n), want))}
+        if drop == 1:
+            one = words
+    bit_exact = None
+    if not args.no_oracle_check:
+        from oracle import bgv, hegmm as H
+        from oracle.ring import Params
+        P = Params(cfg.N, cfg.t, cfg.L, cfg.alpha)
+        ks = bgv.KeySet(P, cfg.seed, H.galois_elements(P, [(m, l, n)]))
+        pl = H.plan(m, l, n, P.S)
+        R = H.hegmm(ks, pl, H.encrypt_operand(ks, pl, 0, A, B, 1), H.encrypt_operand(ks, pl, 1, A, B, 1))
+        bit_exact = bool(np.array_equal(one, H.export_d7(bgv.mod_switch(P, R, 1))))
+    ok = all(r["decrypt_ok"] for r in res.values()) and bit_exact is not False
+    ms1 = res[1]["ms_per_switch"]
+    print(json.dumps({
+        "metric": "modulus switches/s of a 64x32x48 N=8192 result (one prime dropped)",
+        "value": 1000.0 / ms1 if ok else 0.0, "unit": "switches/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms1, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "BGV modulus switching of the HEGMM-En 64x32x48 result, N=8192 t=65537 L=4 alpha=1"},
+        "bit_exact": bit_exact, "full_level_words": full_words,
+        "drops": {str(k): v for k, v in res.items()}}), flush=True)
+
+
 def run_blocked(args):
     """A 100x100 by 100x100 product, whose 10000-entry result does not fit
     one ciphertext of the headline ring, as a blocked product: A split into
@@ -479,6 +535,8 @@ def main():
         return run_blocked(args)
     if args.workload == "eager":
         return run_eager(args)
+    if args.workload == "modswitch":
+        return run_modswitch(args)
     import torch
     import paper_2405_02238_amd as hg
     import workloads
