@@ -340,8 +340,7 @@ struct Exec {
         }
         // a kernel reads the tables straight out of the pinned buffer: cheaper
         // on the stream than a copy-engine transfer and its barrier
-        copy_from_host(tab, A.pinned_dev, tl.total, st);
-        if (!C.capturing) HGCHK(hipEventRecord(A.staged, st));
+        copy_from_host(tab, A.pinned_dev, tl.total, st, C.capturing ? nullptr : A.staged);
     }
 
     // True when a pass's result per job is exactly its division by P (every

@@ -159,8 +159,9 @@ void sum_cts_launch(const DevTables &T, const double *in, const int2 *groups, do
 void kernels_init();
 
 // ---- utilities ----
-// Copy `bytes` (a multiple of 16) from device-mapped pinned host memory.
-void copy_from_host(void *dst, const void *src_host_mapped, size_t bytes, hipStream_t s);
+// Copy `bytes` (a multiple of 16) from device-mapped pinned host memory;
+// `done` (optional) is recorded by the copy's own completion.
+void copy_from_host(void *dst, const void *src_host_mapped, size_t bytes, hipStream_t s, hipEvent_t done = nullptr);
 void u64_to_dbl(const uint64_t *in, double *out, size_t n, hipStream_t s);
 void dbl_to_u64(const double *in, uint64_t *out, size_t n, hipStream_t s);
 void mul_rows(const DevTables &T, double *out, const double *a, const double *b, int rows,

@@ -733,11 +733,17 @@ void sum_cts_launch(const DevTables &T, const double *in, const int2 *groups, do
     hipLaunchKernelGGL(k_sum_cts, ew_grid(T.N / 2, 2 * T.L, ngroups), dim3(EW_THREADS), 0, s, T, in, groups, out);
 }
 
-void copy_from_host(void *dst, const void *src, size_t bytes, hipStream_t s) {
+void copy_from_host(void *dst, const void *src, size_t bytes, hipStream_t s, hipEvent_t done) {
     const size_t n = bytes / 16;
-    if (!n) return;
-    hipLaunchKernelGGL(k_copy16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint4 *)dst,
-                       (const uint4 *)src, n);
+    if (!n) {
+        if (done) (void)hipEventRecord(done, s);   // a failed record surfaces at the next wait on it
+        return;
+    }
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (done)   // the dispatch's own completion signal, no separate marker packet
+        hipExtLaunchKernelGGL(k_copy16, grid, dim3(256), 0, s, nullptr, done, 0, (uint4 *)dst, (const uint4 *)src, n);
+    else
+        hipLaunchKernelGGL(k_copy16, grid, dim3(256), 0, s, (uint4 *)dst, (const uint4 *)src, n);
 }
 
 void u64_to_dbl(const uint64_t *in, double *out, size_t n, hipStream_t s) {
