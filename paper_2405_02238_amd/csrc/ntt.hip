@@ -202,13 +202,16 @@ __device__ __forceinline__ void fwd_tw(double *w, const double *__restrict__ tw,
         for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (S0 + u)) + (blk << u) + c];
 }
 
-// Forward stages [S0, S0 + K) on the 2^K elements of one group; odd global
-// stages and the last one reduce.
+// Forward stages [S0, S0 + K) on the 2^K elements of one group.  Stages
+// 2, 5, 8, ... and the last one reduce: from |x| < q the two stages in
+// between grow the values to below 3q (each twiddle product is below q),
+// so the reduced sums stay below 4q, well inside the exact range of redm
+// and mulm.
 template <int LOGN, int S0, int K>
 __device__ __forceinline__ void fwd_bfly(double *x, const double *w, double q, double qi) {
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-        const bool red = ((S0 + u) & 1) || (S0 + u == LOGN - 1);
+        const bool red = ((S0 + u) % 3 == 2) || (S0 + u == LOGN - 1);
         const int half = 1 << (K - 1 - u);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) {
@@ -239,17 +242,21 @@ __device__ __forceinline__ void inv_tw(double *w, const double *__restrict__ tw,
     }
 }
 
-template <int K>
+// Inverse stages of half-size 2^LTS0 .. 2^(LTS0 + K - 1) on one group.  The
+// sums are reduced on odd stages and the last one (from |x| < q they stay
+// below 4q); the differences always go through a twiddle product.
+template <int LOGN, int LTS0, int K>
 __device__ __forceinline__ void inv_bfly(double *x, const double *w, double q, double qi) {
     int wo = 0;
 #pragma unroll
     for (int u = 0; u < K; ++u) {
         const int d = 1 << u;
+        const bool red = ((LTS0 + u) & 1) || (LTS0 + u == LOGN - 1);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) {
             if (b & d) continue;
             const double X = x[b], Y = x[b + d];
-            x[b] = redm(X + Y, q, qi);
+            x[b] = red ? redm(X + Y, q, qi) : X + Y;
             x[b + d] = mulm(X - Y, w[wo + (b >> (u + 1))], q, qi);
         }
         wo += 1 << (K - u - 1);
@@ -334,7 +341,7 @@ __device__ __forceinline__ void inv_mid(double *sh, const double *__restrict__ t
         for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         double wnext[(1 << K) - 1];
         if constexpr (L1 < LOGN - K) inv_tw<LOGN, L1, K>(wnext, tw, t >> L1);
-        inv_bfly<K>(x, wcur, q, qi);
+        inv_bfly<LOGN, LTS0, K>(x, wcur, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
@@ -358,7 +365,7 @@ __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restr
         inv_tw<LOGN, 0, KT>(w, tw, grp);
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) y[b] = ld((grp << KT) + b);
-        inv_bfly<KT>(y, w, q, qi);
+        inv_bfly<LOGN, 0, KT>(y, w, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) sh[lds_ix((grp << KT) + b)] = y[b];
     }
@@ -370,7 +377,7 @@ __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restr
     inv_tw<LOGN, LOGN - K, K>(w, tw, 0);
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<NT>(t, b)];
-    inv_bfly<K>(x, w, q, qi);
+    inv_bfly<LOGN, LOGN - K, K>(x, w, q, qi);
 }
 
 // K forward stages [s0, s0 + K) of nsub independent 2^ls-point transforms
