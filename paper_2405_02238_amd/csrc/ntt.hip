@@ -203,15 +203,16 @@ __device__ __forceinline__ void fwd_tw(double *w, const double *__restrict__ tw,
 }
 
 // Forward stages [S0, S0 + K) on the 2^K elements of one group.  Stages
-// 2, 5, 8, ... and the last one reduce: from |x| < q the two stages in
-// between grow the values to below 3q (each twiddle product is below q),
-// so the reduced sums stay below 4q, well inside the exact range of redm
-// and mulm.
+// 3, 7, 11, ... and the last one reduce.  A twiddle product (twiddles are
+// centered, below q/2) is below 1.5q even with both roundings of the
+// quotient estimate off, so from inputs below 2q the values stay below 7q
+// before each reduction: under 2^53 (q < 2^50), where redm and mulm are
+// exact, and the residues do not depend on the reduction schedule.
 template <int LOGN, int S0, int K>
 __device__ __forceinline__ void fwd_bfly(double *x, const double *w, double q, double qi) {
 #pragma unroll
     for (int u = 0; u < K; ++u) {
-        const bool red = ((S0 + u) % 3 == 2) || (S0 + u == LOGN - 1);
+        const bool red = ((S0 + u) % 4 == 3) || (S0 + u == LOGN - 1);
         const int half = 1 << (K - 1 - u);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) {
@@ -243,8 +244,11 @@ __device__ __forceinline__ void inv_tw(double *w, const double *__restrict__ tw,
 }
 
 // Inverse stages of half-size 2^LTS0 .. 2^(LTS0 + K - 1) on one group.  The
-// sums are reduced on odd stages and the last one (from |x| < q they stay
-// below 4q); the differences always go through a twiddle product.
+// sums are reduced on odd stages and the last one, the differences always
+// go through a twiddle product.  With the bound on twiddle products above
+// and inputs below q (stored rows are reduced), every value of a row of up
+// to 2^14 points stays below 7.3q < 2^53; the outputs (last differences)
+// are below 2q, and every consumer multiplies them before anything else.
 template <int LOGN, int LTS0, int K>
 __device__ __forceinline__ void inv_bfly(double *x, const double *w, double q, double qi) {
     int wo = 0;

@@ -623,6 +623,28 @@ def test_algorithm1_variant(shape, method):
     assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
 
 
+@pytest.mark.parametrize("method", [1, 3])
+def test_algorithm1_eager_relin(method):
+    """The variants compose: Algorithm 1 (client- or cloud-side sigma/tau)
+    with every loop product relinearised on its own, against the oracle."""
+    c = workloads.TINY
+    m, l, n = 3, 4, 2
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, method=method, relin=1)
+    ctx.keygen(c.seed, [(m, l, n)])
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [(m, l, n)], method=method))
+    pl = H.plan(m, l, n, P.S, method=method)
+    rng = np.random.default_rng(17 + method)
+    A = rng.integers(-8, 9, size=(m, l))
+    B = rng.integers(-8, 9, size=(l, n))
+    ca, cb = ctx.encrypt(0, A, m, l, n, nonce=6), ctx.encrypt(1, B, m, l, n, nonce=6)
+    ox = H.encrypt_operand(ks, pl, 0, A, B, 6)
+    oy = H.encrypt_operand(ks, pl, 1, A, B, 6)
+    cc = ctx.hegmm(ca, cb, m, l, n)
+    assert np.array_equal(cc.export(), flat(H.hegmm(ks, pl, ox, oy, eager=True)))
+    assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
+
+
 def test_execution_knobs_bit_identical():
     """Every execution knob changes only the schedule: pipelined passes on a
     second stream, split-row transforms, fused or unfused chains, launch
