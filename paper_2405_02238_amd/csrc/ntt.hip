@@ -13,8 +13,9 @@
 // of a forward transform takes its inputs from registers and its last round
 // writes the outputs, and the inverse mirrors this, so an 8192-point row
 // (13 stages: 3+3+3+3+1) makes three full LDS round trips.  Reductions are
-// lazy: a forward stage whose outputs feed another multiplication keeps them
-// unreduced (|x| < 2q), every second stage reduces.
+// lazy: forward stages reduce every fourth stage (values below 7q in between),
+// inverse rows of up to 2^14 points reduce their sums every second stage;
+// all within the exact range of the FP64 arithmetic (below 2^53).
 //
 // The load and store steps fuse the neighbouring work of key switching:
 // LOAD_MODUP lifts one digit of a coefficient-form polynomial to the prime of
@@ -388,8 +389,9 @@ __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restr
 // stored one after another in LDS.  Sub-transform sb takes its stage-s
 // twiddles from tw[C * 2^s + local], C = cb + sb * cs (C = 1 for a whole row
 // or for the columns of a split row; 2^a + block for the blocks of a split
-// row).  Stage s is global stage sg0 + s; odd global stages, the last global
-// stage, and (force_last) the last local stage reduce their outputs.
+// row).  Stage s is global stage sg0 + s; global stages 3, 7, 11, ..., the
+// last global stage, and (force_last) the last local stage reduce their
+// outputs (the bound of the row transforms: below 7q in between).
 template <int K>
 __device__ __forceinline__ void fwd_round(double *sh, const double *__restrict__ tw, int ls, int nsub, int s0,
                                           int cb, int cs, int sg0, int logN, bool force_last, double q, double qi) {
@@ -411,7 +413,7 @@ __device__ __forceinline__ void fwd_round(double *sh, const double *__restrict__
         for (int u = 0; u < K; ++u) {
             const int s = s0 + u;
             const int sg = sg0 + s;
-            const bool red = (sg & 1) || (sg == logN - 1) || (force_last && s == ls - 1);
+            const bool red = (sg % 4 == 3) || (sg == logN - 1) || (force_last && s == ls - 1);
             const int half = 1 << (K - 1 - u);
             const double *twu = tw + (C << s) + (blk << u);
 #pragma unroll
@@ -532,7 +534,7 @@ __device__ __forceinline__ void fwd_round_t(double *sh, const double *__restrict
             (void)dummy;
             const int s = S0 + u;
             const int sg = SG0 + s;
-            const bool red = (sg & 1) || (sg == LOGN - 1) || (FL && s == LS - 1);
+            const bool red = (sg % 4 == 3) || (sg == LOGN - 1) || (FL && s == LS - 1);
             const int half = 1 << (K - 1 - u);
 #pragma unroll
             for (int b = 0; b < (1 << K); ++b) {
