@@ -412,6 +412,31 @@ def test_serving_errors_and_budget():
                               workloads.plain_matmul_mod(A, B, c.t))
 
 
+@pytest.mark.parametrize("variant", [{"relin": 1}, {"method": 3}, {"method": 3, "relin": 1}])
+def test_serving_variants_equal_alone(variant):
+    """The request loop serves contexts of every variant (eager
+    relinearisation, Algorithm 1 with cloud-side sigma/tau): each served
+    result is the bit pattern of the same product run alone."""
+    c = workloads.TINY
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, **variant)
+    shapes = [(4, 3, 5), (2, 5, 3), (3, 3, 3)]
+    ctx.keygen(c.seed, shapes)
+    rng = np.random.default_rng(31)
+    reqs = []
+    for i, (m, l, n) in enumerate(shapes * 2):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        ca, cb = ctx.encrypt(0, A, m, l, n, nonce=50 + i), ctx.encrypt(1, B, m, l, n, nonce=50 + i)
+        reqs.append((m, l, n, A, B, ca, cb))
+    alone = [ctx.hegmm(ca, cb, m, l, n).export() for (m, l, n, A, B, ca, cb) in reqs]
+    with hg.Server(ctx, max_batch=4, lanes=2) as srv:
+        tickets = [srv.submit(ca.export(), cb.export(), m, l, n) for (m, l, n, A, B, ca, cb) in reqs]
+        outs = [srv.wait(t)[0] for t in tickets]
+    for (m, l, n, A, B, ca, cb), o, w in zip(reqs, outs, alone):
+        assert np.array_equal(o, w), (m, l, n)
+        assert np.array_equal(ctx.decrypt(ctx.import_ct(o, 1, 2), m, l, n), workloads.plain_matmul_mod(A, B, c.t))
+
+
 def _sha(words):
     import hashlib
     return hashlib.sha256(np.ascontiguousarray(words, dtype="<u8").tobytes()).hexdigest()
