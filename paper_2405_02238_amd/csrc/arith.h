@@ -33,7 +33,9 @@ __device__ __forceinline__ double mulm(double a, double b, double q, double qi) 
     return r + l;
 }
 
-// any |x| < 2^52  ->  x (mod q) with |r| <= q/2 + 1
+// any integer-valued |x| < 2^53  ->  x (mod q) with |r| <= q/2 + 1 (x * fl(1/q)
+// is then within 2^-49 of x/q, so the estimated quotient is off by at most
+// one at a near-tie, and the fused remainder is an exact small integer)
 __device__ __forceinline__ double redm(double x, double q, double qi) {
     return __fma_rn(-rint(x * qi), q, x);
 }
