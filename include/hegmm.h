@@ -307,6 +307,10 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
  *                together; 0: in pass order
  *   "split_rows" transforms of fewer rows than this split each row over
  *                N/1024 workgroups (two passes)
+ *   "half_rows"  fused transform chains (few-row passes) of at most this many
+ *                rows run two workgroups per row, each finishing one half of
+ *                the forward transform (default 128; 0: off); like
+ *                "split_rows" it holds for every context of the process
  *   "ntt_radix"  radix of the one-workgroup row transforms of 4096- and
  *                8192-point rows: 8, 16, or 0 for the built-in choice (8);
  *                like "split_rows" it holds for every context of the process

@@ -26,6 +26,7 @@ DEFAULT_SPACE = {
     "ip_chunk": [0, 16, 64],
     "ip_order": [0, 1],
     "ntt_radix": [8, 16],
+    "half_rows": [0, 128],
     "batch_window": [0, 64, 128],
 }
 

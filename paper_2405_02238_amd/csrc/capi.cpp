@@ -396,6 +396,7 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
         else if (n == "ip_chunk") X.ip_chunk = (int)value;
         else if (n == "ip_order") X.ip_order = (int)value;
         else if (n == "split_rows") hg::ntt_set_split_rows((int)value);
+        else if (n == "half_rows") hg::ntt_set_half_rows((int)value);
         else if (n == "ntt_radix") {
             need(value == 0 || value == 8 || value == 16, "ntt_radix must be 0, 8 or 16");
             hg::ntt_set_radix((int)value);

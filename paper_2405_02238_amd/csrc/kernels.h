@@ -121,6 +121,12 @@ void ntt_set_split_rows(int rows);
 // the same for every radix.  Throws std::invalid_argument for other values.
 void ntt_set_radix(int radix);
 
+// Fused chains (hoist_fused, moddown_fused) of at most this many rows run
+// two workgroups per row, each finishing half of the forward transform after
+// applying its first stage (the inverse is done by both); 0: off, default
+// 128 (one workgroup per CU at most).  Results are the same either way.
+void ntt_set_half_rows(int rows);
+
 // Inner products: U[slot][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
 // the unswitched part on the ciphertext primes (see IpTerm).

@@ -270,9 +270,12 @@ __device__ __forceinline__ void inv_bfly(double *x, const double *w, double q, d
 
 // Full forward rounds from stage S0 up to the short round, one group per
 // thread, the next round's twiddles loaded while this one computes.
-template <int LOGN, int RKX, int S0>
+// SG = 1, hb = h: the transform is half h of a 2^(LOGN + 1)-point row whose
+// first stage has been applied, i.e. its local stage s is the row's stage
+// s + 1 and its group blk at local stage s is the row's group (h << s) + blk.
+template <int LOGN, int RKX, int S0, int SG = 0>
 __device__ __forceinline__ void fwd_mid(double *sh, const double *__restrict__ tw, double q, double qi, int t,
-                                        const double *wcur) {
+                                        const double *wcur, int hb = 0) {
     using R = Rows<LOGN, RKX>;
     if constexpr (S0 < R::SL) {
         constexpr int K = R::RK, LTS = LOGN - S0 - K, TS = 1 << LTS;
@@ -283,43 +286,66 @@ __device__ __forceinline__ void fwd_mid(double *sh, const double *__restrict__ t
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         double wnext[(1 << K) - 1];
-        if constexpr (S1 < R::SL) fwd_tw<S1, K>(wnext, tw, t >> (LOGN - S1 - K));
-        fwd_bfly<LOGN, S0, K>(x, wcur, q, qi);
+        if constexpr (S1 < R::SL) fwd_tw<S1 + SG, K>(wnext, tw, (hb << S1) + (t >> (LOGN - S1 - K)));
+        fwd_bfly<LOGN + SG, S0 + SG, K>(x, wcur, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
-        fwd_mid<LOGN, RKX, S1>(sh, tw, q, qi, t, wnext);
+        fwd_mid<LOGN, RKX, S1, SG>(sh, tw, q, qi, t, wnext, hb);
     }
 }
 
 // Forward transform of a row of which thread t holds elements t + b NT in
 // x (|x| < q); st(i, v) receives output position i (bit-reversed order).
-// Uses sh as scratch; the caller must not touch sh concurrently.
-template <int LOGN, int RKX, class Store>
+// Uses sh as scratch; the caller must not touch sh concurrently.  With SG = 1
+// the row is half hb of a twice longer row after that row's first stage
+// (see fwd_mid; st then receives positions within the half).
+template <int LOGN, int RKX, int SG = 0, class Store>
 __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restrict__ tw, double q, double qi,
-                                             double *x, Store st) {
+                                             double *x, Store st, int hb = 0) {
     using R = Rows<LOGN, RKX>;
     constexpr int K = R::RK, NT = R::NT, KT = R::KT, SL = R::SL;
     const int t = threadIdx.x;
     double w0[(1 << K) - 1], w1[(1 << K) - 1];
-    fwd_tw<0, K>(w0, tw, 0);
-    fwd_tw<K, K>(w1, tw, t >> (LOGN - 2 * K));
-    fwd_bfly<LOGN, 0, K>(x, w0, q, qi);
+    fwd_tw<SG, K>(w0, tw, hb);
+    fwd_tw<K + SG, K>(w1, tw, (hb << K) + (t >> (LOGN - 2 * K)));
+    fwd_bfly<LOGN + SG, SG, K>(x, w0, q, qi);
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<NT>(t, b)] = x[b];
     __syncthreads();
-    fwd_mid<LOGN, RKX, K>(sh, tw, q, qi, t, w1);
+    fwd_mid<LOGN, RKX, K, SG>(sh, tw, q, qi, t, w1, hb);
 #pragma unroll
     for (int g = 0; g < R::GPT; ++g) {
         const int grp = t + g * NT;
         double w[(1 << KT) - 1], y[1 << KT];
-        fwd_tw<SL, KT>(w, tw, grp);
+        fwd_tw<SL + SG, KT>(w, tw, (hb << SL) + grp);
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) y[b] = sh[lds_ix((grp << KT) + b)];
-        fwd_bfly<LOGN, SL, KT>(y, w, q, qi);
+        fwd_bfly<LOGN + SG, SL + SG, KT>(y, w, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) st((grp << KT) + b, y[b]);
     }
+}
+
+// The forward transform of the register-held row x (thread t: elements
+// t + b NT, NT = 2^(LOGN - RKX)) restricted to output half h: the row's first
+// stage pairs elements b and b + 2^(RKX-1) of each thread, so the thread
+// keeps X + w Y (h = 0) or X - w Y (h = 1) and the rest is an independent
+// 2^(LOGN-1)-point transform at radix 2^(RKX-1) on the same NT threads; st
+// receives the half's output positions h 2^(LOGN-1) + i.  Two workgroups,
+// one per half, finish a row in about the time of one half.
+template <int LOGN, int RKX, class Store>
+__device__ __forceinline__ void fwd_row_regs_half(double *sh, const double *__restrict__ tw, double q, double qi,
+                                                  double *x, Store st, int h) {
+    constexpr int HALF = 1 << (RKX - 1);
+    const double w = tw[1];
+    double z[HALF];
+#pragma unroll
+    for (int b = 0; b < HALF; ++b) {
+        const double t = mulm(x[b + HALF], w, q, qi);
+        z[b] = h ? x[b] - t : x[b] + t;
+    }
+    fwd_row_regs<LOGN - 1, RKX - 1, 1>(sh, tw, q, qi, z, [&](int i, double v) { st((h << (LOGN - 1)) + i, v); }, h);
 }
 
 template <int LOGN, int RKX, class Load, class Store>
@@ -915,17 +941,21 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
 // r, all in LDS.  Row r = j is the source row itself.
 template <int LOGN, int RK = rk_of(LOGN)>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
-k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
+k_hoist_fused(DevTables T, double *y, const double *const *srcs, int split) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    const int row = blockIdx.x;
+    // split: two workgroups per row, each finishing one half of the forward
+    // transform (hh = the half)
+    const int row = split ? blockIdx.x >> 1 : blockIdx.x;
+    const int hh = split ? (int)(blockIdx.x & 1) : -1;
     const int r = row % T.nExt;
     const int j = (row / T.nExt) % T.beta;
     const int src = row / (T.nExt * T.beta);
     const double *c = srcs[src] + (size_t)j * N;
     double *out = y + (size_t)row * N;
     if (r == j) {
-        for (int i = threadIdx.x; i < N; i += blockDim.x) gst(out)[i] = gld(c)[i];
+        const int i0 = hh < 0 ? 0 : hh * (N / 2), i1 = hh < 0 ? N : i0 + N / 2;
+        for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) gst(out)[i] = gld(c)[i];
         return;
     }
     const double *twj = T.twi + (size_t)j * N;
@@ -937,7 +967,14 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = centerm(mulm(x[b], nj, qj, qij), qj, qij);
         const double q = T.qt[r].x, qi = T.qt[r].y;
-        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, [&](int i, double v) { gst(out)[i] = v; });
+        const auto st = [&](int i, double v) { gst(out)[i] = v; };
+        if constexpr (RK >= 2) {
+            if (hh >= 0) {
+                fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st, hh);
+                return;
+            }
+        }
+        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st);
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = gld(c)[i];
@@ -965,10 +1002,11 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
 // running three transforms against two 70 KB workgroups running two.)
 template <int LOGN, int RK = rk_of(LOGN)>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
-k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
+k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs, int split) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    const int row = blockIdx.x;
+    const int row = split ? blockIdx.x >> 1 : blockIdx.x;
+    const int hh = split ? (int)(blockIdx.x & 1) : -1;   // the half of the forward transform (split)
     const int iq = row % T.L;
     const int slot = row / T.L;
     const double *u = U + (size_t)slot * T.nExt * N;
@@ -985,8 +1023,14 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = mulm(centerm(mulm(x[b], cf, qp, qip), qp, qip), h, q, qi);
         const double *ui = u + (size_t)iq * N;
         double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
-        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x,
-                           [&](int i, double v) { gst(out)[i] = mulm(gld(ui)[i] - v, pinv, q, qi); });
+        const auto st = [&](int i, double v) { gst(out)[i] = mulm(gld(ui)[i] - v, pinv, q, qi); };
+        if constexpr (RK >= 2) {
+            if (hh >= 0) {
+                fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st, hh);
+                return;
+            }
+        }
+        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st);
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
@@ -1010,6 +1054,7 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
 }
 
 int g_radix = 0;   // radix exponent of 4096- and 8192-point rows (0: rk_of)
+int g_half_rows = 128; // fused chains of at most this many rows split their forward transforms in halves
 
 // Radix exponent the row kernels of 2^logn points run with.
 int row_rk(int logn) { return (logn == 12 || logn == 13) && g_radix ? g_radix : rk_of(logn); }
@@ -1087,6 +1132,8 @@ void kernels_init() {
 
 void ntt_set_split_rows(int rows) { g_split_rows = rows; }
 
+void ntt_set_half_rows(int rows) { g_half_rows = rows; }
+
 void ntt_set_radix(int radix) {
     if (radix != 0 && radix != 8 && radix != 16) throw std::invalid_argument("row radix must be 0, 8 or 16");
     g_radix = radix == 8 ? 3 : radix == 16 ? 4 : 0;
@@ -1150,20 +1197,30 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
 
 bool fused_ok(const DevTables &T) { return T.alpha == 1 && T.N <= 16384; }
 
+// Few-row chains (at most g_half_rows rows, one-workgroup rows only) run two
+// workgroups per row, each finishing half of the forward transform.
+bool half_split(const DevTables &T, int rows) {
+    return g_half_rows > 0 && rows <= g_half_rows && T.logN >= 10 && T.logN <= 14;
+}
+
 void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s) {
     if (nsrc <= 0) return;
+    const int rows = nsrc * T.beta * T.nExt;
+    const int split = half_split(T, rows) ? 1 : 0;
 #define HG_HF(LN, RK)                                                                                           \
-    hipLaunchKernelGGL((k_hoist_fused<LN, RK>), dim3(nsrc * T.beta * T.nExt), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
-                       s, T, y, srcs)
+    hipLaunchKernelGGL((k_hoist_fused<LN, RK>), dim3(rows << split), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
+                       s, T, y, srcs, split)
     HG_LOGN_RK_SWITCH(T.logN, HG_HF)
 #undef HG_HF
 }
 
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s, double *const *outs) {
     if (nslots <= 0) return;
+    const int rows = nslots * T.L;
+    const int split = half_split(T, rows) ? 1 : 0;
 #define HG_MF(LN, RK)                                                                                           \
-    hipLaunchKernelGGL((k_moddown_fused<LN, RK>), dim3(nslots * T.L), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, \
-                       T, E, U, outs)
+    hipLaunchKernelGGL((k_moddown_fused<LN, RK>), dim3(rows << split), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, \
+                       T, E, U, outs, split)
     HG_LOGN_RK_SWITCH(T.logN, HG_MF)
 #undef HG_MF
 }

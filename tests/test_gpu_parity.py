@@ -689,9 +689,10 @@ def test_execution_knobs_bit_identical():
     ref_batch = [o.export() for o in ctx.hegmm_batch(As, Bs, shapes)]
     settings = [{"pipeline": 2}, {"pipeline": 3, "fuse_rows": 0}, {"split_rows": 64, "fuse_rows": 0},
                 {"fuse_rows": 4096}, {"batch_window": 1}, {"ip_chunk": 16}, {"ip_chunk": 4, "batch_window": 0},
-                {"ip_order": 0}, {"ntt_radix": 16}, {"ntt_radix": 16, "fuse_rows": 0, "pipeline": 2}]
+                {"ip_order": 0}, {"ntt_radix": 16}, {"ntt_radix": 16, "fuse_rows": 0, "pipeline": 2},
+                {"half_rows": 0}, {"half_rows": 4096, "fuse_rows": 4096}, {"half_rows": 0, "ntt_radix": 16}]
     defaults = {"pipeline": 1, "fuse_rows": 256, "split_rows": 0, "batch_window": 64, "ip_chunk": 0, "ip_order": 1,
-                "ntt_radix": 0}
+                "ntt_radix": 0, "half_rows": 128}
     for st in settings:
         for k, v in st.items():
             ctx.tune(k, v)
