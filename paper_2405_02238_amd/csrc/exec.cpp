@@ -365,7 +365,11 @@ struct Exec {
             return;
         }
         double *rk = dv.rk + (size_t)j0 * 2 * alpha * N;
+        // few rows: each inverse row on two workgroups (input halves), its
+        // last stage done by the forward transform's load step
+        const int halves = ntt_halves_ok(T, nj * 2 * alpha) ? 1 : 0;
         NttArgs md;
+        md.halves = halves;
         md.out = rk;
         md.in = U;
         md.rows = nj * 2 * alpha;
@@ -376,6 +380,7 @@ struct Exec {
         md.in_offset = (long long)L * N;
         ntt_inv(T, STORE_MDR, md, s);
         NttArgs dl;
+        dl.halves = halves;
         dl.out = E;
         dl.in = rk;
         dl.aux = U;

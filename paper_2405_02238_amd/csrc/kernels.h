@@ -67,8 +67,8 @@ struct FinJob {
     int t0, nt;         // terms [t0, t0 + nt)
 };
 
-enum NttLoad { LOAD_PLAIN = 0, LOAD_MODUP = 1, LOAD_DELTA = 2 };
-enum NttStore { STORE_PLAIN = 0, STORE_MDR = 1, STORE_CANON = 2 };
+enum NttLoad { LOAD_PLAIN = 0, LOAD_MODUP = 1, LOAD_DELTA = 2, LOAD_DELTA_H = 3 };
+enum NttStore { STORE_PLAIN = 0, STORE_MDR = 1, STORE_CANON = 2, STORE_MDR_H = 3 };
 
 struct NttArgs {
     double *out = nullptr;
@@ -81,6 +81,11 @@ struct NttArgs {
     long long in_offset = 0;
     const double *const *in_tab = nullptr;  // LOAD_PLAIN / inverse: per-group source pointers (device)
     const double *aux = nullptr;            // LOAD_DELTA: U (the un-divided sums), slot stride nExt*N
+    // STORE_MDR with halves: two workgroups per row each run the first logN - 1
+    // stages on one input half and store them unscaled; the matching
+    // LOAD_DELTA (halves) applies the last stage and the centering while it
+    // loads (one special prime only; see ntt_halves_ok)
+    int halves = 0;
 };
 
 // Forward transform of `rows` rows (natural order in, bit-reversed out).
@@ -126,6 +131,10 @@ void ntt_set_radix(int radix);
 // applying its first stage (the inverse is done by both); 0: off, default
 // 128 (one workgroup per CU at most).  Results are the same either way.
 void ntt_set_half_rows(int rows);
+// Whether a division by P whose inverse has `rows` rows may use the halves
+// form of STORE_MDR / LOAD_DELTA (one special prime, one-workgroup rows, at
+// most half_rows rows, no split-row transforms).
+bool ntt_halves_ok(const DevTables &T, int rows);
 
 // Inner products: U[slot][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times

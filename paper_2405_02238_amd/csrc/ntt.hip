@@ -359,9 +359,13 @@ __device__ __forceinline__ void fwd_row_direct(double *sh, const double *__restr
 }
 
 // Full inverse rounds from half-size 2^LTS0 up to the last round.
-template <int LOGN, int RKX, int LTS0>
+// SG = 1, hb = h: the transform is the first LOGN stages of a 2^(LOGN + 1)-
+// point inverse on input half h (which they do not mix with the other
+// half); its group blk of 2^(LTS + K) elements is the row's group
+// (h << (LOGN - LTS - K)) + blk.
+template <int LOGN, int RKX, int LTS0, int SG = 0>
 __device__ __forceinline__ void inv_mid(double *sh, const double *__restrict__ tw, double q, double qi, int t,
-                                        const double *wcur) {
+                                        const double *wcur, int hb = 0) {
     using R = Rows<LOGN, RKX>;
     if constexpr (LTS0 < LOGN - R::RK) {
         constexpr int K = R::RK, TS = 1 << LTS0, L1 = LTS0 + K;
@@ -371,21 +375,24 @@ __device__ __forceinline__ void inv_mid(double *sh, const double *__restrict__ t
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
         double wnext[(1 << K) - 1];
-        if constexpr (L1 < LOGN - K) inv_tw<LOGN, L1, K>(wnext, tw, t >> L1);
-        inv_bfly<LOGN, LTS0, K>(x, wcur, q, qi);
+        if constexpr (L1 < LOGN - K)
+            inv_tw<LOGN + SG, L1, K>(wnext, tw, (hb << (LOGN - L1 - K)) + (t >> L1));
+        inv_bfly<LOGN + SG, LTS0, K>(x, wcur, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
         __syncthreads();
-        inv_mid<LOGN, RKX, L1>(sh, tw, q, qi, t, wnext);
+        inv_mid<LOGN, RKX, L1, SG>(sh, tw, q, qi, t, wnext, hb);
     }
 }
 
 // Inverse transform (without the N^-1 scaling) of the row read through
 // ld(i) (bit-reversed order); on return thread t holds output positions
-// t + b NT in x, |x| < q.  sh is scratch.
-template <int LOGN, int RKX, class Load>
+// t + b NT in x, |x| < 2q.  sh is scratch.  With SG = 1 the row is input
+// half hb of a twice longer row and the transform stops before that row's
+// last stage (see inv_mid).
+template <int LOGN, int RKX, int SG = 0, class Load>
 __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restrict__ tw, double q, double qi, Load ld,
-                                               double *x) {
+                                               double *x, int hb = 0) {
     using R = Rows<LOGN, RKX>;
     constexpr int K = R::RK, NT = R::NT, KT = R::KT;
     const int t = threadIdx.x;
@@ -393,22 +400,22 @@ __device__ __forceinline__ void inv_row_direct(double *sh, const double *__restr
     for (int g = 0; g < R::GPT; ++g) {
         const int grp = t + g * NT;
         double w[(1 << KT) - 1], y[1 << KT];
-        inv_tw<LOGN, 0, KT>(w, tw, grp);
+        inv_tw<LOGN + SG, 0, KT>(w, tw, (hb << (LOGN - KT)) + grp);
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) y[b] = ld((grp << KT) + b);
-        inv_bfly<LOGN, 0, KT>(y, w, q, qi);
+        inv_bfly<LOGN + SG, 0, KT>(y, w, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) sh[lds_ix((grp << KT) + b)] = y[b];
     }
     double w1[(1 << K) - 1];
-    if constexpr (KT < LOGN - K) inv_tw<LOGN, KT, K>(w1, tw, t >> KT);
+    if constexpr (KT < LOGN - K) inv_tw<LOGN + SG, KT, K>(w1, tw, (hb << (LOGN - KT - K)) + (t >> KT));
     __syncthreads();
-    inv_mid<LOGN, RKX, KT>(sh, tw, q, qi, t, w1);
+    inv_mid<LOGN, RKX, KT, SG>(sh, tw, q, qi, t, w1, hb);
     double w[(1 << K) - 1];
-    inv_tw<LOGN, LOGN - K, K>(w, tw, 0);
+    inv_tw<LOGN + SG, LOGN - K, K>(w, tw, hb);
 #pragma unroll
     for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<NT>(t, b)];
-    inv_bfly<LOGN, LOGN - K, K>(x, w, q, qi);
+    inv_bfly<LOGN + SG, LOGN - K, K>(x, w, q, qi);
 }
 
 // K forward stages [s0, s0 + K) of nsub independent 2^ls-point transforms
@@ -669,7 +676,7 @@ __device__ __forceinline__ FwdRow fwd_row(const DevTables &T, const NttArgs &a, 
         R.in = a.in + (size_t)src * a.in_stride;
         R.d0 = j * T.alpha;
         R.d1 = min(R.d0 + T.alpha, T.L);
-    } else if (LOAD == LOAD_DELTA) {
+    } else if (LOAD == LOAD_DELTA || LOAD == LOAD_DELTA_H) {
         const int i_q = row % T.L;
         const int slot = row / T.L;
         R.prime = i_q;
@@ -719,7 +726,7 @@ __device__ __forceinline__ double fwd_load(const DevTables &T, const FwdRow &R, 
 // Final store of position i (after the last stage).
 template <int LOAD>
 __device__ __forceinline__ void fwd_store(const DevTables &T, const FwdRow &R, int i, double v, double q, double qi) {
-    if (LOAD == LOAD_DELTA) {
+    if (LOAD == LOAD_DELTA || LOAD == LOAD_DELTA_H) {
         // E = (U - delta) * P^-1: the finished, divided output of the job
         gst(R.out)[i] = mulm(gld(R.aux)[i] - v, T.pinv[R.prime], q, qi);
     } else {
@@ -764,18 +771,40 @@ k_ntt_fwd(DevTables T, NttArgs a) {
     constexpr int N = 1 << LOGN;
     const FwdRow R = fwd_row<LOAD>(T, a, blockIdx.x);
     const double *tw = T.twf + (size_t)R.prime * N;
-    if constexpr (direct_rows<LOGN>()) {
+    if constexpr (LOAD == LOAD_DELTA_H) {
+        if constexpr (direct_rows<LOGN>()) {
+            // the r rows hold the two halves of the special prime's inverse
+            // before its last stage: apply that stage (pairs i, i + N/2), the
+            // scaling and centering of STORE_MDR, then the lift of LOAD_DELTA
+            using RW = Rows<LOGN, RK>;
+            constexpr int HALF = 1 << (RW::RK - 1);
+            const int pk = T.L;
+            const double qp = T.qt[pk].x, qip = T.qt[pk].y, wl = T.twi[(size_t)pk * N + 1];
+            const double cf = T.md_coef[0], hat = T.md_hat[R.prime];
+            const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+            double x[1 << RW::RK];
+#pragma unroll
+            for (int b = 0; b < HALF; ++b) {
+                const int i = (int)threadIdx.x + b * RW::NT;
+                const double A = gld(R.in)[i], B = gld(R.in)[i + N / 2];
+                const double s0 = redm(A + B, qp, qip), d0 = mulm(A - B, wl, qp, qip);
+                x[b] = mulm(centerm(mulm(s0, cf, qp, qip), qp, qip), hat, q, qi);
+                x[b + HALF] = mulm(centerm(mulm(d0, cf, qp, qip), qp, qip), hat, q, qi);
+            }
+            fwd_row_regs<LOGN, RK>(sh, tw, q, qi, x, [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
+        }
+    } else if constexpr (direct_rows<LOGN>()) {
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
         fwd_row_direct<LOGN, RK>(
             sh, tw, q, qi, [&](int i) { return fwd_load<LOAD>(T, R, i); },
             [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
-        return;
+    } else {
+        for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
+        __syncthreads();
+        const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+        fwd_rows_c<LOGN, 0>(sh, tw, q, qi);
+        for (int i = threadIdx.x; i < N; i += blockDim.x) fwd_store<LOAD>(T, R, i, sh[lds_ix(i)], q, qi);
     }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
-    __syncthreads();
-    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-    fwd_rows_c<LOGN, 0>(sh, tw, q, qi);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) fwd_store<LOAD>(T, R, i, sh[lds_ix(i)], q, qi);
 }
 
 template <int STORE, int LOGN, int RK = rk_of(LOGN)>
@@ -783,8 +812,24 @@ __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_p
 k_ntt_inv(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    const InvRow R = inv_row(T, a, blockIdx.x);
+    const InvRow R = inv_row(T, a, STORE == STORE_MDR_H ? blockIdx.x >> 1 : blockIdx.x);
     const double *tw = T.twi + (size_t)R.prime * N;
+    if constexpr (STORE == STORE_MDR_H) {
+        if constexpr (direct_rows<LOGN>() && RK >= 2) {
+            // input half hh through the first logN - 1 stages, stored as is
+            // (the consumer applies the last stage; see k_ntt_fwd)
+            using RH = Rows<LOGN - 1, RK - 1>;
+            const int hh = blockIdx.x & 1;
+            const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+            double x[1 << RH::RK];
+            inv_row_direct<LOGN - 1, RK - 1, 1>(
+                sh, tw, q, qi, [&](int i) { return gld(R.in)[(hh << (LOGN - 1)) + i]; }, x, hh);
+#pragma unroll
+            for (int b = 0; b < (1 << RH::RK); ++b)
+                gst(R.out)[(hh << (LOGN - 1)) + (int)threadIdx.x + b * RH::NT] = x[b];
+        }
+        return;
+    }
     if constexpr (direct_rows<LOGN>()) {
         using RW = Rows<LOGN, RK>;
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
@@ -939,15 +984,15 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
 // evaluation-form row j of the source's c1 is inverse-transformed, centered
 // (the digit lift of a one-prime digit) and forward-transformed under prime
 // r, all in LDS.  Row r = j is the source row itself.
-template <int LOGN, int RK = rk_of(LOGN)>
+template <int LOGN, int RK = rk_of(LOGN), int SPLIT = 0>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
-k_hoist_fused(DevTables T, double *y, const double *const *srcs, int split) {
+k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    // split: two workgroups per row, each finishing one half of the forward
+    // SPLIT: two workgroups per row, each finishing one half of the forward
     // transform (hh = the half)
-    const int row = split ? blockIdx.x >> 1 : blockIdx.x;
-    const int hh = split ? (int)(blockIdx.x & 1) : -1;
+    const int row = SPLIT ? blockIdx.x >> 1 : blockIdx.x;
+    const int hh = SPLIT ? (int)(blockIdx.x & 1) : -1;
     const int r = row % T.nExt;
     const int j = (row / T.nExt) % T.beta;
     const int src = row / (T.nExt * T.beta);
@@ -968,13 +1013,10 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs, int split) {
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = centerm(mulm(x[b], nj, qj, qij), qj, qij);
         const double q = T.qt[r].x, qi = T.qt[r].y;
         const auto st = [&](int i, double v) { gst(out)[i] = v; };
-        if constexpr (RK >= 2) {
-            if (hh >= 0) {
-                fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st, hh);
-                return;
-            }
-        }
-        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st);
+        if constexpr (SPLIT && RK >= 2)
+            fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st, hh);
+        else
+            fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st);
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = gld(c)[i];
@@ -1000,13 +1042,13 @@ k_hoist_fused(DevTables T, double *y, const double *const *srcs, int split) {
 // (Giving a workgroup several primes of a slot, to share the inverse
 // transform, was measured slower at 8192 points: one 135 KB workgroup per CU
 // running three transforms against two 70 KB workgroups running two.)
-template <int LOGN, int RK = rk_of(LOGN)>
+template <int LOGN, int RK = rk_of(LOGN), int SPLIT = 0>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
-k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs, int split) {
+k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    const int row = split ? blockIdx.x >> 1 : blockIdx.x;
-    const int hh = split ? (int)(blockIdx.x & 1) : -1;   // the half of the forward transform (split)
+    const int row = SPLIT ? blockIdx.x >> 1 : blockIdx.x;
+    const int hh = SPLIT ? (int)(blockIdx.x & 1) : -1;   // the half of the forward transform (SPLIT)
     const int iq = row % T.L;
     const int slot = row / T.L;
     const double *u = U + (size_t)slot * T.nExt * N;
@@ -1024,13 +1066,10 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs, in
         const double *ui = u + (size_t)iq * N;
         double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
         const auto st = [&](int i, double v) { gst(out)[i] = mulm(gld(ui)[i] - v, pinv, q, qi); };
-        if constexpr (RK >= 2) {
-            if (hh >= 0) {
-                fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st, hh);
-                return;
-            }
-        }
-        fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st);
+        if constexpr (SPLIT && RK >= 2)
+            fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st, hh);
+        else
+            fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st);
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
@@ -1116,8 +1155,12 @@ void set_lds_attrs() {
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_PLAIN, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_CANON, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA_H, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR_H, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 }  // namespace
@@ -1161,7 +1204,12 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) 
 #define HG_FWD(LN, RK)                                                                                        \
     switch (mode) {                                                                                          \
         case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd<LOAD_MODUP, LN, RK>), grid, block, lds, s, T, a); break; \
-        case LOAD_DELTA: hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA, LN, RK>), grid, block, lds, s, T, a); break; \
+        case LOAD_DELTA:                                                                                     \
+            if (a.halves)                                                                                    \
+                hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA_H, LN, RK>), grid, block, lds, s, T, a);            \
+            else                                                                                             \
+                hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA, LN, RK>), grid, block, lds, s, T, a);              \
+            break;                                                                                           \
         default: hipLaunchKernelGGL((k_ntt_fwd<LOAD_PLAIN, LN, RK>), grid, block, lds, s, T, a); break;         \
     }
     HG_LOGN_RK_SWITCH(T.logN, HG_FWD)
@@ -1184,10 +1232,15 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
-    dim3 grid(a.rows), block(ntt_threads(T.N));
+    dim3 grid(a.rows << (mode == STORE_MDR && a.halves ? 1 : 0)), block(ntt_threads(T.N));
 #define HG_INV(LN, RK)                                                                                          \
     switch (mode) {                                                                                            \
-        case STORE_MDR: hipLaunchKernelGGL((k_ntt_inv<STORE_MDR, LN, RK>), grid, block, lds, s, T, a); break;     \
+        case STORE_MDR:                                                                                        \
+            if (a.halves)                                                                                      \
+                hipLaunchKernelGGL((k_ntt_inv<STORE_MDR_H, LN, RK>), grid, block, lds, s, T, a);               \
+            else                                                                                               \
+                hipLaunchKernelGGL((k_ntt_inv<STORE_MDR, LN, RK>), grid, block, lds, s, T, a);                 \
+            break;                                                                                             \
         case STORE_CANON: hipLaunchKernelGGL((k_ntt_inv<STORE_CANON, LN, RK>), grid, block, lds, s, T, a); break; \
         default: hipLaunchKernelGGL((k_ntt_inv<STORE_PLAIN, LN, RK>), grid, block, lds, s, T, a); break;         \
     }
@@ -1199,8 +1252,12 @@ bool fused_ok(const DevTables &T) { return T.alpha == 1 && T.N <= 16384; }
 
 // Few-row chains (at most g_half_rows rows, one-workgroup rows only) run two
 // workgroups per row, each finishing half of the forward transform.
-bool half_split(const DevTables &T, int rows) {
+static bool half_split(const DevTables &T, int rows) {
     return g_half_rows > 0 && rows <= g_half_rows && T.logN >= 10 && T.logN <= 14;
+}
+
+bool ntt_halves_ok(const DevTables &T, int rows) {
+    return T.alpha == 1 && half_split(T, rows) && g_split_rows == 0;
 }
 
 void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s) {
@@ -1208,8 +1265,12 @@ void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int n
     const int rows = nsrc * T.beta * T.nExt;
     const int split = half_split(T, rows) ? 1 : 0;
 #define HG_HF(LN, RK)                                                                                           \
-    hipLaunchKernelGGL((k_hoist_fused<LN, RK>), dim3(rows << split), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
-                       s, T, y, srcs, split)
+    if (split)                                                                                                  \
+        hipLaunchKernelGGL((k_hoist_fused<LN, RK, 1>), dim3(rows << 1), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
+                           s, T, y, srcs);                                                                     \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_hoist_fused<LN, RK, 0>), dim3(rows), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, \
+                           y, srcs)
     HG_LOGN_RK_SWITCH(T.logN, HG_HF)
 #undef HG_HF
 }
@@ -1219,8 +1280,12 @@ void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, h
     const int rows = nslots * T.L;
     const int split = half_split(T, rows) ? 1 : 0;
 #define HG_MF(LN, RK)                                                                                           \
-    hipLaunchKernelGGL((k_moddown_fused<LN, RK>), dim3(rows << split), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, \
-                       T, E, U, outs, split)
+    if (split)                                                                                                  \
+        hipLaunchKernelGGL((k_moddown_fused<LN, RK, 1>), dim3(rows << 1), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
+                           s, T, E, U, outs);                                                                  \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_moddown_fused<LN, RK, 0>), dim3(rows), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, \
+                           T, E, U, outs)
     HG_LOGN_RK_SWITCH(T.logN, HG_MF)
 #undef HG_MF
 }
