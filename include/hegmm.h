@@ -336,9 +336,16 @@ hg_status hg_primes(hg_ctx *ctx, uint64_t *out);
  * the transform pass, and the number of those launches).  With pipelining
  * the inner-product and division phases overlap: out[1] ends with the last
  * inner-product launch and out[2] with the last division.  Only filled when
- * timing was enabled with hg_set_timing(ctx, 1); synchronises the stream. */
+ * timing was enabled with hg_set_timing(ctx, 1); synchronises the stream.
+ * hg_set_timing(ctx, 2) instead times only the transform-pass inner-product
+ * launches, with start / stop events carried by the dispatches themselves
+ * (no markers between kernels and no synchronisation per call), kept across
+ * calls until hg_launch_timing reads them: out[0] = mean duration in ms,
+ * out[1] = number of launches; it waits for them and starts a new tally.
+ * 0 turns timing off.  Errors: HG_EINVAL (mode outside 0..2). */
 hg_status hg_set_timing(hg_ctx *ctx, int enable);
 hg_status hg_last_timing(hg_ctx *ctx, double *out9);
+hg_status hg_launch_timing(hg_ctx *ctx, double *out2);
 
 const char *hg_last_error(void);
 

@@ -76,6 +76,7 @@ _SIGS = {
     "hg_set_timing": [_P, ctypes.c_int],
     "hg_tune": [_P, ctypes.c_char_p, ctypes.c_int64],
     "hg_last_timing": [_P, _f64p],
+    "hg_launch_timing": [_P, _f64p],
     "hg_request_footprint": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)],
     "hg_server_create": [_P, _P, _PP],
     "hg_server_submit": [_P, _u64p, ctypes.c_size_t, _u64p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
@@ -327,6 +328,16 @@ class Context:
 
     def set_timing(self, on: bool):
         _check(_lib.hg_set_timing(self.ptr, 1 if on else 0))
+
+    def set_launch_timing(self, on: bool):
+        """hg_set_timing mode 2: time the transform-pass inner-product launches
+        of the following calls, read with launch_timing()."""
+        _check(_lib.hg_set_timing(self.ptr, 2 if on else 0))
+
+    def launch_timing(self) -> dict:
+        out = np.zeros(2, dtype=np.float64)
+        _check(_lib.hg_launch_timing(self.ptr, out))
+        return {"ip_kernel": float(out[0]), "ip_launches": int(out[1])}
 
     def last_timing(self) -> dict:
         out = np.zeros(9, dtype=np.float64)

@@ -413,7 +413,31 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
 hg_status hg_set_timing(hg_ctx *ctx, int enable) {
     return guard([&] {
         need(ctx, "null context");
-        ctx->c->timing.enabled = enable != 0;
+        need(enable >= 0 && enable <= 2, "timing mode must be 0, 1 or 2");
+        ctx->c->timing.enabled = enable == 1;
+        ctx->c->launch_timing = enable == 2;
+    });
+}
+
+hg_status hg_launch_timing(hg_ctx *ctx, double *out2) {
+    return guard([&] {
+        need(ctx && out2, "null argument");
+        hg::Ctx &X = *ctx->c;
+        HGCHK(hipSetDevice(X.device));
+        double sum = 0;
+        for (auto &pr : X.lt_pairs) {
+            HGCHK(hipEventSynchronize(pr.second));
+            float ms = 0;
+            HGCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+            sum += ms;
+        }
+        out2[0] = X.lt_pairs.empty() ? 0.0 : sum / X.lt_pairs.size();
+        out2[1] = (double)X.lt_pairs.size();
+        for (auto &pr : X.lt_pairs) {
+            X.lt_free.push_back(pr.first);
+            X.lt_free.push_back(pr.second);
+        }
+        X.lt_pairs.clear();
     });
 }
 

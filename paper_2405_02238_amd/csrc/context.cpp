@@ -216,6 +216,11 @@ Ctx::~Ctx() {
             for (hipEvent_t e : ring) (void)hipEventDestroy(e);
         if (kv.second.side) (void)hipStreamDestroy(kv.second.side);
     }
+    for (auto &pr : lt_pairs) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (hipEvent_t e : lt_free) (void)hipEventDestroy(e);
     for (auto &kv : mask_cache) (void)hipFree(kv.second);
     for (auto &kv : rot_keys) (void)hipFree(kv.second);
     if (relin_key) (void)hipFree(relin_key);
@@ -252,6 +257,17 @@ hipEvent_t Ctx::event(hipStream_t st, bool timing) {
     }
     hipEvent_t e = ring[nx];
     nx = (nx + 1) % RING;
+    return e;
+}
+
+hipEvent_t Ctx::lt_event() {
+    if (!lt_free.empty()) {
+        hipEvent_t e = lt_free.back();
+        lt_free.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    HGCHK(hipEventCreate(&e));
     return e;
 }
 

@@ -72,6 +72,7 @@ struct Timing {
     bool enabled = false;
     double ms[9] = {0};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ip_pairs;   // transform-pass inner-product launches
+    bool pooled = false;   // ip_pairs take events from Ctx::lt_event (kept until read) instead of the ring
 };
 
 // Per user stream: the second stream of the pipelined passes and two rings
@@ -119,6 +120,14 @@ struct Ctx {
     bool capturing = false;
     Arena &arena_for(hipStream_t st);
     Timing timing;
+    // Launch timing (hg_set_timing mode 2): the transform-pass inner-product
+    // launches of every call record start / stop events carried by the
+    // dispatch itself, kept across calls without synchronising; read and
+    // recycled by hg_launch_timing.
+    bool launch_timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> lt_pairs;
+    std::vector<hipEvent_t> lt_free;
+    hipEvent_t lt_event();
     int min_blocks = 1;   // inner blocks of every plan at least this many (fixed at creation)
     // the caller's allocator for ciphertext handles (null: hipMalloc / hipFree)
     CtAllocFn ct_alloc_fn = nullptr;

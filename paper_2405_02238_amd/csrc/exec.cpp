@@ -437,8 +437,8 @@ struct Exec {
             for (size_t s = 0; s + 1 < dv.rounds.size(); ++s) {
                 hipEvent_t t0 = nullptr, t1 = nullptr;
                 if (tm) {
-                    t0 = C.event(st, true);
-                    t1 = C.event(st, true);
+                    t0 = tm->pooled ? C.lt_event() : C.event(st, true);
+                    t1 = tm->pooled ? C.lt_event() : C.event(st, true);
                 }
                 ip_keyed_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs, terms, chunks + dv.rounds[s],
                                 (const int2 *)(dv.tab + dv.t_tasks), dv.rounds[s + 1] - dv.rounds[s], s == 0,
@@ -460,8 +460,8 @@ struct Exec {
             const int j0 = (int)((long long)dv.nks * c / nch), j1 = (int)((long long)dv.nks * (c + 1) / nch);
             hipEvent_t t0 = nullptr, t1 = nullptr;
             if (tm) {
-                t0 = C.event(st, true);
-                t1 = C.event(st, true);
+                t0 = tm->pooled ? C.lt_event() : C.event(st, true);
+                t1 = tm->pooled ? C.lt_event() : C.event(st, true);
             }
             ip_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0, transform_pass, st, t0, t1);
             if (tm) tm->ip_pairs.push_back({t0, t1});
@@ -752,7 +752,11 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     }
     const Exec::Dev &dv = sp[i_main].dv;
     timing.ip_pairs.clear();
-    ex.launch(dv, timing.enabled ? ev : nullptr, true, timing.enabled ? &timing : nullptr);
+    Timing lt;
+    lt.pooled = true;
+    Timing *tm = timing.enabled ? &timing : launch_timing ? &lt : nullptr;
+    ex.launch(dv, timing.enabled ? ev : nullptr, true, tm);
+    if (tm == &lt) lt_pairs.insert(lt_pairs.end(), lt.ip_pairs.begin(), lt.ip_pairs.end());
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
                       (double *const *)(dv.extra + tensor_pairs.size() * sizeof(int2)), nacc, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
