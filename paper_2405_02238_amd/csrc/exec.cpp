@@ -496,8 +496,10 @@ struct Exec {
 Graph::Graph(Ctx &c, std::vector<Ctx::Request> &reqs) : C(&c) {
     HGCHK(hipSetDevice(c.device));
     HGCHK(hipStreamCreateWithFlags(&gs, hipStreamNonBlocking));
-    const bool timing = c.timing.enabled;
+    // neither timing mode applies to the recorded launches
+    const bool timing = c.timing.enabled, launch_timing = c.launch_timing;
     c.timing.enabled = false;
+    c.launch_timing = false;
     c.capture_arenas = &arenas;
     c.capture_next = 0;
     bool recording = false;
@@ -523,6 +525,7 @@ Graph::Graph(Ctx &c, std::vector<Ctx::Request> &reqs) : C(&c) {
         c.capturing = false;
         c.capture_arenas = nullptr;
         c.timing.enabled = timing;
+        c.launch_timing = launch_timing;
         (void)hipStreamSynchronize(gs);
         for (auto &a : arenas) a->release();
         (void)hipStreamDestroy(gs);
@@ -532,6 +535,7 @@ Graph::Graph(Ctx &c, std::vector<Ctx::Request> &reqs) : C(&c) {
     c.capturing = false;
     c.capture_arenas = nullptr;
     c.timing.enabled = timing;
+    c.launch_timing = launch_timing;
 }
 
 void Graph::launch(hipStream_t st) {

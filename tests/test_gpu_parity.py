@@ -702,3 +702,36 @@ def test_execution_knobs_bit_identical():
             assert np.array_equal(got[i].export(), ref_batch[i]), (st, s)
         for k in st:
             ctx.tune(k, defaults[k])
+
+
+def test_launch_timing_counts_and_bits(tiny):
+    """Launch timing (hg_set_timing mode 2) keeps one event pair per
+    transform-pass inner-product launch across calls, changes no bits, leaves
+    graph recording untimed, and starts a new tally once read."""
+    m, l, n = 4, 3, 5
+    A, B = workloads.tiny_operands()
+    ctx = tiny.ctx
+    ca, cb = ctx.encrypt(0, A, m, l, n, nonce=1), ctx.encrypt(1, B, m, l, n, nonce=1)
+    ref = ctx.hegmm(ca, cb, m, l, n).export()
+    ctx.set_timing(True)
+    ctx.hegmm(ca, cb, m, l, n)
+    per_call = int(ctx.last_timing()["ip_launches"])
+    ctx.set_timing(False)
+    assert per_call >= 1
+    ctx.set_launch_timing(True)
+    try:
+        outs = [ctx.hegmm(ca, cb, m, l, n) for _ in range(3)]
+        g = ctx.record_batch([ca], [cb], [(m, l, n)])
+        g.launch()
+        torch.cuda.synchronize()
+        lt = ctx.launch_timing()
+        again = ctx.launch_timing()
+    finally:
+        ctx.set_launch_timing(False)
+    # three eager calls; the graph's first (eager) pass is not timed either
+    assert lt["ip_launches"] == 3 * per_call
+    assert lt["ip_kernel"] > 0
+    assert again == {"ip_kernel": 0.0, "ip_launches": 0}
+    for o in outs + list(g.outputs):
+        assert np.array_equal(o.export(), ref)
+    g.close()
