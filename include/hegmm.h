@@ -342,6 +342,7 @@ hg_status hg_primes(hg_ctx *ctx, uint64_t *out);
  * (no markers between kernels and no synchronisation per call), kept across
  * calls until hg_launch_timing reads them: out[0] = mean duration in ms,
  * out[1] = number of launches; it waits for them and starts a new tally.
+ * At most 65536 launches are kept until read; later ones are not timed.
  * 0 turns timing off; launches recorded into a graph are never timed.
  * Errors: HG_EINVAL (mode outside 0..2). */
 hg_status hg_set_timing(hg_ctx *ctx, int enable);

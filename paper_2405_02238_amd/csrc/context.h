@@ -124,6 +124,8 @@ struct Ctx {
     // launches of every call record start / stop events carried by the
     // dispatch itself, kept across calls without synchronising; read and
     // recycled by hg_launch_timing.
+    // At most LT_MAX launches are kept until read; later ones go untimed.
+    static constexpr size_t LT_MAX = 1 << 16;
     bool launch_timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> lt_pairs;
     std::vector<hipEvent_t> lt_free;

@@ -758,7 +758,7 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     timing.ip_pairs.clear();
     Timing lt;
     lt.pooled = true;
-    Timing *tm = timing.enabled ? &timing : launch_timing ? &lt : nullptr;
+    Timing *tm = timing.enabled ? &timing : launch_timing && lt_pairs.size() < LT_MAX ? &lt : nullptr;
     ex.launch(dv, timing.enabled ? ev : nullptr, true, tm);
     if (tm == &lt) lt_pairs.insert(lt_pairs.end(), lt.ip_pairs.begin(), lt.ip_pairs.end());
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
