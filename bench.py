@@ -607,6 +607,28 @@ def main():
     ip_bytes = ip_kernel_bytes(ctx, info, cfg.N, cfg.L, cfg.alpha, nsrc=2, launches=launches)
     achieved = ip_bytes / (ip_ms * 1e-3) / 1e9
 
+    # informational: the same product from host buffers (canonical words of
+    # both operands loaded into their handles, the product, its words
+    # exported), i.e. with the PCIe transfers and the form conversions at the
+    # boundary
+    wa, wb = ca.export(), cb.export()
+    ha = ctx.encrypt(0, A, m, l, n, nonce=2)
+    hb = ctx.encrypt(1, B, m, l, n, nonce=2)
+
+    def from_host():
+        ctx.load_ct(ha, wa)
+        ctx.load_ct(hb, wb)
+        return ctx.hegmm(ha, hb, m, l, n).export()
+
+    for _ in range(2):
+        from_host()
+    host_steps = max(10, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(host_steps):
+        w = from_host()
+    host_ms = (time.perf_counter() - t0) * 1000.0 / host_steps
+    host_ok = bool(np.array_equal(w, ctx.hegmm(ca, cb, m, l, n).export()))
+
     # correctness of the timed results
     last = outs[-1]
     C = ctx.decrypt(last, m, l, n)
@@ -685,6 +707,9 @@ def main():
         "rotations_per_s_standalone": rot_standalone,
         "rotation_amounts": len(zs),
         "phase_ms": phases,
+        "host_buffers": {"value": 1000.0 / host_ms, "unit": "HE matmuls/s", "ms_per_step": host_ms,
+                         "bits_equal_resident": host_ok,
+                         "what": "operand words loaded from host memory, product, result words exported"},
         "roofline": {"kernel": "k_ip<4,0> (transform-pass key-switch inner products)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
