@@ -633,6 +633,21 @@ def main():
     host_ms = (time.perf_counter() - t0) * 1000.0 / host_steps
     host_ok = bool(np.array_equal(w, ctx.hegmm(ca, cb, m, l, n).export()))
 
+    # informational: the same product recorded once as a HIP graph and
+    # replayed (no host work per product; the output is rewritten each replay)
+    g = ctx.record_batch([ca], [cb], [(m, l, n)])
+    for _ in range(3):
+        g.launch()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        g.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = e0.elapsed_time(e1) / args.steps
+    graph_ok = bool(np.array_equal(g.outputs[0].export(), outs[-1].export()))
+    g.close()
+
     # correctness of the timed results
     last = outs[-1]
     C = ctx.decrypt(last, m, l, n)
@@ -711,6 +726,8 @@ def main():
         "rotations_per_s_standalone": rot_standalone,
         "rotation_amounts": len(zs),
         "phase_ms": phases,
+        "graph_replay": {"value": 1000.0 / graph_ms, "unit": "HE matmuls/s", "ms_per_step": graph_ms,
+                         "bits_equal_eager": graph_ok},
         "host_buffers": {"value": 1000.0 / host_ms, "unit": "HE matmuls/s", "ms_per_step": host_ms,
                          "bits_equal_resident": host_ok,
                          "what": "operand words loaded from host memory, product, result words exported"},
