@@ -282,8 +282,41 @@ def rot_sum(P: Params, ks: KeySet, ct: Ct, terms: Sequence[Tuple[int, Optional[M
 
 
 def rotate(P: Params, ks: KeySet, ct: Ct, z: int) -> Ct:
-    """HE-Rot(ct, z): left rotation of the row-0 slots by z (negative: right)."""
-    return rot_sum(P, ks, ct, [(z, None)])
+    """HE-Rot(ct, z) of Section II-A: left rotation of the row-0 slots by z
+    (negative: right).  With g = 5^(z mod S) mod 2N:
+
+      (phi_g(c0) + ModDown(u0), ModDown(u1)),  u = inner product of ModUp(phi_g(c1))
+                                                with the key for phi_g(s),
+
+    one division by P per rotation.  z = 0 (mod S) is the identity."""
+    assert len(ct) == 2
+    zz = z % P.S
+    if zz == 0:
+        return [c.copy() for c in ct]
+    g = P.galois(zz)
+    if g not in ks.rot:
+        raise KeyError(f"no rotation key for z={z} (g={g})")
+    c0, c1 = ct
+    u0, u1 = ks_inner(P, ring.automorph(c1, g, P.q_arr), ks.rot[g])
+    return [ring.add(ring.automorph(c0, g, P.q_arr), moddown_eval(P, u0), P.q_arr),
+            moddown_eval(P, u1)]
+
+
+def lin_transform(P: Params, ks: KeySet, ct: Ct, terms: Sequence[Tuple[int, Optional[Mask]]]) -> Ct:
+    """The diagonal method of Section III-B-1, Eq. (lintrans), in the paper's
+    own primitive order: for every nonzero diagonal z one complete HE-Rot
+    (its own division by P), then HE-CMult by the diagonal's mask u_z, then
+    HE-Add into the sum.  A term with mask None is added unmasked.
+
+    Decrypts to the same slots as rot_sum; the ciphertext bits differ, because
+    here each rotation is divided by P before its mask multiplies it."""
+    out = None
+    for z, mask in terms:
+        r = rotate(P, ks, ct, z)
+        if mask is not None:
+            r = he_cmult(P, r, mask)
+        out = r if out is None else he_add(P, out, r)
+    return out
 
 
 def relinearize(P: Params, ks: KeySet, ct: Ct) -> Ct:

@@ -402,7 +402,7 @@ def encrypt_operand(ks: bgv.KeySet, pl: Plan, role: int, A, B, nonce: int) -> Li
 
 
 def hegmm(ks: bgv.KeySet, pl: Plan, ctX: List[bgv.Ct], ctY: List[bgv.Ct],
-          masks: Optional[MaskCache] = None, eager: bool = False) -> bgv.Ct:
+          masks: Optional[MaskCache] = None, eager: bool = False, ks_order: int = 0) -> bgv.Ct:
     """Cloud side of Algorithm 2:  Acc = sum_{blocks, k < K} eps^k(ctX) x omega^k(ctY),
     one relinearisation, then the fold sum_h Rot(R, h*mo) that gathers the d
     row blocks (the extraction of Theorem 5's partial products).
@@ -411,23 +411,39 @@ def hegmm(ks: bgv.KeySet, pl: Plan, ctX: List[bgv.Ct], ctY: List[bgv.Ct],
     relinearisation, the HE-Mult of Section II-A) and sums the relinearised
     two-component ciphertexts; the default relinearises the three-component
     sum once.  Both decrypt to the same matrix; their bits differ (the key
-    switch lifts and rounds each input on its own)."""
+    switch lifts and rounds each input on its own).
+
+    ks_order selects how every linear transform (eps^k, omega^k, sigma, tau,
+    the fold) is composed:
+      0  rot_sum: the masked key-switching sums of a transform are divided by
+         P once (deferred division);
+      1  lin_transform: the paper's primitive order of Eq. (lintrans), one
+         complete HE-Rot per diagonal (its own division by P), then HE-CMult
+         by the mask, then HE-Add.
+    Both decrypt to the same matrix; their bits differ."""
     P = ks.P
     masks = masks or MaskCache(P)
+    if ks_order not in (0, 1):
+        raise ValueError("ks_order must be 0 or 1")
+    transform = bgv.lin_transform if ks_order == 1 else bgv.rot_sum
+
+    def terms(tms):
+        return [(z, None if s is None else masks.get(s)) for z, s in tms]
+
     if pl.method == 3:   # sigma and tau of Algorithm 1 on the ciphertexts (Theorems 1 and 2)
-        ctX = [bgv.rot_sum(P, ks, ctX[0], [(z, None if s is None else masks.get(s)) for z, s in pl.sigma])]
-        ctY = [bgv.rot_sum(P, ks, ctY[0], [(z, None if s is None else masks.get(s)) for z, s in pl.tau])]
+        ctX = [transform(P, ks, ctX[0], terms(pl.sigma))]
+        ctY = [transform(P, ks, ctY[0], terms(pl.tau))]
     acc = None
     for b in range(pl.nb):
         for k in range(pl.K):
-            e = bgv.rot_sum(P, ks, ctX[b], [(z, None if s is None else masks.get(s)) for z, s in pl.eps[k]])
-            f = bgv.rot_sum(P, ks, ctY[b], [(z, None if s is None else masks.get(s)) for z, s in pl.omega[k]])
+            e = transform(P, ks, ctX[b], terms(pl.eps[k]))
+            f = transform(P, ks, ctY[b], terms(pl.omega[k]))
             prod = bgv.he_mult(P, ks, e, f) if eager else bgv.tensor(P, e, f)
             acc = prod if acc is None else bgv.he_add(P, acc, prod)
     R = acc if eager else bgv.relinearize(P, ks, acc)
     if pl.d == 1:
         return R
-    return bgv.rot_sum(P, ks, R, [(z, None) for z in pl.fold])
+    return transform(P, ks, R, [(z, None) for z in pl.fold])
 
 
 def decrypt_result(ks: bgv.KeySet, pl: Plan, ct: bgv.Ct) -> np.ndarray:

@@ -132,12 +132,13 @@ class Params:
     descending order.
     """
 
-    def __init__(self, N: int, t: int, L: int, alpha: int):
+    def __init__(self, N: int, t: int, L: int, alpha: int, prime_bits: int = PRIME_BITS):
         assert N & (N - 1) == 0 and N >= 4
         assert (t - 1) % (2 * N) == 0 and is_prime(t)
         self.N, self.t, self.L, self.alpha = N, t, L, alpha
+        self.prime_bits = prime_bits
         self.S = N // 2
-        primes = ntt_primes(N, L + alpha)
+        primes = ntt_primes(N, L + alpha, prime_bits)
         self.p = primes[:alpha]
         self.q = primes[alpha:]
         self.ext = self.q + self.p

@@ -126,6 +126,44 @@ def test_masked_rot_sum(setup):
     assert bgv.decrypt_slots(ks, out) == want
 
 
+def test_rotate_is_the_one_term_rot_sum(setup):
+    """HE-Rot written out on its own (one division by P) and the deferred
+    rotation sum with a single unmasked term are the same computation: equal
+    bits, for rotated and unrotated terms."""
+    P, ks = setup
+    ct = bgv.encrypt_slots(ks, rand_slots(P, 41), nonce=12)
+    for z in (1, -3, 7, 0, P.S):
+        a = bgv.rotate(P, ks, ct, z)
+        b = bgv.rot_sum(P, ks, ct, [(z, None)])
+        assert all((x == y).all() for x, y in zip(a, b)), z
+
+
+def test_paper_order_lin_transform(setup):
+    """Eq. (lintrans) in the paper's primitive order (HE-Rot, HE-CMult, HE-Add
+    per diagonal) decrypts to the masked slot sum; the deferred division by P
+    gives the same plaintext with different bits.  The noise of the two orders
+    agrees within a quarter bit: in both it is dominated by the mask times the
+    input's own noise, and they differ only in where one rounding term of the
+    division by P enters."""
+    P, ks = setup
+    v = rand_slots(P, 42)
+    ct = bgv.encrypt_slots(ks, v, nonce=13)
+    m1 = [1 if s < P.S // 3 else 0 for s in range(P.S)]
+    m2 = [1 - x for x in m1]
+    terms = [(5, bgv.Mask(P, m1)), (-3, bgv.Mask(P, m2)), (0, bgv.Mask(P, m2))]
+    paper = bgv.lin_transform(P, ks, ct, terms)
+    deferred = bgv.rot_sum(P, ks, ct, terms)
+    want = [(m1[s] * v[(s + 5) % P.S] + m2[s] * v[(s - 3) % P.S] + m2[s] * v[s]) % P.t for s in range(P.S)]
+    assert bgv.decrypt_slots(ks, paper) == want
+    assert bgv.decrypt_slots(ks, deferred) == want
+    assert any((x != y).any() for x, y in zip(paper, deferred))
+    mu = ring.encode(P, want)
+    assert abs(bgv.noise_bits(ks, deferred, mu) - bgv.noise_bits(ks, paper, mu)) <= 0.25
+    # a transform of one unmasked diagonal is the rotation itself in both orders
+    one = bgv.lin_transform(P, ks, ct, [(7, None)])
+    assert all((x == y).all() for x, y in zip(one, bgv.rotate(P, ks, ct, 7)))
+
+
 def test_moddown_is_exact_division(setup):
     """out * P = u - delta with delta = 0 (mod t) and |delta| <= t * alpha * P / 2."""
     P, ks = setup

@@ -230,6 +230,53 @@ def test_encrypted_small_shapes_alpha2():
     run_encrypted(P, [(3, 7, 5), (7, 5, 3), (2, 9, 4)], 78)
 
 
+def _noise_and_bits(P, shapes, seed, min_blocks=1):
+    """Both transform orders on the same encrypted operands: per shape the
+    decryptions, the noise of each result and whether their bits differ."""
+    ks = bgv.KeySet(P, seed, H.galois_elements(P, shapes, min_blocks=min_blocks))
+    rng = np.random.default_rng(seed)
+    masks = H.MaskCache(P)
+    out = []
+    for idx, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        pl = H.plan(m, l, n, P.S, min_blocks=min_blocks)
+        cx = H.encrypt_operand(ks, pl, 0, A, B, nonce=idx)
+        cy = H.encrypt_operand(ks, pl, 1, A, B, nonce=idx)
+        want = workloads.plain_matmul_mod(A, B, P.t)
+        res = {}
+        for order in (0, 1):
+            C = H.hegmm(ks, pl, cx, cy, masks, ks_order=order)
+            assert (H.decrypt_result(ks, pl, C) == want).all(), ((m, l, n), order)
+            res[order] = (C, bgv.noise_bits(ks, C, bgv.decrypt_poly(ks, C)))
+        differ = any((x != y).any() for x, y in zip(res[0][0], res[1][0]))
+        out.append(((m, l, n), pl, res[0][1], res[1][1], differ))
+    return out
+
+
+@pytest.mark.parametrize("alpha", [1, 2])
+def test_paper_order_decrypts_like_deferred(alpha):
+    """HEGMM-En with every transform in the paper's primitive order (one
+    HE-Rot, HE-CMult, HE-Add per diagonal) and with the deferred division by P
+    decrypt to the same A.B mod t on fold (2x5x7), transposed (5x4x2),
+    inner-blocked (3x11x6) and square shapes, at alpha = 1 and alpha = 2.
+    Their noise agrees within a quarter bit (neither order is noisier; the
+    mask times the input noise dominates both), and products whose transforms
+    carry masks give different bits."""
+    P = Params(128, 12289, 3 + alpha - 1, alpha)
+    shapes = [(2, 5, 7), (5, 4, 2), (3, 11, 6), (4, 4, 4)]
+    cases = set()
+    for (m, l, n), pl, nb_def, nb_pap, differ in _noise_and_bits(P, shapes, 80 + alpha):
+        shape = (m, l, n)
+        assert abs(nb_def - nb_pap) <= 0.25, (shape, nb_def, nb_pap)
+        assert nb_pap < np.log2(float(P.Q)) - 2, shape
+        masked = any(s is not None for t in pl.eps + pl.omega for _, s in t)
+        assert differ == masked, shape
+        cases |= {c for c, on in (("fold", pl.d > 1), ("transposed", pl.transposed), ("blocked", pl.nb > 1),
+                                  ("square", m == l == n)) if on}
+    assert cases == {"fold", "transposed", "blocked", "square"}
+
+
 def test_tiny_config_end_to_end():
     cfg = workloads.TINY
     P = Params(cfg.N, cfg.t, cfg.L, cfg.alpha)

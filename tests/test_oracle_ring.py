@@ -82,16 +82,17 @@ def test_automorphism_is_substitution():
     assert [int(x) for x in got] == expect
 
 
-def test_primes_rule():
+@pytest.mark.parametrize("bits", [50, 40])
+def test_primes_rule(bits):
     for N, L, alpha in [(1024, 3, 1), (8192, 4, 1), (16384, 6, 2), (32768, 8, 2)]:
-        ps = ring.ntt_primes(N, L + alpha)
+        ps = ring.ntt_primes(N, L + alpha, bits)
         assert ps == sorted(ps, reverse=True)
         for p in ps:
-            assert p < 2 ** 50 and p % (2 * N) == 1
+            assert 2 ** (bits - 1) < p < 2 ** bits and p % (2 * N) == 1
             # an independent probable-prime check (Fermat, bases other than MR's)
             assert all(pow(b, p - 1, p) == 1 for b in (41, 43, 47, 53))
         # no skipped candidate above the first or between consecutive primes
-        for hi, lo in zip([2 ** 50] + ps, ps):
+        for hi, lo in zip([2 ** bits] + ps, ps):
             for c in range(lo + 2 * N, hi, 2 * N):
                 assert not all(pow(b, c - 1, c) == 1 for b in (2, 3, 5, 7))
 
