@@ -51,14 +51,17 @@ enum {
 typedef struct hg_ctx hg_ctx;  /* parameters, device tables, device-resident evaluation keys */
 typedef struct hg_ct hg_ct;    /* one packed operand/result: nb >= 1 ciphertexts on the device */
 
-/* BGV parameter set.  N: ring degree, a power of two in [64, 32768]
- * (rows longer than 16384 use two-pass transforms).
- * t: plaintext modulus, prime, t = 1 (mod 2N) so that all N/2 slots of a
- * rotation row are usable.  L: ciphertext primes (1..12).  alpha: special
- * primes, also the number of primes per key-switching digit (1..4, L+alpha
- * <= 16).  The primes are the first L+alpha primes below 2^50 that are
- * 1 (mod 2N), in descending order; the alpha largest are the special ones.
- * The error distribution is the discrete Gaussian of width 3.2 on [-19, 19]. */
+/* BGV parameter set over the ring Z_q[X]/(X^N + 1) of Section IV-A.
+ * N: ring degree, a power of two in [64, 32768] (rows longer than 16384 use
+ * two-pass transforms).  t: plaintext modulus, prime, t = 1 (mod 2N) so that
+ * all N/2 slots of a rotation row are usable.  L: ciphertext primes
+ * (1..12).  alpha: special primes, also the number of primes per
+ * key-switching digit (1..4, L+alpha <= 16).  The primes are the first
+ * L+alpha primes below 2^prime_bits that are 1 (mod 2N), in descending
+ * order; the alpha largest are the special ones.  The error distribution is
+ * the discrete Gaussian of width sigma on [-19, 19].  The paper fixes none of
+ * q, t, sigma or the key-switching method (its experiments used a library's
+ * defaults); zero-initialised trailing fields select the defaults. */
 typedef struct {
     uint32_t N;
     uint64_t t;
@@ -83,6 +86,20 @@ typedef struct {
                           switch per loop product instead of one per product, the same
                           decrypted result, different bits.  Either method.  HG_EINVAL
                           for other values. */
+    uint32_t ks_order; /* how a linear transform sum_z u_z (.) Rot(ct, z) (Eq. (lintrans),
+                          Section III-B-1: the eps/omega transforms, sigma / tau of method 3,
+                          the fold) is composed.  0: the masked key-switching sums of all its
+                          rotations are divided by the special modulus P once (the default,
+                          fewer transforms); 1: the paper's primitive order, each rotation a
+                          complete HE-Rot with its own division by P, then HE-CMult by its
+                          mask, then HE-Add.  Same decrypted result, different bits.
+                          HG_EINVAL for other values. */
+    uint32_t prime_bits; /* 0 (= 50) or 32..50: bit bound of the ciphertext and special
+                            primes.  The FP64 residue arithmetic needs primes below 2^50.
+                            HG_EINVAL outside that range. */
+    double sigma;      /* 0 (= 3.2) or 3.2: width of the discrete Gaussian error; the
+                          sampler's cumulative table is fixed for 3.2, other widths are
+                          HG_EINVAL. */
 } hg_params;
 
 /* Create a context on HIP device `hip_device` (must be gfx950).

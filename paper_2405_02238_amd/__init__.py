@@ -38,7 +38,8 @@ class _ServerConfig(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("t", ctypes.c_uint64), ("L", ctypes.c_uint32),
                 ("alpha", ctypes.c_uint32), ("method", ctypes.c_uint32), ("min_blocks", ctypes.c_uint32),
-                ("relin", ctypes.c_uint32)]
+                ("relin", ctypes.c_uint32), ("ks_order", ctypes.c_uint32), ("prime_bits", ctypes.c_uint32),
+                ("sigma", ctypes.c_double)]
 
 
 _lib = None
@@ -169,18 +170,22 @@ class Context:
     """hg_ctx: one BGV parameter set on one GPU."""
 
     def __init__(self, N: int, t: int, L: int, alpha: int, device: int = 0, method: int = 2, min_blocks: int = 1,
-                 relin: int = 0):
+                 relin: int = 0, ks_order: int = 0, prime_bits: int = 50, sigma: float = 3.2):
         """method 2: HEGMM-En (Algorithm 2); method 1: Algorithm 1, for comparison
         (method 3: Algorithm 1 with sigma / tau evaluated on the ciphertexts).
         min_blocks > 1 forces that many inner blocks per product; relin 1
-        relinearises every loop product on its own (eager; hg_params)."""
+        relinearises every loop product on its own (eager); ks_order 1 composes
+        every linear transform in the paper's HE-Rot, HE-CMult, HE-Add order
+        (one division by P per rotation); prime_bits bounds the primes; sigma
+        is the error width (hg_params)."""
         load()
-        p = _Params(N, t, L, alpha, method, min_blocks, relin)
+        p = _Params(N, t, L, alpha, method, min_blocks, relin, ks_order, prime_bits, sigma)
         out = ctypes.c_void_p()
         _check(_lib.hg_ctx_create(ctypes.byref(p), device, ctypes.byref(out)))
         self.ptr = out.value
         self.N, self.t, self.L, self.alpha, self.method, self.min_blocks = N, t, L, alpha, method, min_blocks
         self.relin = relin
+        self.ks_order, self.prime_bits = ks_order, prime_bits
         self.device = device
         self.S = N // 2
 

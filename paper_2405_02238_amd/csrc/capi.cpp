@@ -79,9 +79,14 @@ hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
         need(p->method <= 3, "method must be 0, 1, 2 or 3");
         need(p->min_blocks <= 1 || p->method == 0 || p->method == 2, "forced blocking needs HEGMM-En (method 2)");
         need(p->relin <= 1, "relin must be 0 (lazy) or 1 (eager)");
-        hg::Ctx *c = new hg::Ctx(p->N, p->t, p->L, p->alpha, dev, p->method == 0 ? 2 : (int)p->method);
+        need(p->ks_order <= 1, "ks_order must be 0 (one division by P per transform) or 1 (per rotation)");
+        need(p->prime_bits == 0 || (p->prime_bits >= 32 && p->prime_bits <= 50), "prime_bits must be 0 or in [32, 50]");
+        need(p->sigma == 0.0 || p->sigma == 3.2, "sigma must be 0 or 3.2 (the sampler's table is fixed for 3.2)");
+        hg::Ctx *c = new hg::Ctx(p->N, p->t, p->L, p->alpha, dev, p->method == 0 ? 2 : (int)p->method,
+                                 p->prime_bits ? (int)p->prime_bits : 50);
         c->min_blocks = p->min_blocks > 1 ? (int)p->min_blocks : 1;
         c->relin = (int)p->relin;
+        c->ks_order = (int)p->ks_order;
         hg_ctx *h = new hg_ctx;
         h->c = c;
         *out = h;
@@ -391,15 +396,22 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
         need(ctx && name, "null argument");
         need(value >= 0 && value < (1LL << 30), "value out of range");
         hg::Ctx &X = *ctx->c;
+        if (X.servers > 0) throw hg::Error(HG_ESTATE, "a server owns this context; tune it before hg_server_create");
         const std::string n(name);
+        // transform knobs live in the context's tables (and those of its
+        // modulus-switching divisions), so contexts do not share them
+        auto set_tables = [&](int hg::DevTables::*field, int v) {
+            X.T.*field = v;
+            for (auto &M : X.ms_tabs) M.*field = v;
+        };
         if (n == "fuse_rows") X.fuse_rows = (int)value;
         else if (n == "ip_chunk") X.ip_chunk = (int)value;
         else if (n == "ip_order") X.ip_order = (int)value;
-        else if (n == "split_rows") hg::ntt_set_split_rows((int)value);
-        else if (n == "half_rows") hg::ntt_set_half_rows((int)value);
+        else if (n == "split_rows") set_tables(&hg::DevTables::split_rows, (int)value);
+        else if (n == "half_rows") set_tables(&hg::DevTables::half_rows, (int)value);
         else if (n == "ntt_radix") {
             need(value == 0 || value == 8 || value == 16, "ntt_radix must be 0, 8 or 16");
-            hg::ntt_set_radix((int)value);
+            set_tables(&hg::DevTables::row_rk, hg::ntt_radix_rk((int)value));
         }
         else if (n == "batch_window") X.batch_window = (int)value;
         else if (n == "pipeline") {

@@ -74,7 +74,7 @@ void Ctx::ct_alloc(Ct *c, hipStream_t st) {
 // set-up
 // ---------------------------------------------------------------------------
 
-Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, int method_) {
+Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, int method_, int prime_bits_) {
     if (method_ < 1 || method_ > 3) throw Error(-1, "method must be 1, 2 or 3");
     method = method_;
     if (N_ < 64 || N_ > 32768 || (N_ & (N_ - 1))) throw Error(-1, "N must be a power of two in [64, 32768]");
@@ -82,6 +82,9 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, in
         throw Error(-1, "need 1 <= L <= 12, 1 <= alpha <= 4, L + alpha <= 16");
     if (t_ < 3 || t_ >= (1ULL << 30) || !is_prime_u64(t_) || (t_ - 1) % (2 * N_) != 0)
         throw Error(-1, "t must be a prime below 2^30 with t = 1 (mod 2N)");
+    // FP64 residues need q < 2^50 (arith.h); every prime must exceed t
+    if (prime_bits_ < 32 || prime_bits_ > 50) throw Error(-1, "prime_bits must be in [32, 50]");
+    prime_bits = prime_bits_;
     device = device_;
     HGCHK(hipSetDevice(device));
     hipDeviceProp_t prop;
@@ -98,7 +101,7 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, in
     S = N / 2;
     t = t_;
     zeta = smallest_neg_root(t, (uint64_t)N);
-    std::vector<uint64_t> pr = find_ntt_primes((uint64_t)N, L + alpha);
+    std::vector<uint64_t> pr = find_ntt_primes((uint64_t)N, L + alpha, prime_bits);
     if ((int)pr.size() != L + alpha) throw Error(-1, "not enough primes");
     // the alpha largest are the special primes; extended order q..., p...
     qs.assign(pr.begin() + alpha, pr.end());

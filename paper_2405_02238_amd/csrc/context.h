@@ -148,7 +148,13 @@ struct Ctx {
 
     int method = 2;        // 2: HEGMM-En; 1: the paper's Algorithm 1
     int relin = 0;         // 0: one relinearisation per product; 1: one per loop product (eager)
-    Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device, int method = 2);
+    // 0: a linear transform's masked key-switched terms are summed and divided
+    // by P once; 1: each rotation is divided by P on its own and masked after
+    // (the paper's HE-Rot, HE-CMult, HE-Add order)
+    int ks_order = 0;
+    int servers = 0;       // request loops (hg_server) that own this context now
+    int prime_bits = 50;   // ciphertext and special primes lie below 2^prime_bits
+    Ctx(uint32_t N, uint64_t t, uint32_t L, uint32_t alpha, int device, int method = 2, int prime_bits = 50);
     ~Ctx();
 
     double *dev_alloc(size_t words);

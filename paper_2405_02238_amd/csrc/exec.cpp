@@ -103,9 +103,40 @@ struct Exec {
         fj.nt = 0;
         fj.ks = -1;
         bool ks = relin_key != nullptr;
-        for (auto &tm : terms) ks |= C.galois_of(tm.first) != 1;
+        int nrot = 0;
+        for (auto &tm : terms) nrot += C.galois_of(tm.first) != 1;
+        ks |= nrot > 0;
+        // The paper's primitive order (ks_order 1): every rotated diagonal is
+        // one complete HE-Rot (its own key switch and division by P), then its
+        // mask (HE-CMult), then the sum (HE-Add).  A lone unmasked rotation is
+        // the same in both orders and stays one job.
+        const bool per_rotation =
+            C.ks_order == 1 && !relin_key && nrot > 0 && !(terms.size() == 1 && terms[0].second == nullptr);
         if (!ks) {
-            for (auto &tm : terms) ps.fin_terms.push_back({1, ps.mask_id(tm.second)});
+            for (auto &tm : terms) ps.fin_terms.push_back({1, ps.mask_id(tm.second), -1});
+            fj.nt = (int)ps.fin_terms.size() - fj.t0;
+        } else if (per_rotation) {
+            for (auto &tm : terms) {
+                const int g = C.galois_of(tm.first);
+                const int mid = ps.mask_id(tm.second);
+                if (g == 1) {
+                    ps.fin_terms.push_back({1, mid, -1});
+                    continue;
+                }
+                auto it = C.rot_keys.find(g);
+                if (it == C.rot_keys.end())
+                    throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
+                IpJob ij;
+                ij.c0 = fj.c0;
+                ij.c1 = fj.c1;
+                ij.src = src;
+                ij.t0 = (int)ps.ip_terms.size();
+                ij.nt = 1;
+                ij.slot = (int)ps.ip_jobs.size();
+                ps.ip_terms.push_back({g, -1, ps.key_id(it->second), IP_ROT});
+                ps.fin_terms.push_back({1, mid, ij.slot});
+                ps.ip_jobs.push_back(ij);
+            }
             fj.nt = (int)ps.fin_terms.size() - fj.t0;
         } else {
             IpJob ij;

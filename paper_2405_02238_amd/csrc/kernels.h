@@ -29,6 +29,10 @@ struct DevTables {
     double *pinv = nullptr;       // [L]: P^-1 mod q_i, centered
     double *pmod = nullptr;       // [L]: P mod q_i, centered
     double t = 0.0, tinv = 0.0;   // plaintext modulus and fl(1/t), by value
+    // Launch-shape knobs of the context's transforms (host side, bit-neutral):
+    int row_rk = 0;       // radix exponent of 4096- and 8192-point rows (3, 4; 0: built-in)
+    int half_rows = 128;  // fused chains of at most this many rows split their forward transforms in halves
+    int split_rows = 0;   // transforms of fewer rows split each row over N/1024 workgroups (0: only N > 16384)
 };
 
 // Terms of an inner-product job.  A job computes, over the extended basis,
@@ -54,10 +58,14 @@ struct IpJob {
                         // launch order of the jobs may differ)
 };
 
-// One term of a finishing job without key switching (the identity transforms).
+// One term of a finishing job: the job's own (c0, c1), or (ks >= 0) the
+// finished rotation E[ks] of a key-switched job, times the mask.  The
+// second form composes a transform in the primitive order of the diagonal
+// method: every rotation divided by P on its own, its mask applied after.
 struct FinTerm {
     int g;      // must be 1
     int mask;   // -1 = none
+    int ks;     // -1: the job's c0, c1; >= 0: the key-switch slot E[ks]
 };
 
 struct FinJob {
@@ -116,21 +124,20 @@ void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int n
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s,
                    double *const *outs = nullptr);
 
-// Row count below which a transform is split into a column pass and a block
-// pass of 1024-element workgroups (spreading each row over N/1024 CUs);
-// rows longer than 16384 always use the split form.
-void ntt_set_split_rows(int rows);
-
-// Radix of the row transforms of 4096- and 8192-point rows: 8 or 16, or 0
-// for the built-in choice (8); other lengths have one radix.  Results are
-// the same for every radix.  Throws std::invalid_argument for other values.
-void ntt_set_radix(int radix);
-
-// Fused chains (hoist_fused, moddown_fused) of at most this many rows run
-// two workgroups per row, each finishing half of the forward transform after
-// applying its first stage (the inverse is done by both); 0: off, default
-// 128 (one workgroup per CU at most).  Results are the same either way.
-void ntt_set_half_rows(int rows);
+// Knob values of DevTables::row_rk / half_rows / split_rows:
+//  - split_rows: transforms of fewer rows than this are split into a column
+//    pass and a block pass of 1024-element workgroups (spreading each row
+//    over N/1024 CUs); rows longer than 16384 always use the split form;
+//  - row_rk: radix exponent of the 4096- and 8192-point row transforms,
+//    3 (radix 8, the built-in choice) or 4 (radix 16); other lengths have
+//    one radix;
+//  - half_rows: fused chains (hoist_fused, moddown_fused) of at most this
+//    many rows run two workgroups per row, each finishing half of the forward
+//    transform after applying its first stage (the inverse is done by both);
+//    0: off, default 128 (one workgroup per CU at most).
+// Results are the same for every setting.  Returns the row_rk of a radix
+// (0, 8 or 16); throws std::invalid_argument for other values.
+int ntt_radix_rk(int radix);
 // Whether a division by P whose inverse has `rows` rows may use the halves
 // form of STORE_MDR / LOAD_DELTA (one special prime, one-workgroup rows, at
 // most half_rows rows, no split-row transforms).

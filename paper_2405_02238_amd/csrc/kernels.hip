@@ -59,6 +59,12 @@ __device__ __forceinline__ void st2(double *p, double2 v) {
     *gst((dvec2 *)p) = w;
 }
 
+// The digit sums of the inner products add BETA products of |x| < 0.875 q
+// (arith.h) before one reduction; with q < 2^50 that stays below 2^53, where
+// FP64 holds every integer exactly, for up to 9 terms.  Longer sums (BETA up
+// to 12) are reduced after every 8th term (then below q/2 + 1 + 7 q).
+#define IP_REDUCE_AFTER(j, BETA) ((BETA) > 9 && ((j) & 7) == 7 && (j) + 1 < (BETA))
+
 // Key-switching inner products with the automorphism folded into the gather
 // of the hoisted digits; two consecutive positions per thread (16-byte key
 // loads), the digit loop unrolled (BETA digits) so that all key loads of a
@@ -113,6 +119,12 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
                 s0y += mulm(y1[j], kbv[j].y, q, qi);
                 s1x += mulm(y0[j], kav[j].x, q, qi);
                 s1y += mulm(y1[j], kav[j].y, q, qi);
+                if (IP_REDUCE_AFTER(j, BETA)) {
+                    s0x = redm(s0x, q, qi);
+                    s0y = redm(s0y, q, qi);
+                    s1x = redm(s1x, q, qi);
+                    s1y = redm(s1y, q, qi);
+                }
             }
             s0x = redm(s0x, q, qi);
             s0y = redm(s0y, q, qi);
@@ -218,6 +230,12 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
             a0y += mulm(y1[j], kb[j].y, q, qi);
             a1x += mulm(y0[j], ka[j].x, q, qi);
             a1y += mulm(y1[j], ka[j].y, q, qi);
+            if (IP_REDUCE_AFTER(j, BETA)) {
+                a0x = redm(a0x, q, qi);
+                a0y = redm(a0y, q, qi);
+                a1x = redm(a1x, q, qi);
+                a1y = redm(a1y, q, qi);
+            }
         }
         a0x = redm(a0x, q, qi);
         a0y = redm(a0y, q, qi);
@@ -281,14 +299,15 @@ k_ip_keyed(DevTables T, double *U, const double *y, const double *const *keys, c
 }
 
 // One finished rotation sum at (prime i, position p): a key-switched job's
-// output sits in E; an identity job adds its (masked) c0, c1.
+// output sits in E; otherwise the job adds its terms, each its (c0, c1) or a
+// finished rotation E[ks], times the term's mask.
 __device__ __forceinline__ void finish_one(const DevTables &T, const FinJob &J, const FinTerm *terms,
                                            const double *E, const double *const *masks, int i, int p, double q,
                                            double qi, double &e0, double &e1) {
     const int N = 1 << T.logN;
     const size_t off = (size_t)i * N;
+    const size_t plane = (size_t)T.L * N;
     if (J.ks >= 0) {
-        const size_t plane = (size_t)T.L * N;
         const double *e = E + (size_t)J.ks * 2 * plane + off + p;
         e0 = e[0];
         e1 = e[plane];
@@ -298,7 +317,9 @@ __device__ __forceinline__ void finish_one(const DevTables &T, const FinJob &J, 
     e1 = 0.0;
     for (int t = J.t0; t < J.t0 + J.nt; ++t) {
         const FinTerm ft = terms[t];
-        double x0 = gld(J.c0)[off + p], x1 = gld(J.c1)[off + p];
+        const double *s0 = ft.ks >= 0 ? E + (size_t)ft.ks * 2 * plane : J.c0;
+        const double *s1 = ft.ks >= 0 ? s0 + plane : J.c1;
+        double x0 = gld(s0)[off + p], x1 = gld(s1)[off + p];
         if (ft.mask >= 0) {
             const double mv = gld(masks[ft.mask])[off + p];
             x0 = mulm(x0, mv, q, qi);
@@ -315,8 +336,8 @@ __device__ __forceinline__ void finish_two(const DevTables &T, const FinJob &J, 
                                            double qi, double2 &e0, double2 &e1) {
     const int N = 1 << T.logN;
     const size_t off = (size_t)i * N + p;
+    const size_t plane = (size_t)T.L * N;
     if (J.ks >= 0) {
-        const size_t plane = (size_t)T.L * N;
         const double *e = E + (size_t)J.ks * 2 * plane + off;
         e0 = *(const double2 *)e;
         e1 = *(const double2 *)(e + plane);
@@ -326,7 +347,9 @@ __device__ __forceinline__ void finish_two(const DevTables &T, const FinJob &J, 
     e1 = make_double2(0.0, 0.0);
     for (int t = J.t0; t < J.t0 + J.nt; ++t) {
         const FinTerm ft = terms[t];
-        double2 x0 = ld2(J.c0 + off), x1 = ld2(J.c1 + off);
+        const double *s0 = ft.ks >= 0 ? E + (size_t)ft.ks * 2 * plane : J.c0;
+        const double *s1 = ft.ks >= 0 ? s0 + plane : J.c1;
+        double2 x0 = ld2(s0 + off), x1 = ld2(s1 + off);
         if (ft.mask >= 0) {
             const double2 mv = ld2(masks[ft.mask] + off);
             x0 = make_double2(mulm(x0.x, mv.x, q, qi), mulm(x0.y, mv.y, q, qi));

@@ -1092,16 +1092,12 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) gst(out)[i] = mulm(gld(ui)[i] - sh[lds_ix(i)], pinv, q, qi);
 }
 
-int g_radix = 0;   // radix exponent of 4096- and 8192-point rows (0: rk_of)
-int g_half_rows = 128; // fused chains of at most this many rows split their forward transforms in halves
-
 // Radix exponent the row kernels of 2^logn points run with.
-int row_rk(int logn) { return (logn == 12 || logn == 13) && g_radix ? g_radix : rk_of(logn); }
+int row_rk(const DevTables &T, int logn) { return (logn == 12 || logn == 13) && T.row_rk ? T.row_rk : rk_of(logn); }
 
-int ntt_threads(int N) {
-    int logn = 0;
-    while ((1 << logn) < N) ++logn;
-    int t = N >> row_rk(logn);
+int ntt_threads(const DevTables &T) {
+    const int N = T.N;
+    int t = N >> row_rk(T, T.logN);
     if (t < 64) t = 64;
     if (t > NTT_THREADS_MAX) t = NTT_THREADS_MAX;
     return t;
@@ -1109,11 +1105,9 @@ int ntt_threads(int N) {
 
 size_t ntt_lds_bytes(int N) { return (size_t)(N + N / 16) * sizeof(double); }
 
-int g_split_rows = 0;     // row counts below this use the split transform (N >= 8192); 0: only N > 16384
-
 bool use_split(const DevTables &T, int rows) {
     if (T.N > 16384) return true;
-    return T.N >= 2 * SPLIT_ELEMS && rows < g_split_rows;
+    return T.N >= 2 * SPLIT_ELEMS && rows < T.split_rows;
 }
 
 // Dispatch on log2 N for the compile-time-size kernels.
@@ -1140,8 +1134,8 @@ bool use_split(const DevTables &T, int rows) {
         case 9: CALL(9, rk_of(9)); break;                            \
         case 10: CALL(10, rk_of(10)); break;                         \
         case 11: CALL(11, rk_of(11)); break;                         \
-        case 12: if (row_rk(12) == 4) { CALL(12, 4); } else { CALL(12, 3); } break; \
-        case 13: if (row_rk(13) == 4) { CALL(13, 4); } else { CALL(13, 3); } break; \
+        case 12: if (row_rk(T, 12) == 4) { CALL(12, 4); } else { CALL(12, 3); } break; \
+        case 13: if (row_rk(T, 13) == 4) { CALL(13, 4); } else { CALL(13, 3); } break; \
         case 14: CALL(14, rk_of(14)); break;                         \
         default: break;                                              \
     }
@@ -1173,13 +1167,9 @@ void kernels_init() {
     set_lds_attrs<13, 4>();
 }
 
-void ntt_set_split_rows(int rows) { g_split_rows = rows; }
-
-void ntt_set_half_rows(int rows) { g_half_rows = rows; }
-
-void ntt_set_radix(int radix) {
+int ntt_radix_rk(int radix) {
     if (radix != 0 && radix != 8 && radix != 16) throw std::invalid_argument("row radix must be 0, 8 or 16");
-    g_radix = radix == 8 ? 3 : radix == 16 ? 4 : 0;
+    return radix == 8 ? 3 : radix == 16 ? 4 : 0;
 }
 
 void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) {
@@ -1200,7 +1190,7 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) 
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
-    dim3 grid(a.rows), block(ntt_threads(T.N));
+    dim3 grid(a.rows), block(ntt_threads(T));
 #define HG_FWD(LN, RK)                                                                                        \
     switch (mode) {                                                                                          \
         case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd<LOAD_MODUP, LN, RK>), grid, block, lds, s, T, a); break; \
@@ -1232,7 +1222,7 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
-    dim3 grid(a.rows << (mode == STORE_MDR && a.halves ? 1 : 0)), block(ntt_threads(T.N));
+    dim3 grid(a.rows << (mode == STORE_MDR && a.halves ? 1 : 0)), block(ntt_threads(T));
 #define HG_INV(LN, RK)                                                                                          \
     switch (mode) {                                                                                            \
         case STORE_MDR:                                                                                        \
@@ -1250,14 +1240,14 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
 
 bool fused_ok(const DevTables &T) { return T.alpha == 1 && T.N <= 16384; }
 
-// Few-row chains (at most g_half_rows rows, one-workgroup rows only) run two
+// Few-row chains (at most T.half_rows rows, one-workgroup rows only) run two
 // workgroups per row, each finishing half of the forward transform.
 static bool half_split(const DevTables &T, int rows) {
-    return g_half_rows > 0 && rows <= g_half_rows && T.logN >= 10 && T.logN <= 14;
+    return T.half_rows > 0 && rows <= T.half_rows && T.logN >= 10 && T.logN <= 14;
 }
 
 bool ntt_halves_ok(const DevTables &T, int rows) {
-    return T.alpha == 1 && half_split(T, rows) && g_split_rows == 0;
+    return T.alpha == 1 && half_split(T, rows) && T.split_rows == 0;
 }
 
 void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s) {
@@ -1266,10 +1256,10 @@ void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int n
     const int split = half_split(T, rows) ? 1 : 0;
 #define HG_HF(LN, RK)                                                                                           \
     if (split)                                                                                                  \
-        hipLaunchKernelGGL((k_hoist_fused<LN, RK, 1>), dim3(rows << 1), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
+        hipLaunchKernelGGL((k_hoist_fused<LN, RK, 1>), dim3(rows << 1), dim3(ntt_threads(T)), ntt_lds_bytes(T.N), \
                            s, T, y, srcs);                                                                     \
     else                                                                                                        \
-        hipLaunchKernelGGL((k_hoist_fused<LN, RK, 0>), dim3(rows), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, T, \
+        hipLaunchKernelGGL((k_hoist_fused<LN, RK, 0>), dim3(rows), dim3(ntt_threads(T)), ntt_lds_bytes(T.N), s, T, \
                            y, srcs)
     HG_LOGN_RK_SWITCH(T.logN, HG_HF)
 #undef HG_HF
@@ -1281,10 +1271,10 @@ void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, h
     const int split = half_split(T, rows) ? 1 : 0;
 #define HG_MF(LN, RK)                                                                                           \
     if (split)                                                                                                  \
-        hipLaunchKernelGGL((k_moddown_fused<LN, RK, 1>), dim3(rows << 1), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), \
+        hipLaunchKernelGGL((k_moddown_fused<LN, RK, 1>), dim3(rows << 1), dim3(ntt_threads(T)), ntt_lds_bytes(T.N), \
                            s, T, E, U, outs);                                                                  \
     else                                                                                                        \
-        hipLaunchKernelGGL((k_moddown_fused<LN, RK, 0>), dim3(rows), dim3(ntt_threads(T.N)), ntt_lds_bytes(T.N), s, \
+        hipLaunchKernelGGL((k_moddown_fused<LN, RK, 0>), dim3(rows), dim3(ntt_threads(T)), ntt_lds_bytes(T.N), s, \
                            T, E, U, outs)
     HG_LOGN_RK_SWITCH(T.logN, HG_MF)
 #undef HG_MF

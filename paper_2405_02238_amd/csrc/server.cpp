@@ -43,6 +43,7 @@ Server::Server(Ctx &c, const ServerConfig &cf) : C(c), cfg(cf), lanes(cf.lanes) 
     }
     origin = std::chrono::steady_clock::now();
     th = std::thread([this] { loop(); });
+    ++C.servers;
 }
 
 Server::~Server() {
@@ -52,6 +53,7 @@ Server::~Server() {
     }
     cv_sub.notify_all();
     if (th.joinable()) th.join();
+    --C.servers;
     (void)hipSetDevice(C.device);
     for (auto &ln : lanes) {
         if (ln.st) (void)hipStreamSynchronize(ln.st);

@@ -26,11 +26,13 @@ def flat(ct):
 class Pair:
     """A library context and the oracle's key set for the same parameters and seed."""
 
-    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=(), min_blocks=1, relin=0):
-        self.P = Params(N, t, L, alpha)
+    def __init__(self, N, t, L, alpha, seed, shapes=(), zs=(), min_blocks=1, relin=0, ks_order=0, prime_bits=50):
+        self.P = Params(N, t, L, alpha, prime_bits=prime_bits)
         self.min_blocks = min_blocks
         self.relin = relin
-        self.ctx = hg.Context(N, t, L, alpha, min_blocks=min_blocks, relin=relin)
+        self.ks_order = ks_order
+        self.ctx = hg.Context(N, t, L, alpha, min_blocks=min_blocks, relin=relin, ks_order=ks_order,
+                              prime_bits=prime_bits)
         self.ctx.keygen(seed, shapes)
         if zs:
             self.ctx.keygen_rotations(zs)
@@ -106,7 +108,7 @@ def run_pair(pair, m, l, n, A, B, nonce):
     assert np.array_equal(right.export(), np.concatenate([flat(c) for c in oy]))
     cc = ctx.hegmm(ca, cb, m, l, n)
     got = cc.export()
-    want = flat(H.hegmm(ks, pl, ox, oy, pair.masks, eager=pair.relin == 1))
+    want = flat(H.hegmm(ks, pl, ox, oy, pair.masks, eager=pair.relin == 1, ks_order=pair.ks_order))
     assert np.array_equal(got, want), (m, l, n)
     C = ctx.decrypt(cc, m, l, n)
     assert np.array_equal(C, workloads.plain_matmul_mod(A, B, P.t))
@@ -288,6 +290,97 @@ def test_mod_switch_fresh_large_rings(cfg):
         sw = ctx.mod_switch(ct, drop)
         assert np.array_equal(sw.export(), flat(bgv.mod_switch(P, ref, drop))), drop
         assert np.array_equal(ctx.decrypt_slots(sw), v.astype(np.int64)), drop
+
+
+@pytest.mark.parametrize("alpha", [1, 2])
+def test_paper_order_shapes(alpha):
+    """Linear transforms in the paper's primitive order (ks_order 1: one
+    complete HE-Rot per diagonal, then HE-CMult, then HE-Add; Section III-B-1,
+    Eq. (lintrans)): bits equal the oracle's paper-order composition on the
+    C1 shape and the fold, transposed, blocked and square plans, and every
+    result decrypts to A.B mod t.  The deferred order gives other bits on
+    shapes with masked diagonals, the same decryption."""
+    c = workloads.TINY
+    L = c.L if alpha == 1 else 4
+    shapes = [(4, 3, 5), (2, 5, 7), (5, 4, 2), (3, 11, 6), (7, 7, 7)]
+    pair = Pair(c.N, c.t, L, alpha, c.seed + 7 * alpha, shapes=shapes, ks_order=1)
+    rng = np.random.default_rng(120 + alpha)
+    for i, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        run_pair(pair, m, l, n, A, B, nonce=50 + i)
+    m, l, n = shapes[0]
+    A, B = workloads.tiny_operands()
+    deferred = hg.Context(c.N, c.t, L, alpha)
+    deferred.keygen(c.seed + 7 * alpha, [(m, l, n)])
+    cd = deferred.hegmm(deferred.encrypt(0, A, m, l, n, nonce=1), deferred.encrypt(1, B, m, l, n, nonce=1), m, l, n)
+    cp = pair.ctx.hegmm(pair.ctx.encrypt(0, A, m, l, n, nonce=1), pair.ctx.encrypt(1, B, m, l, n, nonce=1), m, l, n)
+    assert not np.array_equal(cd.export(), cp.export())
+    assert np.array_equal(deferred.decrypt(cd, m, l, n), pair.ctx.decrypt(cp, m, l, n))
+
+
+def test_paper_order_variants():
+    """The paper's primitive order under eager relinearisation, forced inner
+    blocks, and Algorithm 1 with sigma / tau on the ciphertexts (method 3):
+    bits equal the oracle's, results decrypt to A.B mod t."""
+    c = workloads.TINY
+    rng = np.random.default_rng(131)
+    shapes = [(4, 3, 5), (2, 5, 7), (5, 4, 2)]
+    eager = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=shapes, relin=1, ks_order=1)
+    for i, (m, l, n) in enumerate(shapes):
+        run_pair(eager, m, l, n, rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n)), nonce=60 + i)
+    forced = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(5, 4, 2), (4, 3, 5)], min_blocks=2, ks_order=1)
+    for i, (m, l, n) in enumerate([(5, 4, 2), (4, 3, 5)]):
+        run_pair(forced, m, l, n, rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n)), nonce=70 + i)
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha, method=3, ks_order=1)
+    for i, (m, l, n) in enumerate([(3, 4, 5), (5, 3, 4)]):
+        ctx.keygen(c.seed, [(m, l, n)])
+        pl = H.plan(m, l, n, P.S, method=3)
+        ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [(m, l, n)], method=3))
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        cc = ctx.hegmm(ctx.encrypt(0, A, m, l, n, nonce=80 + i), ctx.encrypt(1, B, m, l, n, nonce=80 + i), m, l, n)
+        ox = H.encrypt_operand(ks, pl, 0, A, B, 80 + i)
+        oy = H.encrypt_operand(ks, pl, 1, A, B, 80 + i)
+        assert np.array_equal(cc.export(), flat(H.hegmm(ks, pl, ox, oy, ks_order=1))), (m, l, n)
+        assert np.array_equal(ctx.decrypt(cc, m, l, n), workloads.plain_matmul_mod(A, B, c.t))
+
+
+def test_paper_order_headline_full_size():
+    """64x32x48 at N = 8192 in the paper's primitive order (124 rotations,
+    each divided by P on its own, masks after): the whole output against the
+    oracle's paper-order composition."""
+    c = workloads.HEADLINE
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(64, 32, 48)], ks_order=1)
+    A, B = workloads.headline_operands()
+    run_pair(pair, 64, 32, 48, A, B, nonce=1)
+
+
+def test_prime_bits_honoured():
+    """Primes below 2^40 instead of 2^50 (hg_params.prime_bits): the library's
+    primes are the oracle's, and a product is bit-identical to the oracle's
+    with those primes."""
+    c = workloads.TINY
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=[(4, 3, 5), (2, 5, 7)], prime_bits=40)
+    assert pair.ctx.primes() == pair.P.ext
+    assert all(p < 2 ** 40 for p in pair.P.ext)
+    A, B = workloads.tiny_operands()
+    run_pair(pair, 4, 3, 5, A, B, nonce=1)
+    rng = np.random.default_rng(140)
+    run_pair(pair, 2, 5, 7, rng.integers(-8, 9, size=(2, 5)), rng.integers(-8, 9, size=(5, 7)), nonce=2)
+
+
+def test_hegmm_twelve_digits():
+    """L = 12 ciphertext primes with one-prime digits: the key-switch inner
+    products add 12 digit products, reduced after the 8th (the longest sums
+    the library builds); bits equal the oracle's, the result decrypts."""
+    c = workloads.TINY
+    pair = Pair(c.N, c.t, 12, 1, c.seed, shapes=[(4, 3, 5), (2, 5, 7)])
+    A, B = workloads.tiny_operands()
+    run_pair(pair, 4, 3, 5, A, B, nonce=1)
+    rng = np.random.default_rng(150)
+    run_pair(pair, 2, 5, 7, rng.integers(-8, 9, size=(2, 5)), rng.integers(-8, 9, size=(5, 7)), nonce=2)
 
 
 def test_hegmm_headline_full_size():
