@@ -157,6 +157,32 @@ hg_status hg_encrypt(hg_ctx *ctx, int role, const int64_t *X, int m, int l, int 
 hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n,
                    hg_ct **ctC, void *stream);
 
+/* hg_hegmm for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * product is the one hg_hegmm computes for the same operands, bit for bit,
+ * written into the caller's existing handle ctC, which must hold one
+ * two-component ciphertext at the full level (an earlier hg_hegmm result of
+ * any shape, or hg_ct_import(..., 1, 2, ...) of any valid words) and must not
+ * be one of the operands; its words are overwritten and it becomes the
+ * result of shape (m, l, n).  The call allocates nothing: every workspace
+ * (accumulators, hoisted digits, inner-product sums, the division by P,
+ * descriptor tables) lies in one fixed device array of
+ * HG_NOALLOC_SCRATCH_BYTES (96 MiB) that each GPU the library runs on holds
+ * from the library's first use there until the process ends, and the tables
+ * are staged through 1 MiB of pinned host memory that hg_ctx_create made for
+ * the context.  Nothing in the workspace needs to start at zero.  All calls
+ * on one GPU share that array (it keeps the last call's contents): calls
+ * that overlap on one GPU race -- from two streams, two threads or two
+ * contexts -- so order them on one stream.  Enqueued on `stream` like
+ * hg_hegmm; timing (hg_set_timing) and the "pipeline" knob do not apply.
+ * Errors: HG_EINVAL (as hg_hegmm, a result handle of the wrong form, or a
+ * product whose workspace exceeds the array or whose tables exceed the
+ * staging; nothing is enqueued then), HG_ESTATE (the shape was not listed in
+ * hg_keygen, so its plan and masks do not exist yet), HG_ENOKEY. */
+#define HG_NOALLOC_SCRATCH_BYTES (96ull << 20)
+hg_status hg_hegmm_noalloc(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n, hg_ct *ctC,
+                           void *stream);
+
 /* Many independent HE matmuls of (possibly) different shapes in one call.
  * mln holds cnt triples.  The products share the launches of each phase
  * (one hoisting launch, one key-switching launch, ...), and rotations that

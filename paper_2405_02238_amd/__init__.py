@@ -62,6 +62,7 @@ _SIGS = {
     "hg_encrypt": [_P, ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, _PP],
     "hg_hegmm": [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _PP, _P],
     "hg_hegmm_batch": [_P, ctypes.c_size_t, _PP, _PP, _i32p, _PP, _P],
+    "hg_hegmm_noalloc": [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P],
     "hg_decrypt": [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p],
     "hg_ct_export": [_P, _P, _P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)],
     "hg_ct_import": [_P, _u64p, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _PP],
@@ -252,6 +253,14 @@ class Context:
         s = current_stream() if stream is None else stream
         _check(_lib.hg_hegmm(self.ptr, A.ptr, B.ptr, m, l, n, ctypes.byref(out), s))
         return self._ct(out)
+
+    def hegmm_noalloc(self, A: Ciphertext, B: Ciphertext, m: int, l: int, n: int, out: Ciphertext,
+                      stream: Optional[int] = None) -> Ciphertext:
+        """hg_hegmm_noalloc: the product written into the existing handle `out`
+        with no device allocation (fixed per-GPU workspace); returns `out`."""
+        s = current_stream() if stream is None else stream
+        _check(_lib.hg_hegmm_noalloc(self.ptr, A.ptr, B.ptr, m, l, n, out.ptr, s))
+        return out
 
     def hegmm_batch(self, As: Sequence[Ciphertext], Bs: Sequence[Ciphertext], shapes, stream=None) -> List[Ciphertext]:
         cnt = len(As)

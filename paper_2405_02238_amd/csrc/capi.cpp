@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/hegmm.h"
@@ -56,6 +57,50 @@ hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Workspace of hg_hegmm_noalloc: one fixed device array per GPU, reserved
+// when the library's code object is loaded on that GPU and held until the
+// process ends.  In host code `scratch` names a host-side stand-in, not
+// device memory: its device address on the current GPU comes from
+// hipGetSymbolAddress, looked up once per device when a context is created
+// there, and only that address is handed to kernels.
+// ---------------------------------------------------------------------------
+#define HG_NOALLOC_TABLE_BYTES (1ull << 20)
+static __device__ __align__(256) unsigned char scratch[HG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;   // device -> its copy of `scratch`
+
+// The device address of `scratch` on `dev` (which must be current).
+char *scratch_on(int dev) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        throw hg::Error(HG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char *)ptr;
+    return (char *)ptr;
+}
+
+// Set up a context's fixed arena over the device's scratch, with its own
+// pinned staging for descriptor tables (made here, at creation, so that the
+// allocation-free entry point never allocates).
+void noalloc_setup(hg::Ctx &X) {
+    hg::Arena &a = X.noalloc_arena;
+    a.fixed_base = scratch_on(X.device);
+    a.fixed_bytes = HG_NOALLOC_SCRATCH_BYTES;
+    HGCHK(hipEventCreateWithFlags(&a.staged, hipEventDisableTiming));
+    HGCHK(hipHostMalloc(&a.pinned, HG_NOALLOC_TABLE_BYTES, hipHostMallocDefault));
+    HGCHK(hipHostGetDevicePointer(&a.pinned_dev, a.pinned, 0));
+    a.pinned_cap = HG_NOALLOC_TABLE_BYTES;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *hg_last_error(void) { return g_err.c_str(); }
@@ -87,6 +132,12 @@ hg_status hg_ctx_create(const hg_params *p, int dev, hg_ctx **out) {
         c->min_blocks = p->min_blocks > 1 ? (int)p->min_blocks : 1;
         c->relin = (int)p->relin;
         c->ks_order = (int)p->ks_order;
+        try {
+            noalloc_setup(*c);
+        } catch (...) {
+            delete c;
+            throw;
+        }
         hg_ctx *h = new hg_ctx;
         h->c = c;
         *out = h;
@@ -172,6 +223,51 @@ hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const h
     }
     for (size_t i = 0; i < cnt; ++i) C[i] = wrap(made[i]);
     return HG_OK;
+}
+
+hg_status hg_hegmm_noalloc(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n, hg_ct *ctC,
+                           void *stream) {
+    return guard([&] {
+        need(ctx && ctA && ctB && ctC, "null argument");
+        hg::Ctx &X = *ctx->c;
+        need(ctA->c->ctx == &X && ctB->c->ctx == &X && ctC->c->ctx == &X, "handle from another context");
+        need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
+        need(ctC != ctA && ctC != ctB && ctC->c->d != ctA->c->d && ctC->c->d != ctB->c->d,
+             "the result handle must not be an operand");
+        hg::Ct &R = *ctC->c;
+        need(R.ncts == 1 && R.comps == 2 && R.level == 0 && R.d,
+             "the result handle must hold one two-component ciphertext at the full level");
+        // a plan not made yet would allocate its masks: hg_keygen makes them
+        if (!X.plans.count(std::make_tuple(m, l, n)))
+            throw hg::Error(HG_ESTATE, "shape not prepared: list it in hg_keygen before hg_hegmm_noalloc");
+        HGCHK(hipSetDevice(X.device));
+        std::vector<hg::Ctx::Request> reqs{{ctA->c, ctB->c, m, l, n, &R}};
+        // neither timing mode (events, waits) nor the pipelined passes (a
+        // second stream) run here; the batch is one launch window
+        const bool timing = X.timing.enabled, lt = X.launch_timing;
+        const int pipeline = X.pipeline;
+        X.timing.enabled = false;
+        X.launch_timing = false;
+        X.pipeline = 1;
+        X.fixed_arena = &X.noalloc_arena;
+        try {
+            X.hegmm_batch_window(reqs, as_stream(stream));
+        } catch (...) {
+            X.fixed_arena = nullptr;
+            X.timing.enabled = timing;
+            X.launch_timing = lt;
+            X.pipeline = pipeline;
+            throw;
+        }
+        X.fixed_arena = nullptr;
+        X.timing.enabled = timing;
+        X.launch_timing = lt;
+        X.pipeline = pipeline;
+        R.m = m;
+        R.l = l;
+        R.n = n;
+        R.side = 2;
+    });
 }
 
 hg_status hg_graph_create(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const hg_ct *const *B, const int32_t *mln,

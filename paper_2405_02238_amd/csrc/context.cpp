@@ -214,6 +214,7 @@ Ctx::~Ctx() {
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
     for (auto &kv : arenas) kv.second.release();
+    noalloc_arena.release();
     for (auto &kv : aux) {
         for (auto &ring : kv.second.ev)
             for (hipEvent_t e : ring) (void)hipEventDestroy(e);
@@ -275,16 +276,19 @@ hipEvent_t Ctx::lt_event() {
 }
 
 void Arena::release() {
-    if (base) (void)hipFree(base);
+    if (!fixed_bytes) {
+        if (base) (void)hipFree(base);
+        if (acc) (void)hipFree(acc);
+    }
     if (pinned) (void)hipHostFree(pinned);
     if (staged) (void)hipEventDestroy(staged);
-    if (acc) (void)hipFree(acc);
     base = pinned = pinned_dev = acc = nullptr;
     staged = nullptr;
     cap = pinned_cap = acc_cap = 0;
 }
 
 Arena &Ctx::arena_for(hipStream_t st) {
+    if (fixed_arena) return *fixed_arena;
     if (!capture_arenas) return arena(st);
     auto &v = *capture_arenas;
     if (capture_next == v.size()) {

@@ -65,6 +65,13 @@ struct Arena {
     hipEvent_t staged = nullptr; // completion of the last copy out of `pinned`
     void *acc = nullptr;         // per-call accumulators (3 x L x N per product, R for folds)
     size_t acc_cap = 0;
+    // A fixed arena (fixed_bytes > 0) never grows: each call places its
+    // accumulators at fixed_base and its pass scratch right after them, and
+    // a call that needs more than fixed_bytes (or more descriptor-table
+    // staging than pinned_cap) fails before it enqueues anything.  Its device
+    // memory belongs to someone else and is not freed here.
+    char *fixed_base = nullptr;
+    size_t fixed_bytes = 0;
     void release();              // free everything (device must be idle)
 };
 
@@ -118,6 +125,10 @@ struct Ctx {
     std::vector<std::unique_ptr<Arena>> *capture_arenas = nullptr;
     size_t capture_next = 0;
     bool capturing = false;
+    // While set, every launch window uses this arena (the fixed workspace of
+    // the allocation-free entry point) instead of the stream's.
+    Arena *fixed_arena = nullptr;
+    Arena noalloc_arena;          // staging and device views of that workspace
     Arena &arena_for(hipStream_t st);
     Timing timing;
     // Launch timing (hg_set_timing mode 2): the transform-pass inner-product

@@ -80,6 +80,17 @@ struct Exec {
     // Accumulator space for this call (stream-ordered reuse of one buffer per
     // arena; grown with the stream drained, never while recording a graph).
     double *acc(size_t bytes) {
+        if (A.fixed_bytes) {
+            const size_t a = align_up(bytes, 256);
+            if (a > A.fixed_bytes)
+                throw Error(-1, "the product needs " + std::to_string(a) + " bytes of accumulators; the fixed "
+                                "workspace holds " + std::to_string(A.fixed_bytes));
+            A.acc = A.fixed_base;
+            A.acc_cap = a;
+            A.base = A.fixed_base + a;
+            A.cap = A.fixed_bytes - a;
+            return (double *)A.acc;
+        }
         if (bytes > A.acc_cap) {
             if (C.capturing) throw Error(-5, "graph recording needs a workspace the first pass did not make");
             HGCHK(hipStreamSynchronize(st));
@@ -299,6 +310,11 @@ struct Exec {
         }
         tl.add(256);   // never empty
         const size_t total = scratch + tl.total;
+        if (A.fixed_bytes && (total > A.cap || tl.total > A.pinned_cap))
+            throw Error(-1, "the product needs " + std::to_string(total + (A.fixed_bytes - A.cap)) +
+                                " bytes of workspace (" + std::to_string(tl.total) + " of descriptor tables); the "
+                                "fixed workspace holds " + std::to_string(A.fixed_bytes) + " (" +
+                                std::to_string(A.pinned_cap) + " of tables)");
         if ((total > A.cap || tl.total > A.pinned_cap) && C.capturing)
             throw Error(-5, "graph recording needs a workspace the first pass did not make");
         if (total > A.cap) {
