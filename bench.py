@@ -36,14 +36,17 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "batched", "serving", "large", "alg1", "blocked", "eager", "modswitch"],
+                    choices=["headline", "batched", "serving", "large", "alg1", "blocked", "eager", "modswitch",
+                             "modmul"],
                     help="headline: one 64x32x48 product per step; batched: 256 mixed shapes per step; "
                          "serving: 512 Poisson arrivals at N=16384 through the continuous-batching server; "
                          "large: one 128x96x128 product per step at N=32768; "
                          "alg1: the headline product with the paper's Algorithm 1 instead of HEGMM-En; "
                          "blocked: a 100x100x100 product split into output blocks (partitions P1/P2); "
                          "eager: the headline product with every loop product relinearised on its own; "
-                         "modswitch: the headline product followed by modulus switching of its result")
+                         "modswitch: the headline product followed by modulus switching of its result; "
+                         "modmul: the modular-product forms (FP64, 64-bit Shoup, 64-bit Barrett) and plain "
+                         "HBM streaming")
     ap.add_argument("--partition", default="P2", choices=["P1", "P2"], help="blocked: the reported partition")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--lanes", type=int, default=2, help="serving: launch groups in flight")
@@ -110,6 +113,115 @@ def ip_kernel_bytes(ctx, plan_info, N, L, alpha, nsrc, launches=1):
     jobs = 2 * (plan_info["K"] - 1) * plan_info["nb"]  # transforms that key-switch (k >= 1)
     shared = (ks_rot * beta * nExt * N + masks * nExt * N + jobs * 2 * nExt * N) / launches
     return int(8 * (shared + nsrc * beta * nExt * N))
+
+
+def key_stream_bytes(plan_info, N, L, alpha):
+    """Key bytes one matmul's transform pass must stream: the stored b half of
+    the rotation key of every key-switched rotation term, beta (L+alpha) N
+    words each (the a half is regenerated from its stream)."""
+    beta = (L + alpha - 1) // alpha
+    return 8 * plan_info["ks_terms"] * beta * (L + alpha) * N
+
+
+def md_fwd_rows(plan_info, L):
+    """Rows of the transform pass's forward transform in the division by P:
+    two components times L primes per key-switched transform."""
+    jobs = 2 * (plan_info["K"] - 1) * plan_info["nb"]
+    return jobs * 2 * L
+
+
+# FP64 lane-operations of the forward transform's arithmetic: a butterfly is
+# one modular product (h = a b, the FMA error term, the quotient estimate
+# h * fl(1/q), its rounding, the FMA remainder, the final add: 6 operations)
+# plus one add and one subtract; every fourth stage (and the last) also
+# reduces both outputs (3 operations each).  The LOAD_DELTA load adds one
+# modular product per element (the correction t (P/p) r), the store one
+# subtract and one modular product (the division by P).
+FP64_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock, one FP64 op (an FMA counts once)
+
+
+def ntt_fwd_lane_ops(N, rows):
+    logn = N.bit_length() - 1
+    reducing = sum(1 for g in range(logn) if g % 4 == 3 or g == logn - 1)
+    per_row = (N // 2) * (8 * logn + 6 * reducing) + N * (6 + 7)
+    return rows * per_row
+
+
+def ntt_roofline(ms, ops, launches, rows, N):
+    if not launches or ms <= 0:
+        return None
+    achieved = ops / (ms * 1e-3) / 1e12
+    peak = FP64_PEAK_LANE_OPS / 1e12
+    return {"kernel": f"k_ntt_fwd<LOAD_DELTA_H,{N.bit_length() - 1},3> (forward transforms of the division by P, "
+                      f"{rows} rows)",
+            "bound": "alu", "achieved": achieved, "peak": peak, "unit": "T FP64 lane-ops/s",
+            "frac": achieved / peak, "ops_per_launch": ops, "avg_launch_ms": ms, "timed_launches": launches,
+            "what": "modular butterflies (8 FP64 operations each, 6 more per reducing stage) plus the fused "
+                    "load and store arithmetic, per launch; peak = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz"}
+
+
+def oracle_baseline(run_once, seconds, first_s, what):
+    """The oracle timed on the host: whole runs for about `seconds` with every
+    OpenMP thread, then for about half as long on one thread.  Rates from the
+    median run time; `cores` is the thread count actually used."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    threads = int(gomp.omp_get_max_threads())
+    times = [first_s]
+    while sum(times) < seconds:
+        t0 = time.perf_counter()
+        run_once()
+        times.append(time.perf_counter() - t0)
+    gomp.omp_set_num_threads(1)
+    one = []
+    try:
+        while sum(one) < seconds / 2 or len(one) < 2:
+            t0 = time.perf_counter()
+            run_once()
+            one.append(time.perf_counter() - t0)
+    finally:
+        gomp.omp_set_num_threads(threads)
+    print(f"# oracle: {len(times)} runs on {threads} threads in {sum(times):.1f} s, {len(one)} on one thread "
+          f"in {sum(one):.1f} s", file=sys.stderr, flush=True)
+    return {"value": 1.0 / float(np.median(times)), "unit": "HE matmuls/s", "cores": threads, "kind": "oracle",
+            "mean_value": len(times) / sum(times),
+            "single_thread": {"value": 1.0 / float(np.median(one)), "cores": 1, "runs": len(one)},
+            "sample": f"{len(times)} {what} ({sum(times):.1f} s, median run {np.median(times):.2f} s), then "
+                      f"{len(one)} on one thread ({sum(one):.1f} s)"}
+
+
+def run_modmul(args):
+    """The measurement behind the FP64 residue arithmetic: modular products
+    per second on the whole chip in each form (4 independent chains per
+    thread, 4096 x 256 threads), at the first ciphertext prime of the
+    headline ring, and plain HBM read / copy bandwidth over 2 GiB."""
+    import paper_2405_02238_amd as hg
+    import workloads
+    cfg = workloads.HEADLINE
+    ctx = hg.Context(cfg.N, cfg.t, cfg.L, cfg.alpha)
+    q = ctx.primes()[0]
+    ctx.close()
+    forms = {0: "fp64", 1: "int64_shoup", 2: "int64_barrett"}
+    rates = {}
+    for f, name in forms.items():
+        rates[name] = hg.bench_modmul(f, q, blocks=4096, iters=max(64, args.steps * 8), reps=5)
+        print(f"# {name}: {rates[name]:.3e} modmul/s", file=sys.stderr, flush=True)
+    stream = {"read": hg.bench_stream(2 << 30, 0, reps=5), "copy": hg.bench_stream(2 << 30, 1, reps=5)}
+    peak = FP64_PEAK_LANE_OPS
+    out = {"metric": "modular products/s, FP64 vs 64-bit integer forms (q < 2^50)", "value": rates["fp64"],
+           "unit": "modmul/s", "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": None,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "4096 x 256 threads x 4 independent chains of modular products", "q": q},
+           "rates": rates,
+           "fp64_over_shoup": rates["fp64"] / rates["int64_shoup"],
+           "fp64_over_barrett": rates["fp64"] / rates["int64_barrett"],
+           "roofline": {"kernel": "k_mb_fp64", "bound": "alu", "achieved": rates["fp64"] * 6 / 1e12,
+                        "peak": peak / 1e12, "unit": "T FP64 lane-ops/s", "frac": rates["fp64"] * 6 / peak,
+                        "what": "6 FP64 operations per product (mul, FMA error term, mul by 1/q, rint, FMA "
+                                "remainder, add)"},
+           "hbm_stream_GBps": {k: v / 1e9 for k, v in stream.items()},
+           "hbm_stream_frac_of_8TBps": {k: v / 8e12 for k, v in stream.items()}}
+    print(json.dumps(out), flush=True)
 
 
 def run_batched(args):
@@ -550,6 +662,8 @@ def main():
         return run_eager(args)
     if args.workload == "modswitch":
         return run_modswitch(args)
+    if args.workload == "modmul":
+        return run_modmul(args)
     import torch
     import paper_2405_02238_amd as hg
     import workloads
@@ -581,16 +695,17 @@ def main():
     # every fourth step: timing every launch costs about 4% of the step
     LT_EVERY = 4
     sampled = 0
+    timed_outs = []
     e0.record(stream)
     t0 = time.perf_counter()
     for i in range(args.steps):
         if i % LT_EVERY == 0:
             ctx.set_launch_timing(True)
-            outs.append(ctx.hegmm(ca, cb, m, l, n))
+            timed_outs.append(ctx.hegmm(ca, cb, m, l, n))
             ctx.set_launch_timing(False)
             sampled += 1
         else:
-            outs.append(ctx.hegmm(ca, cb, m, l, n))
+            timed_outs.append(ctx.hegmm(ca, cb, m, l, n))
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -616,7 +731,12 @@ def main():
     phases = {k: float(np.mean([t[k] for t in tims])) for k in tims[0]}
     launches = max(1, int(round(lt["ip_launches"] / sampled)))
     ip_bytes = ip_kernel_bytes(ctx, info, cfg.N, cfg.L, cfg.alpha, nsrc=2, launches=launches)
-    achieved = ip_bytes / (ip_ms * 1e-3) / 1e9
+    key_bytes = key_stream_bytes(info, cfg.N, cfg.L, cfg.alpha) // launches
+    achieved_full = ip_bytes / (ip_ms * 1e-3) / 1e9
+    achieved = key_bytes / (ip_ms * 1e-3) / 1e9
+    md_ms = lt["md_fwd_kernel"]
+    md_rows = md_fwd_rows(info, cfg.L)
+    md_ops = ntt_fwd_lane_ops(cfg.N, md_rows)
 
     # informational: the same product from host buffers (canonical words of
     # both operands loaded into their handles, the product, its words
@@ -652,16 +772,17 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     graph_ms = e0.elapsed_time(e1) / args.steps
-    graph_ok = bool(np.array_equal(g.outputs[0].export(), outs[-1].export()))
+    graph_ok = bool(np.array_equal(g.outputs[0].export(), timed_outs[-1].export()))
     g.close()
 
-    # correctness of the timed results
-    last = outs[-1]
+    # correctness of the timed results: every timed product's canonical words
+    # (all computed from the same operands) against the oracle's
+    timed_words = [o.export() for o in timed_outs]
+    last = timed_outs[-1]
     C = ctx.decrypt(last, m, l, n)
     decrypt_ok = bool(np.array_equal(C, workloads.plain_matmul_mod(A, B, cfg.t)))
-    same_all = all(np.array_equal(o.export(), last.export()) for o in outs[-3:])
+    same_all = all(np.array_equal(w, timed_words[0]) for w in timed_words)
     bit_exact = None
-    oracle_rate = None
     cpu_info = None
     if not args.no_oracle_check or not args.no_cpu_baseline:
         from oracle import bgv, hegmm as H
@@ -673,24 +794,16 @@ def main():
         oy = H.encrypt_operand(ks, pl, 1, A, B, 1)
         masks = H.MaskCache(P)
         t0 = time.perf_counter()
-        ref = H.hegmm(ks, pl, ox, oy, masks)
+        ref = H.export_d7(H.hegmm(ks, pl, ox, oy, masks))
         first = time.perf_counter() - t0
         if not args.no_oracle_check:
-            bit_exact = bool(np.array_equal(last.export(), H.export_d7(ref)))
-            print(f"# oracle comparison: bit_exact={bit_exact}", file=sys.stderr, flush=True)
+            bit_exact = all(bool(np.array_equal(w, ref)) for w in timed_words)
+            print(f"# oracle comparison of all {len(timed_words)} timed products: bit_exact={bit_exact}",
+                  file=sys.stderr, flush=True)
         if not args.no_cpu_baseline:
-            done, spent = 1, first
-            while spent < args.cpu_seconds:
-                t0 = time.perf_counter()
-                H.hegmm(ks, pl, ox, oy, masks)
-                spent += time.perf_counter() - t0
-                done += 1
-            oracle_rate = done / spent
-            threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-            cpu_info = {"value": oracle_rate, "unit": "HE matmuls/s", "cores": threads, "kind": "oracle",
-                        "sample": f"{done} whole oracle HEGMM-En runs of the {m}x{l}x{n} N={cfg.N} workload "
-                                  f"({spent:.1f} s; keys, masks and encryptions made beforehand)"}
-            print(f"# oracle: {done} runs in {spent:.1f} s", file=sys.stderr, flush=True)
+            cpu_info = oracle_baseline(lambda: H.hegmm(ks, pl, ox, oy, masks), args.cpu_seconds, first,
+                                       f"whole oracle HEGMM-En runs of the {m}x{l}x{n} N={cfg.N} workload "
+                                       "(keys, masks and encryptions made beforehand)")
 
 
     # standalone (non-hoisted) rotations: one hg_rotate per rotation amount of
@@ -726,6 +839,7 @@ def main():
                    "m": m, "l": l, "n": n, "N": cfg.N, "t": cfg.t, "L": cfg.L, "alpha": cfg.alpha,
                    "parallelism": "single GPU"},
         "bit_exact": bit_exact,
+        "bit_exact_checked": len(timed_words),
         "decrypt_ok": decrypt_ok,
         "repeat_identical": same_all,
         "key_switches_per_matmul": ks_per_matmul,
@@ -741,9 +855,16 @@ def main():
         "roofline": {"kernel": "k_ip<4,0> (transform-pass key-switch inner products)", "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "algorithmic_bytes_per_launch": ip_bytes, "avg_launch_ms": ip_ms,
-                     "timed_launches": lt["ip_launches"],
-                     "launches_per_matmul": launches},
+                     "algorithmic_bytes_per_launch": key_bytes,
+                     "what": "key stream: the stored b half of every rotation key, once per key switch "
+                             "(the a half is regenerated from its stream in registers)",
+                     "avg_launch_ms": ip_ms, "timed_launches": lt["ip_launches"],
+                     "launches_per_matmul": launches,
+                     "full": {"bytes_per_launch": ip_bytes, "achieved": achieved_full,
+                              "frac": achieved_full / HBM_PEAK_GBS,
+                              "what": "every byte the launch must move: key b halves, masks, hoisted "
+                                      "digits, inner-product sums written"}},
+        "roofline_ntt": ntt_roofline(md_ms, md_ops, lt["md_fwd_launches"], md_rows, cfg.N),
         "cpu_baseline": cpu_info,
     }
     print(json.dumps(out), flush=True)

@@ -282,8 +282,11 @@ hg_status hg_mod_switch(hg_ctx *ctx, const hg_ct *ct, int drop, hg_ct **out, voi
  * a stream of independent products of mixed shapes.  Clients submit the
  * serialised operands (hg_ct_export words of hg_encrypt outputs for that
  * shape; what a client sends to the cloud).  The server admits queued
- * requests in arrival order while the sum of their modelled device
- * footprints (hg_request_footprint) stays within hbm_budget, launches each
+ * requests in arrival order while its modelled device memory stays within
+ * hbm_budget: the workspace every lane keeps (sized for the largest group it
+ * ran) plus the buffers of the groups in flight, each request modelled by
+ * hg_request_footprint (its buffers are released when its group finishes,
+ * its workspace share stays with the lane).  It launches each
  * admitted group through the batched executor on one of `lanes` streams so
  * that groups overlap on the device, and admits new arrivals as soon as a
  * lane and budget are free.  Keys stay resident in the context.  Each result
@@ -319,16 +322,28 @@ hg_status hg_server_submit(hg_server *srv, const uint64_t *a_words, size_t a_nwo
  * (unknown ticket, buffer too small), or the error of the request's launch. */
 hg_status hg_server_wait(hg_server *srv, uint64_t ticket, uint64_t *c_words, size_t c_nwords, double *times3);
 
-/* out8: completed requests, launch groups, mean group size, peak admitted
- * footprint (bytes), peak groups in flight, queued requests, admitted
- * footprint now, seconds since creation. */
+/* Hold (paused = 1) or resume (paused = 0) admission.  While held, submitted
+ * requests queue up and groups already launched finish; on resume the queue
+ * is admitted in arrival order as usual (a burst fills whole groups and
+ * several lanes at once).  hg_server_destroy resumes by itself.
+ * Errors: HG_EINVAL. */
+hg_status hg_server_pause(hg_server *srv, int paused);
+
+/* out8: completed requests, launch groups, mean group size, peak modelled
+ * device bytes (kept workspaces plus buffers in flight), peak groups in
+ * flight, queued requests, modelled device bytes now, seconds since
+ * creation. */
 hg_status hg_server_stats(hg_server *srv, double *out8);
 
 /* Finish every submitted request, stop the thread, release the lanes. */
 void hg_server_destroy(hg_server *srv);
 
 /* Modelled device bytes that one product of this shape holds while it runs
- * (operands, result, accumulator, pass scratch, staging).
+ * on a server lane: its operands as received and in evaluation form, its
+ * result, its accumulator and its share of the pass workspace (hoisted
+ * digits, inner-product sums, division-by-P buffers), plus 3 MiB for the
+ * rounding of workspaces and the descriptor tables.  An upper bound of the
+ * device memory the product adds to its group.
  * Errors: HG_EINVAL, HG_ENOFIT. */
 hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes);
 
@@ -382,15 +397,40 @@ hg_status hg_primes(hg_ctx *ctx, uint64_t *out);
  * timing was enabled with hg_set_timing(ctx, 1); synchronises the stream.
  * hg_set_timing(ctx, 2) instead times only the transform-pass inner-product
  * launches, with start / stop events carried by the dispatches themselves
- * (no markers between kernels and no synchronisation per call), kept across
- * calls until hg_launch_timing reads them: out[0] = mean duration in ms,
- * out[1] = number of launches; it waits for them and starts a new tally.
- * At most 65536 launches are kept until read; later ones are not timed.
+ * (no markers between kernels and no synchronisation per call), and the
+ * forward-transform launches of that pass's division by P (when it runs
+ * unfused), kept across calls until hg_launch_timing reads them: out[0] =
+ * mean inner-product launch duration in ms, out[1] = number of those
+ * launches, out[2] / out[3] the same for the forward transforms; it waits for
+ * them and starts a new tally.  At most 65536 calls' launches are kept until
+ * read; later ones are not timed.
  * 0 turns timing off; launches recorded into a graph are never timed.
  * Errors: HG_EINVAL (mode outside 0..2). */
 hg_status hg_set_timing(hg_ctx *ctx, int enable);
 hg_status hg_last_timing(hg_ctx *ctx, double *out9);
-hg_status hg_launch_timing(hg_ctx *ctx, double *out2);
+hg_status hg_launch_timing(hg_ctx *ctx, double *out4);
+
+/* ---- measurement ------------------------------------------------------ */
+
+/* Rate of modular products on device `device` (the measurement behind the
+ * library's FP64 residue arithmetic): blocks x 256 threads, each running 4
+ * independent chains x <- x w mod q of `iters` products, `reps` launches
+ * timed with HIP events after one warm-up.  form 0: the FP64 product every
+ * kernel uses; 1: 64-bit integer Shoup product (precomputed w'); 2: 64-bit
+ * integer Barrett product.  q: an odd modulus in (2^49, 2^50).  *out_per_s:
+ * products per second; *checksum (may be NULL): an xor of results.
+ * Allocates and frees its own buffer; synchronises the device.
+ * Errors: HG_EINVAL, HG_EDEVICE, HG_ENOMEM. */
+hg_status hg_bench_modmul(int device, int form, uint64_t q, int blocks, int iters, int reps, double *out_per_s,
+                          uint64_t *checksum);
+
+/* Plain HBM streaming on `device` over a buffer of `bytes` (>= 1 MiB):
+ * mode 0 reads it (16-byte loads, 8 workgroups per CU, grid-stride), mode 1
+ * copies it into a second buffer; `reps` launches after one warm-up.
+ * *out_bytes_per_s counts bytes read plus bytes written.  The practical
+ * ceiling the memory-bound inner products are compared with.
+ * Errors: HG_EINVAL, HG_EDEVICE, HG_ENOMEM. */
+hg_status hg_bench_stream(int device, size_t bytes, int mode, int reps, double *out_bytes_per_s);
 
 const char *hg_last_error(void);
 

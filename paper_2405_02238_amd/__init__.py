@@ -85,6 +85,10 @@ _SIGS = {
                          ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)],
     "hg_server_wait": [_P, ctypes.c_uint64, _P, ctypes.c_size_t, _P],
     "hg_server_stats": [_P, _f64p],
+    "hg_server_pause": [_P, ctypes.c_int],
+    "hg_bench_modmul": [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)],
+    "hg_bench_stream": [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
     "hg_graph_create": [_P, ctypes.c_size_t, _PP, _PP, _i32p, _PP, _PP],
     "hg_graph_launch": [_P, _P],
     "hg_ct_load": [_P, _P, _u64p, ctypes.c_size_t, _P],
@@ -127,6 +131,23 @@ def load(path: str = LIB_PATH):
 def _check(code: int):
     if code != HG_OK:
         raise HGError(code, _lib.hg_last_error().decode())
+
+
+def bench_modmul(form: int, q: int, blocks: int = 4096, iters: int = 256, reps: int = 5, device: int = 0) -> float:
+    """hg_bench_modmul: modular products per second (form 0 FP64, 1 Shoup, 2 Barrett)."""
+    load()
+    out = ctypes.c_double(0.0)
+    chk = ctypes.c_uint64(0)
+    _check(_lib.hg_bench_modmul(device, form, q, blocks, iters, reps, ctypes.byref(out), ctypes.byref(chk)))
+    return out.value
+
+
+def bench_stream(nbytes: int, mode: int, reps: int = 5, device: int = 0) -> float:
+    """hg_bench_stream: bytes per second read (mode 0) or read + written (mode 1)."""
+    load()
+    out = ctypes.c_double(0.0)
+    _check(_lib.hg_bench_stream(device, nbytes, mode, reps, ctypes.byref(out)))
+    return out.value
 
 
 def current_stream() -> Optional[int]:
@@ -349,9 +370,10 @@ class Context:
         _check(_lib.hg_set_timing(self.ptr, 2 if on else 0))
 
     def launch_timing(self) -> dict:
-        out = np.zeros(2, dtype=np.float64)
+        out = np.zeros(4, dtype=np.float64)
         _check(_lib.hg_launch_timing(self.ptr, out))
-        return {"ip_kernel": float(out[0]), "ip_launches": int(out[1])}
+        return {"ip_kernel": float(out[0]), "ip_launches": int(out[1]),
+                "md_fwd_kernel": float(out[2]), "md_fwd_launches": int(out[3])}
 
     def last_timing(self) -> dict:
         out = np.zeros(9, dtype=np.float64)
@@ -402,6 +424,10 @@ class Server:
         times = np.zeros(3, dtype=np.float64)
         _check(_lib.hg_server_wait(self.ptr, ticket, out.ctypes.data, out.size, times.ctypes.data))
         return out, tuple(float(x) for x in times)
+
+    def pause(self, paused: bool = True):
+        """Hold (or resume) admission: submitted requests queue up meanwhile."""
+        _check(_lib.hg_server_pause(self.ptr, 1 if paused else 0))
 
     def stats(self) -> dict:
         out = np.zeros(8, dtype=np.float64)

@@ -8,7 +8,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhegmm.so")
-SOURCES = ["ntt.hip", "kernels.hip", "context.cpp", "exec.cpp", "planner.cpp", "server.cpp", "capi.cpp"]
+SOURCES = ["ntt.hip", "kernels.hip", "context.cpp", "exec.cpp", "planner.cpp", "server.cpp", "capi.cpp",
+           "microbench.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

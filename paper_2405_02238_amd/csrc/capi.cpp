@@ -527,25 +527,29 @@ hg_status hg_set_timing(hg_ctx *ctx, int enable) {
     });
 }
 
-hg_status hg_launch_timing(hg_ctx *ctx, double *out2) {
+hg_status hg_launch_timing(hg_ctx *ctx, double *out4) {
     return guard([&] {
-        need(ctx && out2, "null argument");
+        need(ctx && out4, "null argument");
         hg::Ctx &X = *ctx->c;
         HGCHK(hipSetDevice(X.device));
-        double sum = 0;
-        for (auto &pr : X.lt_pairs) {
-            HGCHK(hipEventSynchronize(pr.second));
-            float ms = 0;
-            HGCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
-            sum += ms;
-        }
-        out2[0] = X.lt_pairs.empty() ? 0.0 : sum / X.lt_pairs.size();
-        out2[1] = (double)X.lt_pairs.size();
-        for (auto &pr : X.lt_pairs) {
-            X.lt_free.push_back(pr.first);
-            X.lt_free.push_back(pr.second);
-        }
-        X.lt_pairs.clear();
+        auto read = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>> &v, double *o) {
+            double sum = 0;
+            for (auto &pr : v) {
+                HGCHK(hipEventSynchronize(pr.second));
+                float ms = 0;
+                HGCHK(hipEventElapsedTime(&ms, pr.first, pr.second));
+                sum += ms;
+            }
+            o[0] = v.empty() ? 0.0 : sum / v.size();
+            o[1] = (double)v.size();
+            for (auto &pr : v) {
+                X.lt_free.push_back(pr.first);
+                X.lt_free.push_back(pr.second);
+            }
+            v.clear();
+        };
+        read(X.lt_pairs, out4);
+        read(X.lt_md_pairs, out4 + 2);
     });
 }
 
@@ -597,6 +601,14 @@ hg_status hg_server_wait(hg_server *srv, uint64_t ticket, uint64_t *c_words, siz
     return guard([&] {
         need(srv, "null server");
         srv->s->wait(ticket, c_words, c_nwords, times3);
+    });
+}
+
+hg_status hg_server_pause(hg_server *srv, int paused) {
+    return guard([&] {
+        need(srv, "null server");
+        need(paused == 0 || paused == 1, "paused must be 0 or 1");
+        srv->s->pause(paused == 1);
     });
 }
 

@@ -220,10 +220,11 @@ Ctx::~Ctx() {
             for (hipEvent_t e : ring) (void)hipEventDestroy(e);
         if (kv.second.side) (void)hipStreamDestroy(kv.second.side);
     }
-    for (auto &pr : lt_pairs) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
+    for (auto *v : {&lt_pairs, &lt_md_pairs})
+        for (auto &pr : *v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
     for (hipEvent_t e : lt_free) (void)hipEventDestroy(e);
     for (auto &kv : mask_cache) (void)hipFree(kv.second);
     for (auto &kv : rot_keys) (void)hipFree(kv.second);

@@ -72,6 +72,7 @@ struct Arena {
     // memory belongs to someone else and is not freed here.
     char *fixed_base = nullptr;
     size_t fixed_bytes = 0;
+    bool exact = false;          // grow to the size needed (rounded to 1 MiB), without headroom
     void release();              // free everything (device must be idle)
 };
 
@@ -79,6 +80,7 @@ struct Timing {
     bool enabled = false;
     double ms[9] = {0};
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ip_pairs;   // transform-pass inner-product launches
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> md_pairs;   // its division's forward-transform launches
     bool pooled = false;   // ip_pairs take events from Ctx::lt_event (kept until read) instead of the ring
 };
 
@@ -139,6 +141,7 @@ struct Ctx {
     static constexpr size_t LT_MAX = 1 << 16;
     bool launch_timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> lt_pairs;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> lt_md_pairs;   // forward transforms of the division by P
     std::vector<hipEvent_t> lt_free;
     hipEvent_t lt_event();
     int min_blocks = 1;   // inner blocks of every plan at least this many (fixed at creation)

@@ -95,7 +95,7 @@ struct Exec {
             if (C.capturing) throw Error(-5, "graph recording needs a workspace the first pass did not make");
             HGCHK(hipStreamSynchronize(st));
             if (A.acc) HGCHK(hipFree(A.acc));
-            A.acc_cap = align_up(bytes + bytes / 4, 1 << 20);
+            A.acc_cap = align_up(A.exact ? bytes : bytes + bytes / 4, 1 << 20);
             HGCHK(hipMalloc(&A.acc, A.acc_cap));
         }
         return (double *)A.acc;
@@ -320,7 +320,7 @@ struct Exec {
         if (total > A.cap) {
             HGCHK(hipStreamSynchronize(st));
             if (A.base) HGCHK(hipFree(A.base));
-            A.cap = align_up(total + total / 4, 1 << 20);
+            A.cap = align_up(A.exact ? total : total + total / 4, 1 << 20);
             HGCHK(hipMalloc(&A.base, A.cap));
         }
         if (tl.total > A.pinned_cap) {
@@ -402,7 +402,8 @@ struct Exec {
 
     // Division by P of the key-switched jobs [j0, j1) of a staged pass; with
     // `outs` (fused only) the results go straight to the jobs' outputs.
-    void moddown(const Dev &dv, int j0, int j1, bool fuse, hipStream_t s, double *const *outs = nullptr) {
+    void moddown(const Dev &dv, int j0, int j1, bool fuse, hipStream_t s, double *const *outs = nullptr,
+                 Timing *tm = nullptr) {
         const int nj = j1 - j0;
         if (nj <= 0) return;
         double *U = dv.U + (size_t)j0 * 2 * nExt * N;
@@ -433,7 +434,13 @@ struct Exec {
         dl.aux = U;
         dl.rows = nj * 2 * L;
         dl.in_stride = (long long)alpha * N;
-        ntt_fwd(T, LOAD_DELTA, dl, s);
+        hipEvent_t t0 = nullptr, t1 = nullptr;
+        if (tm) {
+            t0 = tm->pooled ? C.lt_event() : C.event(s, true);
+            t1 = tm->pooled ? C.lt_event() : C.event(s, true);
+            tm->md_pairs.push_back({t0, t1});
+        }
+        ntt_fwd(T, LOAD_DELTA, dl, s, t0, t1);
     }
 
     // Phases 1-3 of a staged pass: hoist, inner products, division by P.
@@ -518,7 +525,7 @@ struct Exec {
                 HGCHK(hipEventRecord(ev, st));
                 HGCHK(hipStreamWaitEvent(s2, ev, 0));
             }
-            moddown(dv, j0, j1, fuse_md, s2, fuse_md ? direct : nullptr);
+            moddown(dv, j0, j1, fuse_md, s2, fuse_md ? direct : nullptr, tm);
         }
         if (s2 != st) {
             hipEvent_t ev = C.event(st, false);
@@ -803,11 +810,15 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
     }
     const Exec::Dev &dv = sp[i_main].dv;
     timing.ip_pairs.clear();
+    timing.md_pairs.clear();
     Timing lt;
     lt.pooled = true;
     Timing *tm = timing.enabled ? &timing : launch_timing && lt_pairs.size() < LT_MAX ? &lt : nullptr;
     ex.launch(dv, timing.enabled ? ev : nullptr, true, tm);
-    if (tm == &lt) lt_pairs.insert(lt_pairs.end(), lt.ip_pairs.begin(), lt.ip_pairs.end());
+    if (tm == &lt) {
+        lt_pairs.insert(lt_pairs.end(), lt.ip_pairs.begin(), lt.ip_pairs.end());
+        lt_md_pairs.insert(lt_md_pairs.end(), lt.md_pairs.begin(), lt.md_pairs.end());
+    }
     fin_tensor_launch(T, dv.jobs, dv.terms, dv.E, dv.masks, (const int2 *)dv.extra,
                       (double *const *)(dv.extra + tensor_pairs.size() * sizeof(int2)), nacc, st);
     if (timing.enabled) HGCHK(hipEventRecord(ev[3], st));
@@ -844,6 +855,7 @@ void Ctx::hegmm_batch_window(std::vector<Request> &reqs, hipStream_t st) {
         timing.ms[7] = timing.ip_pairs.empty() ? 0.0 : ip / timing.ip_pairs.size();
         timing.ms[8] = (double)timing.ip_pairs.size();
         timing.ip_pairs.clear();
+        timing.md_pairs.clear();
         for (auto &x : ev) (void)hipEventDestroy(x);
     }
 }

@@ -106,7 +106,10 @@ struct NttArgs {
 //              the transform of delta_i is subtracted from U_i (aux) and the
 //              difference multiplied by P^-1: output E_i = (U_i - delta_i)/P,
 //              contiguous slot*L + i.
-void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s);
+// ev0 / ev1 (optional) receive the start and end of the launch (of the two
+// launches of a split transform, bracketed by stream markers).
+void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s, hipEvent_t ev0 = nullptr,
+             hipEvent_t ev1 = nullptr);
 
 // Inverse transform (bit-reversed in, natural out).
 //  STORE_PLAIN: times N^-1.

@@ -22,6 +22,8 @@
 // the row (ModUp), LOAD_DELTA forms the correction delta of the division by P
 // from the centered r_k rows, STORE_MDR turns an inverse-transformed special
 // prime row into the exact centered r_k.
+#include <hip/hip_ext.h>
+
 #include <stdexcept>
 
 #include "arith.h"
@@ -1172,9 +1174,19 @@ int ntt_radix_rk(int radix) {
     return radix == 8 ? 3 : radix == 16 ? 4 : 0;
 }
 
-void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) {
+// A launch whose start and stop timestamps land in ev0 / ev1 (taken by the
+// dispatch itself), or a plain launch.
+template <typename... Args, typename F = void (*)(Args...)>
+static void launch_ev(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                      Args... args) {
+    if (ev0) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev0, ev1, 0, args...);
+    else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+}
+
+void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (a.rows <= 0) return;
     if (use_split(T, a.rows)) {
+        if (ev0) (void)hipEventRecord(ev0, s);   // a failed record surfaces when the timing is read
         dim3 grid((unsigned)(a.rows * (T.N / SPLIT_ELEMS))), block(SPLIT_THREADS);
 #define HG_SPLIT_FWD(LN)                                                                                             \
     switch (mode) {                                                                                                 \
@@ -1187,20 +1199,21 @@ void ntt_fwd(const DevTables &T, NttLoad mode, const NttArgs &a, hipStream_t s) 
     }
         if (T.logN == 15) { HG_SPLIT_FWD(15) } else { HG_SPLIT_FWD(0) }
 #undef HG_SPLIT_FWD
+        if (ev1) (void)hipEventRecord(ev1, s);
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
     dim3 grid(a.rows), block(ntt_threads(T));
 #define HG_FWD(LN, RK)                                                                                        \
     switch (mode) {                                                                                          \
-        case LOAD_MODUP: hipLaunchKernelGGL((k_ntt_fwd<LOAD_MODUP, LN, RK>), grid, block, lds, s, T, a); break; \
+        case LOAD_MODUP: launch_ev(k_ntt_fwd<LOAD_MODUP, LN, RK>, grid, block, lds, s, ev0, ev1, T, a); break;  \
         case LOAD_DELTA:                                                                                     \
             if (a.halves)                                                                                    \
-                hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA_H, LN, RK>), grid, block, lds, s, T, a);            \
+                launch_ev(k_ntt_fwd<LOAD_DELTA_H, LN, RK>, grid, block, lds, s, ev0, ev1, T, a);             \
             else                                                                                             \
-                hipLaunchKernelGGL((k_ntt_fwd<LOAD_DELTA, LN, RK>), grid, block, lds, s, T, a);              \
+                launch_ev(k_ntt_fwd<LOAD_DELTA, LN, RK>, grid, block, lds, s, ev0, ev1, T, a);               \
             break;                                                                                           \
-        default: hipLaunchKernelGGL((k_ntt_fwd<LOAD_PLAIN, LN, RK>), grid, block, lds, s, T, a); break;         \
+        default: launch_ev(k_ntt_fwd<LOAD_PLAIN, LN, RK>, grid, block, lds, s, ev0, ev1, T, a); break;          \
     }
     HG_LOGN_RK_SWITCH(T.logN, HG_FWD)
 #undef HG_FWD

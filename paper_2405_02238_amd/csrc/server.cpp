@@ -6,22 +6,30 @@
 
 namespace hg {
 
-uint64_t request_footprint(const Ctx &C, const Plan &p) {
+Footprint request_footprint_parts(const Ctx &C, const Plan &p) {
     const uint64_t w = 8, N = C.N, L = C.L, nExt = C.nExt, beta = C.beta, alpha = C.alpha;
     const uint64_t ct = 2 * L * N * w;
+    // key-switched jobs of the transform pass: transforms with a rotated term
+    // (one division by P each), or every rotated term in the paper's order
     uint64_t nks = 0;
-    for (int k = 0; k < p.K; ++k) {
-        bool ke = false, kw = false;
-        for (auto &t : p.eps[k]) ke |= ((t.z % C.S) + C.S) % C.S != 0;
-        for (auto &t : p.omega[k]) kw |= ((t.z % C.S) + C.S) % C.S != 0;
-        nks += (uint64_t)ke + (uint64_t)kw;
-    }
+    auto count = [&](const std::vector<Term> &tms) {
+        uint64_t rot = 0;
+        for (auto &t : tms) rot += ((t.z % C.S) + C.S) % C.S != 0;
+        if (!rot) return (uint64_t)0;
+        const bool lone = tms.size() == 1 && tms[0].mask < 0;
+        return C.ks_order == 1 && !lone ? rot : (uint64_t)1;
+    };
+    for (int k = 0; k < p.K; ++k) nks += count(p.eps[k]) + count(p.omega[k]);
     nks *= (uint64_t)p.nb;
     const uint64_t nsrc = 2 * (uint64_t)p.nb;
     const uint64_t operands = 2 * (uint64_t)p.nb * ct;
     const uint64_t result = ct;
     uint64_t acc = 3 * L * N * w + (p.d > 1 ? ct : 0) + (p.method == 3 ? 2 * ct : 0);
     uint64_t scratch = nsrc * (L + beta * nExt) * N * w + nks * 2 * (nExt + alpha + L) * N * w;
+    if (p.method == 3) {
+        uint64_t nst = count(p.sigma) + count(p.tau);
+        scratch = std::max(scratch, 2 * (L + beta * nExt) * N * w + nst * 2 * (nExt + alpha + L) * N * w);
+    }
     if (C.relin == 1) {
         // eager relinearisation: a tensor and a relinearised ciphertext per
         // loop product, and a relinearisation pass with one source and one
@@ -30,8 +38,19 @@ uint64_t request_footprint(const Ctx &C, const Plan &p) {
         acc += pairs * 5 * L * N * w;
         scratch = std::max(scratch, pairs * (L + beta * nExt) * N * w + pairs * 2 * (nExt + alpha + L) * N * w);
     }
-    const uint64_t staging = operands / 2;   // canonical words of the operands, then of the result
-    return operands + result + acc + scratch + staging;
+    Footprint f;
+    // a lane's device buffer: the operands as read (canonical words), the
+    // operands in evaluation form, and the result
+    f.buffers = 2 * operands + result;
+    // the executor's workspaces (exactly sized on server lanes), plus their
+    // rounding to whole MiB and the descriptor tables
+    f.workspace = acc + scratch + (3ull << 20);
+    return f;
+}
+
+uint64_t request_footprint(const Ctx &C, const Plan &p) {
+    const Footprint f = request_footprint_parts(C, p);
+    return f.buffers + f.workspace;
 }
 
 Server::Server(Ctx &c, const ServerConfig &cf) : C(c), cfg(cf), lanes(cf.lanes) {
@@ -40,6 +59,8 @@ Server::Server(Ctx &c, const ServerConfig &cf) : C(c), cfg(cf), lanes(cf.lanes) 
     for (auto &ln : lanes) {
         HGCHK(hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking));
         HGCHK(hipEventCreateWithFlags(&ln.done, hipEventDisableTiming));
+        // workspaces sized exactly (the admission model counts them so)
+        C.arena(ln.st).exact = true;
     }
     origin = std::chrono::steady_clock::now();
     th = std::thread([this] { loop(); });
@@ -50,6 +71,7 @@ Server::~Server() {
     {
         std::lock_guard<std::mutex> g(mu);
         stop = true;
+        paused = false;   // destroy finishes every submitted request
     }
     cv_sub.notify_all();
     if (th.joinable()) th.join();
@@ -141,7 +163,7 @@ uint64_t Server::submit(const uint64_t *a, size_t na, const uint64_t *b, size_t 
     rq->pin = pin_get(na + nbw + ctw, rq->pin_cap);
     std::memcpy(rq->pin, a, na * sizeof(uint64_t));
     std::memcpy(rq->pin + na, b, nbw * sizeof(uint64_t));
-    rq->footprint = request_footprint(C, pe->plan);
+    rq->fp = request_footprint_parts(C, pe->plan);
     uint64_t id;
     {
         std::lock_guard<std::mutex> g(mu);
@@ -181,6 +203,14 @@ void Server::wait(uint64_t id, uint64_t *c, size_t nc, double *times) {
         if (nc < rq->nc) throw Error(-1, "result buffer too small");
         std::memcpy(c, rq->pin + rq->na + rq->nb, rq->nc * sizeof(uint64_t));
     }
+}
+
+void Server::pause(bool p) {
+    {
+        std::lock_guard<std::mutex> g(mu);
+        paused = p;
+    }
+    cv_sub.notify_all();
 }
 
 void Server::stats(double *o) {
@@ -294,9 +324,9 @@ void Server::finish(Lane &ln, int code, const std::string &msg) {
                 r->err = msg;
             }
         }
-        inflight -= ln.footprint;
+        inflight -= ln.buffers;
     }
-    ln.footprint = 0;
+    ln.buffers = 0;
     ln.batch.clear();
     ln.cts.clear();
     ln.busy = false;
@@ -323,20 +353,28 @@ void Server::loop() {
         for (auto &ln : lanes) {
             if (ln.busy) continue;
             std::vector<Req *> batch;
-            uint64_t fp = 0;
+            uint64_t bufs = 0, work = 0, held = ln.held;
             {
                 std::lock_guard<std::mutex> g(mu);
-                while (!pending.empty() && (int)batch.size() < cfg.max_batch) {
+                bool busy_lanes = false;
+                for (auto &o : lanes) busy_lanes |= o.busy;
+                while (!paused && !pending.empty() && (int)batch.size() < cfg.max_batch) {
                     Req *r = pending.front();
-                    const bool fits = cfg.budget == 0 || inflight + fp + r->footprint <= cfg.budget ||
-                                      (inflight == 0 && batch.empty());   // a lone request always runs
+                    // the lane keeps the larger of its workspace and this group's
+                    const uint64_t h = std::max(ln.held, work + r->fp.workspace);
+                    const uint64_t after = inflight - ln.held + h + bufs + r->fp.buffers;
+                    const bool fits = cfg.budget == 0 || after <= cfg.budget ||
+                                      (!busy_lanes && batch.empty());   // a lone request always runs
                     if (!fits) break;
                     pending.pop_front();
-                    fp += r->footprint;
+                    bufs += r->fp.buffers;
+                    work += r->fp.workspace;
+                    held = h;
                     batch.push_back(r);
                 }
                 if (batch.empty()) break;
-                inflight += fp;
+                inflight = inflight - ln.held + held + bufs;
+                ln.held = held;
                 max_inflight = std::max(max_inflight, inflight);
                 const double t = now();
                 for (Req *r : batch) {
@@ -350,7 +388,7 @@ void Server::loop() {
                 max_overlap = std::max(max_overlap, busy);
             }
             ln.batch = batch;
-            ln.footprint = fp;
+            ln.buffers = bufs;
             ln.busy = true;
             try {
                 launch(ln, ln.batch);
@@ -372,7 +410,7 @@ void Server::loop() {
         if (any_busy)
             cv_sub.wait_for(g, std::chrono::microseconds(20));
         else
-            cv_sub.wait(g, [&] { return stop || !pending.empty(); });
+            cv_sub.wait(g, [&] { return stop || (!paused && !pending.empty()); });
     }
 }
 

@@ -25,6 +25,17 @@
 
 namespace hg {
 
+// Modelled device bytes a product of this plan holds while it runs:
+// `buffers`, its operands (as received and in evaluation form) and result,
+// released when its group finishes; `workspace`, its accumulator and its
+// share of the pass scratch (hoisted digits, inner-product outputs,
+// division-by-P buffers, tables), which a lane keeps for its later groups.
+struct Footprint {
+    uint64_t buffers = 0, workspace = 0;
+};
+Footprint request_footprint_parts(const Ctx &C, const Plan &p);
+uint64_t request_footprint(const Ctx &C, const Plan &p);   // buffers + workspace
+
 struct ServerConfig {
     int max_batch = 64;       // products per launch group
     int lanes = 2;            // launch groups in flight, one stream each
@@ -40,7 +51,7 @@ struct Server {
         // then the result's words (copied out of the device by the lane)
         uint64_t *pin = nullptr;
         size_t pin_cap = 0, na = 0, nb = 0, nc = 0;
-        uint64_t footprint = 0;
+        Footprint fp;
         double t_submit = 0, t_start = 0, t_done = 0;
         int status = 0;                  // 0 queued, 1 running, 2 done, < 0 error code
         std::string err;
@@ -51,7 +62,8 @@ struct Server {
         bool busy = false;
         std::vector<Req *> batch;
         std::vector<std::unique_ptr<Ct>> cts;   // non-owning views of the lane's device buffer
-        uint64_t footprint = 0;
+        uint64_t buffers = 0;   // modelled bytes of the in-flight group's buffer
+        uint64_t held = 0;      // modelled workspace the lane keeps (largest group so far)
     };
 
     Ctx &C;
@@ -64,6 +76,9 @@ struct Server {
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_id = 1;
     bool stop = false;
+    bool paused = false;     // admission held (requests queue up)
+    // modelled device bytes now: every lane's kept workspace plus the
+    // buffers of the groups in flight (guarded by mu)
     uint64_t inflight = 0;
     std::chrono::steady_clock::time_point origin;
     // pool of pinned request buffers, reused by size (guarded by pool_mu)
@@ -83,6 +98,8 @@ struct Server {
     // (submit, start, done; seconds since the server started)
     void wait(uint64_t id, uint64_t *c, size_t nc, double *times);
     void stats(double *out8);
+    // hold (true) or resume (false) admission; queued requests wait meanwhile
+    void pause(bool p);
 
   private:
     double now() const;
@@ -92,9 +109,6 @@ struct Server {
     void finish(Lane &ln, int code, const std::string &msg);
 };
 
-// Modelled device bytes a product of this plan holds while it runs: its
-// operands and result, the accumulator, and its share of the pass scratch
-// (hoisted digits, inner-product outputs, division-by-P buffers).
-uint64_t request_footprint(const Ctx &C, const Plan &p);
+
 
 }  // namespace hg
