@@ -136,6 +136,26 @@ hg_status hg_set_allocator(hg_ctx *ctx, hg_alloc_fn alloc, hg_release_fn release
  * cannot be planned), HG_ESTATE (after hg_drop_secret with a new seed). */
 hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t nshapes);
 
+/* Output blocking (Section IV-D, the blocked product of large matrices):
+ * register the partition of shape (m, l, n) -- A's row blocks of rows[0..nrows)
+ * rows, B's column blocks of cols[0..ncols) columns, sizes summing to m and n
+ * -- before the shape's keys and operands are made.  Without a registered
+ * partition a shape whose result does not fit one ciphertext gets the
+ * fewest blocks of near-equal sizes whose block products each fit.  Every
+ * block product must fit one ciphertext (its inner dimension is split as it
+ * needs, with one accumulator).  HEGMM-En only.  The batched executor, the
+ * request loop and hg_hegmm_noalloc do not take output-blocked shapes.
+ * Errors: HG_EINVAL (sizes, a shape planned already as one product, more
+ * than 4096 blocks), HG_ENOFIT (a block product does not fit). */
+hg_status hg_set_partition(hg_ctx *ctx, int m, int l, int n, const int32_t *rows, int nrows, const int32_t *cols,
+                           int ncols);
+
+/* The partition of shape (m, l, n): out = {nrows, ncols, rows..., cols...};
+ * a shape that fits one ciphertext reports {1, 1, m, n}.  *count receives the
+ * number of values; out may be NULL to query it.
+ * Errors: HG_EINVAL (buffer too small), HG_ENOFIT. */
+hg_status hg_get_partition(hg_ctx *ctx, int m, int l, int n, int32_t *out, size_t cap, size_t *count);
+
 /* Forget the secret key (server role): evaluation keys stay, encrypt and
  * decrypt then fail with HG_ESTATE while hg_hegmm still works. */
 hg_status hg_drop_secret(hg_ctx *ctx);
@@ -144,16 +164,25 @@ hg_status hg_drop_secret(hg_ctx *ctx);
  * A (m x l) x B (l x n) for the cloud and encrypt it.  role 0: X points to
  * A (row-major m x l); role 1: X points to B (row-major l x n).  The packing
  * depends on the whole shape (duplication count, orientation, inner
- * blocking).  `nonce` selects the encryption randomness; the same (role,
- * nonce, shape) must not be reused for different data.  *out receives a new
- * handle.  Errors: HG_EINVAL, HG_ENOFIT, HG_ESTATE. */
+ * blocking).  A product whose m x n result does not fit one ciphertext is an
+ * output-blocked product (the blocked matrix multiplication of Section
+ * IV-D): A is split into row blocks and B into column blocks (the shape's
+ * partition, see hg_set_partition), block k = (i, j), row-major over the
+ * partition, is the ordinary product A_i (rows_i x l) x B_j (l x cols_j), and
+ * the handle holds, for every k in turn, the packed operand of that product
+ * encrypted with nonce nonce * 65536 + k (nonce < 2^47).  `nonce` selects the
+ * encryption randomness; the same (role, nonce, shape) must not be reused for
+ * different data.  *out receives a new handle.  Errors: HG_EINVAL,
+ * HG_ENOFIT, HG_ESTATE. */
 hg_status hg_encrypt(hg_ctx *ctx, int role, const int64_t *X, int m, int l, int n,
                      uint64_t nonce, hg_ct **out);
 
 /* Cloud multiplication of Algorithm 2 (HEGMM-En) on encrypted operands made
  * by hg_encrypt for the same (m, l, n).  *ctC receives a new result handle;
- * the work is enqueued on `stream`.  Errors: HG_EINVAL (shape differs from
- * the operands'), HG_ENOFIT, HG_ENOKEY, HG_EDEVICE. */
+ * the work is enqueued on `stream`.  An output-blocked product runs all its
+ * block products in one batch and its result holds one ciphertext per
+ * block, in block order.  Errors: HG_EINVAL (shape differs from the
+ * operands'), HG_ENOFIT, HG_ENOKEY, HG_EDEVICE. */
 hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n,
                    hg_ct **ctC, void *stream);
 
@@ -215,10 +244,11 @@ void hg_graph_destroy(hg_graph *g);
 hg_status hg_ct_load(hg_ctx *ctx, hg_ct *ct, const uint64_t *buf, size_t nwords, void *stream);
 
 /* Decrypt a result made by hg_hegmm for shape (m, l, n) -- or the
- * hg_ct_import (one ciphertext, two components) of its exported words, such
- * as a served result -- and unpack it into C (row-major m x n, values in
- * [0, t)).  Synchronises the device.  Errors: HG_EINVAL (a packed operand or
- * a result of another shape), HG_ESTATE. */
+ * hg_ct_import (two components, one ciphertext, or one per output block of
+ * an output-blocked shape) of its exported words, such as a served result --
+ * and unpack it into C (row-major m x n, values in [0, t)); output blocks are
+ * placed at their rows and columns.  Synchronises the device.  Errors:
+ * HG_EINVAL (a packed operand or a result of another shape), HG_ESTATE. */
 hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ctC, int m, int l, int n, uint64_t *C);
 
 /* Canonical serialisation: coefficient form, residues in [0, q_i), the

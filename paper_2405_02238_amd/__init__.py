@@ -86,6 +86,9 @@ _SIGS = {
     "hg_server_wait": [_P, ctypes.c_uint64, _P, ctypes.c_size_t, _P],
     "hg_server_stats": [_P, _f64p],
     "hg_server_pause": [_P, ctypes.c_int],
+    "hg_set_partition": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int, _i32p, ctypes.c_int],
+    "hg_get_partition": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t,
+                         ctypes.POINTER(ctypes.c_size_t)],
     "hg_bench_modmul": [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint64)],
     "hg_bench_stream": [ctypes.c_int, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)],
@@ -274,6 +277,21 @@ class Context:
         s = current_stream() if stream is None else stream
         _check(_lib.hg_hegmm(self.ptr, A.ptr, B.ptr, m, l, n, ctypes.byref(out), s))
         return self._ct(out)
+
+    def set_partition(self, m: int, l: int, n: int, rows: Sequence[int], cols: Sequence[int]):
+        """hg_set_partition: the output blocks of a product (Section IV-D)."""
+        r = np.ascontiguousarray(rows, dtype=np.int32)
+        c = np.ascontiguousarray(cols, dtype=np.int32)
+        _check(_lib.hg_set_partition(self.ptr, m, l, n, r, r.size, c, c.size))
+
+    def partition(self, m: int, l: int, n: int) -> Tuple[List[int], List[int]]:
+        """hg_get_partition: (row block sizes, column block sizes)."""
+        cnt = ctypes.c_size_t(0)
+        _check(_lib.hg_get_partition(self.ptr, m, l, n, None, 0, ctypes.byref(cnt)))
+        out = np.zeros(cnt.value, dtype=np.int32)
+        _check(_lib.hg_get_partition(self.ptr, m, l, n, out.ctypes.data, out.size, ctypes.byref(cnt)))
+        nr, nc = int(out[0]), int(out[1])
+        return [int(x) for x in out[2:2 + nr]], [int(x) for x in out[2 + nr:2 + nr + nc]]
 
     def hegmm_noalloc(self, A: Ciphertext, B: Ciphertext, m: int, l: int, n: int, out: Ciphertext,
                       stream: Optional[int] = None) -> Ciphertext:

@@ -5,7 +5,8 @@ scheduled -- which transform kernels run, how inner products are grouped,
 how many products share a launch group -- never the result.  The tuner runs
 a workload under each candidate setting, checks that the serialised outputs
 are bit-identical to those of the first setting, times the candidates with
-the stream's events, and returns (and optionally stores) the fastest.
+events on the current stream (bracketing the reps, with a host clock as a
+floor), and applies, returns and optionally stores the fastest.
 
 Usage:
     best = autotune(ctx, run_fn, candidates)
@@ -36,14 +37,22 @@ def grid(space: Dict[str, Iterable[int]]) -> List[Dict[str, int]]:
     return [dict(zip(keys, vals)) for vals in itertools.product(*(list(space[k]) for k in keys))]
 
 
-def _time_steps(run_fn: Callable, reps: int) -> float:
+def _time_steps(run_fn: Callable, reps: int):
+    """Seconds per call of run_fn (the later of the stream events around the
+    calls and the host clock), and the last call's outputs."""
     import torch
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    e0.record(stream)
     t0 = time.perf_counter()
     for _ in range(reps):
         outs = run_fn()
+    e1.record(stream)
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps, outs
+    wall = time.perf_counter() - t0
+    return max(e0.elapsed_time(e1) * 1e-3, wall) / reps, outs
 
 
 def autotune(ctx, run_fn: Callable, candidates: List[Dict[str, int]], reps: int = 3,

@@ -156,9 +156,18 @@ hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t ns
         hg::Ctx &C = *ctx->c;
         HGCHK(hipSetDevice(C.device));
         std::vector<int> gal;
-        for (size_t i = 0; i < nshapes; ++i) {
-            const hg::PlanEntry &pe = C.plan_for(shapes[3 * i], shapes[3 * i + 1], shapes[3 * i + 2]);
+        auto add = [&](int m, int l, int n) {
+            const hg::PlanEntry &pe = C.plan_for(m, l, n);
             for (int z : pe.plan.rotations(C.S)) gal.push_back(C.galois_of(z));
+        };
+        for (size_t i = 0; i < nshapes; ++i) {
+            const int m = shapes[3 * i], l = shapes[3 * i + 1], n = shapes[3 * i + 2];
+            if (const hg::Ctx::Partition *pt = C.partition_for(m, l, n)) {
+                for (int mi : pt->rows)
+                    for (int nj : pt->cols) add(mi, l, nj);
+            } else {
+                add(m, l, n);
+            }
         }
         C.keygen(seed, gal);
     });
@@ -188,8 +197,39 @@ hg_status hg_encrypt(hg_ctx *ctx, int role, const int64_t *X, int m, int l, int 
         need(ctx && X && out, "null argument");
         *out = nullptr;
         need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
-        HGCHK(hipSetDevice(ctx->c->device));
-        *out = wrap(ctx->c->encrypt_matrix(role, X, m, l, n, nonce));
+        hg::Ctx &C = *ctx->c;
+        HGCHK(hipSetDevice(C.device));
+        if (const hg::Ctx::Partition *pt = C.partition_for(m, l, n))
+            *out = wrap(C.encrypt_blocked(role, X, m, l, n, nonce, *pt));
+        else
+            *out = wrap(C.encrypt_matrix(role, X, m, l, n, nonce));
+    });
+}
+
+hg_status hg_set_partition(hg_ctx *ctx, int m, int l, int n, const int32_t *rows, int nrows, const int32_t *cols,
+                           int ncols) {
+    return guard([&] {
+        need(ctx && rows && cols && nrows > 0 && ncols > 0, "null argument or empty partition");
+        ctx->c->set_partition(m, l, n, std::vector<int>(rows, rows + nrows), std::vector<int>(cols, cols + ncols));
+    });
+}
+
+hg_status hg_get_partition(hg_ctx *ctx, int m, int l, int n, int32_t *out, size_t cap, size_t *count) {
+    return guard([&] {
+        need(ctx && count, "null argument");
+        const hg::Ctx::Partition *pt = ctx->c->partition_for(m, l, n);
+        std::vector<int32_t> v{pt ? (int32_t)pt->rows.size() : 1, pt ? (int32_t)pt->cols.size() : 1};
+        if (pt) {
+            v.insert(v.end(), pt->rows.begin(), pt->rows.end());
+            v.insert(v.end(), pt->cols.begin(), pt->cols.end());
+        } else {
+            v.push_back(m);
+            v.push_back(n);
+        }
+        *count = v.size();
+        if (!out) return;
+        need(cap >= v.size(), "buffer too small");
+        std::copy(v.begin(), v.end(), out);
     });
 }
 
@@ -201,19 +241,54 @@ hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const h
         hg::Ctx &X = *ctx->c;
         HGCHK(hipSetDevice(X.device));
         std::vector<hg::Ctx::Request> reqs;
+        std::vector<std::unique_ptr<hg::Ct>> views;   // block operands and results of output-blocked products
         for (size_t i = 0; i < cnt; ++i) {
             need(A[i] && B[i], "null operand");
             need(A[i]->c->ctx == &X && B[i]->c->ctx == &X, "operand from another context");
-            need(mln[3 * i] > 0 && mln[3 * i + 1] > 0 && mln[3 * i + 2] > 0, "dimensions must be positive");
+            const int m = mln[3 * i], l = mln[3 * i + 1], n = mln[3 * i + 2];
+            need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
+            const hg::Ctx::Partition *pt = X.partition_for(m, l, n);
             hg::Ct *o = new hg::Ct();
             o->ctx = &X;
-            o->ncts = 1;
+            o->ncts = pt ? pt->blocks() : 1;
             o->comps = 2;
-            o->m = mln[3 * i]; o->l = mln[3 * i + 1]; o->n = mln[3 * i + 2];
-            o->side = 2;
+            o->m = m; o->l = l; o->n = n;
+            o->side = pt ? 12 : 2;
             made.push_back(o);
             X.ct_alloc(o, as_stream(stream));
-            reqs.push_back({A[i]->c, B[i]->c, mln[3 * i], mln[3 * i + 1], mln[3 * i + 2], o});
+            if (!pt) {
+                reqs.push_back({A[i]->c, B[i]->c, m, l, n, o});
+                continue;
+            }
+            // one product per output block, on views into the blocked operands
+            const hg::Ct &a = *A[i]->c, &b = *B[i]->c;
+            need(a.side == 10 && b.side == 11 && a.m == m && a.l == l && a.n == n && b.m == m && b.l == l && b.n == n,
+                 "operands must be hg_encrypt outputs of this output-blocked shape for roles 0 (A) and 1 (B)");
+            int first = 0, k = 0;
+            for (int mi : pt->rows)
+                for (int nj : pt->cols) {
+                    const hg::Plan &p = X.plan_for(mi, l, nj).plan;
+                    auto view = [&](const hg::Ct &src, int side, int ncts, int at) {
+                        auto v = std::make_unique<hg::Ct>();
+                        v->ctx = &X;
+                        v->owns = false;
+                        v->ncts = ncts;
+                        v->comps = 2;
+                        v->m = mi; v->l = l; v->n = nj;
+                        v->side = side;
+                        v->d = src.ct(at);
+                        views.push_back(std::move(v));
+                        return views.back().get();
+                    };
+                    need(first + p.nb <= a.ncts && first + p.nb <= b.ncts, "blocked operand too short");
+                    hg::Ct *va = view(a, hg::side_of_role(p, 0), p.nb, first);
+                    hg::Ct *vb = view(b, hg::side_of_role(p, 1), p.nb, first);
+                    hg::Ct *vc = view(*o, 2, 1, k);
+                    reqs.push_back({va, vb, mi, l, nj, vc});
+                    first += p.nb;
+                    ++k;
+                }
+            need(first == a.ncts && first == b.ncts, "blocked operand of another partition");
         }
         X.hegmm_batch(reqs, as_stream(stream));
     });
@@ -237,6 +312,7 @@ hg_status hg_hegmm_noalloc(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int 
         hg::Ct &R = *ctC->c;
         need(R.ncts == 1 && R.comps == 2 && R.level == 0 && R.d,
              "the result handle must hold one two-component ciphertext at the full level");
+        need(!X.partitions.count(std::make_tuple(m, l, n)), "output-blocked products are not supported here");
         // a plan not made yet would allocate its masks: hg_keygen makes them
         if (!X.plans.count(std::make_tuple(m, l, n)))
             throw hg::Error(HG_ESTATE, "shape not prepared: list it in hg_keygen before hg_hegmm_noalloc");
@@ -340,15 +416,37 @@ hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ct, int m, int l, int n, uint64_t
         need(ctx && ct && C, "null argument");
         hg::Ctx &X = *ctx->c;
         const hg::Ct &R = *ct->c;
-        const bool result = R.side == 2 && R.m == m && R.l == l && R.n == n;
-        const bool imported = R.side == -1 && R.ncts == 1 && R.comps == 2;   // hg_ct_import of a result
+        need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
+        const hg::Ctx::Partition *pt = X.partition_for(m, l, n);
+        const int ncts = pt ? pt->blocks() : 1;
+        const bool result = R.side == (pt ? 12 : 2) && R.m == m && R.l == l && R.n == n;
+        // hg_ct_import of a result's words
+        const bool imported = R.side == -1 && R.ncts == ncts && R.comps == 2;
         need(result || imported, "not a result of this shape");
         HGCHK(hipSetDevice(X.device));
         HGCHK(hipDeviceSynchronize());
-        const hg::PlanEntry &pe = X.plan_for(m, l, n);
-        std::vector<uint64_t> slots = X.decrypt_slot_values(*ct->c, 0);
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < n; ++j) C[(size_t)i * n + j] = slots[hg::result_slot(pe.plan, i, j)];
+        if (!pt) {
+            const hg::PlanEntry &pe = X.plan_for(m, l, n);
+            std::vector<uint64_t> slots = X.decrypt_slot_values(*ct->c, 0);
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < n; ++j) C[(size_t)i * n + j] = slots[hg::result_slot(pe.plan, i, j)];
+            return;
+        }
+        // output blocks: block k = (i, j) holds C's rows r0.., columns c0..
+        int k = 0, r0 = 0;
+        for (int mi : pt->rows) {
+            int c0 = 0;
+            for (int nj : pt->cols) {
+                const hg::PlanEntry &pe = X.plan_for(mi, l, nj);
+                std::vector<uint64_t> slots = X.decrypt_slot_values(*ct->c, k);
+                for (int i = 0; i < mi; ++i)
+                    for (int j = 0; j < nj; ++j)
+                        C[(size_t)(r0 + i) * n + c0 + j] = slots[hg::result_slot(pe.plan, i, j)];
+                ++k;
+                c0 += nj;
+            }
+            r0 += mi;
+        }
     });
 }
 

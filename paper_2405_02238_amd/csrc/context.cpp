@@ -505,24 +505,132 @@ Ct *Ctx::encrypt_matrix(int role, const int64_t *X, int m, int l, int n, uint64_
     if (role != 0 && role != 1) throw Error(-1, "role must be 0 (A) or 1 (B)");
     const PlanEntry &pe = plan_for(m, l, n);
     const Plan &p = pe.plan;
-    const int side = side_of_role(p, role);
     Ct *c = new Ct();
     c->ctx = this;
     c->ncts = p.nb;
     c->comps = 2;
     c->m = m; c->l = l; c->n = n;
-    c->side = side;
+    c->side = side_of_role(p, role);
     ct_alloc(c, nullptr);
     try {
-        for (int b = 0; b < p.nb; ++b) {
-            std::vector<uint64_t> v = pack_operand(p, side, X, b, t, S);
-            encrypt_slots(v, side, b, nonce, c, b);
+        encrypt_matrix_into(role, X, m, l, n, nonce, c, 0);
+    } catch (...) {
+        delete c;
+        throw;
+    }
+    return c;
+}
+
+void Ctx::encrypt_matrix_into(int role, const int64_t *X, int m, int l, int n, uint64_t nonce, Ct *into,
+                              int first) {
+    const Plan &p = plan_for(m, l, n).plan;
+    const int side = side_of_role(p, role);
+    for (int b = 0; b < p.nb; ++b) {
+        std::vector<uint64_t> v = pack_operand(p, side, X, b, t, S);
+        encrypt_slots(v, side, b, nonce, into, first + b);
+    }
+}
+
+Ct *Ctx::encrypt_blocked(int role, const int64_t *X, int m, int l, int n, uint64_t nonce, const Partition &pt) {
+    if (!has_secret) throw Error(-6, "no secret key");
+    if (role != 0 && role != 1) throw Error(-1, "role must be 0 (A) or 1 (B)");
+    if (nonce >= (1ULL << 47)) throw Error(-1, "nonce of an output-blocked operand must be below 2^47");
+    int total = 0;
+    for (int mi : pt.rows)
+        for (int nj : pt.cols) total += plan_for(mi, l, nj).plan.nb;
+    Ct *c = new Ct();
+    c->ctx = this;
+    c->ncts = total;
+    c->comps = 2;
+    c->m = m; c->l = l; c->n = n;
+    c->side = 10 + role;
+    ct_alloc(c, nullptr);
+    try {
+        int first = 0, k = 0, r0 = 0;
+        std::vector<int64_t> sub;
+        for (int mi : pt.rows) {
+            int c0 = 0;
+            for (int nj : pt.cols) {
+                // the block's own matrix, row-major: A's rows r0.., or B's columns c0..
+                if (role == 0) {
+                    sub.assign(X + (size_t)r0 * l, X + (size_t)(r0 + mi) * l);
+                } else {
+                    sub.resize((size_t)l * nj);
+                    for (int r = 0; r < l; ++r)
+                        for (int q = 0; q < nj; ++q) sub[(size_t)r * nj + q] = X[(size_t)r * n + c0 + q];
+                }
+                encrypt_matrix_into(role, sub.data(), mi, l, nj, nonce * 65536 + (uint64_t)k, c, first);
+                first += plan_for(mi, l, nj).plan.nb;
+                ++k;
+                c0 += nj;
+            }
+            r0 += mi;
         }
     } catch (...) {
         delete c;
         throw;
     }
     return c;
+}
+
+bool Ctx::plannable(int m, int l, int n) const {
+    try {
+        (void)make_plan(m, l, n, S, method, min_blocks);
+        return true;
+    } catch (std::range_error &) {
+        return false;
+    }
+}
+
+const Ctx::Partition *Ctx::partition_for(int m, int l, int n) {
+    if (m <= 0 || l <= 0 || n <= 0) throw Error(-1, "dimensions must be positive");
+    auto key = std::make_tuple(m, l, n);
+    auto it = partitions.find(key);
+    if (it != partitions.end()) return &it->second;
+    if (plans.count(key) || plannable(m, l, n)) return nullptr;
+    if (method != 2) throw Error(-2, "output blocking needs HEGMM-En (method 2)");
+    // the fewest output blocks of near-equal sizes (rows of A, columns of B)
+    // whose every block product fits one ciphertext row
+    auto split = [](int x, int parts) {
+        std::vector<int> v(parts, x / parts);
+        for (int i = 0; i < x % parts; ++i) ++v[i];
+        return v;
+    };
+    for (int total = 2; total <= m * n; ++total)
+        for (int br = 1; br <= std::min(total, m); ++br) {
+            if (total % br) continue;
+            const int bc = total / br;
+            if (bc > n) continue;
+            Partition pt{split(m, br), split(n, bc)};
+            bool ok = true;
+            for (int mi : {pt.rows.front(), pt.rows.back()})
+                for (int nj : {pt.cols.front(), pt.cols.back()}) ok = ok && plannable(mi, l, nj);
+            if (!ok) continue;
+            return &(partitions[key] = pt);
+        }
+    throw Error(-2, "no output blocking fits this shape");
+}
+
+void Ctx::set_partition(int m, int l, int n, const std::vector<int> &rows, const std::vector<int> &cols) {
+    if (m <= 0 || l <= 0 || n <= 0) throw Error(-1, "dimensions must be positive");
+    if (method != 2) throw Error(-1, "output blocking needs HEGMM-En (method 2)");
+    auto key = std::make_tuple(m, l, n);
+    if (plans.count(key)) throw Error(-1, "the shape was already planned as one product");
+    int sr = 0, sc = 0;
+    for (int r : rows) {
+        if (r <= 0) throw Error(-1, "block sizes must be positive");
+        sr += r;
+    }
+    for (int c : cols) {
+        if (c <= 0) throw Error(-1, "block sizes must be positive");
+        sc += c;
+    }
+    if (sr != m || sc != n || rows.empty() || cols.empty()) throw Error(-1, "block sizes must add up to m and n");
+    if (rows.size() * cols.size() > 4096) throw Error(-1, "at most 4096 output blocks");
+    for (int r : rows)
+        for (int c : cols)
+            if (!plannable(r, l, c)) throw Error(-2, "a block product does not fit one ciphertext");
+    partitions[key] = Partition{rows, cols};
 }
 
 std::vector<uint64_t> Ctx::to_host_canonical(const double *eval_rows, int rows, hipStream_t st, int per) {

@@ -117,6 +117,19 @@ struct Ctx {
 
     // plans and masks
     std::map<std::tuple<int, int, int>, std::unique_ptr<PlanEntry>> plans;
+    // Output blocking (Section IV-D) of products whose result does not fit
+    // one ciphertext: row sizes of A's blocks, then column sizes of B's.
+    struct Partition {
+        std::vector<int> rows, cols;
+        int blocks() const { return (int)(rows.size() * cols.size()); }
+    };
+    std::map<std::tuple<int, int, int>, Partition> partitions;   // registered or chosen, per shape
+    // The partition of a shape if its result needs output blocks (nullptr
+    // when one ciphertext holds it); chosen on first use unless registered.
+    const Partition *partition_for(int m, int l, int n);
+    // Register a partition (every block must be plannable; sizes sum to m, n).
+    void set_partition(int m, int l, int n, const std::vector<int> &rows, const std::vector<int> &cols);
+    bool plannable(int m, int l, int n) const;
     std::map<std::string, double *> mask_cache;   // slot bitmap -> device mask (nExt x N)
 
     std::map<hipStream_t, Arena> arenas;
@@ -186,6 +199,12 @@ struct Ctx {
     Ct *encrypt_slots(const std::vector<uint64_t> &slots, int side, int block, uint64_t nonce,
                       Ct *into = nullptr, int into_index = 0);
     Ct *encrypt_matrix(int role, const int64_t *X, int m, int l, int n, uint64_t nonce);
+    // pack and encrypt one product's operand into ciphertexts [first, first + nb) of `into`
+    void encrypt_matrix_into(int role, const int64_t *X, int m, int l, int n, uint64_t nonce, Ct *into, int first);
+    // an output-blocked operand: for block k = (i, j) (row-major over the
+    // partition) the operand of product (rows[i], l, cols[j]) with nonce
+    // nonce * 65536 + k, the blocks' ciphertexts one after another
+    Ct *encrypt_blocked(int role, const int64_t *X, int m, int l, int n, uint64_t nonce, const Partition &pt);
     std::vector<uint64_t> decrypt_poly(const Ct &c, int index);   // mu in [0, t), N values
     std::vector<uint64_t> decrypt_slot_values(const Ct &c, int index);
 

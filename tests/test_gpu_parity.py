@@ -597,11 +597,13 @@ def _offsets(sizes):
 @pytest.mark.parametrize("part", ["P1", "P2"])
 def test_blocked_100x100(part):
     """A 100x100 by 100x100 product whose result does not fit one ciphertext
-    (10000 > 4096 slots), computed as the paper's blocked product: the client
-    splits A into row blocks and B into column blocks, the cloud runs the
-    block products in one batch (each splits its inner dimension itself), the
-    client assembles C.  One block is checked against the oracle bit for bit.
-    For P1 the paper's own split of the inner dimension too (eight 50x50x50
+    (10000 > 4096 slots), through the ABI as an output-blocked product with
+    the paper's partitions (Section IV-D, Table IV): hg_set_partition, one
+    hg_encrypt per operand, one hg_hegmm (the four block products in one
+    batch, each splitting its inner dimension itself), one hg_decrypt that
+    places the blocks.  C == A.B mod t; every block's ciphertext equals the
+    oracle's product of that block (nonce 65536 nonce + k) bit for bit.  For
+    P1 the paper's own split of the inner dimension too (eight 50x50x50
     products, partial results added with HE-Add) gives the same C."""
     c = workloads.HEADLINE
     D = workloads.BLOCKED_DIM
@@ -611,24 +613,28 @@ def test_blocked_100x100(part):
     grid = [(i, j) for i in range(len(rows)) for j in range(len(cols))]
     shapes = [(rows[i], D, cols[j]) for (i, j) in grid]
     extra = [(50, 50, 50)] if part == "P1" else []
-    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=shapes[:1] + extra)
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed, shapes=shapes + extra)
     ctx = pair.ctx
-    ctx.keygen(c.seed, shapes)
-    As = [ctx.encrypt(0, A[r0[i]:r0[i] + rows[i], :], *shapes[k], nonce=20 + k) for k, (i, j) in enumerate(grid)]
-    Bs = [ctx.encrypt(1, B[:, c0[j]:c0[j] + cols[j]], *shapes[k], nonce=20 + k) for k, (i, j) in enumerate(grid)]
-    outs = ctx.hegmm_batch(As, Bs, shapes)
-    C = np.zeros((D, D), dtype=np.int64)
-    for k, (i, j) in enumerate(grid):
-        C[r0[i]:r0[i] + rows[i], c0[j]:c0[j] + cols[j]] = ctx.decrypt(outs[k], *shapes[k])
+    ctx.set_partition(D, D, D, rows, cols)
+    assert ctx.partition(D, D, D) == (list(rows), list(cols))
+    ctx.keygen(c.seed, [(D, D, D)])
+    nonce = 20
+    ca, cb = ctx.encrypt(0, A, D, D, D, nonce=nonce), ctx.encrypt(1, B, D, D, D, nonce=nonce)
+    out = ctx.hegmm(ca, cb, D, D, D)
+    C = ctx.decrypt(out, D, D, D)
     assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t))
-    # the first block product against the oracle
-    m, l, n = shapes[0]
-    pl = H.plan(m, l, n, pair.P.S)
-    assert pl.nb > 1
-    Ab, Bb = A[:m, :], B[:, :n]
-    ox = H.encrypt_operand(pair.ks, pl, 0, Ab, Bb, 20)
-    oy = H.encrypt_operand(pair.ks, pl, 1, Ab, Bb, 20)
-    assert np.array_equal(outs[0].export(), flat(H.hegmm(pair.ks, pl, ox, oy, pair.masks)))
+    words = out.export()
+    per = 2 * c.L * c.N
+    assert words.size == len(grid) * per
+    assert np.array_equal(ctx.decrypt(ctx.import_ct(words, len(grid), 2), D, D, D), C)
+    for k, (i, j) in enumerate(grid):
+        m, l, n = shapes[k]
+        pl = H.plan(m, l, n, pair.P.S)
+        assert pl.nb > 1
+        Ab, Bb = A[r0[i]:r0[i] + m, :], B[:, c0[j]:c0[j] + n]
+        ox = H.encrypt_operand(pair.ks, pl, 0, Ab, Bb, nonce * 65536 + k)
+        oy = H.encrypt_operand(pair.ks, pl, 1, Ab, Bb, nonce * 65536 + k)
+        assert np.array_equal(words[k * per:(k + 1) * per], flat(H.hegmm(pair.ks, pl, ox, oy, pair.masks))), k
     if part == "P1":
         # inner dimension split as well: C_ij = A_i1 B_1j + A_i2 B_2j
         k0 = _offsets((50, 50))
@@ -642,6 +648,48 @@ def test_blocked_100x100(part):
         for g, (i, j) in enumerate(grid):
             blk = ctx.add(prods[2 * g], prods[2 * g + 1])
             assert np.array_equal(ctx.decrypt(blk, *s), C[r0[i]:r0[i] + 50, c0[j]:c0[j] + 50])
+
+
+def test_blocked_automatic_partition():
+    """Shapes whose result exceeds the 512 slots of N = 1024 get the fewest
+    near-equal output blocks on their own (and a shape that fits gets none);
+    every block equals the oracle's product bit for bit, C == A.B mod t, and
+    a batch mixing blocked and plain products gives the same bits."""
+    c = workloads.TINY
+    P = Params(c.N, c.t, c.L, c.alpha)
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    shapes = [(30, 7, 30), (40, 3, 17), (4, 3, 5)]
+    parts = [ctx.partition(*s) for s in shapes]
+    assert parts[2] == ([4], [5])
+    for (m, l, n), (rows, cols) in zip(shapes[:2], parts[:2]):
+        assert sum(rows) == m and sum(cols) == n and len(rows) * len(cols) >= 2
+        assert max(rows) - min(rows) <= 1 and max(cols) - min(cols) <= 1
+    ctx.keygen(c.seed, shapes)
+    rng = np.random.default_rng(170)
+    mats = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    As = [ctx.encrypt(0, A, *s, nonce=5 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    Bs = [ctx.encrypt(1, B, *s, nonce=5 + i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    outs = ctx.hegmm_batch(As, Bs, shapes)
+    per = 2 * c.L * c.N
+    for q, ((m, l, n), (A, B), (rows, cols)) in enumerate(zip(shapes, mats, parts)):
+        assert np.array_equal(ctx.decrypt(outs[q], m, l, n), workloads.plain_matmul_mod(A, B, c.t)), (m, l, n)
+        alone = ctx.hegmm(As[q], Bs[q], m, l, n).export()
+        words = outs[q].export()
+        assert np.array_equal(words, alone)
+        if len(rows) * len(cols) == 1:
+            continue
+        blocks = [(mi, nj, ri, cj) for ri, mi in zip(_offsets(rows), rows) for cj, nj in zip(_offsets(cols), cols)]
+        ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [(mi, l, nj) for (mi, nj, _, _) in blocks]))
+        for k, (mi, nj, ri, cj) in enumerate(blocks):
+            pl = H.plan(mi, l, nj, P.S)
+            Ab, Bb = A[ri:ri + mi, :], B[:, cj:cj + nj]
+            ox = H.encrypt_operand(ks, pl, 0, Ab, Bb, (5 + q) * 65536 + k)
+            oy = H.encrypt_operand(ks, pl, 1, Ab, Bb, (5 + q) * 65536 + k)
+            assert np.array_equal(words[k * per:(k + 1) * per], flat(H.hegmm(ks, pl, ox, oy))), ((m, l, n), k)
+    with pytest.raises(hg.HGError):
+        ctx.set_partition(4, 3, 5, [2, 2], [5])     # planned already as one product
+    with pytest.raises(hg.HGError):
+        ctx.set_partition(64, 3, 64, [60, 4], [64])  # a block of 60 x 64 results does not fit
 
 
 def test_large_forced_two_blocks():
@@ -723,6 +771,41 @@ def test_keyed_inner_products_bit_identical(alpha):
     ctx.tune("ip_chunk", 0)
     for i, (s, (A, B)) in enumerate(zip(shapes, mats)):
         assert np.array_equal(ctx.decrypt(ctx.import_ct(plain[i], 1, 2), *s), workloads.plain_matmul_mod(A, B, c.t))
+
+
+def test_autotuner_keeps_bits_and_picks_a_setting():
+    """The autotuner runs a small mixed batch under every setting of the
+    transform radix and the launch-window size, finds the outputs
+    bit-identical across settings (and equal to the oracle for one request),
+    applies the fastest, and stores it for apply_cached."""
+    import tempfile
+    from paper_2405_02238_amd import autotune
+    c = workloads.BATCHED
+    shapes = [(8, 16, 24), (16, 8, 8), (24, 24, 16), (8, 40, 8), (32, 16, 40), (16, 16, 16)]
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, shapes)
+    rng = np.random.default_rng(160)
+    mats = [(rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))) for (m, l, n) in shapes]
+    As = [ctx.encrypt(0, A, *s, nonce=i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    Bs = [ctx.encrypt(1, B, *s, nonce=i) for i, (s, (A, B)) in enumerate(zip(shapes, mats))]
+    space = {"ntt_radix": [8, 16], "batch_window": [2, 0]}
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "tuned.json")
+        rep = autotune.autotune(ctx, lambda: ctx.hegmm_batch(As, Bs, shapes), autotune.grid(space), reps=2,
+                                cache=cache, tag="small")
+        assert len(rep["all"]) == 4 and rep["best"]["knobs"] in autotune.grid(space)
+        other = hg.Context(c.N, c.t, c.L, c.alpha)
+        assert autotune.apply_cached(other, cache, "small") and not autotune.apply_cached(other, cache, "x")
+    outs = ctx.hegmm_batch(As, Bs, shapes)
+    P = Params(c.N, c.t, c.L, c.alpha)
+    m, l, n = shapes[0]
+    A, B = mats[0]
+    ks = bgv.KeySet(P, c.seed, H.galois_elements(P, [shapes[0]]))
+    pl = H.plan(m, l, n, P.S)
+    want = flat(H.hegmm(ks, pl, H.encrypt_operand(ks, pl, 0, A, B, 0), H.encrypt_operand(ks, pl, 1, A, B, 0)))
+    assert np.array_equal(outs[0].export(), want)
+    for i, (s, (A, B)) in enumerate(zip(shapes, mats)):
+        assert np.array_equal(ctx.decrypt(outs[i], *s), workloads.plain_matmul_mod(A, B, c.t)), s
 
 
 def test_graph_replay_matches_eager(tiny):
