@@ -347,6 +347,29 @@ def run_serving(args):
         res3, lat3, span3 = serving.replay(srv, sat)
         st3 = srv.stats()
         print(f"# saturated replay, groups of up to {big}: {span3:.2f} s", file=sys.stderr, flush=True)
+    # device-side capacity: every request queued while admission is held, then
+    # released at once (the span from release to the last result in host
+    # memory; the clients' submission is outside it), per group size
+    prequeued = {}
+    for mb, lanes in ((1, 1), (1, 2), (4, 2), (16, 2), (16, 3), (16, 4), (32, 4)):
+        with hg.Server(ctx, max_batch=mb, lanes=lanes, hbm_budget=budget) as srv:
+            srv.pause(True)
+            tk = [srv.submit(a, b, m, l, n) for (_, m, l, n, a, b) in timed[: 2 * max(mb, 4)]]
+            srv.pause(False)
+            for x in tk:
+                srv.wait(x)
+            srv.pause(True)
+            tk = [srv.submit(a, b, m, l, n) for (_, m, l, n, a, b) in timed]
+            t0 = srv.stats()["clock"]
+            srv.pause(False)
+            got = [srv.wait(x) for x in tk]
+            pspan = max(tm[2] for _, tm in got) - t0
+            okq = all(np.array_equal(got[i * 16][0], w) for i, w in enumerate(alone_words))
+            prequeued[f"groups{mb}_lanes{lanes}"] = {"matmuls_per_s": len(timed) / pspan if okq else 0.0,
+                                                     "mean_group": srv.stats()["mean_group"],
+                                                     "bits_equal_alone": okq}
+        print(f"# prequeued burst, groups of up to {mb} on {lanes} lanes: {len(timed) / pspan:.0f}/s",
+              file=sys.stderr, flush=True)
     ok = 0
     for i, (at, m, l, n, A, B) in enumerate(reqs):
         C = ctx.decrypt(ctx.import_ct(res[i], 1, 2), m, l, n)
@@ -369,6 +392,11 @@ def run_serving(args):
            "capacity_matmuls_per_s": len(reqs) / span2,
            "capacity_p50_ms": serving.percentile_ms(lat2, 50), "capacity_p99_ms": serving.percentile_ms(lat2, 99),
            "capacity_groups_of_32_matmuls_per_s": len(reqs) / span3, "capacity_groups_of_32_mean_group": st3["mean_group"],
+           "capacity_prequeued": prequeued,
+           "capacity_prequeued_best_over_one_at_a_time":
+               max(v["matmuls_per_s"] for v in prequeued.values()) / (len(reqs) / alone_s),
+           "capacity_prequeued_best_over_served_one_at_a_time":
+               max(v["matmuls_per_s"] for v in prequeued.values()) / prequeued["groups1_lanes1"]["matmuls_per_s"],
            "one_at_a_time_matmuls_per_s": len(reqs) / alone_s,
            "decrypt_ok": ok, "served_equals_alone_bits": same}
     print(json.dumps(out), flush=True)
@@ -697,10 +725,12 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    # the dominant kernel is timed inside the timed steps, with events carried
-    # by its own dispatches (no markers, no synchronisation between steps), on
-    # every fourth step: timing every launch costs about 4% of the step
-    LT_EVERY = 4
+    # the dominant kernels are timed inside the timed steps, with events
+    # carried by their own dispatches (no markers, no synchronisation between
+    # steps), on every eighth step: a dispatch the host can wait on ends with a
+    # system-scope release (about 5 us on MI355X), so timing every step would
+    # cost about 6% of it
+    LT_EVERY = 8
     sampled = 0
     timed_outs = []
     e0.record(stream)

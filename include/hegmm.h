@@ -380,7 +380,9 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
 /* ---- tuning ----------------------------------------------------------- */
 
 /* Set an execution knob of the context (used by the autotuner; results are
- * bit-identical for every setting).  Names:
+ * bit-identical for every setting).  Knobs belong to the context: other
+ * contexts keep theirs.  Not while a server owns the context (HG_ESTATE).
+ * Names:
  *   "pipeline"   chunks (1..16) of a pass whose inner products overlap the
  *                division by P of the previous chunk on a second stream
  *                (1: no overlap, one stream)
@@ -397,13 +399,11 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
  *                N/1024 workgroups (two passes)
  *   "half_rows"  fused transform chains (few-row passes) of at most this many
  *                rows run two workgroups per row, each finishing one half of
- *                the forward transform (default 128; 0: off); like
- *                "split_rows" it holds for every context of the process
+ *                the forward transform (default 128; 0: off)
  *   "ntt_radix"  radix of the one-workgroup row transforms of 4096- and
- *                8192-point rows: 8, 16, or 0 for the built-in choice (8);
- *                like "split_rows" it holds for every context of the process
+ *                8192-point rows: 8, 16, or 0 for the built-in choice (8)
  *   "batch_window" products per launch group inside hg_hegmm_batch
- *                (0: all at once)
+ *                (0: all at once; default 64, 16 for N >= 16384)
  * Errors: HG_EINVAL (unknown name, negative value, "pipeline" outside
  * [1, 16], "ntt_radix" other than 0, 8, 16). */
 hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value);
