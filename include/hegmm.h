@@ -128,7 +128,9 @@ typedef void *(*hg_alloc_fn)(size_t bytes, void *stream, void *user);
 typedef void (*hg_release_fn)(void *ptr, void *user);
 hg_status hg_set_allocator(hg_ctx *ctx, hg_alloc_fn alloc, hg_release_fn release, void *user);
 
-/* Key generation (client role).  Samples the secret key from `seed` and
+/* Key generation (client role; Section II-A: clients encrypt the source
+ * matrices and decrypt the results, and SIMD packing needs the key material
+ * for slot rotations).  Samples the secret key from `seed` and
  * generates, on the device, the relinearisation key and every rotation key
  * that the HEGMM-En plans of the given shapes need.  `shapes` holds nshapes
  * triples (m, l, n), row after row.  May be called again to add the keys of
@@ -156,7 +158,8 @@ hg_status hg_set_partition(hg_ctx *ctx, int m, int l, int n, const int32_t *rows
  * Errors: HG_EINVAL (buffer too small), HG_ENOFIT. */
 hg_status hg_get_partition(hg_ctx *ctx, int m, int l, int n, int32_t *out, size_t cap, size_t *count);
 
-/* Forget the secret key (server role): evaluation keys stay, encrypt and
+/* Forget the secret key (server role; the cloud of Section II-A computes on
+ * ciphertexts only): evaluation keys stay, encrypt and
  * decrypt then fail with HG_ESTATE while hg_hegmm still works. */
 hg_status hg_drop_secret(hg_ctx *ctx);
 
@@ -212,7 +215,9 @@ hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l
 hg_status hg_hegmm_noalloc(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l, int n, hg_ct *ctC,
                            void *stream);
 
-/* Many independent HE matmuls of (possibly) different shapes in one call.
+/* Many independent HE matmuls of (possibly) different shapes in one call
+ * (Algorithm 2 per request; the random shape pairs of Section IV-B as one
+ * batch).
  * mln holds cnt triples.  The products share the launches of each phase
  * (one hoisting launch, one key-switching launch, ...), and rotations that
  * several products need read each key once per launch.  C[i] receives new
@@ -243,7 +248,9 @@ void hg_graph_destroy(hg_graph *g);
  * HG_EINVAL (word count, residue range). */
 hg_status hg_ct_load(hg_ctx *ctx, hg_ct *ct, const uint64_t *buf, size_t nwords, void *stream);
 
-/* Decrypt a result made by hg_hegmm for shape (m, l, n) -- or the
+/* Decrypt (client role: the encrypted result returned by the cloud, the last
+ * step of Algorithm 2; Section II-A) a result made by hg_hegmm for shape
+ * (m, l, n) -- or the
  * hg_ct_import (two components, one ciphertext, or one per output block of
  * an output-blocked shape) of its exported words, such as a served result --
  * and unpack it into C (row-major m x n, values in [0, t)); output blocks are
