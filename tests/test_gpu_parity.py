@@ -498,6 +498,28 @@ def test_serving_mix_equals_alone():
         assert np.array_equal(C, workloads.plain_matmul_mod(A, B, c.t)), (i, m, l, n)
 
 
+def test_tune_refused_while_served_and_per_context():
+    """hg_tune is refused while a server owns the context, and a knob set on
+    one context leaves another's results (and knobs) alone."""
+    c = workloads.TINY
+    a = hg.Context(c.N, c.t, c.L, c.alpha)
+    b = hg.Context(c.N, c.t, c.L, c.alpha)
+    for x in (a, b):
+        x.keygen(c.seed, [(4, 3, 5)])
+    A, B = workloads.tiny_operands()
+    want = a.hegmm(a.encrypt(0, A, 4, 3, 5, nonce=1), a.encrypt(1, B, 4, 3, 5, nonce=1), 4, 3, 5).export()
+    with hg.Server(a, max_batch=2, lanes=1) as srv:
+        with pytest.raises(hg.HGError) as e:
+            a.tune("ntt_radix", 16)
+        assert e.value.code == hg.HG_ESTATE
+        b.tune("half_rows", 0)          # another context stays tunable
+        srv.pause(True)
+        srv.pause(False)
+    a.tune("ntt_radix", 16)             # allowed again once the server is gone
+    got = b.hegmm(b.encrypt(0, A, 4, 3, 5, nonce=1), b.encrypt(1, B, 4, 3, 5, nonce=1), 4, 3, 5).export()
+    assert np.array_equal(got, want)
+
+
 def test_serving_memory_within_model():
     """The device memory a server lane takes for an admitted group, measured
     with hipMemGetInfo (free memory before the group against the lowest free
