@@ -143,10 +143,12 @@ hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t ns
  * rows, B's column blocks of cols[0..ncols) columns, sizes summing to m and n
  * -- before the shape's keys and operands are made.  Without a registered
  * partition a shape whose result does not fit one ciphertext gets the
- * fewest blocks of near-equal sizes whose block products each fit.  Every
- * block product must fit one ciphertext (its inner dimension is split as it
- * needs, with one accumulator).  HEGMM-En only.  The batched executor, the
- * request loop and hg_hegmm_noalloc do not take output-blocked shapes.
+ * fewest blocks (at most 4096) of near-equal sizes whose block products each
+ * fit, else HG_ENOFIT.  Every block product must fit one ciphertext (its
+ * inner dimension is split as it needs, with one accumulator).  HEGMM-En
+ * only.  hg_encrypt, hg_hegmm, hg_hegmm_batch and hg_decrypt take
+ * output-blocked shapes; recorded batches (hg_graph_create), the request
+ * server and hg_hegmm_noalloc do not.
  * Errors: HG_EINVAL (sizes, a shape planned already as one product, more
  * than 4096 blocks), HG_ENOFIT (a block product does not fit). */
 hg_status hg_set_partition(hg_ctx *ctx, int m, int l, int n, const int32_t *rows, int nrows, const int32_t *cols,

@@ -601,10 +601,11 @@ const Ctx::Partition *Ctx::partition_for(int m, int l, int n) {
         for (int i = 0; i < x % parts; ++i) ++v[i];
         return v;
     };
-    for (int total = 2; total <= m * n; ++total)
-        for (int br = 1; br <= std::min(total, m); ++br) {
+    const long long most = std::min<long long>((long long)m * n, 4096);   // at most 4096 output blocks
+    for (long long total = 2; total <= most; ++total)
+        for (int br = 1; br <= std::min<long long>(total, m); ++br) {
             if (total % br) continue;
-            const int bc = total / br;
+            const int bc = (int)(total / br);
             if (bc > n) continue;
             Partition pt{split(m, br), split(n, bc)};
             bool ok = true;
