@@ -332,8 +332,10 @@ hg_status hg_mod_switch(hg_ctx *ctx, const hg_ct *ct, int drop, hg_ct **out, voi
  * is bit-identical to hg_hegmm of the same operands alone.
  * While a server exists its thread owns the context: the caller may use only
  * hg_server_* and hg_request_footprint on it until hg_server_destroy, which
- * finishes every submitted request first.  hg_server_submit and
- * hg_server_wait may be called from several threads. */
+ * finishes every submitted request first; every other call on the context
+ * (or on a graph recorded from it), and a second hg_server_create, returns
+ * HG_ESTATE.  hg_ct_free stays allowed.  hg_server_submit and hg_server_wait
+ * may be called from several threads. */
 typedef struct hg_server hg_server;
 typedef struct {
     int32_t max_batch;     /* products per launch group, >= 1 */
@@ -342,7 +344,8 @@ typedef struct {
                               A request larger than the budget still runs when nothing else does. */
 } hg_server_config;
 
-/* Errors: HG_EINVAL (configuration out of range), HG_EDEVICE. */
+/* Errors: HG_EINVAL (configuration out of range), HG_ESTATE (a server owns
+ * the context already), HG_EDEVICE. */
 hg_status hg_server_create(hg_ctx *ctx, const hg_server_config *cfg, hg_server **out);
 
 /* Queue one product.  a_words / b_words: nb * 2 * L * N words each (nb the

@@ -55,6 +55,14 @@ hg_ct *wrap(hg::Ct *c) {
 
 hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
+// While a request server runs, its thread owns the context: every other call
+// that reads or changes the context's state is refused.
+void unowned(const hg::Ctx &X) {
+    if (X.servers > 0)
+        throw hg::Error(HG_ESTATE, "a server owns this context: only hg_server_* and hg_request_footprint may be "
+                                   "called until hg_server_destroy");
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -108,6 +116,7 @@ const char *hg_last_error(void) { return g_err.c_str(); }
 hg_status hg_set_allocator(hg_ctx *ctx, hg_alloc_fn alloc, hg_release_fn release, void *user) {
     return guard([&] {
         need(ctx, "null argument");
+        unowned(*ctx->c);
         need((alloc == nullptr) == (release == nullptr), "alloc and release must be given together");
         hg::Ctx &X = *ctx->c;
         X.ct_alloc_fn = alloc;
@@ -153,6 +162,7 @@ void hg_ctx_destroy(hg_ctx *ctx) {
 hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t nshapes) {
     return guard([&] {
         need(ctx && (shapes || nshapes == 0), "null argument");
+        unowned(*ctx->c);
         hg::Ctx &C = *ctx->c;
         HGCHK(hipSetDevice(C.device));
         std::vector<int> gal;
@@ -176,6 +186,7 @@ hg_status hg_keygen(hg_ctx *ctx, uint64_t seed, const int32_t *shapes, size_t ns
 hg_status hg_keygen_rotations(hg_ctx *ctx, const int32_t *z, size_t count) {
     return guard([&] {
         need(ctx && (z || count == 0), "null argument");
+        unowned(*ctx->c);
         hg::Ctx &C = *ctx->c;
         if (!C.has_secret) throw hg::Error(HG_ESTATE, "keygen with a seed first");
         HGCHK(hipSetDevice(C.device));
@@ -188,6 +199,7 @@ hg_status hg_keygen_rotations(hg_ctx *ctx, const int32_t *z, size_t count) {
 hg_status hg_drop_secret(hg_ctx *ctx) {
     return guard([&] {
         need(ctx, "null context");
+        unowned(*ctx->c);
         ctx->c->drop_secret();
     });
 }
@@ -195,6 +207,7 @@ hg_status hg_drop_secret(hg_ctx *ctx) {
 hg_status hg_encrypt(hg_ctx *ctx, int role, const int64_t *X, int m, int l, int n, uint64_t nonce, hg_ct **out) {
     return guard([&] {
         need(ctx && X && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
         hg::Ctx &C = *ctx->c;
@@ -210,6 +223,7 @@ hg_status hg_set_partition(hg_ctx *ctx, int m, int l, int n, const int32_t *rows
                            int ncols) {
     return guard([&] {
         need(ctx && rows && cols && nrows > 0 && ncols > 0, "null argument or empty partition");
+        unowned(*ctx->c);
         ctx->c->set_partition(m, l, n, std::vector<int>(rows, rows + nrows), std::vector<int>(cols, cols + ncols));
     });
 }
@@ -217,6 +231,7 @@ hg_status hg_set_partition(hg_ctx *ctx, int m, int l, int n, const int32_t *rows
 hg_status hg_get_partition(hg_ctx *ctx, int m, int l, int n, int32_t *out, size_t cap, size_t *count) {
     return guard([&] {
         need(ctx && count, "null argument");
+        unowned(*ctx->c);
         const hg::Ctx::Partition *pt = ctx->c->partition_for(m, l, n);
         std::vector<int32_t> v{pt ? (int32_t)pt->rows.size() : 1, pt ? (int32_t)pt->cols.size() : 1};
         if (pt) {
@@ -238,6 +253,7 @@ hg_status hg_hegmm_batch(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const h
     std::vector<hg::Ct *> made;
     hg_status st = guard([&] {
         need(ctx && A && B && mln && C, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         HGCHK(hipSetDevice(X.device));
         std::vector<hg::Ctx::Request> reqs;
@@ -304,6 +320,7 @@ hg_status hg_hegmm_noalloc(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int 
                            void *stream) {
     return guard([&] {
         need(ctx && ctA && ctB && ctC, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         need(ctA->c->ctx == &X && ctB->c->ctx == &X && ctC->c->ctx == &X, "handle from another context");
         need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
@@ -352,6 +369,7 @@ hg_status hg_graph_create(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const 
     hg::Graph *gr = nullptr;
     hg_status st = guard([&] {
         need(ctx && A && B && mln && C && out, "null argument");
+        unowned(*ctx->c);
         need(cnt > 0, "empty batch");
         *out = nullptr;
         hg::Ctx &X = *ctx->c;
@@ -385,6 +403,7 @@ hg_status hg_graph_create(hg_ctx *ctx, size_t cnt, const hg_ct *const *A, const 
 hg_status hg_graph_launch(hg_graph *g, void *stream) {
     return guard([&] {
         need(g, "null graph");
+        unowned(*g->g->C);
         g->g->launch(as_stream(stream));
     });
 }
@@ -398,6 +417,7 @@ void hg_graph_destroy(hg_graph *g) {
 hg_status hg_ct_load(hg_ctx *ctx, hg_ct *ct, const uint64_t *buf, size_t nwords, void *stream) {
     return guard([&] {
         need(ctx && ct && buf, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         need(ct->c->ctx == &X, "handle from another context");
         HGCHK(hipSetDevice(X.device));
@@ -414,6 +434,7 @@ hg_status hg_hegmm(hg_ctx *ctx, const hg_ct *ctA, const hg_ct *ctB, int m, int l
 hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ct, int m, int l, int n, uint64_t *C) {
     return guard([&] {
         need(ctx && ct && C, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         const hg::Ct &R = *ct->c;
         need(m > 0 && l > 0 && n > 0, "dimensions must be positive");
@@ -453,6 +474,7 @@ hg_status hg_decrypt(hg_ctx *ctx, const hg_ct *ct, int m, int l, int n, uint64_t
 hg_status hg_ct_export(hg_ctx *ctx, const hg_ct *ct, uint64_t *buf, size_t nwords, size_t *needed) {
     return guard([&] {
         need(ctx && ct, "null argument");
+        unowned(*ctx->c);
         const size_t w = ct->c->words();
         if (needed) *needed = w;
         if (!buf) return;
@@ -466,6 +488,7 @@ hg_status hg_ct_export(hg_ctx *ctx, const hg_ct *ct, uint64_t *buf, size_t nword
 hg_status hg_ct_import(hg_ctx *ctx, const uint64_t *buf, size_t nwords, int ncts, int comps, hg_ct **out) {
     return guard([&] {
         need(ctx && buf && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         need(ncts > 0 && (comps == 2 || comps == 3), "bad ciphertext count or component count");
         hg::Ctx &X = *ctx->c;
@@ -484,6 +507,7 @@ void hg_ct_free(hg_ct *ct) {
 hg_status hg_encrypt_slots(hg_ctx *ctx, const int64_t *slots, uint64_t nonce, hg_ct **out) {
     return guard([&] {
         need(ctx && slots && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         hg::Ctx &X = *ctx->c;
         HGCHK(hipSetDevice(X.device));
@@ -499,6 +523,7 @@ hg_status hg_encrypt_slots(hg_ctx *ctx, const int64_t *slots, uint64_t nonce, hg
 hg_status hg_decrypt_slots(hg_ctx *ctx, const hg_ct *ct, uint64_t *slots) {
     return guard([&] {
         need(ctx && ct && slots, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         HGCHK(hipSetDevice(X.device));
         HGCHK(hipDeviceSynchronize());
@@ -510,6 +535,7 @@ hg_status hg_decrypt_slots(hg_ctx *ctx, const hg_ct *ct, uint64_t *slots) {
 hg_status hg_rotate(hg_ctx *ctx, const hg_ct *ct, int z, hg_ct **out, void *stream) {
     return guard([&] {
         need(ctx && ct && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         *out = wrap(ctx->c->rotate(*ct->c, z, as_stream(stream)));
     });
@@ -518,6 +544,7 @@ hg_status hg_rotate(hg_ctx *ctx, const hg_ct *ct, int z, hg_ct **out, void *stre
 hg_status hg_mul(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void *stream) {
     return guard([&] {
         need(ctx && a && b && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         *out = wrap(ctx->c->mul(*a->c, *b->c, as_stream(stream)));
     });
@@ -526,6 +553,7 @@ hg_status hg_mul(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void 
 hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void *stream) {
     return guard([&] {
         need(ctx && a && b && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         *out = wrap(ctx->c->add(*a->c, *b->c, as_stream(stream)));
     });
@@ -534,6 +562,7 @@ hg_status hg_add(hg_ctx *ctx, const hg_ct *a, const hg_ct *b, hg_ct **out, void 
 hg_status hg_mod_switch(hg_ctx *ctx, const hg_ct *ct, int drop, hg_ct **out, void *stream) {
     return guard([&] {
         need(ctx && ct && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         *out = wrap(ctx->c->mod_switch(*ct->c, drop, as_stream(stream)));
     });
@@ -542,6 +571,7 @@ hg_status hg_mod_switch(hg_ctx *ctx, const hg_ct *ct, int drop, hg_ct **out, voi
 hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out, void *stream) {
     return guard([&] {
         need(ctx && a && slots && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         hg::Ctx &X = *ctx->c;
         std::vector<uint64_t> v(X.S);
@@ -556,6 +586,7 @@ hg_status hg_cmul(hg_ctx *ctx, const hg_ct *a, const int64_t *slots, hg_ct **out
 hg_status hg_plan_info(hg_ctx *ctx, int m, int l, int n, int64_t *out) {
     return guard([&] {
         need(ctx && out, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         hg::Plan p;
         try {
@@ -619,6 +650,7 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
 hg_status hg_set_timing(hg_ctx *ctx, int enable) {
     return guard([&] {
         need(ctx, "null context");
+        unowned(*ctx->c);
         need(enable >= 0 && enable <= 2, "timing mode must be 0, 1 or 2");
         ctx->c->timing.enabled = enable == 1;
         ctx->c->launch_timing = enable == 2;
@@ -628,6 +660,7 @@ hg_status hg_set_timing(hg_ctx *ctx, int enable) {
 hg_status hg_launch_timing(hg_ctx *ctx, double *out4) {
     return guard([&] {
         need(ctx && out4, "null argument");
+        unowned(*ctx->c);
         hg::Ctx &X = *ctx->c;
         HGCHK(hipSetDevice(X.device));
         auto read = [&](std::vector<std::pair<hipEvent_t, hipEvent_t>> &v, double *o) {
@@ -654,6 +687,7 @@ hg_status hg_launch_timing(hg_ctx *ctx, double *out4) {
 hg_status hg_last_timing(hg_ctx *ctx, double *out9) {
     return guard([&] {
         need(ctx && out9, "null argument");
+        unowned(*ctx->c);
         for (int i = 0; i < 9; ++i) out9[i] = ctx->c->timing.ms[i];
     });
 }
@@ -677,6 +711,7 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
 hg_status hg_server_create(hg_ctx *ctx, const hg_server_config *cfg, hg_server **out) {
     return guard([&] {
         need(ctx && cfg && out, "null argument");
+        unowned(*ctx->c);
         *out = nullptr;
         hg::ServerConfig sc;
         sc.max_batch = cfg->max_batch;

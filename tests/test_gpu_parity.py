@@ -499,19 +499,30 @@ def test_serving_mix_equals_alone():
 
 
 def test_tune_refused_while_served_and_per_context():
-    """hg_tune is refused while a server owns the context, and a knob set on
-    one context leaves another's results (and knobs) alone."""
+    """hg_tune, and every other call on the context but hg_server_* and
+    hg_request_footprint (a product, an encryption, a decryption, a second
+    server), is refused while a server owns the context; a knob set on one
+    context leaves another's results (and knobs) alone."""
     c = workloads.TINY
     a = hg.Context(c.N, c.t, c.L, c.alpha)
     b = hg.Context(c.N, c.t, c.L, c.alpha)
     for x in (a, b):
         x.keygen(c.seed, [(4, 3, 5)])
     A, B = workloads.tiny_operands()
-    want = a.hegmm(a.encrypt(0, A, 4, 3, 5, nonce=1), a.encrypt(1, B, 4, 3, 5, nonce=1), 4, 3, 5).export()
+    ca, cb = a.encrypt(0, A, 4, 3, 5, nonce=1), a.encrypt(1, B, 4, 3, 5, nonce=1)
+    want = a.hegmm(ca, cb, 4, 3, 5).export()
+    wa, wb = ca.export(), cb.export()
     with hg.Server(a, max_batch=2, lanes=1) as srv:
-        with pytest.raises(hg.HGError) as e:
-            a.tune("ntt_radix", 16)
-        assert e.value.code == hg.HG_ESTATE
+        refused = [lambda: a.tune("ntt_radix", 16), lambda: a.hegmm(ca, cb, 4, 3, 5),
+                   lambda: a.encrypt(0, A, 4, 3, 5, nonce=2), lambda: a.decrypt(ca, 4, 3, 5),
+                   lambda: ca.export(), lambda: hg.Server(a, max_batch=2, lanes=1)]
+        for call in refused:
+            with pytest.raises(hg.HGError) as e:
+                call()
+            assert e.value.code == hg.HG_ESTATE
+        assert a.request_footprint(4, 3, 5) > 0
+        served, _ = srv.wait(srv.submit(wa, wb, 4, 3, 5))
+        assert np.array_equal(served, want)   # the server runs on after the refusals
         b.tune("half_rows", 0)          # another context stays tunable
         srv.pause(True)
         srv.pause(False)
@@ -599,8 +610,9 @@ def test_serving_variants_equal_alone(variant):
         ca, cb = ctx.encrypt(0, A, m, l, n, nonce=50 + i), ctx.encrypt(1, B, m, l, n, nonce=50 + i)
         reqs.append((m, l, n, A, B, ca, cb))
     alone = [ctx.hegmm(ca, cb, m, l, n).export() for (m, l, n, A, B, ca, cb) in reqs]
+    words = [(ca.export(), cb.export()) for (m, l, n, A, B, ca, cb) in reqs]
     with hg.Server(ctx, max_batch=4, lanes=2) as srv:
-        tickets = [srv.submit(ca.export(), cb.export(), m, l, n) for (m, l, n, A, B, ca, cb) in reqs]
+        tickets = [srv.submit(wa, wb, m, l, n) for (wa, wb), (m, l, n, A, B, ca, cb) in zip(words, reqs)]
         outs = [srv.wait(t)[0] for t in tickets]
     for (m, l, n, A, B, ca, cb), o, w in zip(reqs, outs, alone):
         assert np.array_equal(o, w), (m, l, n)
