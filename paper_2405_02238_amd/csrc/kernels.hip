@@ -360,19 +360,23 @@ __device__ __forceinline__ void finish_two(const DevTables &T, const FinJob &J, 
     }
 }
 
-constexpr int FT_P = 64;  // threads along positions per block (two positions each)
-constexpr int FT_C = 8;   // pair chunks per block, reduced through LDS
+constexpr int FT_P = 64;  // threads along positions per block (two positions each): one wave
+constexpr int FT_C = 16;  // pair chunks per block (one per wave), reduced through LDS
 
-// Tensor accumulation: block (128 positions x 8 pair chunks) per (prime i,
-// request); each thread takes two adjacent positions and a strided eighth of
+// Tensor accumulation: block (128 positions x 16 pair chunks) per (prime i,
+// request); each thread takes two adjacent positions and a strided 16th of
 // the request's (eps, omega) pairs, then the partial sums are added in LDS.
 __global__ void __launch_bounds__(FT_P * FT_C)
 k_fin_tensor(DevTables T, const FinJob *jobs, const FinTerm *terms, const double *E, const double *const *masks,
              const int2 *req_pairs, double *const *acc) {
+    static_assert(FT_P == 64, "one pair chunk per wave");
     __shared__ double2 part[3][FT_C][FT_P];
     const int N = 1 << T.logN;
     const int p = 2 * (blockIdx.x * FT_P + threadIdx.x);
-    const int c = threadIdx.y;
+    // threadIdx.y is the same on every lane of a wave: said so, the job
+    // descriptors are scalar loads and the branches on them uniform, instead
+    // of a vector load and a wait per field
+    const int c = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int i = blockIdx.y;
     const int req = blockIdx.z;
     const double q = T.qt[i].x, qi = T.qt[i].y;
