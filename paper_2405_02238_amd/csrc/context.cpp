@@ -291,6 +291,8 @@ void Arena::release() {
     base = pinned = pinned_dev = acc = nullptr;
     staged = nullptr;
     cap = pinned_cap = acc_cap = 0;
+    slot = 0;
+    copies = 0;
 }
 
 Arena &Ctx::arena_for(hipStream_t st) {
@@ -307,7 +309,10 @@ Arena &Ctx::arena_for(hipStream_t st) {
 
 Arena &Ctx::arena(hipStream_t st) {
     Arena &a = arenas[st];
-    if (!a.staged) HGCHK(hipEventCreateWithFlags(&a.staged, hipEventDisableTiming));
+    if (!a.staged) {
+        HGCHK(hipEventCreateWithFlags(&a.staged, hipEventDisableTiming));
+        a.ring = 8;
+    }
     return a;
 }
 

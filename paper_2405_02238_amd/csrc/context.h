@@ -59,10 +59,20 @@ struct Arena {
     void *base = nullptr;
     size_t cap = 0;
     size_t used = 0;
-    void *pinned = nullptr;      // host staging for descriptor tables
+    void *pinned = nullptr;      // host staging for descriptor tables: `ring` slots of pinned_cap bytes
     void *pinned_dev = nullptr;  // the same memory as the device addresses it
     size_t pinned_cap = 0;
-    hipEvent_t staged = nullptr; // completion of the last copy out of `pinned`
+    hipEvent_t staged = nullptr; // completion of the copy out of the ring's last slot (ring 1: of every copy)
+    // Stream arenas stage call after call in a ring of slots, one stream
+    // ordering every copy, so only the copy out of the last slot carries a
+    // completion signal (a dispatch the host can wait on ends with a
+    // system-scope release, a few microseconds), and the host waits on it
+    // before it writes the first slot again.  Graph and fixed arenas keep
+    // one slot: a graph replays the bytes of its slot, a fixed arena is used
+    // from any stream.
+    int ring = 1;
+    int slot = 0;                // the slot the next call writes
+    uint64_t copies = 0;         // copies out of the ring since it was made
     void *acc = nullptr;         // per-call accumulators (3 x L x N per product, R for folds)
     size_t acc_cap = 0;
     // A fixed arena (fixed_bytes > 0) never grows: each call places its

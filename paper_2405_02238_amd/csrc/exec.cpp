@@ -323,17 +323,27 @@ struct Exec {
             A.cap = align_up(A.exact ? total : total + total / 4, 1 << 20);
             HGCHK(hipMalloc(&A.base, A.cap));
         }
+        const bool ringed = A.ring > 1;
         if (tl.total > A.pinned_cap) {
-            HGCHK(hipEventSynchronize(A.staged));
+            // every copy out of the old staging is done (a ring's last
+            // signal need not cover the latest copies: drain its stream)
+            if (ringed) HGCHK(hipStreamSynchronize(st));
+            else HGCHK(hipEventSynchronize(A.staged));
             if (A.pinned) HGCHK(hipHostFree(A.pinned));
             A.pinned_cap = align_up(tl.total * 2, 1 << 16);
-            HGCHK(hipHostMalloc(&A.pinned, A.pinned_cap, hipHostMallocDefault));
+            HGCHK(hipHostMalloc(&A.pinned, A.pinned_cap * (size_t)A.ring, hipHostMallocDefault));
             HGCHK(hipHostGetDevicePointer(&A.pinned_dev, A.pinned, 0));
+            A.slot = 0;
+            A.copies = 0;
         }
-        // the previous copy out of staging is done (a graph's arenas are
-        // private and were drained before recording)
-        if (!C.capturing) HGCHK(hipEventSynchronize(A.staged));
-        char *h = (char *)A.pinned;
+        // the previous copy out of the slot about to be written is done: one
+        // slot, the last copy; a ring, on entering its first slot again, the
+        // copy out of its last slot and so every earlier one on the stream
+        // (a graph's arenas are private and were drained before recording)
+        if (!C.capturing && (!ringed || (A.slot == 0 && A.copies >= (uint64_t)A.ring)))
+            HGCHK(hipEventSynchronize(A.staged));
+        char *h = (char *)A.pinned + (size_t)A.slot * A.pinned_cap;
+        const char *h_dev = (const char *)A.pinned_dev + (size_t)A.slot * A.pinned_cap;
         char *base = (char *)A.base;
         char *tab = base + scratch;
         auto put = [&](size_t o, const void *src, size_t bytes) {
@@ -387,7 +397,12 @@ struct Exec {
         }
         // a kernel reads the tables straight out of the pinned buffer: cheaper
         // on the stream than a copy-engine transfer and its barrier
-        copy_from_host(tab, A.pinned_dev, tl.total, st, C.capturing ? nullptr : A.staged);
+        const bool signal = !C.capturing && (!ringed || A.slot == A.ring - 1);
+        copy_from_host(tab, h_dev, tl.total, st, signal ? A.staged : nullptr);
+        if (ringed) {
+            A.slot = (A.slot + 1) % A.ring;
+            ++A.copies;
+        }
     }
 
     // True when a pass's result per job is exactly its division by P (every
