@@ -132,6 +132,31 @@ def test_hegmm_shapes(tiny, shape):
     run_pair(tiny, m, l, n, A, B, nonce=7)
 
 
+def test_hegmm_degenerate_shapes():
+    """Shapes at the method's edges, each bit-identical to the oracle and
+    decrypting to A.B mod t: 1x1x1 and an inner dimension of 1 (one loop
+    trip, no rotation at all: only the relinearisation key switch), a single
+    row of A (six stacked copies of A and a fold of five rotations), a single
+    column of B (the transposed orientation), and a product that fills the
+    512 slots of the ring exactly (M W = 16 x 32)."""
+    c = workloads.TINY
+    shapes = [(1, 1, 1), (1, 5, 1), (1, 1, 6), (6, 1, 1), (3, 1, 4), (1, 6, 4), (4, 6, 1), (16, 16, 32)]
+    pair = Pair(c.N, c.t, c.L, c.alpha, c.seed + 5, shapes=shapes)
+    assert pair.ctx.plan_info(1, 1, 1)["rotations"] == 0
+    rng = np.random.default_rng(77)
+    ops = []
+    for i, (m, l, n) in enumerate(shapes):
+        A = rng.integers(-8, 9, size=(m, l))
+        B = rng.integers(-8, 9, size=(l, n))
+        run_pair(pair, m, l, n, A, B, nonce=60 + i)
+        ops.append((pair.ctx.encrypt(0, A, m, l, n, nonce=60 + i), pair.ctx.encrypt(1, B, m, l, n, nonce=60 + i)))
+    # the same products in one batch (shared launches): each result as alone
+    alone = [pair.ctx.hegmm(a, b, *s).export() for (a, b), s in zip(ops, shapes)]
+    batch = pair.ctx.hegmm_batch([a for a, _ in ops], [b for _, b in ops], shapes)
+    for s, got, want in zip(shapes, batch, alone):
+        assert np.array_equal(got.export(), want), s
+
+
 @pytest.mark.parametrize("min_blocks", [2, 3])
 def test_hegmm_forced_blocks(min_blocks):
     """The blockwise product (inner dimension split into at least k blocks,
