@@ -191,6 +191,9 @@ struct Exec {
         std::vector<int> rounds;  // first chunk of each round, then the chunk count
         double *coef = nullptr, *y = nullptr, *rk = nullptr;
         int nsrc = 0, nks = 0;
+        // the pass's key-switched terms use each key at least twice on
+        // average: its inner products read keys and masks through the caches
+        bool key_reuse = false;
     };
 
     struct Staged {
@@ -388,6 +391,9 @@ struct Exec {
             dv.t_srcs = o.srcs;
             dv.nsrc = (int)ps.srcs.size();
             dv.nks = (int)ps.ip_jobs.size();
+            size_t switched = 0;
+            for (const IpTerm &tm : ps.ip_terms) switched += tm.kind != IP_PLAIN;
+            dv.key_reuse = switched >= 2 * ps.keys.size() && !ps.keys.empty();
             Layout lay;
             dv.coef = (double *)(base + lay.add((size_t)dv.nsrc * L * N * 8));
             dv.y = (double *)(base + lay.add((size_t)dv.nsrc * beta * nExt * N * 8));
@@ -532,7 +538,8 @@ struct Exec {
                 t0 = tm->pooled ? C.lt_event() : C.event(st, true);
                 t1 = tm->pooled ? C.lt_event() : C.event(st, true);
             }
-            ip_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0, transform_pass, st, t0, t1);
+            ip_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0, transform_pass, st, t0, t1,
+                      dv.key_reuse);
             if (tm) tm->ip_pairs.push_back({t0, t1});
             if (tev && c == nch - 1) HGCHK(hipEventRecord(tev[1], st));
             if (s2 != st) {

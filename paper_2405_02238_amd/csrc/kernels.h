@@ -149,10 +149,14 @@ bool ntt_halves_ok(const DevTables &T, int rows);
 // Inner products: U[slot][c][r][p] = sum over the job's key-switched terms of
 // mask[r][p] * sum_j key[j][c][r][p] * y[src][j][r][perm_g(p)], plus P times
 // the unswitched part on the ciphertext primes (see IpTerm).
-// ev0 / ev1 (optional) receive the start and end of the launch.
+// ev0 / ev1 (optional) receive the start and end of the launch.  Keys and
+// masks are read with non-temporal loads (each word once per launch), or,
+// with key_reuse (the launch's terms share keys, jobs in key order),
+// through the caches, so that jobs started side by side find them there.
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
-               bool transform_pass, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+               bool transform_pass, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+               bool key_reuse = false);
 
 // Key-stationary variant, one launch per round of key-switched terms:
 // tasks[i] = (job, term); chunks[c] = (first task, count), all tasks of a

@@ -69,8 +69,11 @@ __device__ __forceinline__ void st2(double *p, double2 v) {
 // of the hoisted digits; two consecutive positions per thread (16-byte key
 // loads), the digit loop unrolled (BETA digits) so that all key loads of a
 // term are in flight together.  grid: (N / 512, nExt, jobs).
-// TAG only names the launch for profilers (0: the eps/omega transform pass,
-// 1: relinearisation, fold and single-ciphertext passes); the code is the same.
+// TAG names the launch for profilers (0: the eps/omega transform pass,
+// 1: relinearisation, fold and single-ciphertext passes; the code is the
+// same) and selects the load of keys and masks: non-temporal (0, 1: each
+// word is read once per launch), or through the caches (2: a transform pass
+// whose terms share keys, its jobs started in key order).
 template <int BETA, int TAG>
 __global__ void __launch_bounds__(IP_THREADS)
 k_ip(DevTables T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
@@ -89,7 +92,8 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
     for (int tix = J.t0; tix < J.t0 + J.nt; ++tix) {
         const IpTerm tm = terms[tix];
         double2 mv = make_double2(1.0, 1.0);
-        if (tm.mask >= 0) mv = ld_stream2(masks[tm.mask] + (size_t)r * N + p);
+        if (tm.mask >= 0)
+            mv = TAG == 2 ? ld2(masks[tm.mask] + (size_t)r * N + p) : ld_stream2(masks[tm.mask] + (size_t)r * N + p);
         // positions p, p + 1 (p even) gather from the aligned pair {pb, pb + 1}
         // (the automorphism flips bit 0 of the source with bit 0 of p), in
         // swapped order when sw
@@ -107,7 +111,7 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
                 const double2 v = ld2(ys + (size_t)j * plane + pb);
                 y0[j] = sw ? v.y : v.x;
                 y1[j] = sw ? v.x : v.y;
-                kbv[j] = ld_stream2(kb + (size_t)j * plane);
+                kbv[j] = TAG == 2 ? ld2(kb + (size_t)j * plane) : ld_stream2(kb + (size_t)j * plane);
             }
 #pragma unroll
             for (int j = 0; j < BETA; ++j)
@@ -666,14 +670,14 @@ static void launch_timed(F kernel, dim3 grid, dim3 block, hipStream_t s, hipEven
 
 void ip_launch(const DevTables &T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs, bool transform_pass,
-               hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+               hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, bool key_reuse) {
     if (njobs <= 0 || njobs > MAX_GRID_Z) {
         // nothing to launch, or the z extent of a launch is limited: split,
         // timed by events around the launches
         if (ev0) (void)hipEventRecord(ev0, s);   // a failed record surfaces when the timing is read
         for (int o = 0; o < njobs; o += MAX_GRID_Z)
             ip_launch(T, U, y, keys, streams, masks, jobs + o, terms, std::min(MAX_GRID_Z, njobs - o),
-                      transform_pass, s);
+                      transform_pass, s, nullptr, nullptr, key_reuse);
         if (ev1) (void)hipEventRecord(ev1, s);
         return;
     }
@@ -681,7 +685,9 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
     switch (T.beta) {
 #define HG_IP_CASE(B)                                                                                        \
     case B:                                                                                                  \
-        if (transform_pass)                                                                                  \
+        if (transform_pass && key_reuse)                                                                     \
+            launch_timed(k_ip<B, 2>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, terms); \
+        else if (transform_pass)                                                                             \
             launch_timed(k_ip<B, 0>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, terms); \
         else                                                                                                 \
             launch_timed(k_ip<B, 1>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, keys, streams, masks, jobs, terms); \
