@@ -77,6 +77,23 @@ struct Exec {
     Exec(Ctx &c, hipStream_t s)
         : C(c), st(s), A(c.arena_for(s)), T(c.T), N(c.N), L(c.L), nExt(c.nExt), beta(c.beta), alpha(c.alpha) {}
 
+    // The staged tables' copy to the device, not yet enqueued: the first
+    // launch after stage() either does it in extra workgroups of a fused
+    // hoist (sources by value) or enqueues it on its own (flush) before
+    // anything reads the tables.
+    struct Pending {
+        void *dst = nullptr;
+        const void *src = nullptr;
+        size_t bytes = 0;
+        hipEvent_t done = nullptr;   // completion signal the staging ring waits on
+    } pend;
+
+    void flush() {
+        if (!pend.dst) return;
+        copy_from_host(pend.dst, pend.src, pend.bytes, st, pend.done);
+        pend = Pending();
+    }
+
     // Accumulator space for this call (stream-ordered reuse of one buffer per
     // arena; grown with the stream drained, never while recording a graph).
     double *acc(size_t bytes) {
@@ -191,6 +208,7 @@ struct Exec {
         std::vector<int> rounds;  // first chunk of each round, then the chunk count
         double *coef = nullptr, *y = nullptr, *rk = nullptr;
         int nsrc = 0, nks = 0;
+        const std::vector<const double *> *srcs_h = nullptr;   // the hoisted sources (host copy of the table)
         // the pass's key-switched terms use each key at least twice on
         // average: its inner products read keys and masks through the caches
         bool key_reuse = false;
@@ -390,6 +408,7 @@ struct Exec {
             dv.t_streams = o.streams;
             dv.t_srcs = o.srcs;
             dv.nsrc = (int)ps.srcs.size();
+            dv.srcs_h = &ps.srcs;
             dv.nks = (int)ps.ip_jobs.size();
             size_t switched = 0;
             for (const IpTerm &tm : ps.ip_terms) switched += tm.kind != IP_PLAIN;
@@ -404,7 +423,11 @@ struct Exec {
         // a kernel reads the tables straight out of the pinned buffer: cheaper
         // on the stream than a copy-engine transfer and its barrier
         const bool signal = !C.capturing && (!ringed || A.slot == A.ring - 1);
-        copy_from_host(tab, h_dev, tl.total, st, signal ? A.staged : nullptr);
+        flush();   // a previous stage's copy (not expected: every stage is launched)
+        pend.dst = tab;
+        pend.src = h_dev;
+        pend.bytes = tl.total;
+        pend.done = signal ? A.staged : nullptr;
         if (ringed) {
             A.slot = (A.slot + 1) % A.ring;
             ++A.copies;
@@ -478,8 +501,23 @@ struct Exec {
         // separate launches (throughput bound)
         const bool fuse_hoist = fused_ok(T) && dv.nsrc * beta * nExt <= C.fuse_rows;
         if (dv.nks > 0 && fuse_hoist) {
-            hoist_fused(T, dv.y, (const double *const *)(dv.tab + dv.t_srcs), dv.nsrc, st);
+            if (pend.dst && dv.srcs_h && (int)dv.srcs_h->size() == dv.nsrc && hoist_copy_ok(dv.nsrc, pend.bytes)) {
+                // the first launch of the call: the hoist takes its sources
+                // by value and copies the tables in extra workgroups
+                HoistSrc a{};
+                for (int i = 0; i < dv.nsrc; ++i) a.p[i] = (*dv.srcs_h)[i];
+                a.copy_src = (const uint4 *)pend.src;
+                a.copy_dst = (uint4 *)pend.dst;
+                a.copy_n = pend.bytes / 16;
+                a.copy_wgs = (int)std::min<size_t>(8, (a.copy_n + 1023) / 1024);
+                hoist_fused_copy(T, dv.y, a, dv.nsrc, st, pend.done);
+                pend = Pending();
+            } else {
+                flush();
+                hoist_fused(T, dv.y, (const double *const *)(dv.tab + dv.t_srcs), dv.nsrc, st);
+            }
         }
+        flush();
         if (dv.nks <= 0) {
             if (tev)
                 for (int i = 0; i < 3; ++i) HGCHK(hipEventRecord(tev[i], st));

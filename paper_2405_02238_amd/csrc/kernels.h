@@ -124,6 +124,24 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
 //  moddown_fused: E[slot][i] = (U_i - NTT_i(t (P/p) center(INTT_p(U_p) ...))) P^-1
 bool fused_ok(const DevTables &T);
 void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int nsrc, hipStream_t s);
+
+// hoist_fused with its sources by value and a copy out of pinned host memory
+// (a call's descriptor tables, needed by the launches after it) done by extra
+// workgroups of the same launch: n16 16-byte words from copy_src (device
+// address of pinned memory) to copy_dst.  `done` (optional) is recorded by
+// the launch's own completion.  At most HOIST_MAX_SRC sources and
+// HOIST_MAX_COPY words (hoist_copy_ok).
+constexpr int HOIST_MAX_SRC = 8;
+constexpr size_t HOIST_MAX_COPY = (size_t)1 << 16;
+struct HoistSrc {
+    const double *p[HOIST_MAX_SRC];
+    const uint4 *copy_src;
+    uint4 *copy_dst;
+    unsigned long long copy_n;
+    int copy_wgs;
+};
+bool hoist_copy_ok(int nsrc, size_t copy_bytes);
+void hoist_fused_copy(const DevTables &T, double *y, const HoistSrc &a, int nsrc, hipStream_t s, hipEvent_t done);
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s,
                    double *const *outs = nullptr);
 

@@ -986,19 +986,53 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
 // evaluation-form row j of the source's c1 is inverse-transformed, centered
 // (the digit lift of a one-prime digit) and forward-transformed under prime
 // r, all in LDS.  Row r = j is the source row itself.
+// The row of workgroup `wg`: (source, digit j, prime r), and with SPLIT the
+// half of the forward transform it finishes (two workgroups per row).
+template <int SPLIT>
+__device__ __forceinline__ void hoist_row(const DevTables &T, int wg, int &row, int &hh, int &r, int &j, int &src) {
+    row = SPLIT ? wg >> 1 : wg;
+    hh = SPLIT ? (wg & 1) : -1;
+    r = row % T.nExt;
+    j = (row / T.nExt) % T.beta;
+    src = row / (T.nExt * T.beta);
+}
+
+template <int LOGN, int RK, int SPLIT>
+__device__ __forceinline__ void hoist_body(const DevTables &T, double *y, const double *c1, int row, int hh, int r,
+                                           int j, double *sh);
+
 template <int LOGN, int RK = rk_of(LOGN), int SPLIT = 0>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
 k_hoist_fused(DevTables T, double *y, const double *const *srcs) {
     extern __shared__ double sh[];
+    int row, hh, r, j, src;
+    hoist_row<SPLIT>(T, (int)blockIdx.x, row, hh, r, j, src);
+    hoist_body<LOGN, RK, SPLIT>(T, y, srcs[src], row, hh, r, j, sh);
+}
+
+// The same with the sources by value; workgroups past the hoist's copy a
+// call's descriptor tables out of pinned host memory meanwhile.
+template <int LOGN, int RK = rk_of(LOGN), int SPLIT = 0>
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
+k_hoist_fused_copy(DevTables T, double *y, HoistSrc a) {
+    extern __shared__ double sh[];
+    const int hoist_wgs = (int)gridDim.x - a.copy_wgs;
+    if ((int)blockIdx.x >= hoist_wgs) {
+        const size_t stride = (size_t)a.copy_wgs * blockDim.x;
+        for (size_t i = (size_t)(blockIdx.x - hoist_wgs) * blockDim.x + threadIdx.x; i < a.copy_n; i += stride)
+            a.copy_dst[i] = a.copy_src[i];
+        return;
+    }
+    int row, hh, r, j, src;
+    hoist_row<SPLIT>(T, (int)blockIdx.x, row, hh, r, j, src);
+    hoist_body<LOGN, RK, SPLIT>(T, y, a.p[src], row, hh, r, j, sh);
+}
+
+template <int LOGN, int RK, int SPLIT>
+__device__ __forceinline__ void hoist_body(const DevTables &T, double *y, const double *c1, int row, int hh, int r,
+                                           int j, double *sh) {
     constexpr int N = 1 << LOGN;
-    // SPLIT: two workgroups per row, each finishing one half of the forward
-    // transform (hh = the half)
-    const int row = SPLIT ? blockIdx.x >> 1 : blockIdx.x;
-    const int hh = SPLIT ? (int)(blockIdx.x & 1) : -1;
-    const int r = row % T.nExt;
-    const int j = (row / T.nExt) % T.beta;
-    const int src = row / (T.nExt * T.beta);
-    const double *c = srcs[src] + (size_t)j * N;
+    const double *c = c1 + (size_t)j * N;
     double *out = y + (size_t)row * N;
     if (r == j) {
         const int i0 = hh < 0 ? 0 : hh * (N / 2), i1 = hh < 0 ? N : i0 + N / 2;
@@ -1154,6 +1188,8 @@ void set_lds_attrs() {
     (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused_copy<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused_copy<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA_H, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR_H, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -1179,7 +1215,7 @@ int ntt_radix_rk(int radix) {
 template <typename... Args, typename F = void (*)(Args...)>
 static void launch_ev(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
                       Args... args) {
-    if (ev0) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev0, ev1, 0, args...);
+    if (ev0 || ev1) hipExtLaunchKernelGGL(kernel, grid, block, lds, s, ev0, ev1, 0, args...);
     else hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
 }
 
@@ -1276,6 +1312,25 @@ void hoist_fused(const DevTables &T, double *y, const double *const *srcs, int n
                            y, srcs)
     HG_LOGN_RK_SWITCH(T.logN, HG_HF)
 #undef HG_HF
+}
+
+bool hoist_copy_ok(int nsrc, size_t copy_bytes) {
+    return nsrc > 0 && nsrc <= HOIST_MAX_SRC && copy_bytes % 16 == 0 && copy_bytes / 16 <= HOIST_MAX_COPY;
+}
+
+void hoist_fused_copy(const DevTables &T, double *y, const HoistSrc &a, int nsrc, hipStream_t s, hipEvent_t done) {
+    if (!hoist_copy_ok(nsrc, a.copy_n * 16) || a.copy_wgs < 1)
+        throw std::invalid_argument("hoist_fused_copy: sources or copy outside the launch's range");
+    const int rows = nsrc * T.beta * T.nExt;
+    const int split = half_split(T, rows) ? 1 : 0;
+    const dim3 grid((unsigned)((rows << split) + a.copy_wgs)), block(ntt_threads(T));
+#define HG_HFC(LN, RK)                                                                                 \
+    if (split)                                                                                         \
+        launch_ev(k_hoist_fused_copy<LN, RK, 1>, grid, block, ntt_lds_bytes(T.N), s, nullptr, done, T, y, a); \
+    else                                                                                               \
+        launch_ev(k_hoist_fused_copy<LN, RK, 0>, grid, block, ntt_lds_bytes(T.N), s, nullptr, done, T, y, a)
+    HG_LOGN_RK_SWITCH(T.logN, HG_HFC)
+#undef HG_HFC
 }
 
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s, double *const *outs) {
