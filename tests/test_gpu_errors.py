@@ -136,6 +136,34 @@ def test_repeat_and_stream_determinism(ctx):
     assert np.array_equal(ctx.hegmm(ca, cb, 4, 3, 5).export(), first)
 
 
+def test_back_to_back_products_through_the_staging_ring():
+    """24 products of alternating shapes and operands enqueued back to back
+    on one stream with no synchronisation: the host stages each call's
+    descriptor tables in the next slot of its ring while the device may
+    still be copying out of earlier ones (only every eighth copy is waited
+    for), three times round the ring.  Each result equals the same product
+    computed on its own."""
+    c = workloads.TINY
+    shapes = [(4, 3, 5), (2, 5, 7), (5, 4, 2)]
+    ctx = hg.Context(c.N, c.t, c.L, c.alpha)
+    ctx.keygen(c.seed, shapes)
+    rng = np.random.default_rng(24)
+    ops = []
+    for i, (m, l, n) in enumerate(shapes * 2):
+        A, B = rng.integers(-8, 9, size=(m, l)), rng.integers(-8, 9, size=(l, n))
+        ops.append(((m, l, n), ctx.encrypt(0, A, m, l, n, nonce=90 + i), ctx.encrypt(1, B, m, l, n, nonce=90 + i)))
+    alone = []
+    for shape, a, b in ops:
+        alone.append(ctx.hegmm(a, b, *shape).export())
+        torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        outs = [ctx.hegmm(ops[i % len(ops)][1], ops[i % len(ops)][2], *ops[i % len(ops)][0]) for i in range(24)]
+    s.synchronize()
+    for i, o in enumerate(outs):
+        assert np.array_equal(o.export(), alone[i % len(ops)]), i
+
+
 def test_batch_rejects_before_any_work(ctx):
     """A batch with one request that cannot run (no rotation keys for its
     shape) is refused as a whole before anything is enqueued; the same
