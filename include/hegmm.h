@@ -414,10 +414,13 @@ hg_status hg_request_footprint(hg_ctx *ctx, int m, int l, int n, uint64_t *bytes
  *                the forward transform (default 128; 0: off)
  *   "ntt_radix"  radix of the one-workgroup row transforms of 4096- and
  *                8192-point rows: 8, 16, or 0 for the built-in choice (8)
+ *   "xcd_rows"   1 (default): one-workgroup forward transforms hand each
+ *                XCD a contiguous block of rows, so rows reading the same
+ *                input row share an L2; 0: rows in workgroup order
  *   "batch_window" products per launch group inside hg_hegmm_batch
  *                (0: all at once; default 64, 16 for N >= 16384)
  * Errors: HG_EINVAL (unknown name, negative value, "pipeline" outside
- * [1, 16], "ntt_radix" other than 0, 8, 16). */
+ * [1, 16], "ntt_radix" other than 0, 8, 16, "xcd_rows" other than 0, 1). */
 hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value);
 
 /* ---- introspection ---------------------------------------------------- */

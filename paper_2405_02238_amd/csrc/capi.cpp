@@ -634,6 +634,10 @@ hg_status hg_tune(hg_ctx *ctx, const char *name, int64_t value) {
         else if (n == "ip_order") X.ip_order = (int)value;
         else if (n == "split_rows") set_tables(&hg::DevTables::split_rows, (int)value);
         else if (n == "half_rows") set_tables(&hg::DevTables::half_rows, (int)value);
+        else if (n == "xcd_rows") {
+            need(value == 0 || value == 1, "xcd_rows must be 0 or 1");
+            set_tables(&hg::DevTables::xcd_rows, (int)value);
+        }
         else if (n == "ntt_radix") {
             need(value == 0 || value == 8 || value == 16, "ntt_radix must be 0, 8 or 16");
             set_tables(&hg::DevTables::row_rk, hg::ntt_radix_rk((int)value));

@@ -33,6 +33,7 @@ struct DevTables {
     int row_rk = 0;       // radix exponent of 4096- and 8192-point rows (3, 4; 0: built-in)
     int half_rows = 128;  // fused chains of at most this many rows split their forward transforms in halves
     int split_rows = 0;   // transforms of fewer rows split each row over N/1024 workgroups (0: only N > 16384)
+    int xcd_rows = 1;     // 1: one-workgroup forward rows assigned to XCDs in contiguous blocks (0: by index)
 };
 
 // Terms of an inner-product job.  A job computes, over the extended basis,

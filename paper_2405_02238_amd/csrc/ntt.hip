@@ -766,12 +766,26 @@ __device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, i
 
 // ---- one workgroup per row ----
 
+// Workgroups of a launch go to the 8 XCDs (each with its own L2) in turn by
+// index.  With xcd_rows set, workgroup w takes the row that makes each XCD's
+// workgroups a contiguous block of rows, so rows that read the same input
+// row (the L primes of a division slot, the nExt primes of a hoisted digit)
+// share that XCD's L2.  A permutation of the rows: every row is still done
+// once, by one workgroup.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_row(int w, int n) {
+    const int x = w % NUM_XCD, k = w / NUM_XCD;
+    const int per = n / NUM_XCD, extra = n % NUM_XCD;   // XCD x holds per + (x < extra) workgroups
+    return x * per + min(x, extra) + k;
+}
+
 template <int LOAD, int LOGN, int RK = rk_of(LOGN)>
 __global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
 k_ntt_fwd(DevTables T, NttArgs a) {
     extern __shared__ double sh[];
     constexpr int N = 1 << LOGN;
-    const FwdRow R = fwd_row<LOAD>(T, a, blockIdx.x);
+    const int wrow = T.xcd_rows ? xcd_row((int)blockIdx.x, (int)gridDim.x) : (int)blockIdx.x;
+    const FwdRow R = fwd_row<LOAD>(T, a, wrow);
     const double *tw = T.twf + (size_t)R.prime * N;
     if constexpr (LOAD == LOAD_DELTA_H) {
         if constexpr (direct_rows<LOGN>()) {
