@@ -212,6 +212,9 @@ struct Exec {
         // the pass's key-switched terms use each key at least twice on
         // average: its inner products read keys and masks through the caches
         bool key_reuse = false;
+        // one job with one term: its inner products take it by value
+        bool one_ok = false;
+        IpOne one{};
     };
 
     struct Staged {
@@ -413,6 +416,28 @@ struct Exec {
             size_t switched = 0;
             for (const IpTerm &tm : ps.ip_terms) switched += tm.kind != IP_PLAIN;
             dv.key_reuse = switched >= 2 * ps.keys.size() && !ps.keys.empty();
+            dv.one_ok = false;
+            if (ps.ip_jobs.size() == 1 && ps.ip_jobs[0].nt <= IP_ONE_MAX_TERMS && beta <= IP_ONE_MAX_BETA) {
+                const IpJob &J = ps.ip_jobs[0];
+                dv.one = IpOne{};
+                dv.one.J = J;
+                int key = -1;
+                bool ok = true;
+                for (int u = 0; u < J.nt; ++u) {
+                    const IpTerm &tm = ps.ip_terms[J.t0 + u];
+                    dv.one.tm[u] = tm;
+                    dv.one.mask[u] = tm.mask >= 0 ? ps.masks[tm.mask] : nullptr;
+                    if (tm.kind != IP_PLAIN) {
+                        ok = ok && tm.key >= 0 && (key < 0 || key == tm.key);
+                        key = tm.key;
+                    }
+                }
+                if (key >= 0) {
+                    dv.one.key = ps.keys[key];
+                    for (int j = 0; j < beta; ++j) dv.one.st[j] = streams[i][(size_t)key * beta + j];
+                }
+                dv.one_ok = ok;
+            }
             Layout lay;
             dv.coef = (double *)(base + lay.add((size_t)dv.nsrc * L * N * 8));
             dv.y = (double *)(base + lay.add((size_t)dv.nsrc * beta * nExt * N * 8));
@@ -512,6 +537,11 @@ struct Exec {
                 a.copy_wgs = (int)std::min<size_t>(8, (a.copy_n + 1023) / 1024);
                 hoist_fused_copy(T, dv.y, a, dv.nsrc, st, pend.done);
                 pend = Pending();
+            } else if (dv.srcs_h && (int)dv.srcs_h->size() == dv.nsrc && dv.nsrc <= HOIST_MAX_SRC) {
+                flush();
+                HoistSrc a{};
+                for (int i = 0; i < dv.nsrc; ++i) a.p[i] = (*dv.srcs_h)[i];
+                hoist_fused_v(T, dv.y, a, dv.nsrc, st);
             } else {
                 flush();
                 hoist_fused(T, dv.y, (const double *const *)(dv.tab + dv.t_srcs), dv.nsrc, st);
@@ -576,8 +606,11 @@ struct Exec {
                 t0 = tm->pooled ? C.lt_event() : C.event(st, true);
                 t1 = tm->pooled ? C.lt_event() : C.event(st, true);
             }
-            ip_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0, transform_pass, st, t0, t1,
-                      dv.key_reuse);
+            if (dv.one_ok && nch == 1)
+                ip_one_launch(T, dv.U, dv.y, dv.one, st, t0, t1);
+            else
+                ip_launch(T, dv.U, dv.y, keys, streams, dv.masks, jobs + j0, terms, j1 - j0, transform_pass, st, t0,
+                          t1, dv.key_reuse);
             if (tm) tm->ip_pairs.push_back({t0, t1});
             if (tev && c == nch - 1) HGCHK(hipEventRecord(tev[1], st));
             if (s2 != st) {

@@ -143,6 +143,9 @@ struct HoistSrc {
 };
 bool hoist_copy_ok(int nsrc, size_t copy_bytes);
 void hoist_fused_copy(const DevTables &T, double *y, const HoistSrc &a, int nsrc, hipStream_t s, hipEvent_t done);
+// hoist_fused with its sources a.p[0 .. nsrc) by value and no copy (the
+// copy fields are ignored): the row loads start without a table read first.
+void hoist_fused_v(const DevTables &T, double *y, const HoistSrc &a, int nsrc, hipStream_t s);
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s,
                    double *const *outs = nullptr);
 
@@ -176,6 +179,23 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
                const double *const *masks, const IpJob *jobs, const IpTerm *terms, int njobs,
                bool transform_pass, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
                bool key_reuse = false);
+
+// A launch of one job of at most two terms whose key-switched terms share
+// one key (a relinearisation: the unswitched term and the key switch of
+// c2; a single rotation), everything the kernel would look up in the pass's
+// tables given by value, so that its loads of keys, digits and masks start
+// without three dependent table reads first.  J.t0 is not used.
+constexpr int IP_ONE_MAX_BETA = 12;
+constexpr int IP_ONE_MAX_TERMS = 2;
+struct IpOne {
+    IpJob J;
+    IpTerm tm[IP_ONE_MAX_TERMS];
+    const double *mask[IP_ONE_MAX_TERMS];   // each term's mask (null: none)
+    const double *key;                      // b half of the key (null: no key-switched term)
+    uint64_t st[IP_ONE_MAX_BETA];           // a-half streams of that key, one per digit
+};
+void ip_one_launch(const DevTables &T, double *U, const double *y, const IpOne &one, hipStream_t s,
+                   hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Key-stationary variant, one launch per round of key-switched terms:
 // tasks[i] = (job, term); chunks[c] = (first task, count), all tasks of a

@@ -5,6 +5,7 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <stdexcept>
 
 #include "arith.h"
 #include "dev_common.h"
@@ -73,11 +74,13 @@ __device__ __forceinline__ void st2(double *p, double2 v) {
 // 1: relinearisation, fold and single-ciphertext passes; the code is the
 // same) and selects the load of keys and masks: non-temporal (0, 1: each
 // word is read once per launch), or through the caches (2: a transform pass
-// whose terms share keys, its jobs started in key order).
+// whose terms share keys, its jobs started in key order).  TAG 3: the
+// launch's single job and its terms come by value in `one` (ip_one_launch)
+// and the tables are not read; keys and masks load as with TAG 1.
 template <int BETA, int TAG>
-__global__ void __launch_bounds__(IP_THREADS)
-k_ip(DevTables T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
-     const double *const *masks, const IpJob *jobs, const IpTerm *terms) {
+__device__ __forceinline__ void ip_body(const DevTables &T, double *U, const double *y, const double *const *keys,
+                                        const uint64_t *streams, const double *const *masks, const IpJob *jobs,
+                                        const IpTerm *terms, const IpOne &one) {
     const int N = 1 << T.logN;
     const int p = 2 * (blockIdx.x * blockDim.x + threadIdx.x);
     const int r = blockIdx.y;
@@ -85,15 +88,18 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
     if (p >= N) return;
     const double q = T.qt[r].x, qi = T.qt[r].y;
     const size_t plane = (size_t)T.nExt * N;   // one digit (or component) of all primes
-    const IpJob J = jobs[job];
+    const IpJob J = TAG == 3 ? one.J : jobs[job];
     const bool qrow = r < T.L;
     double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;   // key-switched sums
     double c0x = 0.0, c0y = 0.0, c1x = 0.0, c1y = 0.0;   // unswitched sums (ciphertext primes)
-    for (int tix = J.t0; tix < J.t0 + J.nt; ++tix) {
-        const IpTerm tm = terms[tix];
+    // one term: its mask (mbase, when tm.mask >= 0), key b half (kbase) and
+    // a-half streams (ks, both when tm.kind != IP_PLAIN)
+    const auto term = [&](const IpTerm &tm, const double *mbase, const double *kbase, const uint64_t *ks) {
         double2 mv = make_double2(1.0, 1.0);
-        if (tm.mask >= 0)
-            mv = TAG == 2 ? ld2(masks[tm.mask] + (size_t)r * N + p) : ld_stream2(masks[tm.mask] + (size_t)r * N + p);
+        if (tm.mask >= 0) {
+            const double *mrow = mbase + (size_t)r * N + p;
+            mv = TAG == 2 ? ld2(mrow) : ld_stream2(mrow);
+        }
         // positions p, p + 1 (p even) gather from the aligned pair {pb, pb + 1}
         // (the automorphism flips bit 0 of the source with bit 0 of p), in
         // swapped order when sw
@@ -102,8 +108,7 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
         const bool sw = pp & 1;
         if (tm.kind != IP_PLAIN) {
             const double *ys = y + (size_t)J.src * BETA * plane + (size_t)r * N;
-            const double *kb = keys[tm.key] + (size_t)r * N + p;
-            const uint64_t *ks = streams + (size_t)tm.key * BETA;
+            const double *kb = kbase + (size_t)r * N + p;
             double y0[BETA], y1[BETA];
             double2 kbv[BETA], kav[BETA];
 #pragma unroll
@@ -165,6 +170,17 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
                 c1y = redm(c1y + z1, q, qi);
             }
         }
+    };
+    if constexpr (TAG == 3) {
+#pragma unroll
+        for (int u = 0; u < IP_ONE_MAX_TERMS; ++u)
+            if (u < J.nt) term(one.tm[u], one.mask[u], one.key, one.st);
+    } else {
+        for (int tix = J.t0; tix < J.t0 + J.nt; ++tix) {
+            const IpTerm tm = terms[tix];
+            term(tm, tm.mask >= 0 ? masks[tm.mask] : nullptr, tm.kind != IP_PLAIN ? keys[tm.key] : nullptr,
+                 streams + (size_t)tm.key * BETA);
+        }
     }
     if (qrow) {
         const double P = T.pmod[r];
@@ -176,6 +192,19 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
     double *u = U + (size_t)J.slot * 2 * plane + (size_t)r * N + p;
     *(double2 *)u = make_double2(a0x, a0y);
     *(double2 *)(u + plane) = make_double2(a1x, a1y);
+}
+
+template <int BETA, int TAG>
+__global__ void __launch_bounds__(IP_THREADS)
+k_ip(DevTables T, double *U, const double *y, const double *const *keys, const uint64_t *streams,
+     const double *const *masks, const IpJob *jobs, const IpTerm *terms) {
+    const IpOne none{};
+    ip_body<BETA, TAG>(T, U, y, keys, streams, masks, jobs, terms, none);
+}
+
+template <int BETA>
+__global__ void __launch_bounds__(IP_THREADS) k_ip_one(DevTables T, double *U, const double *y, IpOne one) {
+    ip_body<BETA, 3>(T, U, y, nullptr, nullptr, nullptr, nullptr, nullptr, one);
 }
 
 // Key-stationary inner products for batches.  The key-switched terms of a
@@ -695,6 +724,25 @@ void ip_launch(const DevTables &T, double *U, const double *y, const double *con
         HG_IP_CASE(1) HG_IP_CASE(2) HG_IP_CASE(3) HG_IP_CASE(4) HG_IP_CASE(5) HG_IP_CASE(6)
         HG_IP_CASE(7) HG_IP_CASE(8) HG_IP_CASE(9) HG_IP_CASE(10) HG_IP_CASE(11) HG_IP_CASE(12)
 #undef HG_IP_CASE
+        default: break;
+    }
+}
+
+void ip_one_launch(const DevTables &T, double *U, const double *y, const IpOne &one, hipStream_t s, hipEvent_t ev0,
+                   hipEvent_t ev1) {
+    bool ok = T.beta >= 1 && T.beta <= IP_ONE_MAX_BETA && one.J.nt >= 1 && one.J.nt <= IP_ONE_MAX_TERMS;
+    for (int u = 0; ok && u < one.J.nt; ++u)
+        ok = (one.tm[u].kind == IP_PLAIN || one.key) && (one.tm[u].mask < 0 || one.mask[u]);
+    if (!ok) throw std::invalid_argument("ip_one_launch: one job of at most two terms, with its key and masks");
+    dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, 1);
+    switch (T.beta) {
+#define HG_IP1_CASE(B)                                                              \
+    case B:                                                                         \
+        launch_timed(k_ip_one<B>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, one); \
+        break;
+        HG_IP1_CASE(1) HG_IP1_CASE(2) HG_IP1_CASE(3) HG_IP1_CASE(4) HG_IP1_CASE(5) HG_IP1_CASE(6)
+        HG_IP1_CASE(7) HG_IP1_CASE(8) HG_IP1_CASE(9) HG_IP1_CASE(10) HG_IP1_CASE(11) HG_IP1_CASE(12)
+#undef HG_IP1_CASE
         default: break;
     }
 }

@@ -1042,6 +1042,16 @@ k_hoist_fused_copy(DevTables T, double *y, HoistSrc a) {
     hoist_body<LOGN, RK, SPLIT>(T, y, a.p[src], row, hh, r, j, sh);
 }
 
+// The same with the sources by value and no copy.
+template <int LOGN, int RK = rk_of(LOGN), int SPLIT = 0>
+__global__ void __launch_bounds__(NTT_THREADS_MAX) __attribute__((amdgpu_waves_per_eu(waves_of(LOGN, RK))))
+k_hoist_fused_v(DevTables T, double *y, HoistSrc a) {
+    extern __shared__ double sh[];
+    int row, hh, r, j, src;
+    hoist_row<SPLIT>(T, (int)blockIdx.x, row, hh, r, j, src);
+    hoist_body<LOGN, RK, SPLIT>(T, y, a.p[src], row, hh, r, j, sh);
+}
+
 template <int LOGN, int RK, int SPLIT>
 __device__ __forceinline__ void hoist_body(const DevTables &T, double *y, const double *c1, int row, int hh, int r,
                                            int j, double *sh) {
@@ -1204,6 +1214,8 @@ void set_lds_attrs() {
     (void)hipFuncSetAttribute((const void *)k_hoist_fused<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_hoist_fused_copy<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_hoist_fused_copy<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused_v<LN, RK, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void *)k_hoist_fused_v<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_moddown_fused<LN, RK, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_fwd<LOAD_DELTA_H, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     (void)hipFuncSetAttribute((const void *)k_ntt_inv<STORE_MDR_H, LN, RK>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -1345,6 +1357,21 @@ void hoist_fused_copy(const DevTables &T, double *y, const HoistSrc &a, int nsrc
         launch_ev(k_hoist_fused_copy<LN, RK, 0>, grid, block, ntt_lds_bytes(T.N), s, nullptr, done, T, y, a)
     HG_LOGN_RK_SWITCH(T.logN, HG_HFC)
 #undef HG_HFC
+}
+
+void hoist_fused_v(const DevTables &T, double *y, const HoistSrc &a, int nsrc, hipStream_t s) {
+    if (nsrc <= 0) return;
+    if (nsrc > HOIST_MAX_SRC) throw std::invalid_argument("hoist_fused_v: more sources than a launch takes");
+    const int rows = nsrc * T.beta * T.nExt;
+    const int split = half_split(T, rows) ? 1 : 0;
+    const dim3 grid((unsigned)(rows << split)), block(ntt_threads(T));
+#define HG_HFV(LN, RK)                                                                                          \
+    if (split)                                                                                                  \
+        hipLaunchKernelGGL((k_hoist_fused_v<LN, RK, 1>), grid, block, ntt_lds_bytes(T.N), s, T, y, a);          \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_hoist_fused_v<LN, RK, 0>), grid, block, ntt_lds_bytes(T.N), s, T, y, a)
+    HG_LOGN_RK_SWITCH(T.logN, HG_HFV)
+#undef HG_HFV
 }
 
 void moddown_fused(const DevTables &T, double *E, const double *U, int nslots, hipStream_t s, double *const *outs) {
