@@ -833,12 +833,15 @@ k_ntt_inv(DevTables T, NttArgs a) {
     if constexpr (STORE == STORE_MDR_H) {
         if constexpr (direct_rows<LOGN>() && RK >= 2) {
             // input half hh through the first logN - 1 stages, stored as is
-            // (the consumer applies the last stage; see k_ntt_fwd)
-            using RH = Rows<LOGN - 1, RK - 1>;
+            // (the consumer applies the last stage; see k_ntt_fwd), at the
+            // row's radix on half as many threads (launched with N / 2^(RK+1)):
+            // 4096-point halves in four radix-8 rounds rather than six
+            // radix-4 rounds on twice the threads
+            using RH = Rows<LOGN - 1, RK>;
             const int hh = blockIdx.x & 1;
             const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
             double x[1 << RH::RK];
-            inv_row_direct<LOGN - 1, RK - 1, 1>(
+            inv_row_direct<LOGN - 1, RK, 1>(
                 sh, tw, q, qi, [&](int i) { return gld(R.in)[(hh << (LOGN - 1)) + i]; }, x, hh);
 #pragma unroll
             for (int b = 0; b < (1 << RH::RK); ++b)
@@ -1297,7 +1300,8 @@ void ntt_inv(const DevTables &T, NttStore mode, const NttArgs &a, hipStream_t s)
         return;
     }
     const size_t lds = ntt_lds_bytes(T.N);
-    dim3 grid(a.rows << (mode == STORE_MDR && a.halves ? 1 : 0)), block(ntt_threads(T));
+    const int halves = mode == STORE_MDR && a.halves ? 1 : 0;   // two workgroups per row, each half the threads
+    dim3 grid(a.rows << halves), block(ntt_threads(T) >> halves);
 #define HG_INV(LN, RK)                                                                                          \
     switch (mode) {                                                                                            \
         case STORE_MDR:                                                                                        \
