@@ -99,6 +99,10 @@ Ctx::Ctx(uint32_t N_, uint64_t t_, uint32_t L_, uint32_t alpha_, int device_, in
     beta = (L + alpha - 1) / alpha;
     nExt = L + alpha;
     S = N / 2;
+    // 5^z mod 2N for every z in [0, S): looked up for every term of every pass
+    galois_tab.resize(S);
+    galois_tab[0] = 1;
+    for (int z = 1; z < S; ++z) galois_tab[z] = (int)((5ULL * (uint64_t)galois_tab[z - 1]) % (2ULL * (uint64_t)N));
     t = t_;
     // products per launch window of a batch: large rings keep fewer products'
     // hoisted digits in flight (their inner products gather them from cache;
@@ -317,8 +321,8 @@ Arena &Ctx::arena(hipStream_t st) {
 }
 
 int Ctx::galois_of(int z) const {
-    int zz = ((z % S) + S) % S;
-    return (int)hpow(5, (uint64_t)zz, 2 * (uint64_t)N);
+    const int zz = ((z % S) + S) % S;
+    return galois_tab[zz];
 }
 
 const PlanEntry &Ctx::plan_for(int m, int l, int n) {

@@ -52,6 +52,9 @@ struct Ct {
 struct PlanEntry {
     Plan plan;
     std::vector<const double *> mask_ptrs;   // device masks, plan.masks order
+    // every rotation key the plan needs was found once (keys are only ever
+    // added to a context, so the check need not be repeated)
+    mutable bool keys_found = false;
 };
 
 // Per-stream scratch arena, grown on demand.
@@ -200,6 +203,7 @@ struct Ctx {
     void keygen(uint64_t seed, const std::vector<int> &galois);
     void drop_secret();
     int galois_of(int z) const;   // 5^(z mod S) mod 2N
+    std::vector<int> galois_tab;  // galois_of for z in [0, S)
 
     // encode slot values (S values in [0, t)) into a centered-lifted plaintext
     // polynomial (N doubles, coefficient form) on `st`
