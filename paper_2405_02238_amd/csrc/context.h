@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <atomic>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -53,8 +54,9 @@ struct PlanEntry {
     Plan plan;
     std::vector<const double *> mask_ptrs;   // device masks, plan.masks order
     // every rotation key the plan needs was found once (keys are only ever
-    // added to a context, so the check need not be repeated)
-    mutable bool keys_found = false;
+    // added to a context, so the check need not be repeated; set from the
+    // serving thread and the submitting thread alike)
+    mutable std::atomic<bool> keys_found{false};
 };
 
 // Per-stream scratch arena, grown on demand.

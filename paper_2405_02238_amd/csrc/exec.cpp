@@ -711,10 +711,10 @@ const PlanEntry &Ctx::check_request(const Request &r) {
     if (A->ncts != pe.plan.nb || B->ncts != pe.plan.nb) throw Error(-1, "block count mismatch");
     need_full_level(*A);
     need_full_level(*B);
-    if (!pe.keys_found) {
+    if (!pe.keys_found.load(std::memory_order_relaxed)) {
         for (auto &rz : pe.plan.rotations(S))
             if (!rot_keys.count(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
-        pe.keys_found = true;
+        pe.keys_found.store(true, std::memory_order_relaxed);
     }
     return pe;
 }

@@ -138,8 +138,11 @@ uint64_t Server::submit(const uint64_t *a, size_t na, const uint64_t *b, size_t 
     auto it = C.plans.find(std::make_tuple(m, l, n));
     if (it == C.plans.end()) throw Error(-3, "shape has no plan and keys (list it in hg_keygen)");
     const PlanEntry *pe = it->second.get();
-    for (int z : pe->plan.rotations(C.S))
-        if (!C.rot_keys.count(C.galois_of(z))) throw Error(-3, "missing rotation key for z = " + std::to_string(z));
+    if (!pe->keys_found.load(std::memory_order_relaxed)) {
+        for (int z : pe->plan.rotations(C.S))
+            if (!C.rot_keys.count(C.galois_of(z))) throw Error(-3, "missing rotation key for z = " + std::to_string(z));
+        pe->keys_found.store(true, std::memory_order_relaxed);
+    }
     const size_t ctw = (size_t)2 * C.L * C.N;
     const size_t want = (size_t)pe->plan.nb * ctw;
     if (na != want || nbw != want) throw Error(-1, "operand word count differs from the shape's packing");
