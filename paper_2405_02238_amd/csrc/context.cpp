@@ -456,6 +456,8 @@ void Ctx::keygen(uint64_t seed_, const std::vector<int> &galois) {
         if (g == 1 || rot_keys.count(g)) continue;
         automorph_rows(T, sp, s_eval, nExt, g, st);          // phi_g(s)
         rot_keys[g] = make_key(TAG_ROT, (uint64_t)g * 256ULL, sp);
+        if (key_of_g.empty()) key_of_g.assign((size_t)2 * N, nullptr);
+        key_of_g[g] = rot_keys[g];
     }
     HGCHK(hipStreamSynchronize(st));
     (void)hipFree(dgad);

@@ -128,6 +128,8 @@ struct Ctx {
     double *relin_key = nullptr;
     std::map<const double *, std::vector<uint64_t>> key_streams;   // key -> beta stream states
     std::map<int, double *> rot_keys;   // Galois element -> key
+    std::vector<double *> key_of_g;     // the same indexed by Galois element (2N entries, null: none)
+    double *rot_key(int g) const { return g > 0 && g < (int)key_of_g.size() ? key_of_g[g] : nullptr; }
     size_t key_words() const { return (size_t)beta * nExt * N; }
 
     // plans and masks

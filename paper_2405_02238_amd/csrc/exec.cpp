@@ -33,9 +33,9 @@ struct Pass {
     std::vector<FinJob> fin_jobs;
     std::vector<FinTerm> fin_terms;
     std::vector<const double *> keys;
-    std::map<const double *, int> key_index;
+    std::unordered_map<const double *, int> key_index;
     std::vector<const double *> masks;
-    std::map<const double *, int> mask_index;
+    std::unordered_map<const double *, int> mask_index;
 
     int key_id(const double *k) {
         auto it = key_index.find(k);
@@ -151,9 +151,8 @@ struct Exec {
                     ps.fin_terms.push_back({1, mid, -1});
                     continue;
                 }
-                auto it = C.rot_keys.find(g);
-                if (it == C.rot_keys.end())
-                    throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
+                const double *key = C.rot_key(g);
+                if (!key) throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
                 IpJob ij;
                 ij.c0 = fj.c0;
                 ij.c1 = fj.c1;
@@ -161,7 +160,7 @@ struct Exec {
                 ij.t0 = (int)ps.ip_terms.size();
                 ij.nt = 1;
                 ij.slot = (int)ps.ip_jobs.size();
-                ps.ip_terms.push_back({g, -1, ps.key_id(it->second), IP_ROT});
+                ps.ip_terms.push_back({g, -1, ps.key_id(key), IP_ROT});
                 ps.fin_terms.push_back({1, mid, ij.slot});
                 ps.ip_jobs.push_back(ij);
             }
@@ -179,10 +178,9 @@ struct Exec {
                 if (g == 1) {
                     ps.ip_terms.push_back({1, mid, -1, IP_PLAIN});
                 } else {
-                    auto it = C.rot_keys.find(g);
-                    if (it == C.rot_keys.end())
-                        throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
-                    ps.ip_terms.push_back({g, mid, ps.key_id(it->second), IP_ROT});
+                    const double *key = C.rot_key(g);
+                    if (!key) throw Error(-3, "missing rotation key for z = " + std::to_string(tm.first));
+                    ps.ip_terms.push_back({g, mid, ps.key_id(key), IP_ROT});
                 }
             }
             if (relin_key) ps.ip_terms.push_back({1, -1, ps.key_id(relin_key), IP_RELIN});
@@ -713,7 +711,7 @@ const PlanEntry &Ctx::check_request(const Request &r) {
     need_full_level(*B);
     if (!pe.keys_found.load(std::memory_order_relaxed)) {
         for (auto &rz : pe.plan.rotations(S))
-            if (!rot_keys.count(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
+            if (!rot_key(galois_of(rz))) throw Error(-3, "missing rotation key for z = " + std::to_string(rz));
         pe.keys_found.store(true, std::memory_order_relaxed);
     }
     return pe;

@@ -140,7 +140,7 @@ uint64_t Server::submit(const uint64_t *a, size_t na, const uint64_t *b, size_t 
     const PlanEntry *pe = it->second.get();
     if (!pe->keys_found.load(std::memory_order_relaxed)) {
         for (int z : pe->plan.rotations(C.S))
-            if (!C.rot_keys.count(C.galois_of(z))) throw Error(-3, "missing rotation key for z = " + std::to_string(z));
+            if (!C.rot_key(C.galois_of(z))) throw Error(-3, "missing rotation key for z = " + std::to_string(z));
         pe->keys_found.store(true, std::memory_order_relaxed);
     }
     const size_t ctw = (size_t)2 * C.L * C.N;
