@@ -963,7 +963,8 @@ def test_algorithm1_eager_relin(method):
 def test_execution_knobs_bit_identical():
     """Every execution knob changes only the schedule: pipelined passes on a
     second stream, split-row transforms, fused or unfused chains, launch
-    windows -- the 64x32x48 product and a small batch keep their bits."""
+    windows, the XCD row map -- the 64x32x48 product and a small batch keep
+    their bits."""
     c = workloads.HEADLINE
     m, l, n = 64, 32, 48
     A, B = workloads.headline_operands()
@@ -980,9 +981,12 @@ def test_execution_knobs_bit_identical():
     settings = [{"pipeline": 2}, {"pipeline": 3, "fuse_rows": 0}, {"split_rows": 64, "fuse_rows": 0},
                 {"fuse_rows": 4096}, {"batch_window": 1}, {"ip_chunk": 16}, {"ip_chunk": 4, "batch_window": 0},
                 {"ip_order": 0}, {"ntt_radix": 16}, {"ntt_radix": 16, "fuse_rows": 0, "pipeline": 2},
-                {"half_rows": 0}, {"half_rows": 4096, "fuse_rows": 4096}, {"half_rows": 0, "ntt_radix": 16}]
+                {"half_rows": 0}, {"half_rows": 4096, "fuse_rows": 4096}, {"half_rows": 0, "ntt_radix": 16},
+                {"xcd_rows": 0}, {"xcd_rows": 0, "ntt_radix": 16, "fuse_rows": 0}]
     defaults = {"pipeline": 1, "fuse_rows": 256, "split_rows": 0, "batch_window": 64, "ip_chunk": 0, "ip_order": 1,
-                "ntt_radix": 0, "half_rows": 128}
+                "ntt_radix": 0, "half_rows": 128, "xcd_rows": 1}
+    with pytest.raises(hg.HGError):
+        ctx.tune("xcd_rows", 2)
     for st in settings:
         for k, v in st.items():
             ctx.tune(k, v)
