@@ -210,7 +210,9 @@ struct Exec {
         // the pass's key-switched terms use each key at least twice on
         // average: its inner products read keys and masks through the caches
         bool key_reuse = false;
-        // one job with one term: its inner products take it by value
+        // one job of at most two terms whose key switches share one key (a
+        // relinearisation, a single rotation): its inner products take the
+        // job, terms, key and streams by value (ip_one_launch)
         bool one_ok = false;
         IpOne one{};
     };
@@ -415,7 +417,8 @@ struct Exec {
             for (const IpTerm &tm : ps.ip_terms) switched += tm.kind != IP_PLAIN;
             dv.key_reuse = switched >= 2 * ps.keys.size() && !ps.keys.empty();
             dv.one_ok = false;
-            if (ps.ip_jobs.size() == 1 && ps.ip_jobs[0].nt <= IP_ONE_MAX_TERMS && beta <= IP_ONE_MAX_BETA) {
+            if (ps.ip_jobs.size() == 1 && ps.ip_jobs[0].nt >= 1 && ps.ip_jobs[0].nt <= IP_ONE_MAX_TERMS &&
+                beta <= IP_ONE_MAX_BETA) {
                 const IpJob &J = ps.ip_jobs[0];
                 dv.one = IpOne{};
                 dv.one.J = J;

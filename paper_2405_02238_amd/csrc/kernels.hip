@@ -178,8 +178,9 @@ __device__ __forceinline__ void ip_body(const DevTables &T, double *U, const dou
     } else {
         for (int tix = J.t0; tix < J.t0 + J.nt; ++tix) {
             const IpTerm tm = terms[tix];
-            term(tm, tm.mask >= 0 ? masks[tm.mask] : nullptr, tm.kind != IP_PLAIN ? keys[tm.key] : nullptr,
-                 streams + (size_t)tm.key * BETA);
+            const bool ksw = tm.kind != IP_PLAIN;
+            term(tm, tm.mask >= 0 ? masks[tm.mask] : nullptr, ksw ? keys[tm.key] : nullptr,
+                 ksw ? streams + (size_t)tm.key * BETA : nullptr);
         }
     }
     if (qrow) {
