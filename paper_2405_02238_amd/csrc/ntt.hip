@@ -600,6 +600,26 @@ __device__ __forceinline__ void fwd_stages_t(double *sh, const double *tw, int c
     }
 }
 
+// Inverse butterflies of one group of 2^K elements (stages of half-size
+// 1, 2, ..., 2^(K-1) within the group), every sum reduced; w holds the
+// twiddles stage by stage (2^(K-1), then 2^(K-2), ... of them).
+template <int K>
+__device__ __forceinline__ void inv_bfly_red(double *x, const double *w, double q, double qi) {
+    int wo = 0;
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int d = 1 << u;
+#pragma unroll
+        for (int b = 0; b < (1 << K); ++b) {
+            if (b & d) continue;
+            const double X = x[b], Y = x[b + d];
+            x[b] = redm(X + Y, q, qi);
+            x[b + d] = mulm(X - Y, w[wo + (b >> (u + 1))], q, qi);
+        }
+        wo += 1 << (K - u - 1);
+    }
+}
+
 template <int K, int LS, int NSUB, int LTS>
 __device__ __forceinline__ void inv_round_t(double *sh, const double *__restrict__ tw, int cb, int cs, double q,
                                             double qi) {
@@ -625,19 +645,7 @@ __device__ __forceinline__ void inv_round_t(double *sh, const double *__restrict
         double x[1 << K];
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) x[b] = sh[lds_ix_step<TS>(base, b)];
-        wo = 0;
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            const int d = 1 << u;
-#pragma unroll
-            for (int b = 0; b < (1 << K); ++b) {
-                if (b & d) continue;
-                const double X = x[b], Y = x[b + d];
-                x[b] = redm(X + Y, q, qi);
-                x[b + d] = mulm(X - Y, w[wo + (b >> (u + 1))], q, qi);
-            }
-            wo += 1 << (K - u - 1);
-        }
+        inv_bfly_red<K>(x, w, q, qi);
 #pragma unroll
         for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<TS>(base, b)] = x[b];
     }
@@ -879,6 +887,45 @@ __device__ __forceinline__ void split_dims(int logN, int &a, int &b) {
 
 // LOGN > 0: a size known at compile time (rounds fully unrolled, twiddles
 // preloaded); LOGN = 0: any size, runtime rounds.
+// Column passes of 32768-point rows (256-point columns, 16 per workgroup,
+// two radix-16 rounds) with both ends in registers: thread t owns column
+// t % 16 and, in the first round, rows t / 16 + 16 b, in the second rows
+// 16 (t / 16) + b, so every global access of a wave covers 16 adjacent
+// columns (128 bytes) of 4 rows, and only the exchange between the rounds
+// goes through LDS (one barrier instead of three).  The butterflies, twiddles
+// and reductions are those of the staged rounds, so the values are the same.
+constexpr int COL_LA = 8, COL_LB = 7, COL_W = SPLIT_ELEMS >> COL_LA;
+static_assert(COL_W * 16 == SPLIT_THREADS, "one thread per (column, group) in each round");
+
+template <int LOAD>
+__device__ __forceinline__ void fwd_cols_direct(const DevTables &T, const FwdRow &R, int c0, double *sh) {
+    const int sb = (int)threadIdx.x % COL_W, g = (int)threadIdx.x / COL_W;
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    const double *__restrict__ tw = T.twf + (size_t)R.prime * (1 << (COL_LA + COL_LB));
+    double x[16], w[15];
+    // round 1: stages 0..3 of the column, rows g + 16 b (group g of stride 16)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) x[b] = fwd_load<LOAD>(T, R, c0 + sb + ((g + 16 * b) << COL_LB));
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << u) + c];
+    fwd_bfly<COL_LA + COL_LB, 0, 4>(x, w, q, qi);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) sh[lds_ix_step<16>((sb << COL_LA) + g, b)] = x[b];
+    __syncthreads();
+    // round 2: stages 4..7, rows 16 g + b (block g of the column)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) x[b] = sh[lds_ix((sb << COL_LA) + (g << 4) + b)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(1 << (4 + u)) + (g << u) + c];
+    fwd_bfly<COL_LA + COL_LB, 4, 4>(x, w, q, qi);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) gst(R.out)[c0 + sb + ((16 * g + b) << COL_LB)] = x[b];
+}
+
 template <int LOAD, int LOGN>
 __global__ void __launch_bounds__(SPLIT_THREADS)
 k_ntt_fwd_cols(DevTables T, NttArgs a) {
@@ -892,6 +939,13 @@ k_ntt_fwd_cols(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int c0 = (blockIdx.x % wpr) * cw;
     const FwdRow R = fwd_row<LOAD>(T, a, row);
+    if constexpr (LOGN == COL_LA + COL_LB && LOAD == LOAD_PLAIN) {
+        // (with the lifting loads, LOAD_MODUP and LOAD_DELTA, measured no
+        // faster or slower than the staged pass: 22.6 against 19.9 us for the
+        // large product's hoist, 317 us either way for its division)
+        fwd_cols_direct<LOAD>(T, R, c0, sh);
+        return;
+    }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
         sh[lds_ix((cc << la) + j)] = fwd_load<LOAD>(T, R, c0 + cc + (j << lb));
@@ -965,6 +1019,49 @@ k_ntt_inv_blocks(DevTables T, NttArgs a) {
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) gst(R.out)[off + e] = sh[lds_ix(e)];
 }
 
+// The inverse column pass of 32768-point rows with both ends in registers
+// (see fwd_cols_direct): the first round takes rows 16 (t / 16) + b of
+// column t % 16 straight from memory, the second stores rows t / 16 + 16 b.
+template <int STORE>
+__device__ __forceinline__ void inv_cols_direct(const DevTables &T, const InvRow &R, int c0, double *sh) {
+    const int sb = (int)threadIdx.x % COL_W, g = (int)threadIdx.x / COL_W;
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    const double *__restrict__ tw = T.twi + (size_t)R.prime * (1 << (COL_LA + COL_LB));
+    double x[16], w[15];
+    // round 1: half-sizes 1..8, rows 16 g + b (block g of the column)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) x[b] = gld(R.out)[c0 + sb + ((16 * g + b) << COL_LB)];
+    {
+        int wo = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int c = 0; c < (1 << (3 - u)); ++c)
+                w[wo + c] = tw[((1 << COL_LA) >> (u + 1)) + (g << (3 - u)) + c];
+            wo += 1 << (3 - u);
+        }
+    }
+    inv_bfly_red<4>(x, w, q, qi);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) sh[lds_ix((sb << COL_LA) + (g << 4) + b)] = x[b];
+    __syncthreads();
+    // round 2: half-sizes 16..128, rows g + 16 b
+#pragma unroll
+    for (int b = 0; b < 16; ++b) x[b] = sh[lds_ix_step<16>((sb << COL_LA) + g, b)];
+    {
+        int wo = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int c = 0; c < (1 << (3 - u)); ++c) w[wo + c] = tw[((1 << COL_LA) >> (4 + u + 1)) + c];
+            wo += 1 << (3 - u);
+        }
+    }
+    inv_bfly_red<4>(x, w, q, qi);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) inv_store<STORE>(T, R, c0 + sb + ((g + 16 * b) << COL_LB), x[b], q, qi);
+}
+
 template <int STORE, int LOGN>
 __global__ void __launch_bounds__(SPLIT_THREADS)
 k_ntt_inv_cols(DevTables T, NttArgs a) {
@@ -978,6 +1075,10 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int c0 = (blockIdx.x % wpr) * cw;
     const InvRow R = inv_row(T, a, row);
+    if constexpr (LOGN == COL_LA + COL_LB) {
+        inv_cols_direct<STORE>(T, R, c0, sh);
+        return;
+    }
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
         sh[lds_ix((cc << la) + j)] = gld(R.out)[c0 + cc + (j << lb)];
