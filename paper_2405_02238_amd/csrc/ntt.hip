@@ -978,11 +978,34 @@ k_ntt_fwd_blocks(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int off = (blockIdx.x % wpr) * SPLIT_ELEMS;
     const FwdRow R = fwd_row<LOAD>(T, a, row);
-    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = gld(R.out)[off + e];
-    __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     const int B0 = off >> lb;
     const double *tw = T.twf + (size_t)R.prime * N;
+    if constexpr (LOGN == COL_LA + COL_LB) {
+        // 128-point blocks, 32 per workgroup: the first radix-16 round
+        // (stages 8..11) straight from memory, thread t on elements
+        // 8 b + t mod 8 of block t / 8 (64-byte runs per access), the rest as
+        // in the staged rounds
+        const int sb = (int)threadIdx.x >> 3, low = (int)threadIdx.x & 7;
+        const int C = (1 << COL_LA) + B0 + sb;
+        double x[16], w[15];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) x[b] = gld(R.out)[off + (sb << COL_LB) + low + 8 * b];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < (1 << u); ++c) w[(1 << u) - 1 + c] = tw[(C << u) + c];
+        fwd_bfly<COL_LA + COL_LB, COL_LA, 4>(x, w, q, qi);
+#pragma unroll
+        for (int b = 0; b < 16; ++b) sh[lds_ix_step<8>((sb << COL_LB) + low, b)] = x[b];
+        __syncthreads();
+        fwd_stages_t<COL_LB, (SPLIT_ELEMS >> COL_LB), 4, COL_LA, LOGN, false>(sh, tw, (1 << COL_LA) + B0, 1, q, qi);
+        for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x)
+            fwd_store<LOAD>(T, R, off + e, sh[lds_ix(e)], q, qi);
+        return;
+    }
+    for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) sh[lds_ix(e)] = gld(R.out)[off + e];
+    __syncthreads();
     if constexpr (LOGN > 0) {
         constexpr int LA = (LOGN + 1) >> 1, LB = LOGN - LA;
         fwd_stages_t<LB, (SPLIT_ELEMS >> LB), 0, LA, LOGN, false>(sh, tw, (1 << LA) + B0, 1, q, qi);
@@ -1010,6 +1033,34 @@ k_ntt_inv_blocks(DevTables T, NttArgs a) {
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     const int B0 = off >> lb;
     const double *tw = T.twi + (size_t)R.prime * N;
+    if constexpr (LOGN == COL_LA + COL_LB) {
+        // 128-point blocks, 32 per workgroup: the first round (half-sizes
+        // 1..8) in LDS, the last (16, 32, 64) straight to memory, each thread
+        // on elements 16 b + g mod 16 of block g / 16 for its two groups g
+        // (16 adjacent elements of 4 blocks per access)
+        const int C0 = (1 << COL_LA) + B0;
+        inv_round_t<4, COL_LB, (SPLIT_ELEMS >> COL_LB), 0>(sh, tw, C0, 1, q, qi);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int grp = (int)threadIdx.x + k * SPLIT_THREADS;
+            const int sb = grp >> 4, low = grp & 15;
+            double x[8], w[7];
+            int wo = 0;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+#pragma unroll
+                for (int c = 0; c < (1 << (2 - u)); ++c) w[wo + c] = tw[((1 << COL_LB) >> (4 + u + 1)) * (C0 + sb) + c];
+                wo += 1 << (2 - u);
+            }
+#pragma unroll
+            for (int b = 0; b < 8; ++b) x[b] = sh[lds_ix_step<16>((sb << COL_LB) + low, b)];
+            inv_bfly_red<3>(x, w, q, qi);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) gst(R.out)[off + (sb << COL_LB) + low + 16 * b] = x[b];
+        }
+        return;
+    }
     if constexpr (LOGN > 0) {
         constexpr int LA = (LOGN + 1) >> 1, LB = LOGN - LA;
         inv_stages_t<LB, (SPLIT_ELEMS >> LB), 0>(sh, tw, (1 << LA) + B0, 1, q, qi);
