@@ -904,8 +904,30 @@ __device__ __forceinline__ void fwd_cols_direct(const DevTables &T, const FwdRow
     const double *__restrict__ tw = T.twf + (size_t)R.prime * (1 << (COL_LA + COL_LB));
     double x[16], w[15];
     // round 1: stages 0..3 of the column, rows g + 16 b (group g of stride 16)
+    if (LOAD == LOAD_DELTA && T.alpha == 2) {
+        // the lift of two special primes' r rows, every load issued before
+        // the arithmetic (fwd_load's loop over a run-time alpha keeps them
+        // one element at a time); the same sums in the same order
+        const int N = 1 << (COL_LA + COL_LB);
+        const double h0 = T.md_hat[R.prime], h1 = T.md_hat[T.L + R.prime];
+        double r0[16], r1[16];
 #pragma unroll
-    for (int b = 0; b < 16; ++b) x[b] = fwd_load<LOAD>(T, R, c0 + sb + ((g + 16 * b) << COL_LB));
+        for (int b = 0; b < 16; ++b) {
+            const int i = c0 + sb + ((g + 16 * b) << COL_LB);
+            r0[b] = gld(R.in)[i];
+            r1[b] = gld(R.in)[N + i];
+        }
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            double acc = 0.0;
+            acc += mulm(r0[b], h0, q, qi);
+            acc += mulm(r1[b], h1, q, qi);
+            x[b] = redm(acc, q, qi);
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < 16; ++b) x[b] = fwd_load<LOAD>(T, R, c0 + sb + ((g + 16 * b) << COL_LB));
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -939,10 +961,9 @@ k_ntt_fwd_cols(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int c0 = (blockIdx.x % wpr) * cw;
     const FwdRow R = fwd_row<LOAD>(T, a, row);
-    if constexpr (LOGN == COL_LA + COL_LB && LOAD == LOAD_PLAIN) {
-        // (with the lifting loads, LOAD_MODUP and LOAD_DELTA, measured no
-        // faster or slower than the staged pass: 22.6 against 19.9 us for the
-        // large product's hoist, 317 us either way for its division)
+    if constexpr (LOGN == COL_LA + COL_LB && LOAD != LOAD_MODUP) {
+        // (with the digit lift of LOAD_MODUP it measured slower than the
+        // staged pass: 22.6 against 19.9 us for the large product's hoist)
         fwd_cols_direct<LOAD>(T, R, c0, sh);
         return;
     }
