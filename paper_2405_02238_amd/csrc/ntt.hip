@@ -350,16 +350,6 @@ __device__ __forceinline__ void fwd_row_regs_half(double *sh, const double *__re
     fwd_row_regs<LOGN - 1, RKX - 1, 1>(sh, tw, q, qi, z, [&](int i, double v) { st((h << (LOGN - 1)) + i, v); }, h);
 }
 
-template <int LOGN, int RKX, class Load, class Store>
-__device__ __forceinline__ void fwd_row_direct(double *sh, const double *__restrict__ tw, double q, double qi,
-                                               Load ld, Store st) {
-    using R = Rows<LOGN, RKX>;
-    double x[1 << R::RK];
-#pragma unroll
-    for (int b = 0; b < (1 << R::RK); ++b) x[b] = ld((int)threadIdx.x + b * R::NT);
-    fwd_row_regs<LOGN, RKX>(sh, tw, q, qi, x, st);
-}
-
 // Full inverse rounds from half-size 2^LTS0 up to the last round.
 // SG = 1, hb = h: the transform is the first LOGN stages of a 2^(LOGN + 1)-
 // point inverse on input half h (which they do not mix with the other
@@ -733,6 +723,59 @@ __device__ __forceinline__ double fwd_load(const DevTables &T, const FwdRow &R, 
     }
 }
 
+// fwd_load of NB positions pos(0..NB-1).  The lift of a two-prime digit
+// (LOAD_MODUP) or of two special primes (LOAD_DELTA) issues all its loads
+// before the arithmetic: fwd_load's loop over a run-time prime count keeps
+// them one position at a time.  The sums are the same, in the same order.
+template <int LOAD, int NB, class Pos>
+__device__ __forceinline__ void fwd_load_batch(const DevTables &T, const FwdRow &R, Pos pos, double *x) {
+    const int N = 1 << T.logN;
+    if (LOAD == LOAD_DELTA && T.alpha == 2) {
+        const int iq = R.prime;
+        const double q = T.qt[iq].x, qi = T.qt[iq].y;
+        const double h0 = T.md_hat[iq], h1 = T.md_hat[T.L + iq];
+        double v0[NB], v1[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = pos(b);
+            v0[b] = gld(R.in)[i];
+            v1[b] = gld(R.in)[N + i];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double acc = 0.0;
+            acc += mulm(v0[b], h0, q, qi);
+            acc += mulm(v1[b], h1, q, qi);
+            x[b] = redm(acc, q, qi);
+        }
+        return;
+    }
+    if (LOAD == LOAD_MODUP && R.d1 - R.d0 == 2 && (R.prime < R.d0 || R.prime >= R.d1)) {
+        const int r = R.prime, s0 = R.d0, s1 = R.d0 + 1;
+        const double qr = T.qt[r].x, qir = T.qt[r].y;
+        const double q0 = T.qt[s0].x, qi0 = T.qt[s0].y, q1 = T.qt[s1].x, qi1 = T.qt[s1].y;
+        const double mi0 = T.mu_invhat[s0], mi1 = T.mu_invhat[s1];
+        const double mh0 = T.mu_hat[s0 * T.nExt + r], mh1 = T.mu_hat[s1 * T.nExt + r];
+        double v0[NB], v1[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int i = pos(b);
+            v0[b] = gld(R.in)[(size_t)s0 * N + i];
+            v1[b] = gld(R.in)[(size_t)s1 * N + i];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double acc = 0.0;
+            acc += mulm(centerm(mulm(v0[b], mi0, q0, qi0), q0, qi0), mh0, qr, qir);
+            acc += mulm(centerm(mulm(v1[b], mi1, q1, qi1), q1, qi1), mh1, qr, qir);
+            x[b] = redm(acc, qr, qir);
+        }
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) x[b] = fwd_load<LOAD>(T, R, pos(b));
+}
+
 // Final store of position i (after the last stage).
 template <int LOAD>
 __device__ __forceinline__ void fwd_store(const DevTables &T, const FwdRow &R, int i, double v, double q, double qi) {
@@ -818,10 +861,11 @@ k_ntt_fwd(DevTables T, NttArgs a) {
             fwd_row_regs<LOGN, RK>(sh, tw, q, qi, x, [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
         }
     } else if constexpr (direct_rows<LOGN>()) {
+        using RW = Rows<LOGN, RK>;
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
-        fwd_row_direct<LOGN, RK>(
-            sh, tw, q, qi, [&](int i) { return fwd_load<LOAD>(T, R, i); },
-            [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
+        double x[1 << RW::RK];
+        fwd_load_batch<LOAD, (1 << RW::RK)>(T, R, [&](int b) { return (int)threadIdx.x + b * RW::NT; }, x);
+        fwd_row_regs<LOGN, RK>(sh, tw, q, qi, x, [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
     } else {
         for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
         __syncthreads();
@@ -904,30 +948,7 @@ __device__ __forceinline__ void fwd_cols_direct(const DevTables &T, const FwdRow
     const double *__restrict__ tw = T.twf + (size_t)R.prime * (1 << (COL_LA + COL_LB));
     double x[16], w[15];
     // round 1: stages 0..3 of the column, rows g + 16 b (group g of stride 16)
-    if (LOAD == LOAD_DELTA && T.alpha == 2) {
-        // the lift of two special primes' r rows, every load issued before
-        // the arithmetic (fwd_load's loop over a run-time alpha keeps them
-        // one element at a time); the same sums in the same order
-        const int N = 1 << (COL_LA + COL_LB);
-        const double h0 = T.md_hat[R.prime], h1 = T.md_hat[T.L + R.prime];
-        double r0[16], r1[16];
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            const int i = c0 + sb + ((g + 16 * b) << COL_LB);
-            r0[b] = gld(R.in)[i];
-            r1[b] = gld(R.in)[N + i];
-        }
-#pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            double acc = 0.0;
-            acc += mulm(r0[b], h0, q, qi);
-            acc += mulm(r1[b], h1, q, qi);
-            x[b] = redm(acc, q, qi);
-        }
-    } else {
-#pragma unroll
-        for (int b = 0; b < 16; ++b) x[b] = fwd_load<LOAD>(T, R, c0 + sb + ((g + 16 * b) << COL_LB));
-    }
+    fwd_load_batch<LOAD, 16>(T, R, [&](int b) { return c0 + sb + ((g + 16 * b) << COL_LB); }, x);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -961,9 +982,7 @@ k_ntt_fwd_cols(DevTables T, NttArgs a) {
     const int row = blockIdx.x / wpr;
     const int c0 = (blockIdx.x % wpr) * cw;
     const FwdRow R = fwd_row<LOAD>(T, a, row);
-    if constexpr (LOGN == COL_LA + COL_LB && LOAD != LOAD_MODUP) {
-        // (with the digit lift of LOAD_MODUP it measured slower than the
-        // staged pass: 22.6 against 19.9 us for the large product's hoist)
+    if constexpr (LOGN == COL_LA + COL_LB) {
         fwd_cols_direct<LOAD>(T, R, c0, sh);
         return;
     }
