@@ -76,7 +76,8 @@ __device__ __forceinline__ void st2(double *p, double2 v) {
 // word is read once per launch), or through the caches (2: a transform pass
 // whose terms share keys, its jobs started in key order).  TAG 3: the
 // launch's single job and its terms come by value in `one` (ip_one_launch)
-// and the tables are not read; keys and masks load as with TAG 1.
+// and the tables are not read; keys and masks load as with TAG 1.  TAG 4:
+// the same for a relinearisation job, whose two terms are known.
 template <int BETA, int TAG>
 __device__ __forceinline__ void ip_body(const DevTables &T, double *U, const double *y, const double *const *keys,
                                         const uint64_t *streams, const double *const *masks, const IpJob *jobs,
@@ -88,7 +89,7 @@ __device__ __forceinline__ void ip_body(const DevTables &T, double *U, const dou
     if (p >= N) return;
     const double q = T.qt[r].x, qi = T.qt[r].y;
     const size_t plane = (size_t)T.nExt * N;   // one digit (or component) of all primes
-    const IpJob J = TAG == 3 ? one.J : jobs[job];
+    const IpJob J = TAG >= 3 ? one.J : jobs[job];
     const bool qrow = r < T.L;
     double a0x = 0.0, a0y = 0.0, a1x = 0.0, a1y = 0.0;   // key-switched sums
     double c0x = 0.0, c0y = 0.0, c1x = 0.0, c1y = 0.0;   // unswitched sums (ciphertext primes)
@@ -171,7 +172,13 @@ __device__ __forceinline__ void ip_body(const DevTables &T, double *U, const dou
             }
         }
     };
-    if constexpr (TAG == 3) {
+    if constexpr (TAG == 4) {
+        // a relinearisation: the unswitched, unmasked, unrotated term, then
+        // the key switch of the hoisted c2, both known here, so that no
+        // branch on a term's fields holds the second term's loads back
+        term(IpTerm{1, -1, -1, IP_PLAIN}, nullptr, nullptr, nullptr);
+        term(IpTerm{1, -1, 0, IP_RELIN}, nullptr, one.key, one.st);
+    } else if constexpr (TAG == 3) {
 #pragma unroll
         for (int u = 0; u < IP_ONE_MAX_TERMS; ++u)
             if (u < J.nt) term(one.tm[u], one.mask[u], one.key, one.st);
@@ -203,9 +210,9 @@ k_ip(DevTables T, double *U, const double *y, const double *const *keys, const u
     ip_body<BETA, TAG>(T, U, y, keys, streams, masks, jobs, terms, none);
 }
 
-template <int BETA>
+template <int BETA, bool RELIN>
 __global__ void __launch_bounds__(IP_THREADS) k_ip_one(DevTables T, double *U, const double *y, IpOne one) {
-    ip_body<BETA, 3>(T, U, y, nullptr, nullptr, nullptr, nullptr, nullptr, one);
+    ip_body<BETA, RELIN ? 4 : 3>(T, U, y, nullptr, nullptr, nullptr, nullptr, nullptr, one);
 }
 
 // Key-stationary inner products for batches.  The key-switched terms of a
@@ -735,11 +742,18 @@ void ip_one_launch(const DevTables &T, double *U, const double *y, const IpOne &
     for (int u = 0; ok && u < one.J.nt; ++u)
         ok = (one.tm[u].kind == IP_PLAIN || one.key) && (one.tm[u].mask < 0 || one.mask[u]);
     if (!ok) throw std::invalid_argument("ip_one_launch: one job of at most two terms, with its key and masks");
+    // the terms of a relinearisation (the job's c0, c1 as they are, then the
+    // key switch of c2) take the kernel that knows them
+    const bool relin = one.J.nt == 2 && one.tm[0].kind == IP_PLAIN && one.tm[0].g == 1 && one.tm[0].mask < 0 &&
+                       one.tm[1].kind == IP_RELIN && one.tm[1].g == 1 && one.tm[1].mask < 0;
     dim3 grid((T.N / 2 + IP_THREADS - 1) / IP_THREADS, T.nExt, 1);
     switch (T.beta) {
-#define HG_IP1_CASE(B)                                                              \
-    case B:                                                                         \
-        launch_timed(k_ip_one<B>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, one); \
+#define HG_IP1_CASE(B)                                                                       \
+    case B:                                                                                  \
+        if (relin)                                                                           \
+            launch_timed(k_ip_one<B, true>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, one); \
+        else                                                                                 \
+            launch_timed(k_ip_one<B, false>, grid, dim3(IP_THREADS), s, ev0, ev1, T, U, y, one); \
         break;
         HG_IP1_CASE(1) HG_IP1_CASE(2) HG_IP1_CASE(3) HG_IP1_CASE(4) HG_IP1_CASE(5) HG_IP1_CASE(6)
         HG_IP1_CASE(7) HG_IP1_CASE(8) HG_IP1_CASE(9) HG_IP1_CASE(10) HG_IP1_CASE(11) HG_IP1_CASE(12)
