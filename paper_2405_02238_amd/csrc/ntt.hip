@@ -730,6 +730,28 @@ __device__ __forceinline__ double fwd_load(const DevTables &T, const FwdRow &R, 
 template <int LOAD, int NB, class Pos>
 __device__ __forceinline__ void fwd_load_batch(const DevTables &T, const FwdRow &R, Pos pos, double *x) {
     const int N = 1 << T.logN;
+    if (LOAD == LOAD_DELTA && T.alpha == 1) {
+        const int iq = R.prime;
+        const double q = T.qt[iq].x, qi = T.qt[iq].y, h = T.md_hat[iq];
+        double v[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) v[b] = gld(R.in)[pos(b)];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) x[b] = mulm(v[b], h, q, qi);
+        return;
+    }
+    if (LOAD == LOAD_MODUP && R.d1 - R.d0 == 1) {
+        // a one-prime digit: the row itself under its own prime, else its
+        // centered residue
+        const bool own = R.prime == R.d0;
+        const double qd = T.qt[R.d0].x, qid = T.qt[R.d0].y;
+        double v[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) v[b] = gld(R.in)[(size_t)R.d0 * N + pos(b)];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) x[b] = own ? v[b] : centerm(v[b], qd, qid);
+        return;
+    }
     if (LOAD == LOAD_DELTA && T.alpha == 2) {
         const int iq = R.prime;
         const double q = T.qt[iq].x, qi = T.qt[iq].y;
