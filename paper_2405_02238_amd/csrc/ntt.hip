@@ -297,14 +297,23 @@ __device__ __forceinline__ void fwd_mid(double *sh, const double *__restrict__ t
     }
 }
 
+// No value to combine with an output (fwd_row_regs' default `pre`).
+struct NoPre {
+    __device__ double operator()(int) const { return 0.0; }
+};
+
 // Forward transform of a row of which thread t holds elements t + b NT in
-// x (|x| < q); st(i, v) receives output position i (bit-reversed order).
-// Uses sh as scratch; the caller must not touch sh concurrently.  With SG = 1
-// the row is half hb of a twice longer row after that row's first stage
-// (see fwd_mid; st then receives positions within the half).
-template <int LOGN, int RKX, int SG = 0, class Store>
+// x (|x| < q); st(i, v, u) receives output position i (bit-reversed order)
+// with u = pre(i).  Every pre(i) and the last round's twiddles are loaded
+// before the first st: a store through a pointer the compiler cannot tell
+// apart from theirs would otherwise keep each of those loads behind the
+// store before it.  Uses sh as scratch; the caller must not touch sh
+// concurrently.  With SG = 1 the row is half hb of a twice longer row after
+// that row's first stage (see fwd_mid; st then receives positions within
+// the half).
+template <int LOGN, int RKX, int SG = 0, class Store, class Pre = NoPre>
 __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restrict__ tw, double q, double qi,
-                                             double *x, Store st, int hb = 0) {
+                                             double *x, Store st, int hb = 0, Pre pre = Pre()) {
     using R = Rows<LOGN, RKX>;
     constexpr int K = R::RK, NT = R::NT, KT = R::KT, SL = R::SL;
     const int t = threadIdx.x;
@@ -316,16 +325,23 @@ __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restric
     for (int b = 0; b < (1 << K); ++b) sh[lds_ix_step<NT>(t, b)] = x[b];
     __syncthreads();
     fwd_mid<LOGN, RKX, K, SG>(sh, tw, q, qi, t, w1, hb);
+    double wl[R::GPT][(1 << KT) - 1], u[R::GPT][1 << KT];
 #pragma unroll
     for (int g = 0; g < R::GPT; ++g) {
         const int grp = t + g * NT;
-        double w[(1 << KT) - 1], y[1 << KT];
-        fwd_tw<SL + SG, KT>(w, tw, (hb << SL) + grp);
+        fwd_tw<SL + SG, KT>(wl[g], tw, (hb << SL) + grp);
+#pragma unroll
+        for (int b = 0; b < (1 << KT); ++b) u[g][b] = pre((grp << KT) + b);
+    }
+#pragma unroll
+    for (int g = 0; g < R::GPT; ++g) {
+        const int grp = t + g * NT;
+        double y[1 << KT];
 #pragma unroll
         for (int b = 0; b < (1 << KT); ++b) y[b] = sh[lds_ix((grp << KT) + b)];
-        fwd_bfly<LOGN + SG, SL + SG, KT>(y, w, q, qi);
+        fwd_bfly<LOGN + SG, SL + SG, KT>(y, wl[g], q, qi);
 #pragma unroll
-        for (int b = 0; b < (1 << KT); ++b) st((grp << KT) + b, y[b]);
+        for (int b = 0; b < (1 << KT); ++b) st((grp << KT) + b, y[b], u[g][b]);
     }
 }
 
@@ -334,11 +350,11 @@ __device__ __forceinline__ void fwd_row_regs(double *sh, const double *__restric
 // stage pairs elements b and b + 2^(RKX-1) of each thread, so the thread
 // keeps X + w Y (h = 0) or X - w Y (h = 1) and the rest is an independent
 // 2^(LOGN-1)-point transform at radix 2^(RKX-1) on the same NT threads; st
-// receives the half's output positions h 2^(LOGN-1) + i.  Two workgroups,
-// one per half, finish a row in about the time of one half.
-template <int LOGN, int RKX, class Store>
+// and pre receive the half's output positions h 2^(LOGN-1) + i.  Two
+// workgroups, one per half, finish a row in about the time of one half.
+template <int LOGN, int RKX, class Store, class Pre = NoPre>
 __device__ __forceinline__ void fwd_row_regs_half(double *sh, const double *__restrict__ tw, double q, double qi,
-                                                  double *x, Store st, int h) {
+                                                  double *x, Store st, int h, Pre pre = Pre()) {
     constexpr int HALF = 1 << (RKX - 1);
     const double w = tw[1];
     double z[HALF];
@@ -347,7 +363,9 @@ __device__ __forceinline__ void fwd_row_regs_half(double *sh, const double *__re
         const double t = mulm(x[b + HALF], w, q, qi);
         z[b] = h ? x[b] - t : x[b] + t;
     }
-    fwd_row_regs<LOGN - 1, RKX - 1, 1>(sh, tw, q, qi, z, [&](int i, double v) { st((h << (LOGN - 1)) + i, v); }, h);
+    fwd_row_regs<LOGN - 1, RKX - 1, 1>(
+        sh, tw, q, qi, z, [&](int i, double v, double u) { st((h << (LOGN - 1)) + i, v, u); }, h,
+        [&](int i) { return pre((h << (LOGN - 1)) + i); });
 }
 
 // Full inverse rounds from half-size 2^LTS0 up to the last round.
@@ -880,14 +898,25 @@ k_ntt_fwd(DevTables T, NttArgs a) {
                 x[b] = mulm(centerm(mulm(s0, cf, qp, qip), qp, qip), hat, q, qi);
                 x[b + HALF] = mulm(centerm(mulm(d0, cf, qp, qip), qp, qip), hat, q, qi);
             }
-            fwd_row_regs<LOGN, RK>(sh, tw, q, qi, x, [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
+            const double pinv = T.pinv[R.prime];
+            fwd_row_regs<LOGN, RK>(
+                sh, tw, q, qi, x, [&](int i, double v, double u) { gst(R.out)[i] = mulm(u - v, pinv, q, qi); }, 0,
+                [&](int i) { return gld(R.aux)[i]; });
         }
     } else if constexpr (direct_rows<LOGN>()) {
         using RW = Rows<LOGN, RK>;
         const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
         double x[1 << RW::RK];
         fwd_load_batch<LOAD, (1 << RW::RK)>(T, R, [&](int b) { return (int)threadIdx.x + b * RW::NT; }, x);
-        fwd_row_regs<LOGN, RK>(sh, tw, q, qi, x, [&](int i, double v) { fwd_store<LOAD>(T, R, i, v, q, qi); });
+        if constexpr (LOAD == LOAD_DELTA) {
+            // (U - delta) P^-1 with every U word loaded before the first store
+            const double pinv = T.pinv[R.prime];
+            fwd_row_regs<LOGN, RK>(
+                sh, tw, q, qi, x, [&](int i, double v, double u) { gst(R.out)[i] = mulm(u - v, pinv, q, qi); }, 0,
+                [&](int i) { return gld(R.aux)[i]; });
+        } else {
+            fwd_row_regs<LOGN, RK>(sh, tw, q, qi, x, [&](int i, double v, double) { gst(R.out)[i] = v; });
+        }
     } else {
         for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = fwd_load<LOAD>(T, R, i);
         __syncthreads();
@@ -1289,7 +1318,7 @@ __device__ __forceinline__ void hoist_body(const DevTables &T, double *y, const 
 #pragma unroll
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = centerm(mulm(x[b], nj, qj, qij), qj, qij);
         const double q = T.qt[r].x, qi = T.qt[r].y;
-        const auto st = [&](int i, double v) { gst(out)[i] = v; };
+        const auto st = [&](int i, double v, double) { gst(out)[i] = v; };
         if constexpr (SPLIT && RK >= 2)
             fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)r * N, q, qi, x, st, hh);
         else
@@ -1342,11 +1371,12 @@ k_moddown_fused(DevTables T, double *E, const double *U, double *const *outs) {
         for (int b = 0; b < (1 << RW::RK); ++b) x[b] = mulm(centerm(mulm(x[b], cf, qp, qip), qp, qip), h, q, qi);
         const double *ui = u + (size_t)iq * N;
         double *out = outs ? outs[slot >> 1] + ((size_t)(slot & 1) * T.L + iq) * N : E + (size_t)row * N;
-        const auto st = [&](int i, double v) { gst(out)[i] = mulm(gld(ui)[i] - v, pinv, q, qi); };
+        const auto st = [&](int i, double v, double uw) { gst(out)[i] = mulm(uw - v, pinv, q, qi); };
+        const auto pre = [&](int i) { return gld(ui)[i]; };
         if constexpr (SPLIT && RK >= 2)
-            fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st, hh);
+            fwd_row_regs_half<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st, hh, pre);
         else
-            fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st);
+            fwd_row_regs<LOGN, RK>(sh, T.twf + (size_t)iq * N, q, qi, x, st, 0, pre);
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = u[(size_t)pk * N + i];
