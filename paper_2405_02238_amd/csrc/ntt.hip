@@ -844,12 +844,21 @@ __device__ __forceinline__ InvRow inv_row(const DevTables &T, const NttArgs &a, 
     return R;
 }
 
+// The factor every inverse output of the row is multiplied by: N^-1, or for
+// STORE_MDR the division's N^-1 t^-1 (P/p_k)^-1.  Read once per row: read in
+// inv_store, the compiler would read it again after every store (it cannot
+// tell the tables from the output row).
 template <int STORE>
-__device__ __forceinline__ void inv_store(const DevTables &T, const InvRow &R, int i, double v, double q, double qi) {
+__device__ __forceinline__ double inv_factor(const DevTables &T, const InvRow &R) {
+    return STORE == STORE_MDR ? T.md_coef[R.rr] : T.ninv[R.prime];
+}
+
+template <int STORE>
+__device__ __forceinline__ void inv_store(const InvRow &R, int i, double v, double f, double q, double qi) {
     if (STORE == STORE_MDR) {
-        gst(R.out)[i] = centerm(mulm(v, T.md_coef[R.rr], q, qi), q, qi);
+        gst(R.out)[i] = centerm(mulm(v, f, q, qi), q, qi);
     } else {
-        double x = mulm(v, T.ninv[R.prime], q, qi);
+        double x = mulm(v, f, q, qi);
         if (STORE == STORE_CANON) x = canonm(centerm(x, q, qi), q);
         gst(R.out)[i] = x;
     }
@@ -954,18 +963,19 @@ k_ntt_inv(DevTables T, NttArgs a) {
     }
     if constexpr (direct_rows<LOGN>()) {
         using RW = Rows<LOGN, RK>;
-        const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+        const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y, f = inv_factor<STORE>(T, R);
         double x[1 << RW::RK];
         inv_row_direct<LOGN, RK>(sh, tw, q, qi, [&](int i) { return gld(R.in)[i]; }, x);
 #pragma unroll
-        for (int b = 0; b < (1 << RW::RK); ++b) inv_store<STORE>(T, R, (int)threadIdx.x + b * RW::NT, x[b], q, qi);
+        for (int b = 0; b < (1 << RW::RK); ++b) inv_store<STORE>(R, (int)threadIdx.x + b * RW::NT, x[b], f, q, qi);
         return;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) sh[lds_ix(i)] = gld(R.in)[i];
     __syncthreads();
     const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
     inv_rows_c<LOGN, 0>(sh, tw, q, qi);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) inv_store<STORE>(T, R, i, sh[lds_ix(i)], q, qi);
+    const double f = inv_factor<STORE>(T, R);
+    for (int i = threadIdx.x; i < N; i += blockDim.x) inv_store<STORE>(R, i, sh[lds_ix(i)], f, q, qi);
 }
 
 // ---- split rows: N = N1 x N2, N1 = 2^a (column length), N2 = 2^b ----
@@ -1167,7 +1177,7 @@ k_ntt_inv_blocks(DevTables T, NttArgs a) {
 template <int STORE>
 __device__ __forceinline__ void inv_cols_direct(const DevTables &T, const InvRow &R, int c0, double *sh) {
     const int sb = (int)threadIdx.x % COL_W, g = (int)threadIdx.x / COL_W;
-    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y;
+    const double q = T.qt[R.prime].x, qi = T.qt[R.prime].y, f = inv_factor<STORE>(T, R);
     const double *__restrict__ tw = T.twi + (size_t)R.prime * (1 << (COL_LA + COL_LB));
     double x[16], w[15];
     // round 1: half-sizes 1..8, rows 16 g + b (block g of the column)
@@ -1201,7 +1211,7 @@ __device__ __forceinline__ void inv_cols_direct(const DevTables &T, const InvRow
     }
     inv_bfly_red<4>(x, w, q, qi);
 #pragma unroll
-    for (int b = 0; b < 16; ++b) inv_store<STORE>(T, R, c0 + sb + ((g + 16 * b) << COL_LB), x[b], q, qi);
+    for (int b = 0; b < 16; ++b) inv_store<STORE>(R, c0 + sb + ((g + 16 * b) << COL_LB), x[b], f, q, qi);
 }
 
 template <int STORE, int LOGN>
@@ -1234,9 +1244,10 @@ k_ntt_inv_cols(DevTables T, NttArgs a) {
     } else {
         inv_stages(sh, tw, la, cw, 1, 0, q, qi);
     }
+    const double f = inv_factor<STORE>(T, R);
     for (int e = threadIdx.x; e < SPLIT_ELEMS; e += blockDim.x) {
         const int cc = e % cw, j = e / cw;
-        inv_store<STORE>(T, R, c0 + cc + (j << lb), sh[lds_ix((cc << la) + j)], q, qi);
+        inv_store<STORE>(R, c0 + cc + (j << lb), sh[lds_ix((cc << la) + j)], f, q, qi);
     }
 }
 
